@@ -1,0 +1,201 @@
+/*
+ * scpl.h -- C ABI of libscpl.so: SCPL video retargeting on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: "Fast Video Retargeting Based on Seam Carving with Parental
+ * Labeling" (C. Zhu, arXiv 1903.03180).  A clip is cut into dynamic
+ * spatiotemporal buffers by the ASDE test (Sec. 3.2, eqs. 7-9); every buffer
+ * is carved to the target width by repeated SCPL iterations (Sec. 3.1): the
+ * uniform energy of the buffer (mean of its motion-aware energy maps, Sec.
+ * 3.3) feeds the cumulative-energy DP of eq. (4), which also carries each
+ * pixel's row-0 parent label; the least child of each parent (eq. 6) is
+ * ranked, up to k seams are traced back and removed from every frame of the
+ * buffer in one pass.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers on the context's device; h_* are
+ *    host pointers.  The caller owns every buffer it passes and the library
+ *    never frees caller memory.  Arrays are dense, row-major, no padding.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is asynchronous unless stated otherwise.  Entry points that return a
+ *    value computed on the device to the host synchronise `stream`.
+ *  - Arguments are validated before any launch; an invalid argument returns
+ *    SCPL_ERR_INVALID_ARG and launches nothing.  On any error the outputs
+ *    are undefined.  A device error raised by earlier asynchronous work is
+ *    reported as SCPL_ERR_DEVICE by the next call that synchronises.
+ *  - A context is used by one host thread at a time.
+ *  - All arithmetic is exact integer arithmetic; results are bit-identical
+ *    from run to run.
+ *
+ * Readings of points the paper leaves open (the same in every entry point):
+ *  - luma Y = (77 R + 150 G + 29 B + 128) >> 8 of interleaved RGB;
+ *  - gradient G = |Gx| + |Gy| of the 3x3 Sobel operator, borders replicated;
+ *  - motion energy e = 2 G + 18 |Y_t - Y_{t-1}| (the 0.4 / 0.6 blend of
+ *    Sec. 3.3 with the difference scaled to the gradient's range), no
+ *    difference term for the clip's first frame; after carving, frame t-1 is
+ *    carved with the same seams as frame t;
+ *  - eq. (4) ties go to the leftmost predecessor; neighbours outside the
+ *    image are skipped;
+ *  - per iteration the per-parent least children are ranked by (cumulative
+ *    energy, column) and k_iter = min(k, parents, width - target) of them
+ *    are removed;
+ *  - ASDE uses the population deviation, per pixel floor(sqrt(n S2 - S1^2));
+ *    a candidate frame is rejected when ASDE > alpha * maxval * sqrt(n-1)/n
+ *    (eq. 9 simplified; n counts the candidate; maxval = 1530 gradient, 7650
+ *    motion), decided exactly; the rejected frame starts the next buffer;
+ *  - the uniform energy is floor(sum of the buffer's energy maps / T).
+ */
+#ifndef SCPL_H
+#define SCPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCPL_OK = 0,
+    SCPL_ERR_INVALID_ARG = 1,
+    SCPL_ERR_OUT_OF_MEMORY = 2,
+    SCPL_ERR_DEVICE = 3,
+    SCPL_ERR_CAPACITY = 4,
+    SCPL_ERR_NOT_READY = 5,
+    SCPL_ERR_INTERNAL = 6
+} scpl_status;
+
+enum {
+    SCPL_ENERGY_GRADIENT = 0, /* e = |Gx| + |Gy|                    (max 1530) */
+    SCPL_ENERGY_MOTION = 1    /* e = 2 (|Gx| + |Gy|) + 18 |Yt - Yt-1| (max 7650) */
+};
+
+/* Limits checked by every entry point. */
+#define SCPL_MAX_WIDTH 32767       /* columns fit int16 */
+#define SCPL_MAX_HEIGHT 32767      /* cumulative energy fits int32 */
+#define SCPL_MAX_PIXELS (1 << 27)  /* H * W, keeps the ASDE test in 128 bits */
+#define SCPL_MAX_FRAMES 16384      /* frames per call */
+#define SCPL_MAX_ALPHA_TERM 1024   /* alpha_num <= 1024, 1 <= alpha_den <= 1024 */
+
+typedef struct {
+    int32_t n_frames;       /* N >= 1 */
+    int32_t height;         /* H >= 1 */
+    int32_t width;          /* W >= 1 */
+    int32_t channels;       /* 1 (luma) or 3 (interleaved RGB), uint8 */
+    int32_t target_width;   /* 1 <= Wt <= W */
+    int32_t seams_per_iter; /* k >= 1; k >= W means every parent's least child (eq. 6) */
+    int32_t energy_mode;    /* SCPL_ENERGY_GRADIENT or SCPL_ENERGY_MOTION */
+    int32_t use_buffer;     /* 1: dynamic spatiotemporal buffer; 0: every frame alone */
+    int32_t alpha_num;      /* alpha = alpha_num / alpha_den (paper: 0.15 .. 0.25) */
+    int32_t alpha_den;
+    int32_t max_buffer;     /* 0: unbounded (paper); > 0: force a new buffer at this length */
+} scpl_params;
+
+typedef struct scpl_ctx scpl_ctx;
+
+/* Create a context on HIP device `hip_device`.  The context owns a
+ * workspace that grows on demand and is freed by scpl_destroy. */
+scpl_status scpl_create(int32_t hip_device, scpl_ctx **out);
+void scpl_destroy(scpl_ctx *ctx);
+const char *scpl_status_str(scpl_status s);
+
+/* Device bytes of workspace the library needs for one clip with params p
+ * (the plain path, one buffer at a time).  Pure host arithmetic. */
+scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
+
+/* Whole retarget of one clip (Secs. 3.1-3.3).
+ * d_frames: N x H x W x C uint8.  d_out: N x H x Wt x C uint8.
+ * d_masks (nullable): N x H x W uint16; 0 = kept, r + 1 = removed in
+ *   iteration r of the frame's buffer (all frames of a buffer share a mask).
+ * d_buffer_id (nullable): N int32, buffer index of each frame.
+ * h_n_buffers (nullable): receives the number of buffers.
+ * The segmentation step synchronises `stream` a few times; the carving is
+ * asynchronous apart from one check of the iteration count per buffer.
+ * Buffers are carved one after another (the plain path). */
+scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
+                          uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream);
+
+/* Many clips at once (the batched path): every buffer of every clip is a job,
+ * and each stage of an SCPL iteration runs as one launch over all jobs, the
+ * iteration loop being captured once into a HIP graph and replayed.
+ * Results are bit-identical to scpl_retarget on each clip alone. */
+typedef struct {
+    scpl_params p;
+    const uint8_t *d_frames;
+    uint8_t *d_out;
+    uint16_t *d_masks;     /* nullable */
+    int32_t *d_buffer_id;  /* nullable */
+} scpl_clip;
+
+scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, void *stream);
+
+/* Per-iteration record of the last scpl_retarget / scpl_retarget_batch call:
+ * for every buffer in order, for every iteration, four int32
+ * (buffer index within its clip, W_r, P_eff, k_iter); clips in order.
+ * Copies at most `cap` records into h_log and stores the total in *h_count. */
+scpl_status scpl_last_log(scpl_ctx *ctx, int32_t *h_log, int64_t cap, int64_t *h_count);
+
+/* ---- kernel timing (measurement) ----
+ * When enabled, every launch of the library's kernels is bracketed by a pair
+ * of HIP events recorded on the launch stream, and graph capture in
+ * scpl_retarget_batch is skipped (the kernels are launched one by one).
+ * scpl_profile_read synchronises the device, returns the summed duration
+ * and launch count of one kernel kind since profiling was (re)enabled. */
+enum {
+    SCPL_KERNEL_LUMA = 0,
+    SCPL_KERNEL_SEGMENT = 1,
+    SCPL_KERNEL_ENERGY = 2,
+    SCPL_KERNEL_DP = 3,
+    SCPL_KERNEL_BORG = 4,
+    SCPL_KERNEL_SELECT = 5,
+    SCPL_KERNEL_FILL = 6,
+    SCPL_KERNEL_COMPACT = 7,
+    SCPL_KERNEL_GATHER = 8,
+    SCPL_KERNEL_INIT = 9,
+    SCPL_KERNEL_COUNT = 10
+};
+scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);
+scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms, int64_t *h_launches);
+
+/* ---- stage entry points (parity checks of single stages) ---- */
+
+/* Luma of npx interleaved RGB pixels (reading of the colour step). */
+scpl_status scpl_luma(scpl_ctx *ctx, const uint8_t *d_rgb, int64_t npx, uint8_t *d_y, void *stream);
+
+/* Energy map of one H x W frame, Sec. 3.3.  d_yprev is nullable (no
+ * difference term).  d_e: H x W int32. */
+scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const uint8_t *d_y,
+                        const uint8_t *d_yprev, int32_t *d_e, void *stream);
+
+/* Cumulative energy, eq. (4), with parent labels (Sec. 3.1) and the
+ * indicator array.  d_u: H x W int32 in [0, 65535].  d_ce_last, d_label_last:
+ * W int32 (last row).  d_dir: H x W int8 in {-1, 0, 1} (predecessor column
+ * minus column; row 0 is 0). */
+scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int32_t *d_ce_last,
+                    int32_t *d_label_last, int8_t *d_dir, void *stream);
+
+/* Per-parent least child (eq. 6) and the k_iter = min(k, P_eff, limit) least
+ * of them by (cumulative energy, column), from the DP's last row.
+ * d_children: at least min(k, W) int32, k_iter columns in increasing order.
+ * h_kiter, h_peff: host results (synchronises `stream`).  Labels must be a
+ * DP's labels (non-decreasing, in [0, W)). */
+scpl_status scpl_select(scpl_ctx *ctx, int32_t W, const int32_t *d_ce_last, const int32_t *d_label_last,
+                        int32_t k, int32_t limit, int32_t *d_children, int32_t *h_kiter, int32_t *h_peff,
+                        void *stream);
+
+/* Trace kk children back through the indicator array (Sec. 3.1).
+ * d_dir: H x W int8 from scpl_dp.  d_children: kk int32 in increasing order.
+ * d_seams: kk x H int32, d_seams[s*H + i] = column of seam s in row i. */
+scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_dir, const int32_t *d_children,
+                           int32_t kk, int32_t *d_seams, void *stream);
+
+/* Buffer segmentation alone (Sec. 3.2) on N x H x W luma.
+ * h_buffer_id: N int32 (host).  h_s_trace (nullable, host): N int64, the
+ * ASDE sum S of each tested candidate, -1 where no test was made.
+ * Synchronises `stream`. */
+scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_luma, int32_t *h_buffer_id,
+                         int64_t *h_s_trace, int32_t *h_n_buffers, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCPL_H */

@@ -1,0 +1,78 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libscpl.so.  Nothing here is part of the C ABI (include/scpl.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scpl {
+
+// Rows per band of the two-level backtrack: the DP's indicator array is cut
+// into bands of kBand rows; for every column at the last row of a band the
+// column it reaches at the last row of the previous band is precomputed
+// (fits int8 because a seam moves at most one column per row).
+constexpr int kBand = 64;
+// Frames per launch of the speculative ASDE scan.
+constexpr int kSegWindow = 64;
+constexpr int kDpThreads = 1024;
+
+// One buffer of one clip: a carving job.  Every iteration of SCPL runs on
+// all jobs of a launch at once; each job advances at its own pace (k_iter
+// depends on its parents) and a finished job makes every kernel return.
+struct Job {
+    const uint8_t *frames;  // clip, N x H x W x C
+    const uint8_t *luma;    // clip luma, N x H x W (== frames when C == 1)
+    uint8_t *out;           // clip output, N x H x Wt x C
+    uint16_t *masks;        // clip masks, N x H x W, or null
+    int32_t H, W, C, Wt, k, mode;
+    int32_t t0, T;          // frames [t0, t0 + T) of the clip
+    int32_t has_prev;       // frame t0 - 1 is the (carved) predecessor of t0
+    int32_t Wp;             // padded row pitch of the job's 2-D workspace
+    int32_t nb;             // bands of kBand rows
+    int32_t kcap;           // min(k, W): room for children / seams
+    int32_t logcap;         // records in log
+    int32_t buffer_index;   // index of the buffer within its clip
+    // workspace (device)
+    int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
+    uint16_t *U;            // uniform energy, H x Wp
+    int8_t *dir;            // indicator array, H x Wp
+    int8_t *borg;           // band origins, nb x Wp
+    uint16_t *bmask;        // buffer mask in original columns, H x W
+    int32_t *ce_last;       // DP last row, Wp
+    int32_t *lab_last;      // labels of the last row, Wp
+    uint64_t *keys;         // 2 x Wp scratch for the selection
+    int32_t *children;      // kcap
+    int32_t *bcol;          // kcap x nb: seam column at the last row of each band
+    int16_t *seams;         // kcap x H
+    int32_t *log;           // logcap x 4: (W_r, P_eff, k_iter, 0)
+    int32_t *state;         // [0]: iteration at which W_r reached Wt (-1 while running)
+};
+
+struct SegArgs {
+    const uint8_t *luma;  // N x H x W
+    uint32_t *s1;         // H x W state
+    uint64_t *s2;         // H x W state
+    unsigned long long *sout;  // kSegWindow sums
+    int32_t H, W, mode;
+    int32_t t0;           // buffer start
+    int32_t tb, te;       // candidate frames [tb, te)
+    int32_t init;         // 1: start the moments from frame t0
+};
+
+// Kernel launchers (scpl_kernels.hip).  All take the stream explicitly.
+void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
+void launch_seg_window(const SegArgs &a, hipStream_t s);
+void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
+void launch_energy(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
+void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s);
+void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Wmax, hipStream_t s);
+void launch_select(const Job *d_jobs, int njobs, int r, int Wmax, int nbmax, size_t lds_cap, hipStream_t s);
+void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s);
+void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, hipStream_t s);
+void launch_compact(const Job *d_jobs, int njobs, int r, int Hmax, hipStream_t s);
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s);
+void launch_u32_to_u16(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
+void launch_u16_to_i32(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
+void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s);
+
+}  // namespace scpl

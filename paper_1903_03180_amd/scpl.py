@@ -1,0 +1,273 @@
+"""Python binding of libscpl.so (C ABI in include/scpl.h).
+
+Argument marshalling only: every step of the retarget runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams; tensors are passed
+by data pointer.  The module raises at import if libscpl.so is missing:
+there is no fallback implementation.
+
+The `scpl_*` functions mirror the C entry points one to one (raw pointers
+and sizes).  `Context` wraps them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscpl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libscpl.so not built ({LIB_PATH}); run paper_1903_03180_amd/build.py")
+
+_lib = C.CDLL(LIB_PATH)
+
+SCPL_OK = 0
+SCPL_ERR_INVALID_ARG = 1
+SCPL_ERR_OUT_OF_MEMORY = 2
+SCPL_ERR_DEVICE = 3
+SCPL_ERR_CAPACITY = 4
+SCPL_ERR_NOT_READY = 5
+SCPL_ERR_INTERNAL = 6
+SCPL_ENERGY_GRADIENT = 0
+SCPL_ENERGY_MOTION = 1
+
+EXPORTS = [
+    "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
+    "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
+    "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read",
+]
+
+KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "compact", "gather", "init"]
+
+
+class scpl_params(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "n_frames", "height", "width", "channels", "target_width", "seams_per_iter", "energy_mode",
+        "use_buffer", "alpha_num", "alpha_den", "max_buffer")]
+
+
+class scpl_clip(C.Structure):
+    _fields_ = [("p", scpl_params), ("d_frames", C.c_void_p), ("d_out", C.c_void_p), ("d_masks", C.c_void_p),
+                ("d_buffer_id", C.c_void_p)]
+
+
+_P, _I32, _I64 = C.c_void_p, C.c_int32, C.c_int64
+_sig = {
+    "scpl_create": ([_I32, C.POINTER(C.c_void_p)], C.c_int),
+    "scpl_destroy": ([_P], None),
+    "scpl_status_str": ([C.c_int], C.c_char_p),
+    "scpl_workspace_size": ([C.POINTER(scpl_params), C.POINTER(C.c_uint64)], C.c_int),
+    "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
+    "scpl_retarget_batch": ([_P, C.POINTER(scpl_clip), _I32, _P], C.c_int),
+    "scpl_last_log": ([_P, _P, _I64, C.POINTER(_I64)], C.c_int),
+    "scpl_luma": ([_P, _P, _I64, _P, _P], C.c_int),
+    "scpl_energy": ([_P, _I32, _I32, _I32, _P, _P, _P, _P], C.c_int),
+    "scpl_dp": ([_P, _I32, _I32, _P, _P, _P, _P, _P], C.c_int),
+    "scpl_select": ([_P, _I32, _P, _P, _I32, _I32, _P, C.POINTER(_I32), C.POINTER(_I32), _P], C.c_int),
+    "scpl_backtrack": ([_P, _I32, _I32, _P, _P, _I32, _P, _P], C.c_int),
+    "scpl_segment": ([_P, C.POINTER(scpl_params), _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
+    "scpl_profile_enable": ([_P, _I32], C.c_int),
+    "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f
+
+
+class ScplError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {scpl_status_str(status).decode()} ({status})")
+
+
+def _check(st: int, what: str) -> None:
+    if st != SCPL_OK:
+        raise ScplError(st, what)
+
+
+@dataclass
+class Params:
+    n_frames: int
+    height: int
+    width: int
+    channels: int
+    target_width: int
+    seams_per_iter: int
+    energy_mode: int = SCPL_ENERGY_MOTION
+    use_buffer: int = 1
+    alpha_num: int = 1
+    alpha_den: int = 5
+    max_buffer: int = 0
+
+    def c(self) -> scpl_params:
+        return scpl_params(self.n_frames, self.height, self.width, self.channels, self.target_width,
+                           self.seams_per_iter, self.energy_mode, self.use_buffer, self.alpha_num,
+                           self.alpha_den, self.max_buffer)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    assert t.is_contiguous(), "tensors passed to libscpl must be contiguous"
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def params_for(frames, target_width: int, seams_per_iter: int, **kw) -> Params:
+    if frames.dim() == 3:
+        N, H, W = frames.shape
+        Cc = 1
+    elif frames.dim() == 4:
+        N, H, W, Cc = frames.shape
+    else:
+        raise ValueError("frames must be N x H x W or N x H x W x 3 uint8")
+    return Params(N, H, W, Cc, target_width, seams_per_iter, **kw)
+
+
+class Context:
+    """A libscpl context on one HIP device (one host thread at a time)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(scpl_create(device, C.byref(h)), "scpl_create")
+        self.h = h
+        self.device = device
+
+    def close(self) -> None:
+        if self.h:
+            scpl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- whole path
+    def retarget(self, frames, target_width: int, seams_per_iter: int, want_masks: bool = True, stream=None,
+                 **kw):
+        """frames: uint8 cuda tensor N x H x W (luma) or N x H x W x 3 (RGB).
+        Returns dict(out, masks, buffer_id, n_buffers)."""
+        import torch
+        p = params_for(frames, target_width, seams_per_iter, **kw)
+        shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if frames.dim() == 4 else ())
+        out = torch.empty(shp, dtype=torch.uint8, device=frames.device)
+        masks = torch.empty((p.n_frames, p.height, p.width), dtype=torch.int16, device=frames.device) \
+            if want_masks else None
+        bid = torch.empty(p.n_frames, dtype=torch.int32, device=frames.device)
+        nb = C.c_int32(0)
+        cp = p.c()
+        _check(scpl_retarget(self.h, C.byref(cp), _ptr(frames), _ptr(out), _ptr(masks), _ptr(bid), C.byref(nb),
+                             _stream(stream)), "scpl_retarget")
+        return dict(out=out, masks=masks, buffer_id=bid, n_buffers=int(nb.value))
+
+    def retarget_batch(self, clips, stream=None):
+        """clips: list of dicts with keys frames (cuda uint8 tensor),
+        target_width, seams_per_iter and optional Params fields, and
+        optionally out / masks / buffer_id tensors (allocated when absent,
+        masks only when want_masks is true).  Returns the list of dicts with
+        the outputs filled in."""
+        import torch
+        arr = (scpl_clip * len(clips))()
+        for i, c in enumerate(clips):
+            fr = c["frames"]
+            kw = {k: c[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer") if k in c}
+            p = params_for(fr, c["target_width"], c["seams_per_iter"], **kw)
+            shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
+            if c.get("out") is None:
+                c["out"] = torch.empty(shp, dtype=torch.uint8, device=fr.device)
+            if c.get("masks") is None and c.get("want_masks", False):
+                c["masks"] = torch.empty((p.n_frames, p.height, p.width), dtype=torch.int16, device=fr.device)
+            if c.get("buffer_id") is None:
+                c["buffer_id"] = torch.empty(p.n_frames, dtype=torch.int32, device=fr.device)
+            arr[i] = scpl_clip(p.c(), _ptr(fr), _ptr(c["out"]), _ptr(c.get("masks")), _ptr(c["buffer_id"]))
+        _check(scpl_retarget_batch(self.h, arr, len(clips), _stream(stream)), "scpl_retarget_batch")
+        return clips
+
+    def last_log(self):
+        """(buffer, W_r, P_eff, k_iter) per iteration of the last call."""
+        import numpy as np
+        n = C.c_int64(0)
+        _check(scpl_last_log(self.h, None, 0, C.byref(n)), "scpl_last_log")
+        a = np.zeros((max(n.value, 1), 4), dtype=np.int32)
+        _check(scpl_last_log(self.h, a.ctypes.data, n.value, C.byref(n)), "scpl_last_log")
+        return a[:n.value]
+
+    # ---------------------------------------------------------- timing
+    def profile(self, on: bool = True) -> None:
+        """Start (and reset) or stop per-kernel event timing."""
+        _check(scpl_profile_enable(self.h, 1 if on else 0), "scpl_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel: (total_ms, launches)} since profiling was enabled."""
+        out = {}
+        for i, name in enumerate(KERNELS):
+            ms, n = C.c_double(0), C.c_int64(0)
+            _check(scpl_profile_read(self.h, i, C.byref(ms), C.byref(n)), "scpl_profile_read")
+            out[name] = (ms.value, n.value)
+        return out
+
+    # ---------------------------------------------------------- stages
+    def luma(self, rgb, stream=None):
+        import torch
+        y = torch.empty(rgb.shape[:-1], dtype=torch.uint8, device=rgb.device)
+        _check(scpl_luma(self.h, _ptr(rgb), y.numel(), _ptr(y), _stream(stream)), "scpl_luma")
+        return y
+
+    def energy(self, y, yprev=None, mode: int = SCPL_ENERGY_GRADIENT, stream=None):
+        import torch
+        H, W = y.shape
+        e = torch.empty((H, W), dtype=torch.int32, device=y.device)
+        _check(scpl_energy(self.h, H, W, mode, _ptr(y), _ptr(yprev), _ptr(e), _stream(stream)), "scpl_energy")
+        return e
+
+    def dp(self, u, stream=None):
+        import torch
+        H, W = u.shape
+        ce = torch.empty(W, dtype=torch.int32, device=u.device)
+        lab = torch.empty(W, dtype=torch.int32, device=u.device)
+        d = torch.empty((H, W), dtype=torch.int8, device=u.device)
+        _check(scpl_dp(self.h, H, W, _ptr(u), _ptr(ce), _ptr(lab), _ptr(d), _stream(stream)), "scpl_dp")
+        return ce, lab, d
+
+    def select(self, ce_last, label_last, k: int, limit: int | None = None, stream=None):
+        import torch
+        W = ce_last.shape[0]
+        if limit is None:
+            limit = W
+        ch = torch.zeros(max(min(k, W), 1), dtype=torch.int32, device=ce_last.device)
+        kk, pe = C.c_int32(0), C.c_int32(0)
+        _check(scpl_select(self.h, W, _ptr(ce_last), _ptr(label_last), k, limit, _ptr(ch), C.byref(kk),
+                           C.byref(pe), _stream(stream)), "scpl_select")
+        return ch[:kk.value], int(pe.value)
+
+    def backtrack(self, d, children, stream=None):
+        import torch
+        H, W = d.shape
+        kk = children.shape[0]
+        seams = torch.zeros((max(kk, 1), H), dtype=torch.int32, device=d.device)
+        _check(scpl_backtrack(self.h, H, W, _ptr(d), _ptr(children), kk, _ptr(seams), _stream(stream)),
+               "scpl_backtrack")
+        return seams[:kk]
+
+    def segment(self, luma, energy_mode=SCPL_ENERGY_MOTION, use_buffer=1, alpha_num=1, alpha_den=5, max_buffer=0,
+                stream=None):
+        import numpy as np
+        N, H, W = luma.shape
+        p = Params(N, H, W, 1, W, 1, energy_mode, use_buffer, alpha_num, alpha_den, max_buffer).c()
+        bid = np.zeros(N, dtype=np.int32)
+        tr = np.zeros(N, dtype=np.int64)
+        nb = C.c_int32(0)
+        _check(scpl_segment(self.h, C.byref(p), _ptr(luma), bid.ctypes.data, tr.ctypes.data, C.byref(nb),
+                            _stream(stream)), "scpl_segment")
+        return bid, tr

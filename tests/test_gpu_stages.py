@@ -1,0 +1,114 @@
+"""GPU parity of every stage entry point of libscpl.so against the CPU oracle,
+element by element and bit-exact (all arithmetic is integer)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1903_03180_amd import scpl
+    c = scpl.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("npx", [1, 15, 16, 17, 4096, 100003])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_luma(ctx, orc, npx, offset):
+    rng = np.random.default_rng(npx + offset)
+    rgb = rng.integers(0, 256, size=(npx + offset, 3)).astype(np.uint8)
+    want = orc.luma(rgb[offset:])
+    d = dev(rgb)[offset:]
+    got = host(ctx.luma(d))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (5, 70), (37, 129), (130, 300), (64, 48)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_energy(ctx, orc, shape, mode):
+    rng = np.random.default_rng(sum(shape) * 3 + mode)
+    y = rng.integers(0, 256, size=shape).astype(np.uint8)
+    yp = rng.integers(0, 256, size=shape).astype(np.uint8)
+    got = host(ctx.energy(dev(y), dev(yp) if mode else None, mode))
+    assert np.array_equal(got, orc.energy(y, yp if mode else None, mode))
+    if mode:
+        got = host(ctx.energy(dev(y), None, mode))
+        assert np.array_equal(got, orc.energy(y, None, mode))
+
+
+DP_SHAPES = [(1, 1), (1, 7), (7, 1), (3, 2), (37, 1100), (70, 2500), (130, 65), (5, 5000), (200, 1920),
+             (65, 129), (64, 64), (129, 3)]
+
+
+@pytest.mark.parametrize("shape", DP_SHAPES)
+@pytest.mark.parametrize("hi", [3, 7650])
+def test_dp(ctx, orc, shape, hi):
+    rng = np.random.default_rng(shape[0] * 7 + shape[1] + hi)
+    u = rng.integers(0, hi + 1, size=shape).astype(np.int32)
+    ce, lab, d = ctx.dp(dev(u))
+    oce, olab, od = orc.dp(u)
+    assert np.array_equal(host(ce), oce[-1])
+    assert np.array_equal(host(lab), olab[-1])
+    assert np.array_equal(host(d), od)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (5, 6), (60, 1920), (9, 3000), (40, 4100)])
+@pytest.mark.parametrize("k", [1, 3, 16, 10**6])
+def test_select(ctx, orc, shape, k):
+    rng = np.random.default_rng(shape[1] + k % 1000)
+    u = rng.integers(0, 4, size=shape).astype(np.int32)
+    oce, olab, od = orc.dp(u)
+    W = shape[1]
+    for limit in sorted({W, max(1, W // 3), 1}):
+        ch, peff = ctx.select(dev(oce[-1]), dev(olab[-1]), k, limit)
+        och, opeff = orc.select(oce[-1], olab[-1], k, limit)
+        assert peff == opeff
+        assert np.array_equal(host(ch), och)
+
+
+@pytest.mark.parametrize("shape", [(1, 5), (2, 9), (64, 64), (65, 70), (200, 300), (129, 1920), (1080, 256)])
+@pytest.mark.parametrize("k", [1, 5, 32])
+def test_backtrack(ctx, orc, shape, k):
+    rng = np.random.default_rng(shape[0] + 13 * shape[1] + k)
+    u = rng.integers(0, 20, size=shape).astype(np.int32)
+    oce, olab, od = orc.dp(u)
+    och, _ = orc.select(oce[-1], olab[-1], k)
+    seams = ctx.backtrack(dev(od), dev(och))
+    assert np.array_equal(host(seams), orc.backtrack(od, och))
+
+
+def _clip(seed, N, H, W, C=1, cut=None):
+    from paper_1903_03180_amd import synth
+    return synth.make_clip(seed, N, H, W, C=C, n_obj=3, cut_at=cut, lattice=8, max_speed=5)
+
+
+@pytest.mark.parametrize("alpha", [(3, 20), (1, 5), (1, 4), (1, 40), (0, 1)])
+@pytest.mark.parametrize("mode", [1, 0])
+def test_segment(ctx, orc, alpha, mode):
+    Y = _clip(71, 150, 21, 35, cut=90)
+    bid, tr = ctx.segment(dev(Y), energy_mode=mode, alpha_num=alpha[0], alpha_den=alpha[1])
+    obid, otr = orc.segment(Y, mode, 1, alpha[0], alpha[1])
+    assert np.array_equal(bid, obid)
+    assert np.array_equal(tr, otr)
+
+
+def test_segment_max_buffer_and_off(ctx, orc):
+    Y = _clip(72, 40, 16, 20)
+    for mb in (1, 2, 7, 64, 65):
+        bid, tr = ctx.segment(dev(Y), alpha_num=1, alpha_den=1, max_buffer=mb)
+        obid, otr = orc.segment(Y, 1, 1, 1, 1, mb)
+        assert np.array_equal(bid, obid) and np.array_equal(tr, otr)
+    bid, _ = ctx.segment(dev(Y), use_buffer=0)
+    assert bid.tolist() == list(range(40))
