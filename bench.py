@@ -1,13 +1,22 @@
-"""Benchmark: SCPL video retargeting of a 1080p clip on one MI355X.
+"""Benchmark: SCPL video retargeting of 1080p clips on one MI355X.
 
-A step is one whole retarget of the workload clip (luma, buffer
-segmentation, every SCPL iteration of every buffer, output gather) with the
-frames already resident in HBM.  The reported value is frames per second of
-the batched path (all buffers of the clip advance together, one launch per
-stage per iteration); the plain path (one buffer after another) is timed
-beside it.  The oracle (plain C, one core) is timed on a bounded sample.
+A step is one whole retarget of the workload (luma, buffer segmentation,
+every SCPL iteration of every buffer, output gather) with the frames already
+resident in HBM.  Workloads:
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1080p|4k]
+  1080p-batch16 (default)  16 clips of the 1080p generator (seeds 2000-2015):
+                           120 frames 1920x1080 RGB each, scene cut at frame
+                           60, retargeted to 1440 wide at k = 16, alpha = 1/5
+  1080p                    the single 1080p clip (seed 2)
+  4k                       60 frames 3840x2160 luma -> 2880 wide, k = 32
+
+`value` is frames per second of the batched path (every buffer of every
+clip advances together, one launch per stage per iteration, iterations
+replayed from a HIP graph); the plain path (one buffer after another, clip
+after clip) is timed beside it.  The oracle (plain C, one core) is timed on
+a bounded sample of the first clip.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
 from __future__ import annotations
 
@@ -21,41 +30,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "1080p frames/s (batched vs plain, bit-exact); HBM GB/s; p50/p99 latency"
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def energy_bytes(log_rows, bid, H, mode):
-    """Algorithmic bytes of the energy kernel over one retarget: per
-    iteration of a buffer of T frames at width W_r, every carved pixel of
-    every frame (plus the predecessor of the first frame in motion mode) is
-    read once (1 B), the column map is read once (2 B per carved pixel) and
-    the uniform energy written once (2 B per carved pixel)."""
-    import numpy as np
-    starts = {}
-    for t in range(len(bid)):
-        b = int(bid[t])
-        if b not in starts:
-            starts[b] = [t, 0]
-        starts[b][1] += 1
-    total = 0
-    for b, Wr, _peff, _kk in log_rows.tolist():
-        t0, T = starts[b]
-        frames = T + (1 if (mode == 1 and t0 > 0) else 0)
-        total += frames * H * Wr + 4 * H * Wr
-    return total
+def _gen(args):
+    kind, seed = args
+    from paper_1903_03180_amd import synth
+    return synth.clip_1080p(seed) if kind == "1080p" else synth.clip_4k(seed)
+
+
+def make_workload(name):
+    from multiprocessing import Pool
+    if name == "1080p-batch16":
+        seeds = list(range(2000, 2016))
+        with Pool(8) as pool:
+            clips = pool.map(_gen, [("1080p", s) for s in seeds])
+        return clips, 1440, 16, ("16 clips x 120 frames 1920x1080 RGB (1080p generator, seeds 2000-2015) -> 1440 "
+                                 "wide, k=16 seams/iteration, alpha=1/5, motion energy")
+    if name == "1080p":
+        return [_gen(("1080p", 2))], 1440, 16, ("1080p RGB clip: 120 frames 1920x1080 -> 1440 wide, k=16 "
+                                                "seams/iteration, alpha=1/5, motion energy")
+    return [_gen(("4k", 3))], 2880, 32, ("4K luma clip: 60 frames 3840x2160 -> 2880 wide, k=32 seams/iteration, "
+                                         "alpha=1/5, motion energy")
+
+
+def dp_bytes(log_rows, H):
+    """Algorithmic bytes of the DP over one retarget: per iteration of a
+    buffer at width W_r, the 4-byte key row of every carved pixel is read
+    once and its 1-byte indicator written once."""
+    return sum(5 * H * int(Wr) for _b, Wr, _p, _k in log_rows.tolist())
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="1080p", choices=["1080p", "4k"])
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--cpu-frames", type=int, default=4, help="frames of the oracle's bounded sample")
+    ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k"])
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -65,33 +82,32 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1903_03180_amd import scpl, synth
+    from paper_1903_03180_amd import scpl
 
-    if args.workload == "1080p":
-        frames_np = synth.clip_1080p(2)
-        Wt, k, anum, aden = 1440, 16, 1, 5
-        wname = "1080p RGB clip: 120 frames 1920x1080 -> 1440 wide, k=16 seams/iteration, alpha=1/5, motion energy"
-    else:
-        frames_np = synth.clip_4k(3)
-        Wt, k, anum, aden = 2880, 32, 1, 5
-        wname = "4K luma clip: 60 frames 3840x2160 -> 2880 wide, k=32 seams/iteration, alpha=1/5, motion energy"
-    N, H, W = frames_np.shape[:3]
-    log(f"workload {wname}; generated {frames_np.nbytes / 1e6:.0f} MB")
-    frames = torch.from_numpy(frames_np).cuda()
-    out = torch.empty((N, H, Wt) + frames_np.shape[3:], dtype=torch.uint8, device="cuda")
-    bid = torch.empty(N, dtype=torch.int32, device="cuda")
+    t_gen = time.perf_counter()
+    clips_np, Wt, k, wname = make_workload(args.workload)
+    N, H, W = clips_np[0].shape[:3]
+    n_frames = sum(c.shape[0] for c in clips_np)
+    log(f"workload {wname}; generated {sum(c.nbytes for c in clips_np) / 1e9:.2f} GB in "
+        f"{time.perf_counter() - t_gen:.1f} s")
     ctx = scpl.Context(0)
-    clip = dict(frames=frames, target_width=Wt, seams_per_iter=k, alpha_num=anum, alpha_den=aden, out=out,
-                buffer_id=bid)
+    clips = []
+    for c in clips_np:
+        fr = torch.from_numpy(c).cuda()
+        clips.append(dict(frames=fr, target_width=Wt, seams_per_iter=k, alpha_num=1, alpha_den=5,
+                          out=torch.empty((c.shape[0], H, Wt) + c.shape[3:], dtype=torch.uint8, device="cuda"),
+                          buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
+    torch.cuda.synchronize()
 
     def step_batched():
-        ctx.retarget_batch([clip])
+        ctx.retarget_batch(clips)
 
     for i in range(args.warmup):
         step_batched()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
 
+    # timed region: every kernel launch bracketed by HIP events on its stream
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -102,33 +118,40 @@ def main() -> int:
     prof = ctx.profile_read()
     ctx.profile(False)
     log_rows = ctx.last_log()
-    bid_np = bid.cpu().numpy()
+    nbuf = sum(int(c["buffer_id"].max().item()) + 1 for c in clips)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fps = N * args.steps / (t1 - t0)
-    log(f"batched: {ms_per_step:.2f} ms/step, {fps:.1f} frames/s, {int(bid_np.max()) + 1} buffers, "
+    fps = n_frames * args.steps / (t1 - t0)
+    log(f"batched: {ms_per_step:.2f} ms/step, {fps:.1f} frames/s, {nbuf} buffers, "
         f"{len(log_rows)} buffer-iterations")
-
-    # dominant kernel and its roofline
-    ktime = {kname: v[0] for kname, v in prof.items()}
-    dom = max(ktime, key=ktime.get)
-    e_ms, e_n = prof["energy"]
-    e_bytes_step = energy_bytes(log_rows, bid_np, H, 1)
-    e_launch_ms = e_ms / max(e_n, 1)
-    e_bytes_launch = e_bytes_step * args.steps / max(e_n, 1)
-    achieved = e_bytes_launch / (e_launch_ms * 1e-3) / 1e9
     log("kernel time per step (ms): " + ", ".join(f"{kn}={v[0] / args.steps:.3f}" for kn, v in prof.items() if v[1]))
 
-    # plain path
+    # graph-replayed timing of the same batched step (no per-launch events)
+    g0 = time.perf_counter()
+    for i in range(args.steps):
+        step_batched()
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    fps_graph = n_frames * args.steps / (g1 - g0)
+    log(f"batched (graph, no event timing): {(g1 - g0) * 1e3 / args.steps:.2f} ms/step, {fps_graph:.1f} frames/s")
+
+    # dominant kernel and its roofline
+    ktime = {kn: v[0] for kn, v in prof.items()}
+    dom = max(ktime, key=ktime.get)
+    dp_ms, dp_n = prof["dp"]
+    dp_launch_ms = dp_ms / max(dp_n, 1)
+    dp_bytes_launch = dp_bytes(log_rows, H) * args.steps / max(dp_n, 1)
+    achieved = dp_bytes_launch / (dp_launch_ms * 1e-3) / 1e9
+
+    # plain path: clips one after another, buffers one after another
     plain_fps = None
     if args.plain_steps > 0:
-        ctx.retarget(frames, Wt, k, want_masks=False, alpha_num=anum, alpha_den=aden)
-        torch.cuda.synchronize()
         p0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            ctx.retarget(frames, Wt, k, want_masks=False, alpha_num=anum, alpha_den=aden)
+            for c in clips:
+                ctx.retarget(c["frames"], Wt, k, want_masks=False, alpha_num=1, alpha_den=5)
         torch.cuda.synchronize()
         p1 = time.perf_counter()
-        plain_fps = N * args.plain_steps / (p1 - p0)
+        plain_fps = n_frames * args.plain_steps / (p1 - p0)
         log(f"plain: {(p1 - p0) * 1e3 / args.plain_steps:.2f} ms/step, {plain_fps:.1f} frames/s")
 
     cpu = None
@@ -136,15 +159,16 @@ def main() -> int:
         import oracle
         nf = min(args.cpu_frames, N)
         c0 = time.perf_counter()
-        oracle.retarget(frames_np[:nf], Wt, k, mode=1, use_buffer=1, anum=anum, aden=aden, want_masks=False)
+        oracle.retarget(clips_np[0][:nf], Wt, k, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
         c1 = time.perf_counter()
         cpu = {"value": round(nf / (c1 - c0), 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {nf} frames of the same clip, whole retarget (segmentation + every iteration), "
-                         f"{c1 - c0:.1f} s on one core"}
+               "sample": f"first {nf} frames of the first clip, whole retarget (segmentation and every "
+                         f"iteration of the sample's buffers), {c1 - c0:.1f} s on one core"}
         log(f"oracle: {nf} frames in {c1 - c0:.1f} s")
 
+    b_alg_frame = (H * W * clips_np[0].shape[-1] if clips_np[0].ndim == 4 else H * W)
     line = {
-        "metric": "1080p frames/s (batched vs plain, bit-exact); HBM GB/s; p50/p99 latency",
+        "metric": METRIC,
         "value": round(fps, 2),
         "unit": "frames/s",
         "n_gpus": 1,
@@ -156,16 +180,18 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u8/int32",
         "data": "synthetic",
-        "config": {"workload": wname, "path": "batched (all buffers per launch)", "frames": N, "height": H,
-                   "width": W, "target_width": Wt, "seams_per_iter": k,
-                   "buffers": int(bid_np.max()) + 1, "buffer_iterations": int(len(log_rows))},
+        "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
+                   "clips": len(clips), "frames": n_frames, "height": H, "width": W, "target_width": Wt,
+                   "seams_per_iter": k, "buffers": nbuf, "buffer_iterations": int(len(log_rows))},
+        "value_graph_no_events": round(fps_graph, 2),
         "plain_fps": None if plain_fps is None else round(plain_fps, 2),
         "batched_over_plain": None if plain_fps is None else round(fps / plain_fps, 3),
         "kernel_ms_per_step": {kn: round(v[0] / args.steps, 4) for kn, v in prof.items() if v[1]},
         "dominant_kernel": dom,
-        "roofline": {"kernel": "energy", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": "dp", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": int(e_bytes_launch), "launch_ms": round(e_launch_ms, 4)},
+                     "bytes_per_launch": int(dp_bytes_launch), "launch_ms": round(dp_launch_ms, 4)},
+        "input_bytes_per_frame": b_alg_frame,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

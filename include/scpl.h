@@ -75,6 +75,7 @@ enum {
 #define SCPL_MAX_PIXELS (1 << 27)  /* H * W, keeps the ASDE test in 128 bits */
 #define SCPL_MAX_FRAMES 16384      /* frames per call */
 #define SCPL_MAX_ALPHA_TERM 1024   /* alpha_num <= 1024, 1 <= alpha_den <= 1024 */
+#define SCPL_MAX_DP_STAGE_HEIGHT 16383 /* scpl_dp with energies up to 65535 */
 
 typedef struct {
     int32_t n_frames;       /* N >= 1 */
@@ -151,7 +152,8 @@ enum {
     SCPL_KERNEL_COMPACT = 7,
     SCPL_KERNEL_GATHER = 8,
     SCPL_KERNEL_INIT = 9,
-    SCPL_KERNEL_COUNT = 10
+    SCPL_KERNEL_UPDATE = 10,
+    SCPL_KERNEL_COUNT = 11
 };
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);
 scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms, int64_t *h_launches);
@@ -167,7 +169,8 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
                         const uint8_t *d_yprev, int32_t *d_e, void *stream);
 
 /* Cumulative energy, eq. (4), with parent labels (Sec. 3.1) and the
- * indicator array.  d_u: H x W int32 in [0, 65535].  d_ce_last, d_label_last:
+ * indicator array.  d_u: H x W int32 in [0, 65535], H <= 16383 (so that
+ * 4 x the cumulative energy fits 32 bits).  d_ce_last, d_label_last:
  * W int32 (last row).  d_dir: H x W int8 in {-1, 0, 1} (predecessor column
  * minus column; row 0 is 0). */
 scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int32_t *d_ce_last,

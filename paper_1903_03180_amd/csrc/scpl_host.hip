@@ -105,10 +105,29 @@ struct Bump {
     }
 };
 
+// Rows per band: 64, or more for wide frames so that the band origins of
+// a whole frame (bands x width bytes) still fit in the selection kernel's
+// LDS next to its keys (16 bytes per column); int8 offsets cap it at 120.
+int32_t band_rows(int32_t H, int32_t W, size_t lds_cap)
+{
+    const size_t keys = (size_t)16 * W;
+    for (int32_t B : {64, 96, 120}) {
+        const size_t nb = (size_t)(H + B - 1) / B;
+        if (keys + nb * (size_t)W <= lds_cap) return B;
+    }
+    return kBandMax;
+}
+
+size_t g_lds_cap = 65536;  // set from the device at context creation
+
 struct JobShape {
     int32_t H, W, Wt, k;
+    int32_t Q = 0;  // DP columns per thread of the launch the job runs in (0: its own width decides)
     int32_t Wp() const { return (int32_t)align_up((size_t)W, 64); }
-    int32_t nb() const { return (H + kBand - 1) / kBand; }
+    int32_t q() const { return Q > 0 ? Q : dp_columns_per_thread(W); }
+    int32_t Wq() const { return q() * dp_threads(W, q()); }
+    int32_t B() const { return band_rows(H, W, g_lds_cap); }
+    int32_t nb() const { return (H + B() - 1) / B(); }
     int32_t kcap() const { return std::min(k, W); }
     int32_t logcap() const { return W - Wt + 2; }
 };
@@ -118,7 +137,8 @@ size_t job_bytes(const JobShape &s)
     const size_t H = s.H, Wp = s.Wp(), W = s.W, nb = s.nb(), kc = s.kcap(), lc = s.logcap();
     size_t b = 0;
     b += 2 * align_up(H * Wp * 2);       // M0, M1
-    b += align_up(H * Wp * 2);           // U
+    b += 2 * align_up((H + 1) * (size_t)s.Wq() * 4);  // K0, K1
+    b += 2 * align_up(H * Wp * 4);       // SE0, SE1
     b += align_up(H * Wp);               // dir
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
@@ -139,13 +159,18 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.Wt = s.Wt;
     J.k = s.k;
     J.Wp = (int32_t)Wp;
+    J.Wq = s.Wq();
+    J.B = s.B();
     J.nb = (int32_t)nb;
     J.kcap = (int32_t)kc;
     J.logcap = (int32_t)lc;
     J.M0 = bp.take<int16_t>(H * Wp);
     J.M1 = bp.take<int16_t>(H * Wp);
-    J.U = bp.take<uint16_t>(H * Wp);
-    J.dir = bp.take<int8_t>(H * Wp);
+    J.K0 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
+    J.K1 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
+    J.SE0 = bp.take<uint32_t>(H * Wp);
+    J.SE1 = bp.take<uint32_t>(H * Wp);
+    J.dir = bp.take<uint8_t>(H * Wp);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
     J.ce_last = bp.take<int32_t>(Wp);
@@ -318,41 +343,43 @@ scpl_status segment_clip(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
 // ------------------------------------------------------------- iterations
 
 struct LaunchShape {
-    int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0;
+    int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0, Q = 0;
     void add(const JobShape &s)
     {
         Hmax = std::max(Hmax, s.H);
         Wmax = std::max(Wmax, s.W);
         nbmax = std::max(nbmax, s.nb());
         kmax = std::max(kmax, s.kcap());
+        Bmax = std::max(Bmax, s.B());
+        Q = std::max(Q, s.q());
     }
 };
 
 void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const LaunchShape &ls, hipStream_t s)
 {
     {
-        ProfScope ps(ctx, SCPL_KERNEL_ENERGY, s);
-        launch_energy(d_jobs, nj, r, ls.Hmax, ls.Wmax, s);
-    }
-    {
         ProfScope ps(ctx, SCPL_KERNEL_DP, s);
-        launch_dp(d_jobs, nj, r, ls.Wmax, s);
+        launch_dp(d_jobs, nj, r, ls.Wmax, ls.Q, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
-        launch_borg(d_jobs, nj, r, ls.nbmax, ls.Wmax, s);
+        launch_borg(d_jobs, nj, r, ls.nbmax, ls.Bmax, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_SELECT, s);
-        launch_select(d_jobs, nj, r, ls.Wmax, ls.nbmax, ctx->lds_cap, s);
+        launch_select(d_jobs, nj, r, 0, ctx->lds_cap, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_FILL, s);
-        launch_fill(d_jobs, nj, r, ls.kmax, ls.nbmax, s);
+        launch_fill(d_jobs, nj, r, ls.kmax, ls.nbmax, ls.Bmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_COMPACT, s);
         launch_compact(d_jobs, nj, r, ls.Hmax, s);
+    }
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
+        launch_update(d_jobs, nj, r, ls.Hmax, ls.Wmax, s);
     }
 }
 
@@ -361,12 +388,16 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const La
 // (captured into a graph when use_graph) before the first look at the
 // per-job states; stragglers (iterations that found fewer parents than k)
 // get further iterations.
-scpl_status run_jobs(scpl_ctx *ctx, const Job *d_jobs, int32_t *d_states, int32_t *h_states, int nj,
-                     const LaunchShape &ls, int r_first_batch, bool use_graph, hipStream_t s)
+scpl_status run_jobs(scpl_ctx *ctx, const Job *d_jobs, const Job *h_jobs, int32_t *d_states, int32_t *h_states,
+                     int nj, const LaunchShape &ls, int r_first_batch, bool use_graph, hipStream_t s)
 {
     {
         ProfScope ps(ctx, SCPL_KERNEL_INIT, s);
         launch_init_jobs(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+    }
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_ENERGY, s);
+        launch_energy(d_jobs, nj, ls.Hmax, ls.Wmax, s);
     }
     SCPL_CHECK_LAUNCH();
     int r = 0;
@@ -404,10 +435,17 @@ scpl_status run_jobs(scpl_ctx *ctx, const Job *d_jobs, int32_t *d_states, int32_
         SCPL_TRY(hipMemcpyAsync(h_states, d_states, (size_t)nj * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SCPL_TRY(hipStreamSynchronize(s));
         bool all = true;
-        for (int j = 0; j < nj; ++j) all = all && h_states[4 * j] >= 0;
+        int more = 1;
+        for (int j = 0; j < nj; ++j) {
+            if (h_states[4 * j] >= 0) continue;
+            all = false;
+            // the job's width and last k_iter bound the iterations it still needs
+            const int rem = h_states[4 * j + 1] - h_jobs[j].Wt;
+            const int last = std::max(1, h_states[4 * j + 2]);
+            more = std::max(more, (rem + last - 1) / last);
+        }
         if (all) break;
         if (r > ls.Wmax + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
-        const int more = 4;
         for (int q = 0; q < more; ++q, ++r) enqueue_iteration(ctx, d_jobs, nj, r, ls, s);
         SCPL_CHECK_LAUNCH();
     }
@@ -507,7 +545,11 @@ scpl_status scpl_create(int32_t hip_device, scpl_ctx **out)
     scpl_ctx *c = new (std::nothrow) scpl_ctx();
     if (!c) return SCPL_ERR_OUT_OF_MEMORY;
     c->device = hip_device;
-    c->lds_cap = std::min<size_t>(65536, prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : 0);
+    // dynamic LDS of the selection kernel: all the device allows per block,
+    // less the kernel's own static LDS
+    c->lds_cap = prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : prop.sharedMemPerBlock;
+    g_lds_cap = c->lds_cap;
+    set_kernel_attributes(c->lds_cap);
     *out = c;
     return SCPL_OK;
 }
@@ -604,8 +646,8 @@ scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_
     ls.add(js);
     ctx->last_log.clear();
     for (size_t b = 0; b < bufs.size(); ++b) {
-        st = run_jobs(ctx, d_jobs + b, d_states + 4 * b, h_states + 4 * b, 1, ls, first_batch_iterations(p), false,
-                      s);
+        st = run_jobs(ctx, d_jobs + b, &jobs[b], d_states + 4 * b, h_states + 4 * b, 1, ls, first_batch_iterations(p),
+                      false, s);
         if (st != SCPL_OK) return st;
         std::vector<Job> one(1, jobs[b]);
         st = collect_logs(ctx, one, s);
@@ -690,10 +732,15 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         }
     }
     const int nj = (int)pend.size();
+    int Wall = 0;
+    for (int c = 0; c < n_clips; ++c) Wall = std::max(Wall, clips[c].p.width);
+    const int Qall = dp_columns_per_thread(Wall);  // one DP launch serves every job
     size_t job_area = 0;
     for (const Pending &q : pend) {
         const scpl_params &p = clips[q.clip].p;
-        job_area += job_bytes(JobShape{p.height, p.width, p.target_width, p.seams_per_iter});
+        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
+        js.Q = Qall;
+        job_area += job_bytes(js);
     }
     const size_t head = luma_b + seg_b;
     const size_t total = head + job_area + align_up(sizeof(Job) * (size_t)nj) + align_up(16 * (size_t)nj);
@@ -727,6 +774,7 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         const scpl_clip &cl = clips[pend[q].clip];
         const scpl_params &p = cl.p;
         JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
+        js.Q = Qall;
         Job J = clip_job(&p, cl.d_frames, lumas[pend[q].clip], cl.d_out, cl.d_masks, pend[q].t0, pend[q].T,
                          pend[q].bindex);
         carve_job(J, js, jb, d_states + 4 * q);
@@ -737,7 +785,7 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     }
     SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)nj, hipMemcpyHostToDevice, s));
     ctx->last_log.clear();
-    scpl_status st = run_jobs(ctx, d_jobs, d_states, h_states, nj, ls, rfirst, true, s);
+    scpl_status st = run_jobs(ctx, d_jobs, jobs.data(), d_states, h_states, nj, ls, rfirst, true, s);
     if (st != SCPL_OK) return st;
     return collect_logs(ctx, jobs, s);
 }
@@ -841,8 +889,8 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
     LaunchShape ls;
     ls.add(JobShape{H, W, 1, 1});
     launch_init_jobs(d_job, 1, ls.Hmax, ls.Wmax, s);
-    launch_energy(d_job, 1, 0, H, W, s);
-    launch_u16_to_i32(J.U, d_e, H, W, J.Wp, s);
+    launch_energy(d_job, 1, H, W, s);
+    launch_keys_to_u(J.K0, d_e, H, W, J.Wq, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));  // the pinned job slot is reused by the next call
     return SCPL_OK;
@@ -851,7 +899,7 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
 scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int32_t *d_ce_last,
                     int32_t *d_label_last, int8_t *d_dir, void *stream)
 {
-    if (!ctx || !d_u || !d_ce_last || !d_label_last || !d_dir || H < 1 || W < 1 || H > SCPL_MAX_HEIGHT ||
+    if (!ctx || !d_u || !d_ce_last || !d_label_last || !d_dir || H < 1 || W < 1 || H > SCPL_MAX_DP_STAGE_HEIGHT ||
         W > SCPL_MAX_WIDTH || (int64_t)H * W > SCPL_MAX_PIXELS)
         return SCPL_ERR_INVALID_ARG;
     SCPL_TRY(hipSetDevice(ctx->device));
@@ -865,10 +913,12 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, 1});
     launch_init_jobs(d_job, 1, H, W, s);
-    launch_u32_to_u16(d_u, J.U, H, W, J.Wp, s);
-    launch_dp(d_job, 1, 0, W, s);
+    launch_u_to_keys(d_u, J.K0, H, W, J.Wq, s);
+    launch_dp(d_job, 1, 0, W, ls.Q, s);
+    launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
+    launch_labels(d_job, 1, W, s);
+    launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);
     SCPL_CHECK_LAUNCH();
-    SCPL_TRY(hipMemcpy2DAsync(d_dir, (size_t)W, J.dir, (size_t)J.Wp, (size_t)W, (size_t)H, hipMemcpyDeviceToDevice, s));
     SCPL_TRY(hipMemcpyAsync(d_ce_last, J.ce_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
     SCPL_TRY(hipMemcpyAsync(d_label_last, J.lab_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
     SCPL_TRY(hipStreamSynchronize(s));
@@ -893,7 +943,7 @@ scpl_status scpl_select(scpl_ctx *ctx, int32_t W, const int32_t *d_ce_last, cons
     launch_init_jobs(d_job, 1, H, W, s);
     SCPL_TRY(hipMemcpyAsync(J.ce_last, d_ce_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
     SCPL_TRY(hipMemcpyAsync(J.lab_last, d_label_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
-    launch_select(d_job, 1, 0, W, 1, ctx->lds_cap, s);
+    launch_select(d_job, 1, 0, 1, ctx->lds_cap, s);
     SCPL_CHECK_LAUNCH();
     int32_t rec[4];
     SCPL_TRY(hipMemcpyAsync(rec, J.log, 16, hipMemcpyDeviceToHost, s));
@@ -922,7 +972,7 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     scpl_status st = stage_job(ctx, H, W, 0, kk, 0, J, d_job, d_state, unused, s);
     if (st != SCPL_OK) return st;
     launch_init_jobs(d_job, 1, H, W, s);
-    SCPL_TRY(hipMemcpy2DAsync(J.dir, (size_t)J.Wp, d_dir, (size_t)W, (size_t)W, (size_t)H, hipMemcpyDeviceToDevice, s));
+    launch_dir_in(d_dir, J.dir, J.Wp, H, W, s);
     SCPL_TRY(hipMemcpyAsync(J.children, d_children, (size_t)kk * 4, hipMemcpyDeviceToDevice, s));
     int32_t rec[4] = {W, 0, kk, 0};
     int32_t *h = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + align_up(sizeof(Job)));
@@ -931,9 +981,9 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     SCPL_TRY(hipMemcpyAsync(J.log, h, 16, hipMemcpyHostToDevice, s));
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, kk});
-    launch_borg(d_job, 1, 0, ls.nbmax, W, s);
+    launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
     launch_jump_only(d_job, 1, 0, s);
-    launch_fill(d_job, 1, 0, kk, ls.nbmax, s);
+    launch_fill(d_job, 1, 0, kk, ls.nbmax, ls.Bmax, s);
     launch_i16_to_i32(J.seams, d_seams, (int64_t)kk * H, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));

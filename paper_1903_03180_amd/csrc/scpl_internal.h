@@ -8,10 +8,12 @@
 namespace scpl {
 
 // Rows per band of the two-level backtrack: the DP's indicator array is cut
-// into bands of kBand rows; for every column at the last row of a band the
-// column it reaches at the last row of the previous band is precomputed
-// (fits int8 because a seam moves at most one column per row).
-constexpr int kBand = 64;
+// into bands of B rows (B <= kBandMax); for every column at the last row of
+// a band the column it reaches at the last row of the previous band is
+// precomputed (fits int8 because a seam moves at most one column per row).
+constexpr int kBandMax = 120;
+// Affected pixels of one row recomputed in parallel by the partial update.
+constexpr int kUpdList = 1024;
 // Frames per launch of the speculative ASDE scan.
 constexpr int kSegWindow = 64;
 constexpr int kDpThreads = 1024;
@@ -28,24 +30,29 @@ struct Job {
     int32_t t0, T;          // frames [t0, t0 + T) of the clip
     int32_t has_prev;       // frame t0 - 1 is the (carved) predecessor of t0
     int32_t Wp;             // padded row pitch of the job's 2-D workspace
-    int32_t nb;             // bands of kBand rows
+    int32_t Wq;             // row pitch of the DP's key rows (DP threads x columns per thread)
+    int32_t B;              // rows per band of the backtrack
+    int32_t nb;             // bands of B rows
     int32_t kcap;           // min(k, W): room for children / seams
     int32_t logcap;         // records in log
     int32_t buffer_index;   // index of the buffer within its clip
     // workspace (device)
     int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
-    uint16_t *U;            // uniform energy, H x Wp
-    int8_t *dir;            // indicator array, H x Wp
+    uint32_t *K0, *K1;      // DP input rows: 4 floor(SE / T), all ones at and beyond W_r,
+                            // (H + 1) x Wq (the extra row is all ones)
+    uint32_t *SE0, *SE1;    // sum of the buffer's energy maps, H x Wp
+    uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
     int32_t *ce_last;       // DP last row, Wp
-    int32_t *lab_last;      // labels of the last row, Wp
+    int32_t *lab_last;      // labels of the last row, Wp (stage entry points only)
     uint64_t *keys;         // 2 x Wp scratch for the selection
     int32_t *children;      // kcap
     int32_t *bcol;          // kcap x nb: seam column at the last row of each band
     int16_t *seams;         // kcap x H
     int32_t *log;           // logcap x 4: (W_r, P_eff, k_iter, 0)
-    int32_t *state;         // [0]: iteration at which W_r reached Wt (-1 while running)
+    int32_t *state;         // [0]: iteration at which W_r reached Wt (-1 while running),
+                            // [1]: current W_r, [2]: last k_iter
 };
 
 struct SegArgs {
@@ -63,16 +70,26 @@ struct SegArgs {
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
 void launch_seg_window(const SegArgs &a, hipStream_t s);
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
-void launch_energy(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s);
-void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Wmax, hipStream_t s);
-void launch_select(const Job *d_jobs, int njobs, int r, int Wmax, int nbmax, size_t lds_cap, hipStream_t s);
+void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
+// columns per DP thread for the widest job, and the threads that covers
+int dp_columns_per_thread(int Wmax);
+int dp_threads(int W, int Q);
+void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, int Q, hipStream_t s);
+void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s);
+void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s);
+void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
 void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s);
-void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, hipStream_t s);
+void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s);
 void launch_compact(const Job *d_jobs, int njobs, int r, int Hmax, hipStream_t s);
+void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s);
-void launch_u32_to_u16(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
-void launch_u16_to_i32(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
+void launch_u_to_keys(const int32_t *src, uint32_t *dst, int H, int W, int pitch, hipStream_t s);
+void launch_keys_to_u(const uint32_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
 void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s);
+// indicator codes <-> int8 {-1, 0, 1} with pitch change (stage entry points)
+void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s);
+void launch_dir_in(const int8_t *src, uint8_t *codes, int pitch, int H, int W, hipStream_t s);
+size_t select_lds_bytes(size_t lds_cap);
+void set_kernel_attributes(size_t lds_cap);
 
 }  // namespace scpl

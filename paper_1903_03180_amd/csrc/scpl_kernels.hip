@@ -22,9 +22,26 @@ namespace scpl {
 
 namespace {
 
-constexpr int kInf = 0x7fffffff;
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int job_width(const Job &J, int r) { return r < J.logcap ? J.log[4 * r] : J.Wt; }
+
+// Global-address-space views of pointers held in job descriptors.  Loads
+// through generic pointers compile to flat instructions, which also count
+// against the LDS wait counter, so every wait for an LDS access would drain
+// the outstanding global loads too (and defeat prefetching).
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T *gp(T *p)
+{
+    return (GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ const GLOBAL T *gp(const T *p)
+{
+    return (const GLOBAL T *)p;
+}
 
 // A column-map entry, kept inside [0, W) so that no address can leave the
 // frame even if the map were corrupt (the parity tests would catch that).
@@ -176,14 +193,27 @@ __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
 
 // ------------------------------------------------------------ job set-up
 
+constexpr uint32_t kKeyInf = 0xffffffffu;
+
 __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
 {
     const Job &J = jobs[blockIdx.y];
     const int i = blockIdx.x;
-    if (i >= J.H) return;
+    if (i > J.H) return;
+    if (i == J.H) {  // the all-ones row read by DP threads past the job's width
+        for (int j = threadIdx.x; j < J.Wq; j += 256) {
+            J.K0[(size_t)i * J.Wq + j] = kKeyInf;
+            J.K1[(size_t)i * J.Wq + j] = kKeyInf;
+        }
+        return;
+    }
     for (int j = threadIdx.x; j < J.W; j += 256) {
         J.M0[(size_t)i * J.Wp + j] = (int16_t)j;
         J.bmask[(size_t)i * J.W + j] = 0;
+    }
+    for (int j = J.W + threadIdx.x; j < J.Wq; j += 256) {
+        J.K0[(size_t)i * J.Wq + j] = kKeyInf;
+        J.K1[(size_t)i * J.Wq + j] = kKeyInf;
     }
     if (i == 0 && threadIdx.x == 0) {
         J.log[0] = J.W;
@@ -191,173 +221,225 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
         J.log[2] = 0;
         J.log[3] = 0;
         J.state[0] = J.W <= J.Wt ? 0 : -1;
+        J.state[1] = J.W;
+        J.state[2] = 0;
     }
 }
 
-// --------------------------------------------------------- uniform energy
+// ------------------------------------------------------------ energy
 //
-// U(i, j) = floor(sum over the buffer's frames of e(i, j) / T) on the carved
-// grid.  Carved pixel (i, j) of every frame of the buffer is original pixel
-// (i, M(i, j)); the nine neighbours of the Sobel stencil are taken on the
-// carved grid (replicated at the carved borders) and looked up through M.
-// The difference term compares a frame with its carved predecessor, which
-// for the buffer's first frame is frame t0 - 1 read through the same map.
+// e of frame t at carved pixel (i, j), Sec. 3.3: the Sobel stencil is taken
+// on the carved grid (rows i-1..i+1, columns j-1..j+1, replicated at the
+// carved borders) and every carved pixel is read as original pixel
+// (row, M(row, column)).  The difference term compares the frame with its
+// carved predecessor: frame t-1, or for the buffer's first frame the frame
+// just before the buffer (read through the same map), or nothing for the
+// clip's first frame.
 
-__global__ __launch_bounds__(256) void energy_kernel(const Job *jobs, int r)
+struct Stencil {
+    int oa0, oa1, oa2, ob0, ob1, ob2, oc0, oc1, oc2;  // offsets in a frame
+};
+
+__device__ __forceinline__ Stencil stencil_at(const int16_t *M, int Wp, int W, int H, int i, int j, int Wcur)
+{
+    const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, Wcur - 1);
+    const int16_t *ma = M + (size_t)im * Wp, *mb = M + (size_t)i * Wp, *mc = M + (size_t)ip * Wp;
+    Stencil s;
+    s.oa0 = im * W + mcol(ma, jm, W);
+    s.oa1 = im * W + mcol(ma, j, W);
+    s.oa2 = im * W + mcol(ma, jp, W);
+    s.ob0 = i * W + mcol(mb, jm, W);
+    s.ob1 = i * W + mcol(mb, j, W);
+    s.ob2 = i * W + mcol(mb, jp, W);
+    s.oc0 = ip * W + mcol(mc, jm, W);
+    s.oc1 = ip * W + mcol(mc, j, W);
+    s.oc2 = ip * W + mcol(mc, jp, W);
+    return s;
+}
+
+// Energy of buffer frame t (0-based within the buffer) at a stencil.
+__device__ __forceinline__ int energy_one(const Job &J, const Stencil &s, int t)
+{
+    const size_t HW = (size_t)J.H * J.W;
+    const GLOBAL uint8_t *f = gp(J.luma) + (size_t)(J.t0 + t) * HW;
+    const int g = sobel9(f[s.oa0], f[s.oa1], f[s.oa2], f[s.ob0], f[s.ob2], f[s.oc0], f[s.oc1], f[s.oc2]);
+    if (J.mode != 1) return g;
+    const int d = (t > 0 || J.has_prev) ? abs((int)f[s.ob1] - (int)f[(ptrdiff_t)s.ob1 - (ptrdiff_t)HW]) : 0;
+    return 2 * g + 18 * d;
+}
+
+// Iteration 0 of every job: SE = sum of the T energy maps and the DP key
+// row 4 floor(SE / T) over the uncarved frames (the column map is the
+// identity).
+__global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
 {
     const Job &J = jobs[blockIdx.z];
-    const int Wr = job_width(J, r);
-    if (Wr <= J.Wt) return;
+    if (J.W <= J.Wt) return;
     const int j = blockIdx.x * 64 + threadIdx.x;
     const int i = blockIdx.y * 4 + threadIdx.y;
-    if (i >= J.H || j >= Wr) return;
-    const int16_t *__restrict__ M = (r & 1) ? J.M1 : J.M0;
-    const int Wp = J.Wp, W = J.W, H = J.H;
-    const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, Wr - 1);
-    const int16_t *ma = M + (size_t)im * Wp, *mb = M + (size_t)i * Wp, *mc = M + (size_t)ip * Wp;
-    const int oa0 = im * W + mcol(ma, jm, W), oa1 = im * W + mcol(ma, j, W), oa2 = im * W + mcol(ma, jp, W);
-    const int ob0 = i * W + mcol(mb, jm, W), ob1 = i * W + mcol(mb, j, W), ob2 = i * W + mcol(mb, jp, W);
-    const int oc0 = ip * W + mcol(mc, jm, W), oc1 = ip * W + mcol(mc, j, W), oc2 = ip * W + mcol(mc, jp, W);
-    const size_t HW = (size_t)H * W;
-    const uint8_t *f = J.luma + (size_t)J.t0 * HW;
-    int acc = 0;
-    if (J.mode == 1) {
-        int prev = J.has_prev ? (int)f[(ptrdiff_t)ob1 - (ptrdiff_t)HW] : 0;
-        for (int t = 0; t < J.T; ++t, f += HW) {
-            const int c = f[ob1];
-            const int g = sobel9(f[oa0], f[oa1], f[oa2], f[ob0], f[ob2], f[oc0], f[oc1], f[oc2]);
-            const int d = (t > 0 || J.has_prev) ? abs(c - prev) : 0;
-            acc += 2 * g + 18 * d;
-            prev = c;
-        }
-    } else {
-        for (int t = 0; t < J.T; ++t, f += HW)
-            acc += sobel9(f[oa0], f[oa1], f[oa2], f[ob0], f[ob2], f[oc0], f[oc1], f[oc2]);
-    }
-    J.U[(size_t)i * Wp + j] = (uint16_t)(acc / J.T);
+    if (i >= J.H || j >= J.W) return;
+    const int W = J.W, H = J.H;
+    const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, W - 1);
+    Stencil st;
+    st.oa0 = im * W + jm;
+    st.oa1 = im * W + j;
+    st.oa2 = im * W + jp;
+    st.ob0 = i * W + jm;
+    st.ob1 = i * W + j;
+    st.ob2 = i * W + jp;
+    st.oc0 = ip * W + jm;
+    st.oc1 = ip * W + j;
+    st.oc2 = ip * W + jp;
+    uint32_t acc = 0;
+    for (int t = 0; t < J.T; ++t) acc += (uint32_t)energy_one(J, st, t);
+    J.SE0[(size_t)i * J.Wp + j] = acc;
+    J.K0[(size_t)i * J.Wq + j] = (acc / (uint32_t)J.T) << 2;
 }
 
 // ------------------------------------------------------------------- DP
 //
-// Eq. (4) row by row inside one workgroup of 1024 threads; thread t owns the
-// Q consecutive columns [tQ, tQ + Q).  Each row needs the previous row's
-// values of the two columns beside a thread's range, exchanged through a
-// ping-pong pair of LDS slots so one barrier per row suffices.  Every pixel
-// takes the leftmost of its least predecessors, its parent label (row-0
-// column) and its indicator (predecessor column - column).
+// Eq. (4) row by row inside one workgroup; thread t owns the Q consecutive
+// columns [tQ, tQ + Q).  Each column keeps key = CE * 4.  The three
+// candidates of a pixel get the offsets 0 (left), 1 (above), 2 (right), so
+// one unsigned min3 picks the least cumulative energy and, among equal
+// ones, the leftmost; the offset left in the two low bits is the indicator
+// code (predecessor column - column + 1).  Key rows hold 4 U and all ones
+// at and beyond the current width; saturating adds keep those columns at
+// all ones, so they never win.  Neighbours inside a wavefront come through
+// DPP wave shifts; the two wavefront-edge values cross through LDS, one
+// barrier per row.  Key rows are requested a group of PF rows ahead.
+// Parent labels are not carried here: they follow from the band origins.
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
 template <int Q>
-__device__ __forceinline__ void store_dir(int8_t *p, const int (&d)[Q])
+struct KRow {
+    uint32_t w[Q];
+};
+
+template <int Q>
+__device__ __forceinline__ void load_krow(KRow<Q> &dst, const uint32_t *p)
 {
     if constexpr (Q == 1) {
-        p[0] = (int8_t)d[0];
+        dst.w[0] = *gp(p);
     } else if constexpr (Q == 2) {
-        *reinterpret_cast<uint16_t *>(p) = (uint16_t)((d[0] & 255) | ((d[1] & 255) << 8));
+        const u32x2 v = *gp(reinterpret_cast<const u32x2 *>(p));
+        dst.w[0] = v.x;
+        dst.w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q / 4; ++q) {
+            const u32x4 v = gp(reinterpret_cast<const u32x4 *>(p))[q];
+            dst.w[4 * q] = v.x;
+            dst.w[4 * q + 1] = v.y;
+            dst.w[4 * q + 2] = v.z;
+            dst.w[4 * q + 3] = v.w;
+        }
+    }
+}
+
+// Stores the low byte of each best key; readers keep its two low bits.
+template <int Q>
+__device__ __forceinline__ void store_codes(uint8_t *p, const uint32_t (&b)[Q])
+{
+    if constexpr (Q == 1) {
+        gp(p)[0] = (uint8_t)b[0];
+    } else if constexpr (Q == 2) {
+        *gp(reinterpret_cast<uint16_t *>(p)) = (uint16_t)__builtin_amdgcn_perm(b[1], b[0], 0x0c0c0400u);
     } else {
 #pragma unroll
         for (int w = 0; w < Q / 4; ++w) {
-            uint32_t v = (uint32_t)(d[4 * w] & 255) | ((uint32_t)(d[4 * w + 1] & 255) << 8) |
-                         ((uint32_t)(d[4 * w + 2] & 255) << 16) | ((uint32_t)(d[4 * w + 3] & 255) << 24);
-            reinterpret_cast<uint32_t *>(p)[w] = v;
+            const uint32_t lo = __builtin_amdgcn_perm(b[4 * w + 1], b[4 * w], 0x0c0c0400u);
+            const uint32_t hi = __builtin_amdgcn_perm(b[4 * w + 3], b[4 * w + 2], 0x0c0c0400u);
+            gp(reinterpret_cast<uint32_t *>(p))[w] = lo | (hi << 16);
         }
     }
 }
 
 template <int Q>
-__global__ __launch_bounds__(kDpThreads) void dp_kernel(const Job *jobs, int r)
+struct DpPrefetch {
+    static constexpr int PF = Q <= 4 ? 8 : (Q == 8 ? 4 : 2);
+};
+
+template <int Q>
+__global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
 {
+    constexpr int PF = DpPrefetch<Q>::PF;
     const Job &J = jobs[blockIdx.x];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
-    __shared__ int xce[2][2][kDpThreads];
-    __shared__ int xlab[2][2][kDpThreads];
-    const int tid = threadIdx.x;
+    __shared__ uint32_t eL[2][16], eR[2][16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nwave = blockDim.x >> 6;
     const int j0 = tid * Q;
-    const int H = J.H, Wp = J.Wp;
-    const uint16_t *__restrict__ U = J.U;
-    int8_t *__restrict__ dir = J.dir;
-    const bool owns = j0 < Wp;
+    const int H = J.H, Wq = J.Wq, Wp = J.Wp;
+    const bool owns = j0 < Wq;
+    const uint32_t *K = (r & 1) ? J.K1 : J.K0;
+    // threads past the job's key pitch read the all-ones row at stride 0
+    const uint32_t *kp = owns ? K + j0 : K + (size_t)H * Wq;
+    const size_t kstride = owns ? (size_t)Wq : 0;
+    uint8_t *__restrict__ dir = J.dir;
+    const bool stores = j0 < Wp;
 
-    int ce[Q], lab[Q], un[Q];
+    uint32_t key[Q];
+    {
+        KRow<Q> k0;
+        load_krow<Q>(k0, kp);
+        uint32_t code[Q];
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        const int j = j0 + c;
-        ce[c] = j < Wr ? (int)U[j] : kInf;
-        lab[c] = j;
+        for (int c = 0; c < Q; ++c) {
+            key[c] = k0.w[c];
+            code[c] = 1;
+        }
+        if (stores) store_codes<Q>(dir + j0, code);
     }
-    if (owns) {
-        int z[Q];
+    if (lane == 0) eL[0][wid] = key[0];
+    if (lane == 63) eR[0][wid] = key[Q - 1];
+
+    KRow<Q> cur[PF], nxt[PF];
 #pragma unroll
-        for (int c = 0; c < Q; ++c) z[c] = 0;
-        store_dir<Q>(dir + j0, z);
-    }
-    xce[0][0][tid] = ce[0];
-    xce[0][1][tid] = ce[Q - 1];
-    xlab[0][0][tid] = lab[0];
-    xlab[0][1][tid] = lab[Q - 1];
-    if (H > 1) {
-#pragma unroll
-        for (int c = 0; c < Q; ++c) un[c] = (j0 + c) < Wr ? (int)U[(size_t)Wp + j0 + c] : 0;
-    }
+    for (int s = 0; s < PF; ++s) load_krow<Q>(cur[s], kp + (size_t)min(1 + s, H - 1) * kstride);
     __syncthreads();
 
-    for (int i = 1; i < H; ++i) {
-        const int p = (i - 1) & 1;
-        int uc[Q];
+    for (int i0 = 1; i0 < H; i0 += PF) {
 #pragma unroll
-        for (int c = 0; c < Q; ++c) uc[c] = un[c];
-        if (i + 1 < H) {
-            const uint16_t *row = U + (size_t)(i + 1) * Wp;
+        for (int s = 0; s < PF; ++s) load_krow<Q>(nxt[s], kp + (size_t)min(i0 + PF + s, H - 1) * kstride);
 #pragma unroll
-            for (int c = 0; c < Q; ++c) un[c] = (j0 + c) < Wr ? (int)row[j0 + c] : 0;
-        }
-        const int lce = tid > 0 ? xce[p][1][tid - 1] : kInf;
-        const int llab = tid > 0 ? xlab[p][1][tid - 1] : 0;
-        const int rce = tid < kDpThreads - 1 ? xce[p][0][tid + 1] : kInf;
-        const int rlab = tid < kDpThreads - 1 ? xlab[p][0][tid + 1] : 0;
-        int nce[Q], nlab[Q], d[Q];
+        for (int s = 0; s < PF; ++s) {
+            const int i = i0 + s;
+            if (i < H) {
+                const int p = (i - 1) & 1;
+                uint32_t lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[Q - 1], 0x138, 0xf, 0xf,
+                                                                     false);
+                uint32_t rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[0], 0x130, 0xf, 0xf,
+                                                                     false);
+                if (lane == 0) lnb = wid > 0 ? eR[p][wid - 1] : kKeyInf;
+                if (lane == 63) rnb = wid < nwave - 1 ? eL[p][wid + 1] : kKeyInf;
+
+                uint32_t best[Q];
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            const int Lv = c == 0 ? lce : ce[c - 1];
-            const int Ll = c == 0 ? llab : lab[c - 1];
-            const int Rv = c == Q - 1 ? rce : ce[c + 1];
-            const int Rl = c == Q - 1 ? rlab : lab[c + 1];
-            int best = Lv, bl = Ll, dd = -1;
-            if (ce[c] < best) {
-                best = ce[c];
-                bl = lab[c];
-                dd = 0;
+                for (int c = 0; c < Q; ++c) {
+                    const uint32_t kl = c == 0 ? lnb : key[c - 1];
+                    const uint32_t kc = sat_add(key[c], 1u);
+                    const uint32_t kr = sat_add(c == Q - 1 ? rnb : key[c + 1], 2u);
+                    best[c] = min(min(kl, kc), kr);
+                }
+#pragma unroll
+                for (int c = 0; c < Q; ++c) key[c] = sat_add(cur[s].w[c], best[c] & ~3u);
+                if (stores) store_codes<Q>(dir + (size_t)i * Wp + j0, best);
+                const int q = i & 1;
+                if (lane == 0) eL[q][wid] = key[0];
+                if (lane == 63) eR[q][wid] = key[Q - 1];
+                __syncthreads();
             }
-            if (Rv < best) {
-                best = Rv;
-                bl = Rl;
-                dd = 1;
-            }
-            const bool valid = (j0 + c) < Wr;
-            nce[c] = valid ? uc[c] + best : kInf;
-            nlab[c] = bl;
-            d[c] = valid ? dd : 0;
         }
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            ce[c] = nce[c];
-            lab[c] = nlab[c];
-        }
-        if (owns) store_dir<Q>(dir + (size_t)i * Wp + j0, d);
-        const int q = i & 1;
-        xce[q][0][tid] = ce[0];
-        xce[q][1][tid] = ce[Q - 1];
-        xlab[q][0][tid] = lab[0];
-        xlab[q][1][tid] = lab[Q - 1];
-        __syncthreads();
+        for (int s = 0; s < PF; ++s) cur[s] = nxt[s];
     }
 #pragma unroll
     for (int c = 0; c < Q; ++c) {
         const int j = j0 + c;
-        if (j < Wr) {
-            J.ce_last[j] = ce[c];
-            J.lab_last[j] = lab[c];
-        }
+        if (j < Wr) J.ce_last[j] = (int)(key[c] >> 2);
     }
 }
 
@@ -365,47 +447,80 @@ __global__ __launch_bounds__(kDpThreads) void dp_kernel(const Job *jobs, int r)
 //
 // For band b (rows [lo, hi]) and every column j at row hi: follow the
 // indicators up to row lo and, for b > 0, one more step into row lo - 1 (the
-// last row of band b - 1).  borg[b][j] = reached column - j, |.| <= kBand.
-// The band's indicator rows around the block's columns are staged in LDS.
+// last row of band b - 1); for b = 0 up to row 0.  borg[b][j] = reached
+// column - j, |.| <= B.  The band's indicator rows around the block's 128
+// columns are staged in LDS with 32-bit loads.
 
-__global__ __launch_bounds__(256) void borg_kernel(const Job *jobs, int r)
+constexpr int kBorgCols = 128;
+
+__device__ __forceinline__ int code_step(uint8_t c) { return (int)(c & 3u) - 1; }
+
+// Copies rows [r0, r0 + nrows) x columns [c0, c1) of a byte matrix with a
+// pitch that is a multiple of 4 into LDS (pitch lp bytes, column c0 & ~3 at
+// LDS column 0), using aligned 32-bit loads.  Returns the LDS column of c0.
+__device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *src, int pitch, int r0, int nrows,
+                                           int c0, int c1, int tid, int nthreads)
 {
+    const int a0 = c0 & ~3;
+    const int nw = (c1 - a0 + 3) >> 2;  // words per row
+    for (int idx = tid; idx < nrows * nw; idx += nthreads) {
+        const int rr = idx / nw, w = idx - rr * nw;
+        const uint32_t v = *gp(reinterpret_cast<const uint32_t *>(src + (size_t)(r0 + rr) * pitch + a0) + w);
+        *reinterpret_cast<uint32_t *>(lds + rr * lp + 4 * w) = v;
+    }
+    return c0 - a0;
+}
+
+__global__ __launch_bounds__(kBorgCols) void borg_kernel(const Job *jobs, int r)
+{
+    extern __shared__ uint8_t tile[];  // B rows x (kBorgCols + 2B + 8) bytes
     const Job &J = jobs[blockIdx.z];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int b = blockIdx.y;
     if (b >= J.nb) return;
-    const int c0 = blockIdx.x * 256;
+    const int c0 = blockIdx.x * kBorgCols;
     if (c0 >= Wr) return;
-    const int lo = b * kBand, hi = min(lo + kBand, J.H) - 1;
+    const int B = J.B;
+    const int lo = b * B, hi = min(lo + B, J.H) - 1;
     const int rlo = max(lo, 1);
     const int nrows = hi - rlo + 1;  // 0 when the job has a single row
-    const int wlo = max(c0 - nrows, 0), whi = min(c0 + 256 + nrows, Wr);
-    const int ww = whi - wlo;
-    __shared__ int8_t tile[kBand][256 + 2 * kBand];
-    for (int idx = threadIdx.x; idx < nrows * ww; idx += 256) {
-        const int rr = idx / ww, cc = idx - rr * ww;
-        tile[rr][cc] = J.dir[(size_t)(rlo + rr) * J.Wp + wlo + cc];
-    }
+    const int wlo = max(c0 - nrows, 0), whi = min(c0 + kBorgCols + nrows, Wr);
+    const int lp = kBorgCols + 2 * B + 8;
+    const int sh = stage_bytes(tile, lp, J.dir, J.Wp, rlo, nrows, wlo, whi, threadIdx.x, kBorgCols) - wlo;
     __syncthreads();
     const int j = c0 + threadIdx.x;
     if (j < Wr) {
         int c = j;
-        for (int i = hi; i >= rlo; --i) c += tile[i - rlo][c - wlo];
+        for (int i = hi; i >= rlo; --i) c += code_step(tile[(i - rlo) * lp + c + sh]);
         J.borg[(size_t)b * J.Wp + j] = (int8_t)(c - j);
     }
 }
 
+// Parent labels of the last row from the band origins (stage entry point
+// of the DP): label(j) = column reached at row 0 from (H-1, j).
+__global__ __launch_bounds__(256) void labels_kernel(const Job *jobs)
+{
+    const Job &J = jobs[blockIdx.y];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= J.W) return;
+    int c = j;
+    for (int b = J.nb - 1; b >= 0; --b) c += J.borg[(size_t)b * J.Wp + c];
+    J.lab_last[j] = c;
+}
+
 // -------------------------------------------------------------- selection
 //
-// One workgroup per job.  (A) least child of every parent: atomicMin of the
-// key (CE << 15 | column) at the parent's label -- the key order is the
-// ranking order (CE, column) and the leftmost least child has the least key.
-// (B) compact the parents' keys in label order, which is column order
-// because labels never decrease along the row.  (C) k_iter = min(k, P_eff,
-// W_r - Wt); a candidate is taken when fewer than k_iter keys are smaller.
-// (D) the taken children in column order.  (E) every taken child walks the
-// band origins upward to get its column at the last row of every band.
+// One workgroup per job.  (A) parent label of every last-row pixel (the
+// row-0 column its seam reaches, Sec. 3.1), by following the band origins;
+// least child of every parent: atomicMin of the key (CE << 15 | column) at
+// the label -- the key order is the ranking order (CE, column) and the
+// leftmost least child has the least key.  (B) compact the parents' keys in
+// label order, which is column order because labels never decrease along
+// the row.  (C) k_iter = min(k, P_eff, W_r - Wt); a candidate is taken when
+// fewer than k_iter keys are smaller.  (D) the taken children in column
+// order.  (E) every taken child walks the band origins upward to get its
+// column at the last row of every band.
 
 __device__ void band_jumps(const Job &J, int kk, const int8_t *bo, int bo_pitch, int tid, int nthreads)
 {
@@ -419,7 +534,7 @@ __device__ void band_jumps(const Job &J, int kk, const int8_t *bo, int bo_pitch,
     }
 }
 
-__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, int lds_bytes)
+__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, int lds_bytes, int use_lab_array)
 {
     extern __shared__ uint64_t dsm[];
     __shared__ int scan_tmp[16];
@@ -434,16 +549,31 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, in
         }
         return;
     }
-    const bool in_lds = (size_t)2 * Wr * sizeof(uint64_t) <= (size_t)lds_bytes;
-    uint64_t *key = in_lds ? dsm : J.keys;
+    const int nb = J.nb;
+    const size_t key_bytes = (size_t)2 * Wr * sizeof(uint64_t);
+    const bool keys_lds = key_bytes <= (size_t)lds_bytes;
+    const size_t key_room = keys_lds ? key_bytes : 0;
+    const int bo_lp = (Wr + 3 + 4) & ~3;  // staged rows may start up to 3 bytes early
+    const bool bo_lds = (size_t)nb * bo_lp + key_room <= (size_t)lds_bytes;
+    uint64_t *key = keys_lds ? dsm : J.keys;
     uint64_t *cand = key + Wr;
+    uint8_t *bo_s = reinterpret_cast<uint8_t *>(dsm) + key_room;
+    const int8_t *bo = bo_lds ? reinterpret_cast<const int8_t *>(bo_s) : J.borg;
+    const int bo_pitch = bo_lds ? bo_lp : J.Wp;
     constexpr uint64_t kNone = ~0ull;
 
     for (int j = tid; j < Wr; j += 1024) key[j] = kNone;
+    if (bo_lds) stage_bytes(bo_s, bo_lp, reinterpret_cast<const uint8_t *>(J.borg), J.Wp, 0, nb, 0, Wr, tid, 1024);
     __syncthreads();
     for (int j = tid; j < Wr; j += 1024) {
+        int l;
+        if (use_lab_array) {
+            l = J.lab_last[j];
+        } else {
+            l = j;
+            for (int b = nb - 1; b >= 0; --b) l += bo[(size_t)b * bo_pitch + l];
+        }
         const uint64_t kv = ((uint64_t)(uint32_t)J.ce_last[j] << 15) | (uint64_t)j;
-        const int l = J.lab_last[j];
         if ((unsigned)l < (unsigned)Wr) atomicMin((unsigned long long *)&key[l], (unsigned long long)kv);
     }
     __syncthreads();
@@ -478,21 +608,6 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, in
         if (selmask & (1u << (a - a0))) J.children[soff++] = (int)(cand[a] & 0x7fff);
     __syncthreads();
 
-    // band origins into LDS when they fit (the key arrays are dead by now)
-    const int nb = J.nb;
-    const bool bo_lds = (size_t)nb * Wr <= (size_t)lds_bytes;
-    const int8_t *bo = J.borg;
-    int bo_pitch = J.Wp;
-    if (bo_lds && nb > 1) {
-        int8_t *s = reinterpret_cast<int8_t *>(dsm);
-        for (int idx = tid; idx < nb * Wr; idx += 1024) {
-            const int b = idx / Wr, c = idx - b * Wr;
-            s[idx] = J.borg[(size_t)b * J.Wp + c];
-        }
-        bo = s;
-        bo_pitch = Wr;
-        __syncthreads();
-    }
     band_jumps(J, kk, bo, bo_pitch, tid, 1024);
 
     if (tid == 0) {
@@ -504,6 +619,8 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, in
             J.log[4 * (r + 1) + 2] = 0;
             J.log[4 * (r + 1) + 3] = 0;
         }
+        J.state[1] = Wr - kk;
+        J.state[2] = kk;
         if (Wr - kk <= J.Wt) J.state[0] = r + 1;
     }
 }
@@ -524,8 +641,12 @@ __global__ __launch_bounds__(256) void jump_kernel(const Job *jobs, int r)
 // marks the removed pixels (original columns, via the column map) in the
 // buffer mask with the iteration number + 1.
 
+constexpr int kFillPitch = 2 * kBandMax + 8;
+
 __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
 {
+    __shared__ uint8_t tile[kBandMax * kFillPitch];
+    __shared__ int16_t path[kBandMax];
     const Job &J = jobs[blockIdx.z];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
@@ -534,24 +655,18 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
     if (b >= J.nb) return;
     const int H = J.H, nb = J.nb, lane = threadIdx.x;
     const int16_t *__restrict__ M = (r & 1) ? J.M1 : J.M0;
-    __shared__ int8_t tile[kBand][2 * kBand];
-    __shared__ int16_t path[kBand];
-    const int lo = b * kBand, hi = min(lo + kBand, H) - 1;
-    const int span = hi - lo;
+    const int lo = b * J.B, hi = min(lo + J.B, H) - 1;
+    const int span = hi - lo;  // < B <= kBandMax
     for (int s = blockIdx.x; s < kk; s += gridDim.x) {
         const int c_end = J.bcol[s * nb + b];
         const int wlo = max(c_end - span, 0), whi = min(c_end + span + 1, Wr);
-        const int ww = whi - wlo;
-        for (int idx = lane; idx < span * ww; idx += 64) {
-            const int rr = idx / ww, cc = idx - rr * ww;
-            tile[rr][cc] = J.dir[(size_t)(lo + 1 + rr) * J.Wp + wlo + cc];
-        }
+        const int sh = stage_bytes(tile, kFillPitch, J.dir, J.Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
         __syncthreads();
         if (lane == 0) {
             int c = c_end;
             path[span] = (int16_t)c;
             for (int i = hi; i > lo; --i) {
-                c += tile[i - lo - 1][c - wlo];
+                c += code_step(tile[(i - lo - 1) * kFillPitch + c + sh]);
                 path[i - 1 - lo] = (int16_t)c;
             }
         }
@@ -573,6 +688,18 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
 // j + #{s : R_s - s <= j}; R_s - s never decreases, so a binary search
 // finds the count.  Only the column map is compacted: frames stay put.
 
+__device__ __forceinline__ int source_column(int j, int kk, const int *R, const int16_t *seams_row_major, int H)
+{
+    int a = 0, b = kk;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        const int v = R ? R[m] : (seams_row_major[(size_t)m * H] - m);
+        if (v <= j) a = m + 1;
+        else b = m;
+    }
+    return j + a;
+}
+
 __global__ __launch_bounds__(256) void compact_kernel(const Job *jobs, int r)
 {
     const Job &J = jobs[blockIdx.y];
@@ -590,15 +717,127 @@ __global__ __launch_bounds__(256) void compact_kernel(const Job *jobs, int r)
         for (int s = threadIdx.x; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
         __syncthreads();
     }
-    for (int j = threadIdx.x; j < Wr - kk; j += 256) {
-        int a = 0, b = kk;
-        while (a < b) {
-            const int m = (a + b) >> 1;
-            const int v = lds ? R[m] : (J.seams[(size_t)m * H + i] - m);
-            if (v <= j) a = m + 1;
-            else b = m;
+    for (int j = threadIdx.x; j < Wr - kk; j += 256)
+        Mn[j] = Mc[source_column(j, kk, lds ? R : nullptr, J.seams + i, H)];
+}
+
+// ---------------------------------------------------------- partial update
+//
+// SE (sum of the buffer's energy maps) and the DP key row 4 floor(SE / T)
+// after removing the seams of iteration r.  A kept pixel's energy in every
+// frame depends only on the original pixels of its 3x3 carved neighbourhood
+// (and on its own original pixel in the predecessor frame for the
+// difference term).  If the neighbourhood around its new position holds the
+// same original pixels as the one around its old position, all its
+// energies -- hence SE and the key -- are unchanged and move with it;
+// otherwise they are recomputed from the T frames.  This is exact: the
+// result equals a full recomputation.  The old and new column maps of rows
+// i-1..i+1 are staged in LDS; the affected pixels of the row (a few per
+// seam) are collected and each gets a share of the block's threads, which
+// split the T frames between them.
+
+constexpr int kUpdMaxW = 4096;  // widest row whose maps are staged in LDS
+
+__global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r, int ws)
+{
+    extern __shared__ int16_t maps[];  // old and new maps of rows i-1..i+1: 6 x ws
+    __shared__ int R[256];
+    __shared__ int list[kUpdList];
+    __shared__ uint32_t sums[kUpdList];
+    __shared__ int nlist;
+    const Job &J = jobs[blockIdx.y];
+    const int Wr = job_width(J, r);
+    if (Wr <= J.Wt) return;
+    const int kk = J.log[4 * r + 2];
+    const int Wn = Wr - kk;
+    if (Wn <= J.Wt) return;  // no further iteration reads the keys
+    const int i = blockIdx.x;
+    if (i >= J.H) return;
+    const int H = J.H, Wp = J.Wp, Wq = J.Wq, W = J.W, T = J.T;
+    const int16_t *__restrict__ Mo = (r & 1) ? J.M1 : J.M0;
+    const int16_t *__restrict__ Mn = (r & 1) ? J.M0 : J.M1;
+    const uint32_t *__restrict__ SEo = (r & 1) ? J.SE1 : J.SE0;
+    uint32_t *__restrict__ SEn = (r & 1) ? J.SE0 : J.SE1;
+    const uint32_t *__restrict__ Ko = (r & 1) ? J.K1 : J.K0;
+    uint32_t *__restrict__ Kn = (r & 1) ? J.K0 : J.K1;
+    const bool lds = kk <= 256;
+    const bool maps_lds = Wr <= ws;
+    int16_t *mo[3] = {maps, maps + ws, maps + 2 * ws};
+    int16_t *mn[3] = {maps + 3 * ws, maps + 4 * ws, maps + 5 * ws};
+    const int tid = threadIdx.x;
+    if (tid == 0) nlist = 0;
+    if (lds)
+        for (int s = tid; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
+    const int rows[3] = {max(i - 1, 0), i, min(i + 1, H - 1)};
+    if (maps_lds) {
+        const int nw = (Wr + 1) >> 1;  // 32-bit words per row (Wp is even)
+        for (int idx = tid; idx < 3 * nw; idx += 256) {
+            const int q = idx / nw, w = idx - q * nw;
+            reinterpret_cast<uint32_t *>(mo[q])[w] =
+                *gp(reinterpret_cast<const uint32_t *>(Mo + (size_t)rows[q] * Wp) + w);
+            reinterpret_cast<uint32_t *>(mn[q])[w] =
+                *gp(reinterpret_cast<const uint32_t *>(Mn + (size_t)rows[q] * Wp) + w);
         }
-        Mn[j] = Mc[j + a];
+    }
+    __syncthreads();
+    // the keys of the vacated columns become all ones; columns beyond the
+    // previous width of this buffer already are
+    const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
+    for (int j = Wn + tid; j < wprev; j += 256) Kn[(size_t)i * Wq + j] = kKeyInf;
+    for (int j = tid; j < Wn; j += 256) {
+        const int src = source_column(j, kk, lds ? R : nullptr, J.seams + i, H);
+        const int jm = max(j - 1, 0), jp = min(j + 1, Wn - 1);
+        const int sm = max(src - 1, 0), sp = min(src + 1, Wr - 1);
+        bool same = true;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int16_t *a = maps_lds ? mn[q] : Mn + (size_t)rows[q] * Wp;
+            const int16_t *b = maps_lds ? mo[q] : Mo + (size_t)rows[q] * Wp;
+            same = same && a[jm] == b[sm] && a[jp] == b[sp] && (q == 1 || a[j] == b[src]);
+        }
+        if (same) {
+            SEn[(size_t)i * Wp + j] = SEo[(size_t)i * Wp + src];
+            Kn[(size_t)i * Wq + j] = Ko[(size_t)i * Wq + src];
+        } else {
+            const int slot = atomicAdd(&nlist, 1);
+            if (slot < kUpdList) {
+                list[slot] = j;
+                sums[slot] = 0;
+            } else {  // more affected pixels than the list holds: this thread does it alone
+                const Stencil st = stencil_at(Mn, Wp, W, H, i, j, Wn);
+                uint32_t acc = 0;
+                for (int t = 0; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
+                SEn[(size_t)i * Wp + j] = acc;
+                Kn[(size_t)i * Wq + j] = (acc / (uint32_t)T) << 2;
+            }
+        }
+    }
+    __syncthreads();
+    const int n = min(nlist, kUpdList);
+    if (n > 0 && n <= 256) {
+        // pixel p gets threads p, p + n, p + 2n, ...; each sums every
+        // tpp-th frame of the buffer
+        const int tpp = 256 / n;
+        const int p = tid % n, sub = tid / n;
+        if (sub < tpp) {
+            const Stencil st = stencil_at(Mn, Wp, W, H, i, list[p], Wn);
+            uint32_t acc = 0;
+            for (int t = sub; t < T; t += tpp) acc += (uint32_t)energy_one(J, st, t);
+            atomicAdd(&sums[p], acc);
+        }
+    } else if (n > 256) {
+        for (int p = tid; p < n; p += 256) {
+            const Stencil st = stencil_at(Mn, Wp, W, H, i, list[p], Wn);
+            uint32_t acc = 0;
+            for (int t = 0; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
+            sums[p] = acc;
+        }
+    }
+    __syncthreads();
+    for (int p = tid; p < n; p += 256) {
+        const int j = list[p];
+        SEn[(size_t)i * Wp + j] = sums[p];
+        Kn[(size_t)i * Wq + j] = (sums[p] / (uint32_t)T) << 2;
     }
 }
 
@@ -636,26 +875,43 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
 
 // ------------------------------------------------- stage-API conversions
 
-__global__ void u32_to_u16_kernel(const int32_t *src, uint16_t *dst, int H, int W, int pitch)
+__global__ void u_to_keys_kernel(const int32_t *src, uint32_t *dst, int H, int W, int pitch)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
     const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
-    dst[(size_t)i * pitch + j] = (uint16_t)src[p];
+    dst[(size_t)i * pitch + j] = (uint32_t)src[p] << 2;
 }
 
-__global__ void u16_to_i32_kernel(const uint16_t *src, int32_t *dst, int H, int W, int pitch)
+__global__ void keys_to_u_kernel(const uint32_t *src, int32_t *dst, int H, int W, int pitch)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
     const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
-    dst[p] = (int32_t)src[(size_t)i * pitch + j];
+    dst[p] = (int32_t)(src[(size_t)i * pitch + j] >> 2);
 }
 
 __global__ void i16_to_i32_kernel(const int16_t *src, int32_t *dst, int64_t n)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p < n) dst[p] = src[p];
+}
+
+__global__ void dir_out_kernel(const uint8_t *codes, int pitch, int8_t *dst, int H, int W)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)H * W) return;
+    const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
+    dst[p] = (int8_t)((int)(codes[(size_t)i * pitch + j] & 3u) - 1);
+}
+
+__global__ void dir_in_kernel(const int8_t *src, uint8_t *codes, int pitch, int H, int W)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)H * W) return;
+    const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
+    const int d = src[p];
+    codes[(size_t)i * pitch + j] = (uint8_t)(min(max(d, -1), 1) + 1);
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -681,34 +937,67 @@ void launch_seg_window(const SegArgs &a, hipStream_t s)
 
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
 {
-    hipLaunchKernelGGL(init_jobs_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(init_jobs_kernel, dim3(Hmax + 1, njobs), dim3(256), 0, s, d_jobs);
 }
 
-void launch_energy(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s)
+void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s)
 {
     hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(Wmax, 64), blocks_for(Hmax, 4), njobs), dim3(64, 4), 0, s,
+                       d_jobs);
+}
+
+int dp_columns_per_thread(int Wmax)
+{
+    if (Wmax <= 512) return 1;
+    if (Wmax <= 2048) return 4;
+    if (Wmax <= 4096) return 4;
+    if (Wmax <= 8192) return 8;
+    if (Wmax <= 16384) return 16;
+    return 32;
+}
+
+int dp_threads(int W, int Q)
+{
+    const int t = (W + Q - 1) / Q;
+    return ((t + 63) / 64) * 64;
+}
+
+void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, int Q, hipStream_t s)
+{
+    const dim3 g(njobs), b(dp_threads(Wmax, Q));
+    switch (Q) {
+    case 1: hipLaunchKernelGGL(dp_kernel<1>, g, b, 0, s, d_jobs, r); break;
+    case 2: hipLaunchKernelGGL(dp_kernel<2>, g, b, 0, s, d_jobs, r); break;
+    case 4: hipLaunchKernelGGL(dp_kernel<4>, g, b, 0, s, d_jobs, r); break;
+    case 8: hipLaunchKernelGGL(dp_kernel<8>, g, b, 0, s, d_jobs, r); break;
+    case 16: hipLaunchKernelGGL(dp_kernel<16>, g, b, 0, s, d_jobs, r); break;
+    default: hipLaunchKernelGGL(dp_kernel<32>, g, b, 0, s, d_jobs, r); break;
+    }
+}
+
+void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s)
+{
+    const size_t lds = (size_t)Bmax * (kBorgCols + 2 * Bmax + 8);
+    hipLaunchKernelGGL(borg_kernel, dim3(blocks_for(Wmax, kBorgCols), nbmax, njobs), dim3(kBorgCols), lds, s,
                        d_jobs, r);
 }
 
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s)
+void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s)
 {
-    const dim3 g(njobs), b(kDpThreads);
-    if (Wmax <= 1024) hipLaunchKernelGGL(dp_kernel<1>, g, b, 0, s, d_jobs, r);
-    else if (Wmax <= 2048) hipLaunchKernelGGL(dp_kernel<2>, g, b, 0, s, d_jobs, r);
-    else if (Wmax <= 4096) hipLaunchKernelGGL(dp_kernel<4>, g, b, 0, s, d_jobs, r);
-    else if (Wmax <= 8192) hipLaunchKernelGGL(dp_kernel<8>, g, b, 0, s, d_jobs, r);
-    else if (Wmax <= 16384) hipLaunchKernelGGL(dp_kernel<16>, g, b, 0, s, d_jobs, r);
-    else hipLaunchKernelGGL(dp_kernel<32>, g, b, 0, s, d_jobs, r);
+    hipLaunchKernelGGL(labels_kernel, dim3(blocks_for(Wmax, 256), njobs), dim3(256), 0, s, d_jobs);
 }
 
-void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Wmax, hipStream_t s)
+size_t select_lds_bytes(size_t lds_cap) { return lds_cap; }
+
+void set_kernel_attributes(size_t lds_cap)
 {
-    hipLaunchKernelGGL(borg_kernel, dim3(blocks_for(Wmax, 256), nbmax, njobs), dim3(256), 0, s, d_jobs, r);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
 }
 
-void launch_select(const Job *d_jobs, int njobs, int r, int, int, size_t lds_cap, hipStream_t s)
+void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(select_kernel, dim3(njobs), dim3(1024), lds_cap, s, d_jobs, r, (int)lds_cap);
+    hipLaunchKernelGGL(select_kernel, dim3(njobs), dim3(1024), lds_cap, s, d_jobs, r, (int)lds_cap, use_lab_array);
 }
 
 void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s)
@@ -716,7 +1005,7 @@ void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s)
     hipLaunchKernelGGL(jump_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, r);
 }
 
-void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, hipStream_t s)
+void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int, hipStream_t s)
 {
     const int gx = kmax < 1024 ? kmax : 1024;
     hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), 0, s, d_jobs, r);
@@ -727,26 +1016,45 @@ void launch_compact(const Job *d_jobs, int njobs, int r, int Hmax, hipStream_t s
     hipLaunchKernelGGL(compact_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs, r);
 }
 
+void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s)
+{
+    const int ws = Wmax <= kUpdMaxW ? ((Wmax + 1) & ~1) : 0;
+    hipLaunchKernelGGL(update_kernel, dim3(Hmax, njobs), dim3(256), (size_t)6 * ws * sizeof(int16_t), s, d_jobs, r,
+                       ws);
+}
+
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s)
 {
     hipLaunchKernelGGL(gather_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs);
 }
 
-void launch_u32_to_u16(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s)
+void launch_u_to_keys(const int32_t *src, uint32_t *dst, int H, int W, int pitch, hipStream_t s)
 {
-    hipLaunchKernelGGL(u32_to_u16_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
+    hipLaunchKernelGGL(u_to_keys_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);
 }
 
-void launch_u16_to_i32(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s)
+void launch_keys_to_u(const uint32_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s)
 {
-    hipLaunchKernelGGL(u16_to_i32_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
+    hipLaunchKernelGGL(keys_to_u_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);
 }
 
 void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(i16_to_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(dir_out_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, codes, pitch, dst, H,
+                       W);
+}
+
+void launch_dir_in(const int8_t *src, uint8_t *codes, int pitch, int H, int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(dir_in_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, codes, pitch, H,
+                       W);
 }
 
 }  // namespace scpl
