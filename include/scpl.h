@@ -142,17 +142,17 @@ scpl_status scpl_last_log(scpl_ctx *ctx, int32_t *h_log, int64_t cap, int64_t *h
  * scpl_profile_read synchronises the device, returns the summed duration
  * and launch count of one kernel kind since profiling was (re)enabled. */
 enum {
-    SCPL_KERNEL_LUMA = 0,
+    SCPL_KERNEL_LUMA = 0,    /* colour -> tiled luma */
     SCPL_KERNEL_SEGMENT = 1,
     SCPL_KERNEL_ENERGY = 2,
     SCPL_KERNEL_DP = 3,
     SCPL_KERNEL_BORG = 4,
     SCPL_KERNEL_SELECT = 5,
     SCPL_KERNEL_FILL = 6,
-    SCPL_KERNEL_COMPACT = 7,
+    SCPL_KERNEL_UPDATE = 7,  /* column-map compaction + energy update */
     SCPL_KERNEL_GATHER = 8,
     SCPL_KERNEL_INIT = 9,
-    SCPL_KERNEL_UPDATE = 10,
+    SCPL_KERNEL_REFRESH = 10, /* energies of the pixels whose neighbourhood changed */
     SCPL_KERNEL_COUNT = 11
 };
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);

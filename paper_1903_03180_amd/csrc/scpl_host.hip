@@ -27,8 +27,10 @@ struct scpl_ctx {
     int64_t prof_n[SCPL_KERNEL_COUNT] = {};
     int device = 0;
     size_t lds_cap = 65536;
-    void *ws = nullptr;        // device workspace
+    void *ws = nullptr;        // device workspace: tiled luma, buffer controller, stage jobs
     size_t ws_size = 0;
+    void *jws = nullptr;       // device workspace of the carving jobs
+    size_t jws_size = 0;
     void *pinned = nullptr;    // host staging (job tables, sums, states)
     size_t pinned_size = 0;
     std::vector<int32_t> last_log;
@@ -138,7 +140,6 @@ size_t job_bytes(const JobShape &s)
     size_t b = 0;
     b += 2 * align_up(H * Wp * 2);       // M0, M1
     b += 2 * align_up((H + 1) * (size_t)s.Wq() * 4);  // K0, K1
-    b += 2 * align_up(H * Wp * 4);       // SE0, SE1
     b += align_up(H * Wp);               // dir
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
@@ -168,8 +169,6 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.M1 = bp.take<int16_t>(H * Wp);
     J.K0 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
     J.K1 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
-    J.SE0 = bp.take<uint32_t>(H * Wp);
-    J.SE1 = bp.take<uint32_t>(H * Wp);
     J.dir = bp.take<uint8_t>(H * Wp);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
@@ -183,19 +182,22 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.state = state;
 }
 
-scpl_status ensure_ws(scpl_ctx *ctx, size_t bytes)
+scpl_status grow(void *&buf, size_t &size, size_t bytes)
 {
-    if (bytes <= ctx->ws_size) return SCPL_OK;
-    if (ctx->ws) {
-        SCPL_TRY(hipFree(ctx->ws));  // implicitly waits for work using it
-        ctx->ws = nullptr;
-        ctx->ws_size = 0;
+    if (bytes <= size) return SCPL_OK;
+    if (buf) {
+        SCPL_TRY(hipFree(buf));  // implicitly waits for work using it
+        buf = nullptr;
+        size = 0;
     }
     size_t want = align_up(bytes, (size_t)1 << 20);
-    SCPL_TRY(hipMalloc(&ctx->ws, want));
-    ctx->ws_size = want;
+    SCPL_TRY(hipMalloc(&buf, want));
+    size = want;
     return SCPL_OK;
 }
+
+scpl_status ensure_ws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->ws, ctx->ws_size, bytes); }
+scpl_status ensure_jws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->jws, ctx->jws_size, bytes); }
 
 scpl_status ensure_pinned(scpl_ctx *ctx, size_t bytes)
 {
@@ -256,87 +258,130 @@ scpl_status prof_drain(scpl_ctx *ctx)
 
 // ------------------------------------------------------------ segmentation
 
-size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8) + align_up(kSegWindow * 8); }
+// Device state of one clip's buffer controller: moments S1, S2 per pixel
+// and the window sums.
+size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8); }
+
+struct SegClip {
+    const scpl_params *p;
+    const uint8_t *tiled;  // N tiled luma frames
+    int64_t FS;
+    int ntc;
+    void *state;           // seg_bytes(H W)
+    int32_t *bid;          // host, N
+    int64_t *trace;        // host, N, nullable
+    int32_t nbuf = 0;
+    // controller
+    int t0 = 0, n = 1, nb = 0, t = 1, te = 0;
+    bool valid = false, done = false, launched = false;
+};
 
 // Dynamic spatiotemporal buffer (Sec. 3.2): frames join the current buffer
-// while the ASDE of the grown buffer stays at or below phi(n).  Each launch
-// scans a window of candidates speculatively; the host accepts them in
-// order and restarts from the first rejected frame.
-scpl_status segment_clip(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_luma, void *seg_ws,
-                         unsigned long long *h_sums, int32_t *bid, int64_t *trace, int32_t *nbuf, hipStream_t s)
+// while the ASDE of the grown buffer stays at or below phi(n).  Each round
+// launches, for every clip still open, a speculative scan of a window of
+// candidate frames; after one synchronisation the host accepts each clip's
+// candidates in order and restarts that clip from its first rejected frame.
+scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long long *d_sums,
+                          unsigned long long *h_sums, hipStream_t s)
 {
-    const int N = p->n_frames;
-    const int64_t HW = (int64_t)p->height * p->width;
-    if (!p->use_buffer) {
-        for (int t = 0; t < N; ++t) {
-            bid[t] = t;
-            if (trace) trace[t] = -1;
-        }
-        *nbuf = N;
-        return SCPL_OK;
-    }
-    Bump bp{static_cast<char *>(seg_ws)};
-    SegArgs a{};
-    a.luma = d_luma;
-    a.s1 = bp.take<uint32_t>(HW);
-    a.s2 = bp.take<uint64_t>(HW);
-    a.sout = bp.take<unsigned long long>(kSegWindow);
-    a.H = p->height;
-    a.W = p->width;
-    a.mode = p->energy_mode;
-    const int32_t emax = energy_max(p->energy_mode);
-
-    int t0 = 0, n = 1, nb = 0, t = 1;
-    bool state_valid = false;
-    bid[0] = 0;
-    if (trace) trace[0] = -1;
-    while (t < N) {
-        if (p->max_buffer > 0 && n >= p->max_buffer) {
-            if (trace) trace[t] = -1;
-            bid[t] = ++nb;
-            t0 = t;
-            n = 1;
-            state_valid = false;
-            ++t;
-            continue;
-        }
-        int te = std::min(N, t + kSegWindow);
-        if (p->max_buffer > 0) te = std::min(te, t + (p->max_buffer - n));
-        a.t0 = t0;
-        a.tb = t;
-        a.te = te;
-        a.init = state_valid ? 0 : 1;
-        SCPL_TRY(hipMemsetAsync(a.sout, 0, kSegWindow * 8, s));
-        {
-            ProfScope ps(ctx, SCPL_KERNEL_SEGMENT, s);
-            launch_seg_window(a, s);
-        }
-        SCPL_CHECK_LAUNCH();
-        SCPL_TRY(hipMemcpyAsync(h_sums, a.sout, (size_t)(te - t) * 8, hipMemcpyDeviceToHost, s));
-        SCPL_TRY(hipStreamSynchronize(s));
-        bool rejected = false;
-        for (int tt = t; tt < te; ++tt) {
-            const uint64_t S = h_sums[tt - t];
-            const int64_t nn = tt - t0 + 1;
-            if (trace) trace[tt] = (int64_t)S;
-            if (asde_rejects(S, nn, HW, emax, p->alpha_num, p->alpha_den)) {
-                bid[tt] = ++nb;
-                t0 = tt;
-                n = 1;
-                state_valid = false;
-                t = tt + 1;
-                rejected = true;
-                break;
+    const int nc = (int)cl.size();
+    for (SegClip &c : cl) {
+        const int N = c.p->n_frames;
+        c.bid[0] = 0;
+        if (c.trace) c.trace[0] = -1;
+        if (!c.p->use_buffer) {
+            for (int t = 0; t < N; ++t) {
+                c.bid[t] = t;
+                if (c.trace) c.trace[t] = -1;
             }
-            bid[tt] = nb;
-            n = (int)nn;
-        }
-        if (!rejected) {
-            state_valid = true;
-            t = te;
+            c.nbuf = N;
+            c.done = true;
+        } else if (N == 1) {
+            c.nbuf = 1;
+            c.done = true;
         }
     }
-    *nbuf = nb + 1;
+    for (;;) {
+        bool any = false;
+        for (int ci = 0; ci < nc; ++ci) {
+            SegClip &c = cl[ci];
+            c.launched = false;
+            if (c.done) continue;
+            const scpl_params *p = c.p;
+            const int N = p->n_frames;
+            // frames forced into a new buffer by max_buffer need no test
+            while (c.t < N && p->max_buffer > 0 && c.n >= p->max_buffer) {
+                if (c.trace) c.trace[c.t] = -1;
+                c.bid[c.t] = ++c.nb;
+                c.t0 = c.t;
+                c.n = 1;
+                c.valid = false;
+                ++c.t;
+            }
+            if (c.t >= N) {
+                c.nbuf = c.nb + 1;
+                c.done = true;
+                continue;
+            }
+            c.te = std::min(N, c.t + kSegWindow);
+            if (p->max_buffer > 0) c.te = std::min(c.te, c.t + (p->max_buffer - c.n));
+            const int64_t HW = (int64_t)p->height * p->width;
+            Bump bp{static_cast<char *>(c.state)};
+            SegArgs a{};
+            a.luma = c.tiled;
+            a.FS = c.FS;
+            a.ntc = c.ntc;
+            a.s1 = bp.take<uint32_t>(HW);
+            a.s2 = bp.take<uint64_t>(HW);
+            a.sout = d_sums + (size_t)ci * kSegWindow;
+            a.H = p->height;
+            a.W = p->width;
+            a.mode = p->energy_mode;
+            a.t0 = c.t0;
+            a.tb = c.t;
+            a.te = c.te;
+            a.init = c.valid ? 0 : 1;
+            if (!any) SCPL_TRY(hipMemsetAsync(d_sums, 0, (size_t)nc * kSegWindow * 8, s));
+            {
+                ProfScope ps(ctx, SCPL_KERNEL_SEGMENT, s);
+                launch_seg_window(a, s);
+            }
+            SCPL_CHECK_LAUNCH();
+            c.launched = true;
+            any = true;
+        }
+        if (!any) break;
+        SCPL_TRY(hipMemcpyAsync(h_sums, d_sums, (size_t)nc * kSegWindow * 8, hipMemcpyDeviceToHost, s));
+        SCPL_TRY(hipStreamSynchronize(s));
+        for (int ci = 0; ci < nc; ++ci) {
+            SegClip &c = cl[ci];
+            if (!c.launched) continue;
+            const scpl_params *p = c.p;
+            const int64_t HW = (int64_t)p->height * p->width;
+            const int32_t emax = energy_max(p->energy_mode);
+            bool rejected = false;
+            for (int tt = c.t; tt < c.te; ++tt) {
+                const uint64_t S = h_sums[(size_t)ci * kSegWindow + (tt - c.t)];
+                const int64_t nn = tt - c.t0 + 1;
+                if (c.trace) c.trace[tt] = (int64_t)S;
+                if (asde_rejects(S, nn, HW, emax, p->alpha_num, p->alpha_den)) {
+                    c.bid[tt] = ++c.nb;
+                    c.t0 = tt;
+                    c.n = 1;
+                    c.valid = false;
+                    c.t = tt + 1;
+                    rejected = true;
+                    break;
+                }
+                c.bid[tt] = c.nb;
+                c.n = (int)nn;
+            }
+            if (!rejected) {
+                c.valid = true;
+                c.t = c.te;
+            }
+        }
+    }
     return SCPL_OK;
 }
 
@@ -374,12 +419,12 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const La
         launch_fill(d_jobs, nj, r, ls.kmax, ls.nbmax, ls.Bmax, s);
     }
     {
-        ProfScope ps(ctx, SCPL_KERNEL_COMPACT, s);
-        launch_compact(d_jobs, nj, r, ls.Hmax, s);
-    }
-    {
         ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
         launch_update(d_jobs, nj, r, ls.Hmax, ls.Wmax, s);
+    }
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_REFRESH, s);
+        launch_refresh(d_jobs, nj, r, ls.kmax, ls.Hmax, s);
     }
 }
 
@@ -482,6 +527,8 @@ Job clip_job(const scpl_params *p, const uint8_t *frames, const uint8_t *luma, u
     Job J{};
     J.frames = frames;
     J.luma = luma;
+    J.ntc = tiles_across(p->width);
+    J.FS = tiled_frame_bytes(p->height, p->width);
     J.out = out;
     J.masks = masks;
     J.C = p->channels;
@@ -564,6 +611,7 @@ void scpl_destroy(scpl_ctx *ctx)
         (void)hipEventDestroy(pp.b);
     }
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->jws) (void)hipFree(ctx->jws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
@@ -575,10 +623,130 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
     if (!device_bytes) return SCPL_ERR_INVALID_ARG;
     const int64_t HW = (int64_t)p->height * p->width;
     JobShape js{p->height, p->width, p->target_width, p->seams_per_iter};
-    size_t b = 0;
-    if (p->channels == 3) b += align_up((size_t)p->n_frames * HW);
-    b += seg_bytes(HW) + job_bytes(js) + align_up(sizeof(Job)) + align_up(16);
+    size_t b = align_up((size_t)p->n_frames * tiled_frame_bytes(p->height, p->width));
+    b += seg_bytes(HW) + align_up(kSegWindow * 8);
+    b += job_bytes(js) + align_up(sizeof(Job) * (size_t)p->n_frames) + align_up(16 * (size_t)p->n_frames);
     *device_bytes = b;
+    return SCPL_OK;
+}
+
+// Retargets clips: tiled luma of every clip, buffer segmentation of all
+// clips together, then the carving jobs (one per buffer) -- all at once
+// (batched) or one buffer after another (plain).
+static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
+                             hipStream_t s)
+{
+    // area A: tiled lumas, controller states, window sums
+    size_t a_bytes = align_up((size_t)nc * kSegWindow * 8);
+    int64_t Ntot = 0;
+    for (int c = 0; c < nc; ++c) {
+        const scpl_params &p = clips[c].p;
+        a_bytes += align_up((size_t)p.n_frames * tiled_frame_bytes(p.height, p.width));
+        a_bytes += seg_bytes((int64_t)p.height * p.width);
+        Ntot += p.n_frames;
+    }
+    SCPL_TRY(ensure_ws(ctx, a_bytes));
+    const size_t pin_b = align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) +
+                         align_up(16 * (size_t)Ntot) + align_up(sizeof(Job) * (size_t)Ntot);
+    SCPL_TRY(ensure_pinned(ctx, pin_b));
+    Bump host{static_cast<char *>(ctx->pinned)};
+    unsigned long long *h_sums = host.take<unsigned long long>((size_t)nc * kSegWindow);
+    int32_t *h_bid_all = host.take<int32_t>((size_t)Ntot);
+    int32_t *h_states = host.take<int32_t>(4 * (size_t)Ntot);
+    Job *h_jobs = host.take<Job>((size_t)Ntot);
+
+    Bump dev{static_cast<char *>(ctx->ws)};
+    unsigned long long *d_sums = dev.take<unsigned long long>((size_t)nc * kSegWindow);
+    std::vector<SegClip> seg(nc);
+    int64_t off = 0;
+    for (int c = 0; c < nc; ++c) {
+        const scpl_params &p = clips[c].p;
+        SegClip &sc = seg[c];
+        sc.p = &p;
+        sc.FS = tiled_frame_bytes(p.height, p.width);
+        sc.ntc = tiles_across(p.width);
+        uint8_t *tiled = dev.take<uint8_t>((size_t)p.n_frames * sc.FS);
+        sc.tiled = tiled;
+        sc.state = dev.take<char>(seg_bytes((int64_t)p.height * p.width));
+        sc.bid = h_bid_all + off;
+        sc.trace = nullptr;
+        off += p.n_frames;
+        ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
+        launch_tile_luma(clips[c].d_frames, p.channels, p.n_frames, p.height, p.width, tiled, s);
+    }
+    SCPL_CHECK_LAUNCH();
+    scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, s);
+    if (st != SCPL_OK) return st;
+    for (int c = 0; c < nc; ++c)
+        if (clips[c].d_buffer_id)
+            SCPL_TRY(hipMemcpyAsync(clips[c].d_buffer_id, seg[c].bid, (size_t)clips[c].p.n_frames * 4,
+                                    hipMemcpyHostToDevice, s));
+    if (h_nbuf_first) *h_nbuf_first = seg[0].nbuf;
+
+    // jobs: one per buffer of every clip
+    struct Pending {
+        int clip, t0, T, bindex;
+    };
+    std::vector<Pending> pend;
+    for (int c = 0; c < nc; ++c) {
+        const auto bufs = buffers_of(seg[c].bid, clips[c].p.n_frames);
+        for (size_t b = 0; b < bufs.size(); ++b) pend.push_back({c, bufs[b].first, bufs[b].second, (int)b});
+    }
+    const int nj = (int)pend.size();
+    int Wall = 0;
+    for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
+    const int Qall = dp_columns_per_thread(Wall);  // a batched DP launch serves every job
+    auto shape_of = [&](const Pending &q) {
+        const scpl_params &p = clips[q.clip].p;
+        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
+        if (batched) js.Q = Qall;
+        return js;
+    };
+    // area B: job workspaces (all jobs when batched; one shared per clip shape
+    // when plain, buffers running one after another), job table, states
+    size_t job_area = 0;
+    for (const Pending &q : pend) {
+        const size_t jb = job_bytes(shape_of(q));
+        job_area = batched ? job_area + jb : std::max(job_area, jb);
+    }
+    SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)nj) + align_up(16 * (size_t)nj)));
+    Bump jdev{static_cast<char *>(ctx->jws)};
+    char *job_ws = jdev.take<char>(job_area);
+    Job *d_jobs = jdev.take<Job>((size_t)nj);
+    int32_t *d_states = jdev.take<int32_t>(4 * (size_t)nj);
+    Bump jb{job_ws};
+    LaunchShape ls;
+    int rfirst = 0;
+    std::vector<Job> jobs;
+    for (int q = 0; q < nj; ++q) {
+        const scpl_clip &cl = clips[pend[q].clip];
+        const JobShape js = shape_of(pend[q]);
+        Job J = clip_job(&cl.p, cl.d_frames, seg[pend[q].clip].tiled, cl.d_out, cl.d_masks, pend[q].t0, pend[q].T,
+                         pend[q].bindex);
+        if (!batched) jb.off = 0;  // plain: every buffer reuses the same area
+        carve_job(J, js, jb, d_states + 4 * q);
+        h_jobs[q] = J;
+        jobs.push_back(J);
+        ls.add(js);
+        rfirst = std::max(rfirst, first_batch_iterations(&cl.p));
+    }
+    SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)nj, hipMemcpyHostToDevice, s));
+    ctx->last_log.clear();
+    if (batched) {
+        st = run_jobs(ctx, d_jobs, h_jobs, d_states, h_states, nj, ls, rfirst, true, s);
+        if (st != SCPL_OK) return st;
+        return collect_logs(ctx, jobs, s);
+    }
+    for (int q = 0; q < nj; ++q) {
+        LaunchShape one;
+        one.add(JobShape{jobs[q].H, jobs[q].W, jobs[q].Wt, jobs[q].k});
+        st = run_jobs(ctx, d_jobs + q, h_jobs + q, d_states + 4 * q, h_states + 4 * q, 1, one,
+                      first_batch_iterations(&clips[pend[q].clip].p), false, s);
+        if (st != SCPL_OK) return st;
+        std::vector<Job> single(1, jobs[q]);
+        st = collect_logs(ctx, single, s);
+        if (st != SCPL_OK) return st;
+    }
     return SCPL_OK;
 }
 
@@ -589,71 +757,8 @@ scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_
     scpl_status st = validate(p);
     if (st != SCPL_OK) return st;
     SCPL_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int N = p->n_frames;
-    const int64_t HW = (int64_t)p->height * p->width;
-    JobShape js{p->height, p->width, p->target_width, p->seams_per_iter};
-
-    // device workspace: [luma] [segmentation] [job] [job table] [states]
-    const size_t luma_b = p->channels == 3 ? align_up((size_t)N * HW) : 0;
-    const size_t seg_b = seg_bytes(HW);
-    const size_t job_b = job_bytes(js);
-    const size_t total = luma_b + seg_b + job_b + align_up(sizeof(Job) * (size_t)N) + align_up(16 * (size_t)N);
-    SCPL_TRY(ensure_ws(ctx, total));
-    // host staging: [sums] [states] [jobs] [buffer ids] [trace unused]
-    const size_t pin_b = align_up(kSegWindow * 8) + align_up(16 * (size_t)N) + align_up(sizeof(Job) * (size_t)N) +
-                         align_up(4 * (size_t)N);
-    SCPL_TRY(ensure_pinned(ctx, pin_b));
-
-    Bump dev{static_cast<char *>(ctx->ws)};
-    uint8_t *d_luma = luma_b ? dev.take<uint8_t>((size_t)N * HW) : nullptr;
-    void *seg_ws = dev.take<char>(seg_b);
-    char *job_ws = dev.take<char>(job_b);
-    Job *d_jobs = dev.take<Job>((size_t)N);
-    int32_t *d_states = dev.take<int32_t>(4 * (size_t)N);
-
-    Bump host{static_cast<char *>(ctx->pinned)};
-    unsigned long long *h_sums = host.take<unsigned long long>(kSegWindow);
-    int32_t *h_states = host.take<int32_t>(4 * (size_t)N);
-    Job *h_jobs = host.take<Job>((size_t)N);
-    int32_t *h_bid = host.take<int32_t>((size_t)N);
-
-    const uint8_t *luma = d_frames;
-    if (p->channels == 3) {
-        ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
-        launch_luma(d_frames, d_luma, (int64_t)N * HW, s);
-        SCPL_CHECK_LAUNCH();
-        luma = d_luma;
-    }
-    int32_t nbuf = 0;
-    st = segment_clip(ctx, p, luma, seg_ws, h_sums, h_bid, nullptr, &nbuf, s);
-    if (st != SCPL_OK) return st;
-    if (d_buffer_id) SCPL_TRY(hipMemcpyAsync(d_buffer_id, h_bid, (size_t)N * 4, hipMemcpyHostToDevice, s));
-    if (h_n_buffers) *h_n_buffers = nbuf;
-
-    // plain path: one buffer at a time, all sharing one job workspace
-    const auto bufs = buffers_of(h_bid, N);
-    std::vector<Job> jobs;
-    for (size_t b = 0; b < bufs.size(); ++b) {
-        Job J = clip_job(p, d_frames, luma, d_out, d_masks, bufs[b].first, bufs[b].second, (int)b);
-        Bump jb{job_ws};
-        carve_job(J, js, jb, d_states + 4 * b);
-        h_jobs[b] = J;
-        jobs.push_back(J);
-    }
-    SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * bufs.size(), hipMemcpyHostToDevice, s));
-    LaunchShape ls;
-    ls.add(js);
-    ctx->last_log.clear();
-    for (size_t b = 0; b < bufs.size(); ++b) {
-        st = run_jobs(ctx, d_jobs + b, &jobs[b], d_states + 4 * b, h_states + 4 * b, 1, ls, first_batch_iterations(p),
-                      false, s);
-        if (st != SCPL_OK) return st;
-        std::vector<Job> one(1, jobs[b]);
-        st = collect_logs(ctx, one, s);
-        if (st != SCPL_OK) return st;
-    }
-    return SCPL_OK;
+    scpl_clip c{*p, d_frames, d_out, d_masks, d_buffer_id};
+    return run_clips(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
 }
 
 scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, void *stream)
@@ -665,129 +770,7 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         if (!clips[c].d_frames || !clips[c].d_out) return SCPL_ERR_INVALID_ARG;
     }
     SCPL_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-
-    // pass 1: luma and segmentation of every clip (luma kept for carving)
-    size_t luma_b = 0, seg_b = 0;
-    int64_t Ntot = 0;
-    for (int c = 0; c < n_clips; ++c) {
-        const scpl_params &p = clips[c].p;
-        const int64_t HW = (int64_t)p.height * p.width;
-        if (p.channels == 3) luma_b += align_up((size_t)p.n_frames * HW);
-        seg_b = std::max(seg_b, seg_bytes(HW));
-        Ntot += p.n_frames;
-    }
-    const size_t pin_b = align_up(kSegWindow * 8) + align_up(4 * (size_t)Ntot) + align_up(16 * (size_t)Ntot) +
-                         align_up(sizeof(Job) * (size_t)Ntot);
-    SCPL_TRY(ensure_pinned(ctx, pin_b));
-    Bump host{static_cast<char *>(ctx->pinned)};
-    unsigned long long *h_sums = host.take<unsigned long long>(kSegWindow);
-    int32_t *h_bid_all = host.take<int32_t>((size_t)Ntot);
-    int32_t *h_states = host.take<int32_t>(4 * (size_t)Ntot);
-    Job *h_jobs = host.take<Job>((size_t)Ntot);
-
-    // segmentation needs only [luma][seg]; the job area is sized afterwards,
-    // so reserve luma + seg first and grow (preserving nothing else) later.
-    SCPL_TRY(ensure_ws(ctx, luma_b + seg_b));
-    std::vector<const uint8_t *> lumas(n_clips);
-    {
-        Bump dev{static_cast<char *>(ctx->ws)};
-        int64_t off = 0;
-        for (int c = 0; c < n_clips; ++c) {
-            const scpl_params &p = clips[c].p;
-            const int64_t HW = (int64_t)p.height * p.width;
-            if (p.channels == 3) {
-                uint8_t *y = dev.take<uint8_t>((size_t)p.n_frames * HW);
-                ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
-                launch_luma(clips[c].d_frames, y, (int64_t)p.n_frames * HW, s);
-                SCPL_CHECK_LAUNCH();
-                lumas[c] = y;
-            } else {
-                lumas[c] = clips[c].d_frames;
-            }
-        }
-        void *seg_ws = dev.take<char>(seg_b);
-        for (int c = 0; c < n_clips; ++c) {
-            int32_t nbuf = 0;
-            scpl_status st = segment_clip(ctx, &clips[c].p, lumas[c], seg_ws, h_sums, h_bid_all + off, nullptr, &nbuf, s);
-            if (st != SCPL_OK) return st;
-            if (clips[c].d_buffer_id)
-                SCPL_TRY(hipMemcpyAsync(clips[c].d_buffer_id, h_bid_all + off, (size_t)clips[c].p.n_frames * 4,
-                                        hipMemcpyHostToDevice, s));
-            off += clips[c].p.n_frames;
-        }
-    }
-
-    // pass 2: one job per buffer of every clip
-    struct Pending {
-        int clip, t0, T, bindex;
-    };
-    std::vector<Pending> pend;
-    {
-        int64_t off = 0;
-        for (int c = 0; c < n_clips; ++c) {
-            const auto bufs = buffers_of(h_bid_all + off, clips[c].p.n_frames);
-            for (size_t b = 0; b < bufs.size(); ++b) pend.push_back({c, bufs[b].first, bufs[b].second, (int)b});
-            off += clips[c].p.n_frames;
-        }
-    }
-    const int nj = (int)pend.size();
-    int Wall = 0;
-    for (int c = 0; c < n_clips; ++c) Wall = std::max(Wall, clips[c].p.width);
-    const int Qall = dp_columns_per_thread(Wall);  // one DP launch serves every job
-    size_t job_area = 0;
-    for (const Pending &q : pend) {
-        const scpl_params &p = clips[q.clip].p;
-        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
-        js.Q = Qall;
-        job_area += job_bytes(js);
-    }
-    const size_t head = luma_b + seg_b;
-    const size_t total = head + job_area + align_up(sizeof(Job) * (size_t)nj) + align_up(16 * (size_t)nj);
-    if (total > ctx->ws_size) {
-        // growing frees the old area: the luma must be recomputed after
-        SCPL_TRY(hipStreamSynchronize(s));
-        SCPL_TRY(ensure_ws(ctx, total));
-        Bump dev{static_cast<char *>(ctx->ws)};
-        for (int c = 0; c < n_clips; ++c) {
-            const scpl_params &p = clips[c].p;
-            const int64_t HW = (int64_t)p.height * p.width;
-            if (p.channels == 3) {
-                uint8_t *y = dev.take<uint8_t>((size_t)p.n_frames * HW);
-                ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
-                launch_luma(clips[c].d_frames, y, (int64_t)p.n_frames * HW, s);
-                SCPL_CHECK_LAUNCH();
-                lumas[c] = y;
-            }
-        }
-    }
-    Bump dev{static_cast<char *>(ctx->ws)};
-    dev.off = head;
-    char *job_ws = dev.take<char>(job_area);
-    Job *d_jobs = dev.take<Job>((size_t)nj);
-    int32_t *d_states = dev.take<int32_t>(4 * (size_t)nj);
-    Bump jb{job_ws};
-    LaunchShape ls;
-    int rfirst = 0;
-    std::vector<Job> jobs;
-    for (int q = 0; q < nj; ++q) {
-        const scpl_clip &cl = clips[pend[q].clip];
-        const scpl_params &p = cl.p;
-        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
-        js.Q = Qall;
-        Job J = clip_job(&p, cl.d_frames, lumas[pend[q].clip], cl.d_out, cl.d_masks, pend[q].t0, pend[q].T,
-                         pend[q].bindex);
-        carve_job(J, js, jb, d_states + 4 * q);
-        h_jobs[q] = J;
-        jobs.push_back(J);
-        ls.add(js);
-        rfirst = std::max(rfirst, first_batch_iterations(&p));
-    }
-    SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)nj, hipMemcpyHostToDevice, s));
-    ctx->last_log.clear();
-    scpl_status st = run_jobs(ctx, d_jobs, jobs.data(), d_states, h_states, nj, ls, rfirst, true, s);
-    if (st != SCPL_OK) return st;
-    return collect_logs(ctx, jobs, s);
+    return run_clips(ctx, clips, n_clips, true, nullptr, static_cast<hipStream_t>(stream));
 }
 
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on)
@@ -864,18 +847,21 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
         return SCPL_ERR_INVALID_ARG;
     SCPL_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t HW = (size_t)H * W;
+    const int64_t FS = tiled_frame_bytes(H, W);
     Job J{};
     Job *d_job;
     int32_t *d_state;
     char *d_two;
-    // the job sees a 2-frame clip [yprev, y] and carves frame 1 with T = 1
-    scpl_status st = stage_job(ctx, H, W, 1, 1, 2 * HW, J, d_job, d_state, d_two, s);
+    // the job sees a 2-frame tiled clip [yprev, y] and carves frame 1 with T = 1
+    scpl_status st = stage_job(ctx, H, W, 1, 1, 2 * (size_t)FS, J, d_job, d_state, d_two, s);
     if (st != SCPL_OK) return st;
-    if (d_yprev) SCPL_TRY(hipMemcpyAsync(d_two, d_yprev, HW, hipMemcpyDeviceToDevice, s));
-    SCPL_TRY(hipMemcpyAsync(d_two + HW, d_y, HW, hipMemcpyDeviceToDevice, s));
-    J.frames = reinterpret_cast<uint8_t *>(d_two);
-    J.luma = reinterpret_cast<uint8_t *>(d_two);
+    uint8_t *two = reinterpret_cast<uint8_t *>(d_two);
+    if (d_yprev) launch_tile_luma(d_yprev, 1, 1, H, W, two, s);
+    launch_tile_luma(d_y, 1, 1, H, W, two + FS, s);
+    J.frames = d_y;
+    J.luma = two;
+    J.ntc = tiles_across(W);
+    J.FS = FS;
     J.C = 1;
     J.mode = mode;
     J.t0 = 1;
@@ -999,12 +985,24 @@ scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
     SCPL_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t HW = (int64_t)p->height * p->width;
-    SCPL_TRY(ensure_ws(ctx, seg_bytes(HW)));
+    const int64_t FS = tiled_frame_bytes(p->height, p->width);
+    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up((size_t)p->n_frames * FS) + seg_bytes(HW)));
     SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8)));
-    int32_t nbuf = 0;
-    st = segment_clip(ctx, p, d_luma, ctx->ws, static_cast<unsigned long long *>(ctx->pinned), h_buffer_id,
-                      h_s_trace, &nbuf, s);
-    if (h_n_buffers) *h_n_buffers = nbuf;
+    Bump dev{static_cast<char *>(ctx->ws)};
+    unsigned long long *d_sums = dev.take<unsigned long long>(kSegWindow);
+    uint8_t *tiled = dev.take<uint8_t>((size_t)p->n_frames * FS);
+    std::vector<SegClip> seg(1);
+    seg[0].p = p;
+    seg[0].tiled = tiled;
+    seg[0].FS = FS;
+    seg[0].ntc = tiles_across(p->width);
+    seg[0].state = dev.take<char>(seg_bytes(HW));
+    seg[0].bid = h_buffer_id;
+    seg[0].trace = h_s_trace;
+    launch_tile_luma(d_luma, 1, p->n_frames, p->height, p->width, tiled, s);
+    SCPL_CHECK_LAUNCH();
+    st = segment_clips(ctx, seg, d_sums, static_cast<unsigned long long *>(ctx->pinned), s);
+    if (h_n_buffers) *h_n_buffers = seg[0].nbuf;
     return st;
 }
 

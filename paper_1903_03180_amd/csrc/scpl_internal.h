@@ -14,6 +14,21 @@ namespace scpl {
 constexpr int kBandMax = 120;
 // Affected pixels of one row recomputed in parallel by the partial update.
 constexpr int kUpdList = 1024;
+// Luma frames are stored in tiles of kTileH rows x kTileW columns (128
+// bytes, one cache line) so that the few pixels around a seam in
+// consecutive rows share lines.
+constexpr int kTileH = 16;
+constexpr int kTileW = 8;
+__host__ __device__ inline int tiles_across(int W) { return (W + kTileW - 1) / kTileW; }
+__host__ __device__ inline int64_t tiled_frame_bytes(int H, int W)
+{
+    return (int64_t)((H + kTileH - 1) / kTileH) * tiles_across(W) * (kTileH * kTileW);
+}
+// Byte offset of pixel (r, c) in a tiled frame with ntc tiles per row.
+__host__ __device__ inline int tofs(int r, int c, int ntc)
+{
+    return (((r >> 4) * ntc + (c >> 3)) << 7) + ((r & 15) << 3) + (c & 7);
+}
 // Frames per launch of the speculative ASDE scan.
 constexpr int kSegWindow = 64;
 constexpr int kDpThreads = 1024;
@@ -23,12 +38,14 @@ constexpr int kDpThreads = 1024;
 // depends on its parents) and a finished job makes every kernel return.
 struct Job {
     const uint8_t *frames;  // clip, N x H x W x C
-    const uint8_t *luma;    // clip luma, N x H x W (== frames when C == 1)
+    const uint8_t *luma;    // clip luma, N tiled frames of FS bytes
     uint8_t *out;           // clip output, N x H x Wt x C
     uint16_t *masks;        // clip masks, N x H x W, or null
     int32_t H, W, C, Wt, k, mode;
     int32_t t0, T;          // frames [t0, t0 + T) of the clip
     int32_t has_prev;       // frame t0 - 1 is the (carved) predecessor of t0
+    int32_t ntc;            // luma tiles per tile row
+    int64_t FS;             // bytes per tiled luma frame
     int32_t Wp;             // padded row pitch of the job's 2-D workspace
     int32_t Wq;             // row pitch of the DP's key rows (DP threads x columns per thread)
     int32_t B;              // rows per band of the backtrack
@@ -40,7 +57,6 @@ struct Job {
     int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
     uint32_t *K0, *K1;      // DP input rows: 4 floor(SE / T), all ones at and beyond W_r,
                             // (H + 1) x Wq (the extra row is all ones)
-    uint32_t *SE0, *SE1;    // sum of the buffer's energy maps, H x Wp
     uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
@@ -56,7 +72,9 @@ struct Job {
 };
 
 struct SegArgs {
-    const uint8_t *luma;  // N x H x W
+    const uint8_t *luma;  // N tiled frames
+    int64_t FS;           // bytes per tiled frame
+    int32_t ntc;          // tiles per tile row
     uint32_t *s1;         // H x W state
     uint64_t *s2;         // H x W state
     unsigned long long *sout;  // kSegWindow sums
@@ -68,6 +86,10 @@ struct SegArgs {
 
 // Kernel launchers (scpl_kernels.hip).  All take the stream explicitly.
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
+// N frames H x W x C (C = 1 or 3, row-major) -> tiled luma
+void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *dst, hipStream_t s);
+// N tiled luma frames -> row-major H x W
+void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s);
 void launch_seg_window(const SegArgs &a, hipStream_t s);
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
@@ -80,8 +102,8 @@ void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
 void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s);
 void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s);
-void launch_compact(const Job *d_jobs, int njobs, int r, int Hmax, hipStream_t s);
 void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
+void launch_refresh(const Job *d_jobs, int njobs, int r, int kmax, int Hmax, hipStream_t s);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s);
 void launch_u_to_keys(const int32_t *src, uint32_t *dst, int H, int W, int pitch, hipStream_t s);
 void launch_keys_to_u(const uint32_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);

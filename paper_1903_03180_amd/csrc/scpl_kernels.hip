@@ -128,6 +128,79 @@ __global__ __launch_bounds__(256) void luma_scalar_kernel(const uint8_t *__restr
     if (p < npx) y[p] = (uint8_t)((77u * rgb[3 * p] + 150u * rgb[3 * p + 1] + 29u * rgb[3 * p + 2] + 128u) >> 8);
 }
 
+// Tiled luma: a block converts a strip of 16 rows x 128 columns of one
+// frame (row-major, C channels) into 16 consecutive tiles.  The strip is
+// read row by row (coalesced), converted into LDS, and written as 2 KB of
+// contiguous tiles.  Columns past W are zero (never read).
+__global__ __launch_bounds__(256) void tile_luma_kernel(const uint8_t *__restrict__ src, int C, int N, int H, int W,
+                                                        uint8_t *__restrict__ dst, int vec)
+{
+    __shared__ uint8_t strip[16][128];
+    const int ntc = tiles_across(W);
+    const int c0 = blockIdx.y * 128;            // first column of the strip
+    const int r0 = (blockIdx.x % ((H + 15) / 16)) * 16;
+    const int n = blockIdx.x / ((H + 15) / 16);
+    const int tid = threadIdx.x;
+    // 16 rows x 128 columns: thread -> (row tid / 16, 8 columns from (tid % 16) * 8)
+    const int rr = tid >> 4, cc = (tid & 15) * 8;
+    const int r = r0 + rr, c = c0 + cc;
+    uint32_t lo = 0, hi = 0;
+    if (r < H && c < W) {
+        const uint8_t *row = src + ((size_t)n * H + r) * (size_t)W * C;
+        if (vec && c + 8 <= W) {
+            if (C == 3) {
+                const u32x2 *q = reinterpret_cast<const u32x2 *>(row + (size_t)c * 3);
+                const u32x2 a = q[0], b = q[1], d = q[2];
+                const uint32_t w[6] = {a.x, a.y, b.x, b.y, d.x, d.y};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int k0 = 3 * k, k1 = 3 * k + 1, k2 = 3 * k + 2;
+                    const uint32_t R = (w[k0 >> 2] >> (8 * (k0 & 3))) & 255u;
+                    const uint32_t G = (w[k1 >> 2] >> (8 * (k1 & 3))) & 255u;
+                    const uint32_t B = (w[k2 >> 2] >> (8 * (k2 & 3))) & 255u;
+                    const uint32_t v = (77u * R + 150u * G + 29u * B + 128u) >> 8;
+                    if (k < 4) lo |= v << (8 * k);
+                    else hi |= v << (8 * (k - 4));
+                }
+            } else {
+                const u32x2 a = *reinterpret_cast<const u32x2 *>(row + c);
+                lo = a.x;
+                hi = a.y;
+            }
+        } else {
+            for (int k = 0; k < 8 && c + k < W; ++k) {
+                const uint8_t *p = row + (size_t)(c + k) * C;
+                const uint32_t v = C == 3 ? (77u * p[0] + 150u * p[1] + 29u * p[2] + 128u) >> 8 : p[0];
+                if (k < 4) lo |= v << (8 * k);
+                else hi |= v << (8 * (k - 4));
+            }
+        }
+    }
+    *reinterpret_cast<uint32_t *>(&strip[rr][cc]) = lo;
+    *reinterpret_cast<uint32_t *>(&strip[rr][cc + 4]) = hi;
+    __syncthreads();
+    // 16 tiles of 16 rows x 8 columns: thread -> (tile tid / 16, tile row tid % 16)
+    const int tile = tid >> 4, trow = tid & 15;
+    const int tc = (c0 >> 3) + tile;
+    if (tc < ntc && r0 + trow < H) {
+        u32x2 o;
+        o.x = *reinterpret_cast<const uint32_t *>(&strip[trow][tile * 8]);
+        o.y = *reinterpret_cast<const uint32_t *>(&strip[trow][tile * 8 + 4]);
+        *reinterpret_cast<u32x2 *>(dst + (size_t)n * tiled_frame_bytes(H, W) + tofs(r0 + trow, tc * 8, ntc)) = o;
+    }
+}
+
+__global__ __launch_bounds__(256) void untile_kernel(const uint8_t *__restrict__ src, int N, int H, int W,
+                                                     uint8_t *__restrict__ dst)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)N * H * W) return;
+    const int c = (int)(p % W);
+    const int64_t nr = p / W;
+    const int r = (int)(nr % H), n = (int)(nr / H);
+    dst[p] = src[(size_t)n * tiled_frame_bytes(H, W) + tofs(r, c, tiles_across(W))];
+}
+
 // ------------------------------------------------------- ASDE window scan
 //
 // One thread per pixel of the original frame.  For a buffer starting at t0
@@ -143,22 +216,28 @@ __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
     const int tid = threadIdx.x;
     if (tid < kSegWindow) part[tid] = 0;
     __syncthreads();
-    const int64_t HW = (int64_t)a.H * a.W;
-    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
-    const bool valid = p < HW;
-    const int i = valid ? (int)(p / a.W) : 0;
-    const int j = valid ? (int)(p - (int64_t)i * a.W) : 0;
-    const int im = max(i - 1, 0), ip = min(i + 1, a.H - 1), jm = max(j - 1, 0), jp = min(j + 1, a.W - 1);
-    const int oa = im * a.W, ob = i * a.W, oc = ip * a.W;
+    // a block covers 16 x 16 pixels; each wavefront an 8 x 8 half tile, so
+    // that a load instruction reads 64 contiguous bytes
+    const int wv = tid >> 6, ln = tid & 63;
+    const int i = blockIdx.y * 16 + (wv >> 1) * 8 + (ln >> 3);
+    const int j = blockIdx.x * 16 + (wv & 1) * 8 + (ln & 7);
+    const bool valid = i < a.H && j < a.W;
+    const int ii = valid ? i : 0, jj = valid ? j : 0;
+    const int im = max(ii - 1, 0), ip = min(ii + 1, a.H - 1), jm = max(jj - 1, 0), jp = min(jj + 1, a.W - 1);
+    const int n = a.ntc;
+    const int o00 = tofs(im, jm, n), o01 = tofs(im, jj, n), o02 = tofs(im, jp, n);
+    const int o10 = tofs(ii, jm, n), o11 = tofs(ii, jj, n), o12 = tofs(ii, jp, n);
+    const int o20 = tofs(ip, jm, n), o21 = tofs(ip, jj, n), o22 = tofs(ip, jp, n);
+    const int64_t FS = a.FS;
     uint32_t s1 = 0;
     uint64_t s2 = 0;
+    const int64_t p = (int64_t)ii * a.W + jj;
     if (valid) {
         if (a.init) {
-            const uint8_t *f = a.luma + (size_t)a.t0 * HW;
-            const int g = sobel9(f[oa + jm], f[oa + j], f[oa + jp], f[ob + jm], f[ob + jp], f[oc + jm], f[oc + j],
-                                 f[oc + jp]);
+            const GLOBAL uint8_t *f = gp(a.luma) + (size_t)a.t0 * FS;
+            const int g = sobel9(f[o00], f[o01], f[o02], f[o10], f[o12], f[o20], f[o21], f[o22]);
             uint32_t e = (uint32_t)g;
-            if (a.mode == 1) e = 2u * g + (a.t0 > 0 ? 18u * (uint32_t)abs((int)f[p] - (int)f[p - HW]) : 0u);
+            if (a.mode == 1) e = 2u * g + (a.t0 > 0 ? 18u * (uint32_t)abs((int)f[o11] - (int)f[(ptrdiff_t)o11 - FS]) : 0u);
             s1 = e;
             s2 = (uint64_t)e * e;
         } else {
@@ -169,15 +248,14 @@ __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
     for (int t = a.tb; t < a.te; ++t) {
         unsigned long long v = 0;
         if (valid) {
-            const uint8_t *f = a.luma + (size_t)t * HW;
-            const int g = sobel9(f[oa + jm], f[oa + j], f[oa + jp], f[ob + jm], f[ob + jp], f[oc + jm], f[oc + j],
-                                 f[oc + jp]);
+            const GLOBAL uint8_t *f = gp(a.luma) + (size_t)t * FS;
+            const int g = sobel9(f[o00], f[o01], f[o02], f[o10], f[o12], f[o20], f[o21], f[o22]);
             uint32_t e = (uint32_t)g;
-            if (a.mode == 1) e = 2u * g + 18u * (uint32_t)abs((int)f[p] - (int)f[p - HW]);
+            if (a.mode == 1) e = 2u * g + 18u * (uint32_t)abs((int)f[o11] - (int)f[(ptrdiff_t)o11 - FS]);
             s1 += e;
             s2 += (uint64_t)e * e;
-            const uint64_t n = (uint64_t)(t - a.t0 + 1);
-            v = isqrt_u64(n * s2 - (uint64_t)s1 * s1);
+            const uint64_t nn = (uint64_t)(t - a.t0 + 1);
+            v = isqrt_u64(nn * s2 - (uint64_t)s1 * s1);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -240,59 +318,60 @@ struct Stencil {
     int oa0, oa1, oa2, ob0, ob1, ob2, oc0, oc1, oc2;  // offsets in a frame
 };
 
-__device__ __forceinline__ Stencil stencil_at(const int16_t *M, int Wp, int W, int H, int i, int j, int Wcur)
+// Stencil of carved pixel (i, j) from the column-map rows of i-1, i, i+1
+// (ma, mb, mc: carved column -> original column).
+__device__ __forceinline__ Stencil stencil_from_rows(const int16_t *ma, const int16_t *mb, const int16_t *mc, int im,
+                                                     int i, int ip, int j, int Wcur, int W, int ntc)
 {
-    const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, Wcur - 1);
-    const int16_t *ma = M + (size_t)im * Wp, *mb = M + (size_t)i * Wp, *mc = M + (size_t)ip * Wp;
+    const int jm = max(j - 1, 0), jp = min(j + 1, Wcur - 1);
     Stencil s;
-    s.oa0 = im * W + mcol(ma, jm, W);
-    s.oa1 = im * W + mcol(ma, j, W);
-    s.oa2 = im * W + mcol(ma, jp, W);
-    s.ob0 = i * W + mcol(mb, jm, W);
-    s.ob1 = i * W + mcol(mb, j, W);
-    s.ob2 = i * W + mcol(mb, jp, W);
-    s.oc0 = ip * W + mcol(mc, jm, W);
-    s.oc1 = ip * W + mcol(mc, j, W);
-    s.oc2 = ip * W + mcol(mc, jp, W);
+    s.oa0 = tofs(im, mcol(ma, jm, W), ntc);
+    s.oa1 = tofs(im, mcol(ma, j, W), ntc);
+    s.oa2 = tofs(im, mcol(ma, jp, W), ntc);
+    s.ob0 = tofs(i, mcol(mb, jm, W), ntc);
+    s.ob1 = tofs(i, mcol(mb, j, W), ntc);
+    s.ob2 = tofs(i, mcol(mb, jp, W), ntc);
+    s.oc0 = tofs(ip, mcol(mc, jm, W), ntc);
+    s.oc1 = tofs(ip, mcol(mc, j, W), ntc);
+    s.oc2 = tofs(ip, mcol(mc, jp, W), ntc);
     return s;
 }
 
 // Energy of buffer frame t (0-based within the buffer) at a stencil.
 __device__ __forceinline__ int energy_one(const Job &J, const Stencil &s, int t)
 {
-    const size_t HW = (size_t)J.H * J.W;
-    const GLOBAL uint8_t *f = gp(J.luma) + (size_t)(J.t0 + t) * HW;
+    const GLOBAL uint8_t *f = gp(J.luma) + (size_t)(J.t0 + t) * J.FS;
     const int g = sobel9(f[s.oa0], f[s.oa1], f[s.oa2], f[s.ob0], f[s.ob2], f[s.oc0], f[s.oc1], f[s.oc2]);
     if (J.mode != 1) return g;
-    const int d = (t > 0 || J.has_prev) ? abs((int)f[s.ob1] - (int)f[(ptrdiff_t)s.ob1 - (ptrdiff_t)HW]) : 0;
+    const int d = (t > 0 || J.has_prev) ? abs((int)f[s.ob1] - (int)f[(ptrdiff_t)s.ob1 - (ptrdiff_t)J.FS]) : 0;
     return 2 * g + 18 * d;
 }
 
-// Iteration 0 of every job: SE = sum of the T energy maps and the DP key
-// row 4 floor(SE / T) over the uncarved frames (the column map is the
-// identity).
+// Iteration 0 of every job: the DP key row 4 floor(sum of the T energy
+// maps / T) over the uncarved frames (the column map is the identity).  A
+// block covers 16 x 16 pixels.
 __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
 {
     const Job &J = jobs[blockIdx.z];
     if (J.W <= J.Wt) return;
-    const int j = blockIdx.x * 64 + threadIdx.x;
-    const int i = blockIdx.y * 4 + threadIdx.y;
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;  // 8 x 8 half tile per wavefront
+    const int i = blockIdx.y * 16 + (wv >> 1) * 8 + (ln >> 3);
+    const int j = blockIdx.x * 16 + (wv & 1) * 8 + (ln & 7);
     if (i >= J.H || j >= J.W) return;
-    const int W = J.W, H = J.H;
+    const int W = J.W, H = J.H, n = J.ntc;
     const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, W - 1);
     Stencil st;
-    st.oa0 = im * W + jm;
-    st.oa1 = im * W + j;
-    st.oa2 = im * W + jp;
-    st.ob0 = i * W + jm;
-    st.ob1 = i * W + j;
-    st.ob2 = i * W + jp;
-    st.oc0 = ip * W + jm;
-    st.oc1 = ip * W + j;
-    st.oc2 = ip * W + jp;
+    st.oa0 = tofs(im, jm, n);
+    st.oa1 = tofs(im, j, n);
+    st.oa2 = tofs(im, jp, n);
+    st.ob0 = tofs(i, jm, n);
+    st.ob1 = tofs(i, j, n);
+    st.ob2 = tofs(i, jp, n);
+    st.oc0 = tofs(ip, jm, n);
+    st.oc1 = tofs(ip, j, n);
+    st.oc2 = tofs(ip, jp, n);
     uint32_t acc = 0;
     for (int t = 0; t < J.T; ++t) acc += (uint32_t)energy_one(J, st, t);
-    J.SE0[(size_t)i * J.Wp + j] = acc;
     J.K0[(size_t)i * J.Wq + j] = (acc / (uint32_t)J.T) << 2;
 }
 
@@ -681,12 +760,25 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
     }
 }
 
-// ---------------------------------------------------------------- compact
+// ------------------------------------------------------ compact + update
 //
 // Row i loses the k_iter columns R_0 < ... < R_{k-1} (seams never share a
-// pixel and keep their order).  Output column j reads source column
+// pixel and keep their order).  New column j of a row reads old column
 // j + #{s : R_s - s <= j}; R_s - s never decreases, so a binary search
 // finds the count.  Only the column map is compacted: frames stay put.
+//
+// The DP key row 4 floor(SE / T) (SE = sum of the buffer's energy maps) is
+// carried the same way.  A kept pixel's energy in every frame depends only
+// on the original pixels of its 3x3 carved neighbourhood (and on its own
+// original pixel in the predecessor frame for the difference term).  If the
+// neighbourhood around its new position holds the same original pixels as
+// the one around its old position, all its energies -- hence its key -- are
+// unchanged and move with it; otherwise they are recomputed from the T
+// frames.  This is exact: the result equals a full recomputation.  One
+// block per row: the old maps of rows i-1..i+1 are staged in LDS and their
+// new maps built there; the affected pixels of the row (a few per seam) are
+// collected and each gets a share of the block's threads, which split the
+// T frames between them.
 
 __device__ __forceinline__ int source_column(int j, int kk, const int *R, const int16_t *seams_row_major, int H)
 {
@@ -700,144 +792,185 @@ __device__ __forceinline__ int source_column(int j, int kk, const int *R, const 
     return j + a;
 }
 
-__global__ __launch_bounds__(256) void compact_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
 {
+    __shared__ int R[256];  // seams of row i: old column - s (when k_iter <= 256)
     const Job &J = jobs[blockIdx.y];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int i = blockIdx.x;
     if (i >= J.H) return;
     const int kk = J.log[4 * r + 2];
-    const int H = J.H;
-    const int16_t *__restrict__ Mc = ((r & 1) ? J.M1 : J.M0) + (size_t)i * J.Wp;
-    int16_t *__restrict__ Mn = ((r & 1) ? J.M0 : J.M1) + (size_t)i * J.Wp;
-    __shared__ int R[256];
-    const bool lds = kk <= 256;
-    if (lds) {
-        for (int s = threadIdx.x; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
+    const int Wn = Wr - kk;
+    const int H = J.H, Wp = J.Wp, Wq = J.Wq;
+    const int16_t *__restrict__ Mo = (r & 1) ? J.M1 : J.M0;
+    int16_t *__restrict__ Mw = (r & 1) ? J.M0 : J.M1;
+    const uint32_t *__restrict__ Ko = (r & 1) ? J.K1 : J.K0;
+    uint32_t *__restrict__ Kn = (r & 1) ? J.K0 : J.K1;
+    const bool rl = kk <= 256;
+    const bool keys = Wn > J.Wt;  // a further iteration reads the keys
+    const int tid = threadIdx.x;
+    if (rl) {
+        for (int s = tid; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
         __syncthreads();
     }
-    for (int j = threadIdx.x; j < Wr - kk; j += 256)
-        Mn[j] = Mc[source_column(j, kk, lds ? R : nullptr, J.seams + i, H)];
+    // every pixel of the row moves to its new column with its key (the
+    // refresh kernel then recomputes the keys whose neighbourhood changed)
+    for (int j = tid; j < Wn; j += 256) {
+        const int src = source_column(j, kk, rl ? R : nullptr, J.seams + i, H);
+        Mw[(size_t)i * Wp + j] = Mo[(size_t)i * Wp + src];
+        if (keys) Kn[(size_t)i * Wq + j] = Ko[(size_t)i * Wq + src];
+    }
+    if (!keys) return;
+    // the keys of the vacated columns become all ones; columns beyond the
+    // previous width of this buffer already are
+    const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
+    for (int j = Wn + tid; j < wprev; j += 256) Kn[(size_t)i * Wq + j] = kKeyInf;
 }
 
-// ---------------------------------------------------------- partial update
+// Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
+// are strictly increasing, so two carved positions hold the same original
+// pixel exactly when they map to the same old column: with R_q the removed
+// old columns of row q (minus their rank), new column c of row q was old
+// column c + #{s : R_q[s] <= c}.  Pixel (i, j) keeps its energy in every
+// frame iff each of its 8 neighbours, taken on the new grid, was the
+// matching neighbour of its old position (i, o_i(j)) on the old grid
+// (borders replicated on each grid).  Only columns within 3 of a removed
+// pixel of rows i-1..i+1 can fail the test.
 //
-// SE (sum of the buffer's energy maps) and the DP key row 4 floor(SE / T)
-// after removing the seams of iteration r.  A kept pixel's energy in every
-// frame depends only on the original pixels of its 3x3 carved neighbourhood
-// (and on its own original pixel in the predecessor frame for the
-// difference term).  If the neighbourhood around its new position holds the
-// same original pixels as the one around its old position, all its
-// energies -- hence SE and the key -- are unchanged and move with it;
-// otherwise they are recomputed from the T frames.  This is exact: the
-// result equals a full recomputation.  The old and new column maps of rows
-// i-1..i+1 are staged in LDS; the affected pixels of the row (a few per
-// seam) are collected and each gets a share of the block's threads, which
-// split the T frames between them.
+// One block per (band of 16 rows, job): the candidates around every seam
+// are tested, the affected ones (usually 2-4 per seam and row) listed in
+// LDS, and each gets a share of the block's threads that sum its energy
+// over the T frames.  Threads next to each other work on pixels of the same
+// band and the same frame, so their loads share a few luma tiles.  A
+// candidate also in the window of the seam on its left is left to that
+// seam.
 
-constexpr int kUpdMaxW = 4096;  // widest row whose maps are staged in LDS
+constexpr int kRefreshRows = 16;
+constexpr int kRefreshList = 512;
+constexpr int kRefreshSeams = 64;  // seams whose positions are staged in LDS
 
-__global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r, int ws)
+__global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
 {
-    extern __shared__ int16_t maps[];  // old and new maps of rows i-1..i+1: 6 x ws
-    __shared__ int R[256];
-    __shared__ int list[kUpdList];
-    __shared__ uint32_t sums[kUpdList];
-    __shared__ int nlist;
+    __shared__ int R[kRefreshRows + 2][kRefreshSeams];  // rows i0-1 .. i0+16 (clamped): old column - s
+    __shared__ int flist[kRefreshList];                 // (row in band << 16) | new column
+    __shared__ Stencil fst[kRefreshList];
+    __shared__ uint32_t fsum[kRefreshList];
+    __shared__ int nf;
     const Job &J = jobs[blockIdx.y];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
-    if (Wn <= J.Wt) return;  // no further iteration reads the keys
-    const int i = blockIdx.x;
-    if (i >= J.H) return;
-    const int H = J.H, Wp = J.Wp, Wq = J.Wq, W = J.W, T = J.T;
-    const int16_t *__restrict__ Mo = (r & 1) ? J.M1 : J.M0;
+    if (Wn <= J.Wt) return;
+    const int H = J.H, Wp = J.Wp, Wq = J.Wq, W = J.W, T = J.T, ntc = J.ntc;
+    const int i0 = blockIdx.x * kRefreshRows;
+    if (i0 >= H) return;
+    const int nrows = min(kRefreshRows, H - i0);
     const int16_t *__restrict__ Mn = (r & 1) ? J.M0 : J.M1;
-    const uint32_t *__restrict__ SEo = (r & 1) ? J.SE1 : J.SE0;
-    uint32_t *__restrict__ SEn = (r & 1) ? J.SE0 : J.SE1;
-    const uint32_t *__restrict__ Ko = (r & 1) ? J.K1 : J.K0;
     uint32_t *__restrict__ Kn = (r & 1) ? J.K0 : J.K1;
-    const bool lds = kk <= 256;
-    const bool maps_lds = Wr <= ws;
-    int16_t *mo[3] = {maps, maps + ws, maps + 2 * ws};
-    int16_t *mn[3] = {maps + 3 * ws, maps + 4 * ws, maps + 5 * ws};
     const int tid = threadIdx.x;
-    if (tid == 0) nlist = 0;
-    if (lds)
-        for (int s = tid; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
-    const int rows[3] = {max(i - 1, 0), i, min(i + 1, H - 1)};
-    if (maps_lds) {
-        const int nw = (Wr + 1) >> 1;  // 32-bit words per row (Wp is even)
-        for (int idx = tid; idx < 3 * nw; idx += 256) {
-            const int q = idx / nw, w = idx - q * nw;
-            reinterpret_cast<uint32_t *>(mo[q])[w] =
-                *gp(reinterpret_cast<const uint32_t *>(Mo + (size_t)rows[q] * Wp) + w);
-            reinterpret_cast<uint32_t *>(mn[q])[w] =
-                *gp(reinterpret_cast<const uint32_t *>(Mn + (size_t)rows[q] * Wp) + w);
+    const bool rl = kk <= kRefreshSeams;
+    if (tid == 0) nf = 0;
+    if (rl)
+        for (int idx = tid; idx < (nrows + 2) * kk; idx += 256) {
+            const int ss = idx / (nrows + 2), rr = idx - ss * (nrows + 2);  // consecutive threads: same seam
+            const int row = min(max(i0 - 1 + rr, 0), H - 1);
+            R[rr][ss] = J.seams[(size_t)ss * H + row] - ss;
         }
-    }
     __syncthreads();
-    // the keys of the vacated columns become all ones; columns beyond the
-    // previous width of this buffer already are
-    const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
-    for (int j = Wn + tid; j < wprev; j += 256) Kn[(size_t)i * Wq + j] = kKeyInf;
-    for (int j = tid; j < Wn; j += 256) {
-        const int src = source_column(j, kk, lds ? R : nullptr, J.seams + i, H);
-        const int jm = max(j - 1, 0), jp = min(j + 1, Wn - 1);
-        const int sm = max(src - 1, 0), sp = min(src + 1, Wr - 1);
+    // seam positions (old column - rank) of row `row` (absolute, clamped)
+    auto rsd = [&](int row, int ss) -> int {
+        row = min(max(row, 0), H - 1);
+        return rl ? R[row - (i0 - 1)][ss] : (int)J.seams[(size_t)ss * H + row] - ss;
+    };
+    // old column of new column c in row `row`
+    auto oldcol = [&](int row, int c) -> int {
+        int a = 0, b = kk;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (rsd(row, m) <= c) a = m + 1;
+            else b = m;
+        }
+        return c + a;
+    };
+    auto full_sum = [&](const Stencil &st) {
+        uint32_t acc = 0;
+        int t = 0;
+        for (; t + 4 <= T; t += 4) {
+            const int e0 = energy_one(J, st, t), e1 = energy_one(J, st, t + 1);
+            const int e2 = energy_one(J, st, t + 2), e3 = energy_one(J, st, t + 3);
+            acc += (uint32_t)(e0 + e1 + e2 + e3);
+        }
+        for (; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
+        return acc;
+    };
+    // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
+    const int ncand = kk * nrows * 9;
+    for (int u = tid; u < ncand; u += 256) {
+        const int s = u / (nrows * 9);
+        const int rem = u - s * (nrows * 9);
+        const int rb = rem / 9, slot = rem - rb * 9;
+        const int i = i0 + rb;
+        const int a0 = rsd(i - 1, s), a1 = rsd(i, s), a2 = rsd(i + 1, s);
+        const int lo = max(min(min(a0, a1), a2) - 3, 0);
+        const int hi = min(max(max(a0, a1), a2) + 3, Wn - 1);
+        const int c = lo + slot;
+        if (c > hi) continue;
+        if (s > 0 && c <= max(max(rsd(i - 1, s - 1), rsd(i, s - 1)), rsd(i + 1, s - 1)) + 3) continue;
+        const int src = oldcol(i, c);
         bool same = true;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int16_t *a = maps_lds ? mn[q] : Mn + (size_t)rows[q] * Wp;
-            const int16_t *b = maps_lds ? mo[q] : Mo + (size_t)rows[q] * Wp;
-            same = same && a[jm] == b[sm] && a[jp] == b[sp] && (q == 1 || a[j] == b[src]);
-        }
-        if (same) {
-            SEn[(size_t)i * Wp + j] = SEo[(size_t)i * Wp + src];
-            Kn[(size_t)i * Wq + j] = Ko[(size_t)i * Wq + src];
-        } else {
-            const int slot = atomicAdd(&nlist, 1);
-            if (slot < kUpdList) {
-                list[slot] = j;
-                sums[slot] = 0;
-            } else {  // more affected pixels than the list holds: this thread does it alone
-                const Stencil st = stencil_at(Mn, Wp, W, H, i, j, Wn);
-                uint32_t acc = 0;
-                for (int t = 0; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
-                SEn[(size_t)i * Wp + j] = acc;
-                Kn[(size_t)i * Wq + j] = (acc / (uint32_t)T) << 2;
+        for (int dq = -1; dq <= 1; ++dq)
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+                if (dq == 0 && dj == 0) continue;
+                const int cn = min(max(c + dj, 0), Wn - 1);
+                const int co = min(max(src + dj, 0), Wr - 1);
+                same = same && oldcol(i + dq, cn) == co;
+            }
+        if (!same) {
+            const int idx = atomicAdd(&nf, 1);
+            if (idx < kRefreshList) {
+                flist[idx] = (rb << 16) | c;
+            } else {  // list full: this thread does the pixel alone
+                const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
+                const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
+                                                     Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W, ntc);
+                Kn[(size_t)i * Wq + c] = (full_sum(st) / (uint32_t)T) << 2;
             }
         }
     }
     __syncthreads();
-    const int n = min(nlist, kUpdList);
-    if (n > 0 && n <= 256) {
-        // pixel p gets threads p, p + n, p + 2n, ...; each sums every
-        // tpp-th frame of the buffer
-        const int tpp = 256 / n;
-        const int p = tid % n, sub = tid / n;
-        if (sub < tpp) {
-            const Stencil st = stencil_at(Mn, Wp, W, H, i, list[p], Wn);
+    const int n = min(nf, kRefreshList);
+    for (int p = tid; p < n; p += 256) {
+        const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
+        const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
+        fst[p] = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp, Mn + (size_t)ip * Wp, im, i, ip, c,
+                                   Wn, W, ntc);
+        fsum[p] = 0;
+    }
+    __syncthreads();
+    if (n > 0) {
+        // pixel p gets threads p, p + n, ...; each sums every tpp-th frame
+        const int tpp = max(256 / n, 1);
+        for (int u = tid; u < n * tpp; u += 256) {
+            const int p = u % n, sub = u / n;
             uint32_t acc = 0;
-            for (int t = sub; t < T; t += tpp) acc += (uint32_t)energy_one(J, st, t);
-            atomicAdd(&sums[p], acc);
-        }
-    } else if (n > 256) {
-        for (int p = tid; p < n; p += 256) {
-            const Stencil st = stencil_at(Mn, Wp, W, H, i, list[p], Wn);
-            uint32_t acc = 0;
-            for (int t = 0; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
-            sums[p] = acc;
+            int t = sub;
+            for (; t + 3 * tpp < T; t += 4 * tpp) {
+                const int e0 = energy_one(J, fst[p], t), e1 = energy_one(J, fst[p], t + tpp);
+                const int e2 = energy_one(J, fst[p], t + 2 * tpp), e3 = energy_one(J, fst[p], t + 3 * tpp);
+                acc += (uint32_t)(e0 + e1 + e2 + e3);
+            }
+            for (; t < T; t += tpp) acc += (uint32_t)energy_one(J, fst[p], t);
+            atomicAdd(&fsum[p], acc);
         }
     }
     __syncthreads();
     for (int p = tid; p < n; p += 256) {
-        const int j = list[p];
-        SEn[(size_t)i * Wp + j] = sums[p];
-        Kn[(size_t)i * Wq + j] = (sums[p] / (uint32_t)T) << 2;
+        const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
+        Kn[(size_t)i * Wq + c] = (fsum[p] / (uint32_t)T) << 2;
     }
 }
 
@@ -920,6 +1053,18 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 // ---------------------------------------------------------------- launchers
 
+void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *dst, hipStream_t s)
+{
+    const int vec = (W % kTileW == 0) && ((((uintptr_t)src) & 7) == 0);
+    const dim3 g((unsigned)((int64_t)N * ((H + 15) / 16)), blocks_for(W, 128));
+    hipLaunchKernelGGL(tile_luma_kernel, g, dim3(256), 0, s, src, C, N, H, W, dst, vec);
+}
+
+void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(untile_kernel, dim3(blocks_for((int64_t)N * H * W, 256)), dim3(256), 0, s, src, N, H, W, dst);
+}
+
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s)
 {
     if (npx <= 0) return;
@@ -931,8 +1076,7 @@ void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s)
 
 void launch_seg_window(const SegArgs &a, hipStream_t s)
 {
-    const int64_t HW = (int64_t)a.H * a.W;
-    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(HW, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(a.W, 16), blocks_for(a.H, 16)), dim3(256), 0, s, a);
 }
 
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
@@ -942,7 +1086,7 @@ void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s
 
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(Wmax, 64), blocks_for(Hmax, 4), njobs), dim3(64, 4), 0, s,
+    hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(Wmax, 16), blocks_for(Hmax, 16), njobs), dim3(256), 0, s,
                        d_jobs);
 }
 
@@ -1011,16 +1155,14 @@ void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int, 
     hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), 0, s, d_jobs, r);
 }
 
-void launch_compact(const Job *d_jobs, int njobs, int r, int Hmax, hipStream_t s)
+void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int, hipStream_t s)
 {
-    hipLaunchKernelGGL(compact_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs, r);
+    hipLaunchKernelGGL(update_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs, r);
 }
 
-void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s)
+void launch_refresh(const Job *d_jobs, int njobs, int r, int, int Hmax, hipStream_t s)
 {
-    const int ws = Wmax <= kUpdMaxW ? ((Wmax + 1) & ~1) : 0;
-    hipLaunchKernelGGL(update_kernel, dim3(Hmax, njobs), dim3(256), (size_t)6 * ws * sizeof(int16_t), s, d_jobs, r,
-                       ws);
+    hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for(Hmax, kRefreshRows), njobs), dim3(256), 0, s, d_jobs, r);
 }
 
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s)

@@ -38,7 +38,7 @@ EXPORTS = [
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read",
 ]
 
-KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "compact", "gather", "init", "update"]
+KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
 
 class scpl_params(C.Structure):
