@@ -124,10 +124,10 @@ size_t g_lds_cap = 65536;  // set from the device at context creation
 
 struct JobShape {
     int32_t H, W, Wt, k;
-    int32_t Q = 0;  // DP columns per thread of the launch the job runs in (0: its own width decides)
+    int32_t Wg = 0;  // width that picks the DP geometry of the launch (0: the job's own)
     int32_t Wp() const { return (int32_t)align_up((size_t)W, 64); }
-    int32_t q() const { return Q > 0 ? Q : dp_columns_per_thread(W); }
-    int32_t Wq() const { return q() * dp_threads(W, q()); }
+    DpGeom geom() const { return dp_geom(Wg > 0 ? Wg : W); }
+    int32_t Kp() const { return kKeyLeft + (int32_t)align_up((size_t)geom().cover(W), 64); }
     int32_t B() const { return band_rows(H, W, g_lds_cap); }
     int32_t nb() const { return (H + B() - 1) / B(); }
     int32_t kcap() const { return std::min(k, W); }
@@ -139,7 +139,7 @@ size_t job_bytes(const JobShape &s)
     const size_t H = s.H, Wp = s.Wp(), W = s.W, nb = s.nb(), kc = s.kcap(), lc = s.logcap();
     size_t b = 0;
     b += 2 * align_up(H * Wp * 2);       // M0, M1
-    b += 2 * align_up((H + 1) * (size_t)s.Wq() * 4);  // K0, K1
+    b += 2 * align_up((H + 1) * (size_t)s.Kp() * 4);  // K0, K1
     b += align_up(H * Wp);               // dir
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
@@ -160,15 +160,17 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.Wt = s.Wt;
     J.k = s.k;
     J.Wp = (int32_t)Wp;
-    J.Wq = s.Wq();
+    J.Kp = s.Kp();
+    J.KL = kKeyLeft;
+    J.dpnw = s.geom().banded ? s.geom().waves(s.W) : 0;
     J.B = s.B();
     J.nb = (int32_t)nb;
     J.kcap = (int32_t)kc;
     J.logcap = (int32_t)lc;
     J.M0 = bp.take<int16_t>(H * Wp);
     J.M1 = bp.take<int16_t>(H * Wp);
-    J.K0 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
-    J.K1 = bp.take<uint32_t>((H + 1) * (size_t)J.Wq);
+    J.K0 = bp.take<uint32_t>((H + 1) * (size_t)J.Kp);
+    J.K1 = bp.take<uint32_t>((H + 1) * (size_t)J.Kp);
     J.dir = bp.take<uint8_t>(H * Wp);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
@@ -388,7 +390,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
 // ------------------------------------------------------------- iterations
 
 struct LaunchShape {
-    int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0, Q = 0;
+    int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0;
     void add(const JobShape &s)
     {
         Hmax = std::max(Hmax, s.H);
@@ -396,7 +398,6 @@ struct LaunchShape {
         nbmax = std::max(nbmax, s.nb());
         kmax = std::max(kmax, s.kcap());
         Bmax = std::max(Bmax, s.B());
-        Q = std::max(Q, s.q());
     }
 };
 
@@ -404,7 +405,7 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const La
 {
     {
         ProfScope ps(ctx, SCPL_KERNEL_DP, s);
-        launch_dp(d_jobs, nj, r, ls.Wmax, ls.Q, s);
+        launch_dp(d_jobs, nj, r, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
@@ -695,11 +696,11 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
     const int nj = (int)pend.size();
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
-    const int Qall = dp_columns_per_thread(Wall);  // a batched DP launch serves every job
+    // a batched DP launch serves every job: its geometry follows the widest
     auto shape_of = [&](const Pending &q) {
         const scpl_params &p = clips[q.clip].p;
         JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
-        if (batched) js.Q = Qall;
+        if (batched) js.Wg = Wall;
         return js;
     };
     // area B: job workspaces (all jobs when batched; one shared per clip shape
@@ -876,7 +877,7 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
     ls.add(JobShape{H, W, 1, 1});
     launch_init_jobs(d_job, 1, ls.Hmax, ls.Wmax, s);
     launch_energy(d_job, 1, H, W, s);
-    launch_keys_to_u(J.K0, d_e, H, W, J.Wq, s);
+    launch_keys_to_u(J.K0 + J.KL, d_e, H, W, J.Kp, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));  // the pinned job slot is reused by the next call
     return SCPL_OK;
@@ -899,8 +900,8 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, 1});
     launch_init_jobs(d_job, 1, H, W, s);
-    launch_u_to_keys(d_u, J.K0, H, W, J.Wq, s);
-    launch_dp(d_job, 1, 0, W, ls.Q, s);
+    launch_u_to_keys(d_u, J.K0 + J.KL, H, W, J.Kp, s);
+    launch_dp(d_job, 1, 0, W, s);
     launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);
     launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);

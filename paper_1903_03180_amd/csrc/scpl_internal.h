@@ -47,7 +47,8 @@ struct Job {
     int32_t ntc;            // luma tiles per tile row
     int64_t FS;             // bytes per tiled luma frame
     int32_t Wp;             // padded row pitch of the job's 2-D workspace
-    int32_t Wq;             // row pitch of the DP's key rows (DP threads x columns per thread)
+    int32_t Kp, KL;         // key rows: pitch, and all-ones columns left of column 0
+    int32_t dpnw;           // wavefronts the banded DP needs for this job
     int32_t B;              // rows per band of the backtrack
     int32_t nb;             // bands of B rows
     int32_t kcap;           // min(k, W): room for children / seams
@@ -55,8 +56,9 @@ struct Job {
     int32_t buffer_index;   // index of the buffer within its clip
     // workspace (device)
     int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
-    uint32_t *K0, *K1;      // DP input rows: 4 floor(SE / T), all ones at and beyond W_r,
-                            // (H + 1) x Wq (the extra row is all ones)
+    uint32_t *K0, *K1;      // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
+                            // all ones left of column 0 and at and beyond W_r; (H + 1) rows,
+                            // the extra row all ones
     uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
@@ -93,10 +95,20 @@ void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStr
 void launch_seg_window(const SegArgs &a, hipStream_t s);
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
-// columns per DP thread for the widest job, and the threads that covers
-int dp_columns_per_thread(int Wmax);
-int dp_threads(int W, int Q);
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, int Q, hipStream_t s);
+// DP geometry of a launch, chosen from its widest job: Q columns per
+// thread; banded kernels give each wavefront C = 64 Q - 2 HB owned columns
+// plus HB halo columns on each side and synchronise every HB rows.
+struct DpGeom {
+    int Q, HB, banded;
+    int C() const { return 64 * Q - 2 * HB; }
+    int waves(int W) const { return (W + C() - 1) / C(); }
+    // columns at or right of column 0 the DP may read for a job of width W
+    int cover(int W) const;
+    int threads(int Wmax) const;
+};
+DpGeom dp_geom(int Wmax);
+constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
+void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s);
 void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s);
 void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s);
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);

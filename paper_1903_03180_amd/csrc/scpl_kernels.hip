@@ -278,10 +278,10 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
     const Job &J = jobs[blockIdx.y];
     const int i = blockIdx.x;
     if (i > J.H) return;
-    if (i == J.H) {  // the all-ones row read by DP threads past the job's width
-        for (int j = threadIdx.x; j < J.Wq; j += 256) {
-            J.K0[(size_t)i * J.Wq + j] = kKeyInf;
-            J.K1[(size_t)i * J.Wq + j] = kKeyInf;
+    if (i == J.H) {  // the all-ones row read by DP lanes past the job's width
+        for (int j = threadIdx.x; j < J.Kp; j += 256) {
+            J.K0[(size_t)i * J.Kp + j] = kKeyInf;
+            J.K1[(size_t)i * J.Kp + j] = kKeyInf;
         }
         return;
     }
@@ -289,9 +289,10 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
         J.M0[(size_t)i * J.Wp + j] = (int16_t)j;
         J.bmask[(size_t)i * J.W + j] = 0;
     }
-    for (int j = J.W + threadIdx.x; j < J.Wq; j += 256) {
-        J.K0[(size_t)i * J.Wq + j] = kKeyInf;
-        J.K1[(size_t)i * J.Wq + j] = kKeyInf;
+    for (int x = threadIdx.x; x < J.Kp; x += 256) {
+        if (x >= J.KL && x < J.KL + J.W) continue;
+        J.K0[(size_t)i * J.Kp + x] = kKeyInf;
+        J.K1[(size_t)i * J.Kp + x] = kKeyInf;
     }
     if (i == 0 && threadIdx.x == 0) {
         J.log[0] = J.W;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
     st.oc2 = tofs(ip, jp, n);
     uint32_t acc = 0;
     for (int t = 0; t < J.T; ++t) acc += (uint32_t)energy_one(J, st, t);
-    J.K0[(size_t)i * J.Wq + j] = (acc / (uint32_t)J.T) << 2;
+    J.K0[(size_t)i * J.Kp + J.KL + j] = (acc / (uint32_t)J.T) << 2;
 }
 
 // ------------------------------------------------------------------- DP
@@ -440,6 +441,25 @@ struct DpPrefetch {
     static constexpr int PF = Q <= 4 ? 8 : (Q == 8 ? 4 : 2);
 };
 
+// One DP row step of a lane holding Q consecutive columns: lnb / rnb are the
+// previous row's keys just left / right of the lane; nxt the key row.
+template <int Q>
+__device__ __forceinline__ void dp_step(uint32_t (&key)[Q], uint32_t lnb, uint32_t rnb, const KRow<Q> &nxt,
+                                        uint32_t (&best)[Q])
+{
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        const uint32_t kl = c == 0 ? lnb : key[c - 1];
+        const uint32_t kc = sat_add(key[c], 1u);
+        const uint32_t kr = sat_add(c == Q - 1 ? rnb : key[c + 1], 2u);
+        best[c] = min(min(kl, kc), kr);
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) key[c] = sat_add(nxt.w[c], best[c] & ~3u);
+}
+
+// Row-synchronous DP for the widest frames: every row, the two
+// wavefront-edge keys cross through LDS and the block meets at a barrier.
 template <int Q>
 __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
 {
@@ -451,12 +471,12 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nwave = blockDim.x >> 6;
     const int j0 = tid * Q;
-    const int H = J.H, Wq = J.Wq, Wp = J.Wp;
-    const bool owns = j0 < Wq;
+    const int H = J.H, Kp = J.Kp, Wp = J.Wp;
+    const bool owns = J.KL + j0 + Q <= Kp;
     const uint32_t *K = (r & 1) ? J.K1 : J.K0;
-    // threads past the job's key pitch read the all-ones row at stride 0
-    const uint32_t *kp = owns ? K + j0 : K + (size_t)H * Wq;
-    const size_t kstride = owns ? (size_t)Wq : 0;
+    // lanes past the job's key rows read the all-ones row at stride 0
+    const uint32_t *kp = owns ? K + J.KL + j0 : K + (size_t)H * Kp;
+    const size_t kstride = owns ? (size_t)Kp : 0;
     uint8_t *__restrict__ dir = J.dir;
     const bool stores = j0 < Wp;
 
@@ -494,17 +514,8 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
                                                                      false);
                 if (lane == 0) lnb = wid > 0 ? eR[p][wid - 1] : kKeyInf;
                 if (lane == 63) rnb = wid < nwave - 1 ? eL[p][wid + 1] : kKeyInf;
-
                 uint32_t best[Q];
-#pragma unroll
-                for (int c = 0; c < Q; ++c) {
-                    const uint32_t kl = c == 0 ? lnb : key[c - 1];
-                    const uint32_t kc = sat_add(key[c], 1u);
-                    const uint32_t kr = sat_add(c == Q - 1 ? rnb : key[c + 1], 2u);
-                    best[c] = min(min(kl, kc), kr);
-                }
-#pragma unroll
-                for (int c = 0; c < Q; ++c) key[c] = sat_add(cur[s].w[c], best[c] & ~3u);
+                dp_step<Q>(key, lnb, rnb, cur[s], best);
                 if (stores) store_codes<Q>(dir + (size_t)i * Wp + j0, best);
                 const int q = i & 1;
                 if (lane == 0) eL[q][wid] = key[0];
@@ -519,6 +530,103 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
     for (int c = 0; c < Q; ++c) {
         const int j = j0 + c;
         if (j < Wr) J.ce_last[j] = (int)(key[c] >> 2);
+    }
+}
+
+// Banded DP.  Wavefront w owns the C = 64 Q - 2 HB columns [wC, wC + C) and
+// also computes HB columns on each side of them: its lanes cover columns
+// [wC - HB, wC + C + HB), neighbours within the wavefront come through DPP
+// wave shifts and the two outermost neighbours count as all ones.  Starting
+// from a row that is exact over the whole cover, the error from the
+// outermost neighbours advances one column per row, so after HB rows the
+// owned columns are still exact.  At the end of each band of HB rows the
+// owners publish their keys of the band's last row in LDS (ping-pong), the
+// block meets at one barrier, and the halo lanes take the neighbours' keys.
+// Only owned columns store indicator codes.
+template <int Q, int HB>
+__global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
+{
+    constexpr int PF = DpPrefetch<Q>::PF;
+    constexpr int C = 64 * Q - 2 * HB;
+    static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
+    extern __shared__ uint32_t rowbuf[];  // 2 x (Kp - KL) keys
+    const Job &J = jobs[blockIdx.x];
+    const int Wr = job_width(J, r);
+    if (Wr <= J.Wt) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int H = J.H, Kp = J.Kp, Wp = J.Wp;
+    const int rb = Kp - J.KL;  // keys per row buffer
+    const int jl = wid * C - HB + lane * Q;  // first column of this lane
+    const bool live = wid < J.dpnw;
+    const bool owner = live && lane * Q >= HB && lane * Q < HB + C;
+    const bool stores = owner && jl < Wp;
+    const uint32_t *K = (r & 1) ? J.K1 : J.K0;
+    const uint32_t *kp = live ? K + J.KL + jl : K + (size_t)H * Kp;
+    const size_t kstride = live ? (size_t)Kp : 0;
+    uint8_t *__restrict__ dir = J.dir;
+
+    uint32_t key[Q];
+    {
+        KRow<Q> k0;
+        load_krow<Q>(k0, kp);
+        uint32_t code[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            key[c] = k0.w[c];
+            code[c] = 1;
+        }
+        if (stores) store_codes<Q>(dir + jl, code);
+    }
+    KRow<Q> cur[PF], nxt[PF];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) load_krow<Q>(cur[s], kp + (size_t)min(1 + s, H - 1) * kstride);
+
+    int band_left = HB;  // rows left in the current band
+    int buf = 0;
+    for (int i0 = 1; i0 < H; i0 += PF) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) load_krow<Q>(nxt[s], kp + (size_t)min(i0 + PF + s, H - 1) * kstride);
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            const int i = i0 + s;
+            if (i < H) {
+                if (band_left == 0) {
+                    // publish the band's last row, meet, refresh the halo
+                    uint32_t *rowp = rowbuf + (size_t)buf * rb;
+                    if (owner) {
+#pragma unroll
+                        for (int c = 0; c < Q; ++c) rowp[jl + c] = key[c];
+                    }
+                    __syncthreads();
+                    if (live && !owner) {
+#pragma unroll
+                        for (int c = 0; c < Q; ++c) {
+                            const int j = jl + c;
+                            key[c] = (j >= 0 && j < Wr) ? rowp[j] : kKeyInf;
+                        }
+                    }
+                    buf ^= 1;
+                    band_left = HB;
+                }
+                const uint32_t lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[Q - 1], 0x138, 0xf,
+                                                                           0xf, false);
+                const uint32_t rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[0], 0x130, 0xf,
+                                                                           0xf, false);
+                uint32_t best[Q];
+                dp_step<Q>(key, lnb, rnb, cur[s], best);
+                if (stores) store_codes<Q>(dir + (size_t)i * Wp + jl, best);
+                --band_left;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < PF; ++s) cur[s] = nxt[s];
+    }
+    if (owner) {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const int j = jl + c;
+            if (j >= 0 && j < Wr) J.ce_last[j] = (int)(key[c] >> 2);
+        }
     }
 }
 
@@ -802,11 +910,11 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
     if (i >= J.H) return;
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
-    const int H = J.H, Wp = J.Wp, Wq = J.Wq;
+    const int H = J.H, Wp = J.Wp;
     const int16_t *__restrict__ Mo = (r & 1) ? J.M1 : J.M0;
     int16_t *__restrict__ Mw = (r & 1) ? J.M0 : J.M1;
-    const uint32_t *__restrict__ Ko = (r & 1) ? J.K1 : J.K0;
-    uint32_t *__restrict__ Kn = (r & 1) ? J.K0 : J.K1;
+    const uint32_t *__restrict__ Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
+    uint32_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
     const bool rl = kk <= 256;
     const bool keys = Wn > J.Wt;  // a further iteration reads the keys
     const int tid = threadIdx.x;
@@ -819,13 +927,13 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
     for (int j = tid; j < Wn; j += 256) {
         const int src = source_column(j, kk, rl ? R : nullptr, J.seams + i, H);
         Mw[(size_t)i * Wp + j] = Mo[(size_t)i * Wp + src];
-        if (keys) Kn[(size_t)i * Wq + j] = Ko[(size_t)i * Wq + src];
+        if (keys) Kn[j] = Ko[src];
     }
     if (!keys) return;
     // the keys of the vacated columns become all ones; columns beyond the
     // previous width of this buffer already are
     const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
-    for (int j = Wn + tid; j < wprev; j += 256) Kn[(size_t)i * Wq + j] = kKeyInf;
+    for (int j = Wn + tid; j < wprev; j += 256) Kn[j] = kKeyInf;
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -863,12 +971,13 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
     if (Wn <= J.Wt) return;
-    const int H = J.H, Wp = J.Wp, Wq = J.Wq, W = J.W, T = J.T, ntc = J.ntc;
+    const int H = J.H, Wp = J.Wp, W = J.W, T = J.T, ntc = J.ntc;
+    const int Kp = J.Kp;
     const int i0 = blockIdx.x * kRefreshRows;
     if (i0 >= H) return;
     const int nrows = min(kRefreshRows, H - i0);
     const int16_t *__restrict__ Mn = (r & 1) ? J.M0 : J.M1;
-    uint32_t *__restrict__ Kn = (r & 1) ? J.K0 : J.K1;
+    uint32_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + J.KL;
     const int tid = threadIdx.x;
     const bool rl = kk <= kRefreshSeams;
     if (tid == 0) nf = 0;
@@ -937,7 +1046,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
                 const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
                 const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
                                                      Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W, ntc);
-                Kn[(size_t)i * Wq + c] = (full_sum(st) / (uint32_t)T) << 2;
+                Kn[(size_t)i * Kp + c] = (full_sum(st) / (uint32_t)T) << 2;
             }
         }
     }
@@ -970,7 +1079,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
     __syncthreads();
     for (int p = tid; p < n; p += 256) {
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
-        Kn[(size_t)i * Wq + c] = (fsum[p] / (uint32_t)T) << 2;
+        Kn[(size_t)i * Kp + c] = (fsum[p] / (uint32_t)T) << 2;
     }
 }
 
@@ -1090,32 +1199,44 @@ void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t
                        d_jobs);
 }
 
-int dp_columns_per_thread(int Wmax)
+int DpGeom::cover(int W) const
 {
-    if (Wmax <= 512) return 1;
-    if (Wmax <= 2048) return 4;
-    if (Wmax <= 4096) return 4;
-    if (Wmax <= 8192) return 8;
-    if (Wmax <= 16384) return 16;
-    return 32;
+    if (banded) return waves(W) * C() + HB;
+    const int t = (W + Q - 1) / Q;
+    return ((t + 63) / 64) * 64 * Q;
 }
 
-int dp_threads(int W, int Q)
+int DpGeom::threads(int Wmax) const
 {
-    const int t = (W + Q - 1) / Q;
+    if (banded) return 64 * waves(Wmax);
+    const int t = (Wmax + Q - 1) / Q;
     return ((t + 63) / 64) * 64;
 }
 
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, int Q, hipStream_t s)
+DpGeom dp_geom(int Wmax)
 {
-    const dim3 g(njobs), b(dp_threads(Wmax, Q));
-    switch (Q) {
-    case 1: hipLaunchKernelGGL(dp_kernel<1>, g, b, 0, s, d_jobs, r); break;
-    case 2: hipLaunchKernelGGL(dp_kernel<2>, g, b, 0, s, d_jobs, r); break;
-    case 4: hipLaunchKernelGGL(dp_kernel<4>, g, b, 0, s, d_jobs, r); break;
-    case 8: hipLaunchKernelGGL(dp_kernel<8>, g, b, 0, s, d_jobs, r); break;
-    case 16: hipLaunchKernelGGL(dp_kernel<16>, g, b, 0, s, d_jobs, r); break;
-    default: hipLaunchKernelGGL(dp_kernel<32>, g, b, 0, s, d_jobs, r); break;
+    if (Wmax <= 512) return DpGeom{2, 8, 1};
+    if (Wmax <= 2240) return DpGeom{4, 16, 1};
+    if (Wmax <= 4480) return DpGeom{8, 32, 1};
+    if (Wmax <= 8960) return DpGeom{16, 64, 1};
+    return DpGeom{32, 0, 0};
+}
+
+void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s)
+{
+    const DpGeom g = dp_geom(Wmax);
+    const dim3 grid(njobs), block(g.threads(Wmax));
+    // two ping-pong rows of keys: the widest job's key row less its left pad
+    const size_t lds = (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t);
+    if (!g.banded) {
+        hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);
+        return;
+    }
+    switch (g.Q) {
+    case 2: hipLaunchKernelGGL((dp_band_kernel<2, 8>), grid, block, lds, s, d_jobs, r); break;
+    case 4: hipLaunchKernelGGL((dp_band_kernel<4, 16>), grid, block, lds, s, d_jobs, r); break;
+    case 8: hipLaunchKernelGGL((dp_band_kernel<8, 32>), grid, block, lds, s, d_jobs, r); break;
+    default: hipLaunchKernelGGL((dp_band_kernel<16, 64>), grid, block, lds, s, d_jobs, r); break;
     }
 }
 

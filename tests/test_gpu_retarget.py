@@ -77,7 +77,8 @@ def test_modes(ctx, orc, kw):
 
 
 @pytest.mark.parametrize("shape,Wt,k", [((1, 1, 1), 1, 1), ((3, 1, 9), 4, 2), ((2, 9, 1), 1, 3), ((4, 5, 6), 6, 2),
-                                        ((2, 1, 3000), 1000, 700), ((3, 5, 3000), 1200, 1500)])
+                                        ((2, 1, 3000), 1000, 700), ((3, 5, 3000), 1200, 1500),
+                                        ((2, 7, 9100), 9000, 40)])
 def test_degenerate(ctx, orc, shape, Wt, k):
     rng = np.random.default_rng(sum(shape))
     clip = rng.integers(0, 256, size=shape).astype(np.uint8)

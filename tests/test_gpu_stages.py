@@ -48,8 +48,11 @@ def test_energy(ctx, orc, shape, mode):
         assert np.array_equal(got, orc.energy(y, None, mode))
 
 
+# widths span every DP geometry: banded with 2, 4, 8 and 16 columns per
+# lane (several wavefronts, bands of 8 to 64 rows, ragged last band) and the
+# row-synchronous kernel beyond 8960 columns
 DP_SHAPES = [(1, 1), (1, 7), (7, 1), (3, 2), (37, 1100), (70, 2500), (130, 65), (5, 5000), (200, 1920),
-             (65, 129), (64, 64), (129, 3)]
+             (65, 129), (64, 64), (129, 3), (33, 513), (17, 2240), (45, 4480), (70, 8960), (4, 9500), (3, 20000)]
 
 
 @pytest.mark.parametrize("shape", DP_SHAPES)
