@@ -74,6 +74,9 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device tensor copy of this many MiB (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -98,6 +101,8 @@ def main() -> int:
                           out=torch.empty((c.shape[0], H, Wt) + c.shape[3:], dtype=torch.uint8, device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
+    dpq, dphb, dpus = ctx.autotune_dp(H, W)
+    log(f"DP autotune for {H}x{W}: {dpq} columns per lane, halo {dphb}: {dpus:.1f} us per launch")
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -154,6 +159,16 @@ def main() -> int:
         plain_fps = n_frames * args.plain_steps / (p1 - p0)
         log(f"plain: {(p1 - p0) * 1e3 / args.plain_steps:.2f} ms/step, {plain_fps:.1f} frames/s")
 
+    if args.copy_calibration > 0:
+        a = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calibration} MiB read and written")
+        del a, b
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -182,7 +197,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
                    "clips": len(clips), "frames": n_frames, "height": H, "width": W, "target_width": Wt,
-                   "seams_per_iter": k, "buffers": nbuf, "buffer_iterations": int(len(log_rows))},
+                   "seams_per_iter": k, "buffers": nbuf, "buffer_iterations": int(len(log_rows)),
+                   "dp_geometry": {"cols_per_lane": dpq, "halo_rows": dphb}},
         "value_graph_no_events": round(fps_graph, 2),
         "plain_fps": None if plain_fps is None else round(plain_fps, 2),
         "batched_over_plain": None if plain_fps is None else round(fps / plain_fps, 3),

@@ -158,6 +158,21 @@ enum {
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);
 scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms, int64_t *h_launches);
 
+/* ---- DP geometry and its autotuner (performance only: every geometry
+ * gives bit-identical results) ----
+ * The cumulative-energy DP of eq. (4) runs one workgroup per buffer; each
+ * wavefront owns a run of columns, computes HB halo columns on each side with
+ * Q columns per lane, and meets the others every HB rows.
+ * scpl_dp_geometry forces (Q, HB) for every later launch it fits
+ * (Q = 0: automatic).  Valid pairs: (2,8) (4,8) (4,16) (8,16) (8,32)
+ * (16,32) (16,64), and (32,0) for the row-synchronous kernel.
+ * scpl_autotune_dp times every geometry that fits width W on an H x W
+ * synthetic energy (null stream, synchronises) and keeps the fastest for
+ * launches whose widest job has width W; h_Q, h_HB, h_us (nullable) receive
+ * the choice and its time per launch in microseconds. */
+scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB);
+scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, int32_t *h_HB, double *h_us);
+
 /* ---- stage entry points (parity checks of single stages) ---- */
 
 /* Luma of npx interleaved RGB pixels (reading of the colour step). */

@@ -20,6 +20,8 @@ struct ProfPair {
 };
 
 struct scpl_ctx {
+    DpGeom forced{0, 0, 0};                       // DP geometry forced by the caller (Q = 0: none)
+    std::vector<std::pair<int, DpGeom>> tuned;    // autotuned geometry per widest-job width
     bool profiling = false;
     std::vector<ProfPair> prof_pending;  // recorded, not yet read
     std::vector<ProfPair> prof_free;     // reusable event pairs
@@ -124,9 +126,9 @@ size_t g_lds_cap = 65536;  // set from the device at context creation
 
 struct JobShape {
     int32_t H, W, Wt, k;
-    int32_t Wg = 0;  // width that picks the DP geometry of the launch (0: the job's own)
+    DpGeom g;  // DP geometry of the launch the job runs in
     int32_t Wp() const { return (int32_t)align_up((size_t)W, 64); }
-    DpGeom geom() const { return dp_geom(Wg > 0 ? Wg : W); }
+    const DpGeom &geom() const { return g; }
     int32_t Kp() const { return kKeyLeft + (int32_t)align_up((size_t)geom().cover(W), 64); }
     int32_t B() const { return band_rows(H, W, g_lds_cap); }
     int32_t nb() const { return (H + B() - 1) / B(); }
@@ -213,6 +215,16 @@ scpl_status ensure_pinned(scpl_ctx *ctx, size_t bytes)
     SCPL_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
     ctx->pinned_size = want;
     return SCPL_OK;
+}
+
+// DP geometry of a launch whose widest job is Wmax: forced, autotuned, or
+// the default table.
+DpGeom select_geom(const scpl_ctx *ctx, int Wmax)
+{
+    if (ctx->forced.Q > 0 && dp_geom_fits(ctx->forced, Wmax)) return ctx->forced;
+    for (const auto &t : ctx->tuned)
+        if (t.first == Wmax) return t.second;
+    return dp_geom(Wmax);
 }
 
 // ----------------------------------------------------------- kernel timing
@@ -391,6 +403,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
 
 struct LaunchShape {
     int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0;
+    DpGeom g{0, 0, 0};
     void add(const JobShape &s)
     {
         Hmax = std::max(Hmax, s.H);
@@ -398,6 +411,7 @@ struct LaunchShape {
         nbmax = std::max(nbmax, s.nb());
         kmax = std::max(kmax, s.kcap());
         Bmax = std::max(Bmax, s.B());
+        g = s.g;
     }
 };
 
@@ -405,7 +419,7 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const La
 {
     {
         ProfScope ps(ctx, SCPL_KERNEL_DP, s);
-        launch_dp(d_jobs, nj, r, ls.Wmax, s);
+        launch_dp(d_jobs, nj, r, ls.g, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
@@ -623,7 +637,7 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
     if (st != SCPL_OK) return st;
     if (!device_bytes) return SCPL_ERR_INVALID_ARG;
     const int64_t HW = (int64_t)p->height * p->width;
-    JobShape js{p->height, p->width, p->target_width, p->seams_per_iter};
+    JobShape js{p->height, p->width, p->target_width, p->seams_per_iter, dp_geom(p->width)};
     size_t b = align_up((size_t)p->n_frames * tiled_frame_bytes(p->height, p->width));
     b += seg_bytes(HW) + align_up(kSegWindow * 8);
     b += job_bytes(js) + align_up(sizeof(Job) * (size_t)p->n_frames) + align_up(16 * (size_t)p->n_frames);
@@ -697,10 +711,10 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
     // a batched DP launch serves every job: its geometry follows the widest
+    const DpGeom gall = select_geom(ctx, Wall);
     auto shape_of = [&](const Pending &q) {
         const scpl_params &p = clips[q.clip].p;
-        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter};
-        if (batched) js.Wg = Wall;
+        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, batched ? gall : select_geom(ctx, p.width)};
         return js;
     };
     // area B: job workspaces (all jobs when batched; one shared per clip shape
@@ -740,7 +754,7 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
     }
     for (int q = 0; q < nj; ++q) {
         LaunchShape one;
-        one.add(JobShape{jobs[q].H, jobs[q].W, jobs[q].Wt, jobs[q].k});
+        one.add(shape_of(pend[q]));
         st = run_jobs(ctx, d_jobs + q, h_jobs + q, d_states + 4 * q, h_states + 4 * q, 1, one,
                       first_batch_iterations(&clips[pend[q].clip].p), false, s);
         if (st != SCPL_OK) return st;
@@ -822,7 +836,7 @@ scpl_status scpl_luma(scpl_ctx *ctx, const uint8_t *d_rgb, int64_t npx, uint8_t 
 static scpl_status stage_job(scpl_ctx *ctx, int32_t H, int32_t W, int32_t Wt, int32_t k, size_t extra, Job &J,
                              Job *&d_job, int32_t *&d_state, char *&d_extra, hipStream_t s)
 {
-    JobShape js{H, W, Wt, k};
+    JobShape js{H, W, Wt, k, select_geom(ctx, W)};
     const size_t total = job_bytes(js) + align_up(sizeof(Job)) + align_up(16) + align_up(extra);
     SCPL_TRY(ensure_ws(ctx, total));
     SCPL_TRY(ensure_pinned(ctx, align_up(sizeof(Job)) + 64));
@@ -874,7 +888,7 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
     *h = J;
     SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job), hipMemcpyHostToDevice, s));
     LaunchShape ls;
-    ls.add(JobShape{H, W, 1, 1});
+    ls.add(JobShape{H, W, 1, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, ls.Hmax, ls.Wmax, s);
     launch_energy(d_job, 1, H, W, s);
     launch_keys_to_u(J.K0 + J.KL, d_e, H, W, J.Kp, s);
@@ -898,10 +912,10 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     scpl_status st = stage_job(ctx, H, W, 0, 1, 0, J, d_job, d_state, unused, s);
     if (st != SCPL_OK) return st;
     LaunchShape ls;
-    ls.add(JobShape{H, W, 0, 1});
+    ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, H, W, s);
     launch_u_to_keys(d_u, J.K0 + J.KL, H, W, J.Kp, s);
-    launch_dp(d_job, 1, 0, W, s);
+    launch_dp(d_job, 1, 0, ls.g, W, s);
     launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);
     launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);
@@ -967,13 +981,99 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     std::memcpy(h, rec, 16);
     SCPL_TRY(hipMemcpyAsync(J.log, h, 16, hipMemcpyHostToDevice, s));
     LaunchShape ls;
-    ls.add(JobShape{H, W, 0, kk});
+    ls.add(JobShape{H, W, 0, kk, select_geom(ctx, W)});
     launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
     launch_jump_only(d_job, 1, 0, s);
     launch_fill(d_job, 1, 0, kk, ls.nbmax, ls.Bmax, s);
     launch_i16_to_i32(J.seams, d_seams, (int64_t)kk * H, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));
+    return SCPL_OK;
+}
+
+scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB)
+{
+    if (!ctx) return SCPL_ERR_INVALID_ARG;
+    if (Q == 0) {
+        ctx->forced = DpGeom{0, 0, 0};
+        return SCPL_OK;
+    }
+    for (int v = 0; v < kNumDpVariants; ++v)
+        if (kDpVariants[v].Q == Q && kDpVariants[v].HB == HB) {
+            ctx->forced = kDpVariants[v];
+            return SCPL_OK;
+        }
+    if (Q == 32 && HB == 0) {
+        ctx->forced = DpGeom{32, 0, 0};
+        return SCPL_OK;
+    }
+    return SCPL_ERR_INVALID_ARG;
+}
+
+scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, int32_t *h_HB, double *h_us)
+{
+    if (!ctx || H < 2 || W < 1 || H > SCPL_MAX_HEIGHT || W > SCPL_MAX_WIDTH || (int64_t)H * W > SCPL_MAX_PIXELS)
+        return SCPL_ERR_INVALID_ARG;
+    SCPL_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = nullptr;
+    std::vector<DpGeom> cand;
+    for (int v = 0; v < kNumDpVariants; ++v)
+        if (dp_geom_fits(kDpVariants[v], W)) cand.push_back(kDpVariants[v]);
+    if (cand.empty()) cand.push_back(dp_geom(W));
+    hipEvent_t e0, e1;
+    SCPL_TRY(hipEventCreate(&e0));
+    SCPL_TRY(hipEventCreate(&e1));
+    DpGeom best = cand[0];
+    double best_us = 1e30;
+    scpl_status st = SCPL_OK;
+    for (const DpGeom &g : cand) {
+        JobShape js{H, W, 0, 1, g};
+        const size_t total = job_bytes(js) + align_up(sizeof(Job)) + align_up(16);
+        st = ensure_ws(ctx, total);
+        if (st != SCPL_OK) break;
+        st = ensure_pinned(ctx, align_up(sizeof(Job)));
+        if (st != SCPL_OK) break;
+        Bump dev{static_cast<char *>(ctx->ws)};
+        char *job_ws = dev.take<char>(job_bytes(js));
+        Job *d_job = dev.take<Job>(1);
+        int32_t *d_state = dev.take<int32_t>(4);
+        Job J{};
+        Bump jb{job_ws};
+        carve_job(J, js, jb, d_state);
+        Job *h = static_cast<Job *>(ctx->pinned);
+        *h = J;
+        SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job), hipMemcpyHostToDevice, s));
+        launch_init_jobs(d_job, 1, H, W, s);
+        launch_tune_fill(J.K0, H, W, J.Kp, J.KL, s);
+        launch_dp(d_job, 1, 0, g, W, s);  // warm-up
+        const int reps = 5;
+        SCPL_TRY(hipEventRecord(e0, s));
+        for (int q = 0; q < reps; ++q) launch_dp(d_job, 1, 0, g, W, s);
+        SCPL_TRY(hipEventRecord(e1, s));
+        SCPL_TRY(hipEventSynchronize(e1));
+        SCPL_CHECK_LAUNCH();
+        float ms = 0.f;
+        SCPL_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (us < best_us) {
+            best_us = us;
+            best = g;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SCPL_OK) return st;
+    for (auto &t : ctx->tuned)
+        if (t.first == W) {
+            t.second = best;
+            best = DpGeom{-1, 0, 0};
+            break;
+        }
+    if (best.Q != -1) ctx->tuned.emplace_back(W, best);
+    const DpGeom chosen = select_geom(ctx, W);
+    if (h_Q) *h_Q = chosen.Q;
+    if (h_HB) *h_HB = chosen.HB;
+    if (h_us) *h_us = best_us;
     return SCPL_OK;
 }
 

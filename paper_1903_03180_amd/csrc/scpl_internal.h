@@ -106,9 +106,13 @@ struct DpGeom {
     int cover(int W) const;
     int threads(int Wmax) const;
 };
-DpGeom dp_geom(int Wmax);
+DpGeom dp_geom(int Wmax);  // default for the widest job of a launch
+bool dp_geom_fits(const DpGeom &g, int Wmax);
+extern const DpGeom kDpVariants[];
+extern const int kNumDpVariants;
 constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s);
+void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s);
+void launch_tune_fill(uint32_t *K, int H, int W, int Kp, int KL, hipStream_t s);
 void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s);
 void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s);
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);

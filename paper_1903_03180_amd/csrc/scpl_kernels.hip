@@ -1213,18 +1213,30 @@ int DpGeom::threads(int Wmax) const
     return ((t + 63) / 64) * 64;
 }
 
+// Banded variants (Q columns per lane, HB halo columns = rows per band).
+const DpGeom kDpVariants[] = {{2, 8, 1}, {4, 8, 1}, {4, 16, 1}, {8, 16, 1}, {8, 32, 1}, {16, 32, 1}, {16, 64, 1}};
+const int kNumDpVariants = (int)(sizeof(kDpVariants) / sizeof(kDpVariants[0]));
+
+bool dp_geom_fits(const DpGeom &g, int Wmax)
+{
+    if (!g.banded) return true;
+    return g.C() > 0 && g.threads(Wmax) <= 1024 && (size_t)2 * (g.cover(Wmax) + 64) * 4 <= 65536;
+}
+
 DpGeom dp_geom(int Wmax)
 {
-    if (Wmax <= 512) return DpGeom{2, 8, 1};
-    if (Wmax <= 2240) return DpGeom{4, 16, 1};
-    if (Wmax <= 4480) return DpGeom{8, 32, 1};
+    // defaults: the fewest wavefronts that cover the width with balanced
+    // SIMDs; the autotuner may replace them
+    if (Wmax <= 448) return DpGeom{2, 8, 1};
+    if (Wmax <= 1920) return DpGeom{4, 8, 1};
+    if (Wmax <= 3840) return DpGeom{8, 16, 1};
+    if (Wmax <= 7680) return DpGeom{16, 32, 1};
     if (Wmax <= 8960) return DpGeom{16, 64, 1};
     return DpGeom{32, 0, 0};
 }
 
-void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s)
+void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s)
 {
-    const DpGeom g = dp_geom(Wmax);
     const dim3 grid(njobs), block(g.threads(Wmax));
     // two ping-pong rows of keys: the widest job's key row less its left pad
     const size_t lds = (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t);
@@ -1232,12 +1244,39 @@ void launch_dp(const Job *d_jobs, int njobs, int r, int Wmax, hipStream_t s)
         hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);
         return;
     }
-    switch (g.Q) {
-    case 2: hipLaunchKernelGGL((dp_band_kernel<2, 8>), grid, block, lds, s, d_jobs, r); break;
-    case 4: hipLaunchKernelGGL((dp_band_kernel<4, 16>), grid, block, lds, s, d_jobs, r); break;
-    case 8: hipLaunchKernelGGL((dp_band_kernel<8, 32>), grid, block, lds, s, d_jobs, r); break;
-    default: hipLaunchKernelGGL((dp_band_kernel<16, 64>), grid, block, lds, s, d_jobs, r); break;
+#define SCPL_DP_CASE(q, hb)                                                                 \
+    if (g.Q == q && g.HB == hb) {                                                           \
+        hipLaunchKernelGGL((dp_band_kernel<q, hb>), grid, block, lds, s, d_jobs, r);        \
+        return;                                                                             \
     }
+    SCPL_DP_CASE(2, 8)
+    SCPL_DP_CASE(4, 8)
+    SCPL_DP_CASE(4, 16)
+    SCPL_DP_CASE(8, 16)
+    SCPL_DP_CASE(8, 32)
+    SCPL_DP_CASE(16, 32)
+    SCPL_DP_CASE(16, 64)
+#undef SCPL_DP_CASE
+    hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);  // unreachable for valid geometries
+}
+
+// Deterministic pseudo-random key rows for the autotuner (xorshift of the
+// position; values 0..7650).
+__global__ void tune_fill_kernel(uint32_t *K, int H, int W, int Kp, int KL)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)H * W) return;
+    const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
+    uint32_t x = (uint32_t)p * 2654435761u + 12345u;
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    K[(size_t)i * Kp + KL + j] = (x % 7651u) << 2;
+}
+
+void launch_tune_fill(uint32_t *K, int H, int W, int Kp, int KL, hipStream_t s)
+{
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, K, H, W, Kp, KL);
 }
 
 void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s)

@@ -35,8 +35,11 @@ SCPL_ENERGY_MOTION = 1
 EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
-    "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read",
+    "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_dp_geometry",
+    "scpl_autotune_dp",
 ]
+
+DP_GEOMETRIES = [(2, 8), (4, 8), (4, 16), (8, 16), (8, 32), (16, 32), (16, 64), (32, 0)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
@@ -69,6 +72,8 @@ _sig = {
     "scpl_segment": ([_P, C.POINTER(scpl_params), _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_profile_enable": ([_P, _I32], C.c_int),
     "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
+    "scpl_dp_geometry": ([_P, _I32, _I32], C.c_int),
+    "scpl_autotune_dp": ([_P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(C.c_double)], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -216,6 +221,18 @@ class Context:
             _check(scpl_profile_read(self.h, i, C.byref(ms), C.byref(n)), "scpl_profile_read")
             out[name] = (ms.value, n.value)
         return out
+
+    # ---------------------------------------------------------- DP geometry
+    def dp_geometry(self, Q: int = 0, HB: int = 0) -> None:
+        """Force the DP geometry (Q columns per lane, HB halo); Q = 0: automatic."""
+        _check(scpl_dp_geometry(self.h, Q, HB), "scpl_dp_geometry")
+
+    def autotune_dp(self, H: int, W: int):
+        """Time every DP geometry for an H x W frame; keep the fastest.
+        Returns (Q, HB, microseconds per launch)."""
+        q, hb, us = C.c_int32(0), C.c_int32(0), C.c_double(0)
+        _check(scpl_autotune_dp(self.h, H, W, C.byref(q), C.byref(hb), C.byref(us)), "scpl_autotune_dp")
+        return int(q.value), int(hb.value), float(us.value)
 
     # ---------------------------------------------------------- stages
     def luma(self, rgb, stream=None):

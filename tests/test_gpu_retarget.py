@@ -187,3 +187,13 @@ def test_4k_clip_full_size(ctx, orc, alpha):
     res = ctx.retarget(dev(frames), 2880, 32, alpha_num=alpha[0], alpha_den=alpha[1])
     torch.cuda.synchronize()
     check_full_size(orc, frames, res, 2880, 32, 1, alpha[0], alpha[1], n_first=1)
+
+
+@pytest.mark.parametrize("geom", [(4, 16), (8, 16), (8, 32), (32, 0)])
+def test_forced_geometry_retarget(ctx, orc, geom):
+    clip = synth.make_clip(610, 8, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
+    ctx.dp_geometry(*geom)
+    try:
+        compare(ctx, orc, clip, 220, 6)
+    finally:
+        ctx.dp_geometry(0)

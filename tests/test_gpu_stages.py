@@ -115,3 +115,35 @@ def test_segment_max_buffer_and_off(ctx, orc):
         assert np.array_equal(bid, obid) and np.array_equal(tr, otr)
     bid, _ = ctx.segment(dev(Y), use_buffer=0)
     assert bid.tolist() == list(range(40))
+
+
+GEOMETRIES = [(2, 8), (4, 8), (4, 16), (8, 16), (8, 32), (16, 32), (16, 64), (32, 0)]
+
+
+@pytest.mark.parametrize("geom", GEOMETRIES)
+def test_dp_every_geometry(ctx, orc, geom):
+    """Every DP geometry (columns per lane, halo / band rows) gives the
+    oracle's result; widths a geometry cannot hold fall back to the default
+    and must agree too."""
+    ctx.dp_geometry(*geom)
+    try:
+        for shape in [(3, 1), (40, 333), (130, 1000), (77, 1920), (20, 3100), (9, 6000)]:
+            rng = np.random.default_rng(shape[1] + geom[0])
+            u = rng.integers(0, 40, size=shape).astype(np.int32)
+            ce, lab, d = ctx.dp(dev(u))
+            oce, olab, od = orc.dp(u)
+            assert np.array_equal(host(ce), oce[-1]), shape
+            assert np.array_equal(host(lab), olab[-1]), shape
+            assert np.array_equal(host(d), od), shape
+    finally:
+        ctx.dp_geometry(0)
+
+
+def test_autotune_then_parity(ctx, orc):
+    q, hb, us = ctx.autotune_dp(256, 1920)
+    assert (q, hb) in GEOMETRIES and us > 0
+    rng = np.random.default_rng(3)
+    u = rng.integers(0, 7651, size=(90, 1920)).astype(np.int32)
+    ce, lab, d = ctx.dp(dev(u))
+    oce, olab, od = orc.dp(u)
+    assert np.array_equal(host(ce), oce[-1]) and np.array_equal(host(d), od)
