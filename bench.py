@@ -72,6 +72,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k"])
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--streams", type=int, default=2, help="job groups (streams) of the batched path")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -94,6 +95,7 @@ def main() -> int:
     log(f"workload {wname}; generated {sum(c.nbytes for c in clips_np) / 1e9:.2f} GB in "
         f"{time.perf_counter() - t_gen:.1f} s")
     ctx = scpl.Context(0)
+    ctx.batch_streams(args.streams)
     clips = []
     for c in clips_np:
         fr = torch.from_numpy(c).cuda()
@@ -101,8 +103,9 @@ def main() -> int:
                           out=torch.empty((c.shape[0], H, Wt) + c.shape[3:], dtype=torch.uint8, device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
-    dpq, dphb, dpus = ctx.autotune_dp(H, W)
-    log(f"DP autotune for {H}x{W}: {dpq} columns per lane, halo {dphb}: {dpus:.1f} us per launch")
+    dpq, dphb, dppf, dpex, dpus = ctx.autotune_dp(H, W, n_jobs=3 * len(clips))
+    log(f"DP autotune for {len(clips) * 3} jobs of {H}x{W}: {dpq} columns per lane, halo {dphb}, prefetch {dppf}, "
+        f"exclusive {dpex}: {dpus:.1f} us per launch")
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -198,7 +201,8 @@ def main() -> int:
         "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
                    "clips": len(clips), "frames": n_frames, "height": H, "width": W, "target_width": Wt,
                    "seams_per_iter": k, "buffers": nbuf, "buffer_iterations": int(len(log_rows)),
-                   "dp_geometry": {"cols_per_lane": dpq, "halo_rows": dphb}},
+                   "dp_geometry": {"cols_per_lane": dpq, "halo_rows": dphb, "prefetch_rows": dppf,
+                                                        "exclusive_cu": dpex}, "streams": args.streams},
         "value_graph_no_events": round(fps_graph, 2),
         "plain_fps": None if plain_fps is None else round(plain_fps, 2),
         "batched_over_plain": None if plain_fps is None else round(fps / plain_fps, 3),

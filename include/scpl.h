@@ -129,6 +129,15 @@ typedef struct {
 
 scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, void *stream);
 
+/* Number of job groups of scpl_retarget_batch (default 2, at most
+ * SCPL_MAX_STREAMS).  The jobs are dealt to the groups in order of
+ * decreasing buffer length; each group advances in lock-step on a stream of
+ * its own (default priority) that starts after the work already on the
+ * caller's stream and that the caller's stream waits for.  Performance
+ * only: results are identical for every count. */
+#define SCPL_MAX_STREAMS 8
+scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
+
 /* Per-iteration record of the last scpl_retarget / scpl_retarget_batch call:
  * for every buffer in order, for every iteration, four int32
  * (buffer index within its clip, W_r, P_eff, k_iter); clips in order.
@@ -162,16 +171,23 @@ scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms,
  * gives bit-identical results) ----
  * The cumulative-energy DP of eq. (4) runs one workgroup per buffer; each
  * wavefront owns a run of columns, computes HB halo columns on each side with
- * Q columns per lane, and meets the others every HB rows.
- * scpl_dp_geometry forces (Q, HB) for every later launch it fits
- * (Q = 0: automatic).  Valid pairs: (2,8) (4,8) (4,16) (8,16) (8,32)
- * (16,32) (16,64), and (32,0) for the row-synchronous kernel.
- * scpl_autotune_dp times every geometry that fits width W on an H x W
- * synthetic energy (null stream, synchronises) and keeps the fastest for
- * launches whose widest job has width W; h_Q, h_HB, h_us (nullable) receive
- * the choice and its time per launch in microseconds. */
-scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB);
-scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, int32_t *h_HB, double *h_us);
+ * Q columns per lane, meets the others every HB rows, and requests its
+ * energy rows PF rows ahead.  EX = 1 makes each DP workgroup reserve the
+ * whole LDS of its compute unit, so that no other workgroup (another
+ * buffer's DP, or a concurrent stream's work) shares the unit.
+ * scpl_dp_geometry forces (Q, HB, PF, EX) for every later launch it fits
+ * (Q = 0: automatic; PF = 0: the default depth of (Q, HB)).  Valid (Q, HB,
+ * PF): (2,8,8) (2,8,16) (4,8,8) (4,8,16) (4,16,8) (4,16,16) (8,16,4)
+ * (8,16,8) (8,32,4) (16,32,2) (16,64,2), and (32,0,2) for the
+ * row-synchronous kernel; EX is 0 or 1.
+ * scpl_autotune_dp times every geometry that fits width W with n_jobs
+ * concurrent H x W synthetic energies per launch (as in a batched launch;
+ * null stream, synchronises) and keeps the fastest for launches whose widest
+ * job has width W; h_Q, h_HB, h_PF, h_EX, h_us (nullable) receive the choice
+ * and its time per launch in microseconds. */
+scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, int32_t EX);
+scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
+                             int32_t *h_PF, int32_t *h_EX, double *h_us);
 
 /* ---- stage entry points (parity checks of single stages) ---- */
 
@@ -184,8 +200,9 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
                         const uint8_t *d_yprev, int32_t *d_e, void *stream);
 
 /* Cumulative energy, eq. (4), with parent labels (Sec. 3.1) and the
- * indicator array.  d_u: H x W int32 in [0, 65535], H <= 16383 (so that
- * 4 x the cumulative energy fits 32 bits).  d_ce_last, d_label_last:
+ * indicator array.  d_u: H x W int32 in [0, 16382] (values outside are
+ * clamped into it: the DP keeps 4 U in 16 bits per column), H <= 16383 (so
+ * that 4 x the cumulative energy fits 32 bits).  d_ce_last, d_label_last:
  * W int32 (last row).  d_dir: H x W int8 in {-1, 0, 1} (predecessor column
  * minus column; row 0 is 0). */
 scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int32_t *d_ce_last,

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/scpl.h"
@@ -20,7 +22,7 @@ struct ProfPair {
 };
 
 struct scpl_ctx {
-    DpGeom forced{0, 0, 0};                       // DP geometry forced by the caller (Q = 0: none)
+    DpGeom forced{0, 0, 0, 0, 0};                       // DP geometry forced by the caller (Q = 0: none)
     std::vector<std::pair<int, DpGeom>> tuned;    // autotuned geometry per widest-job width
     bool profiling = false;
     std::vector<ProfPair> prof_pending;  // recorded, not yet read
@@ -36,6 +38,10 @@ struct scpl_ctx {
     void *pinned = nullptr;    // host staging (job tables, sums, states)
     size_t pinned_size = 0;
     std::vector<int32_t> last_log;
+    int nstreams = 2;                    // job groups of the batched path, one stream each
+    std::vector<hipStream_t> gstreams;   // their streams (default priority)
+    std::vector<hipEvent_t> gevents;     // one per group
+    hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
 };
 
 namespace {
@@ -141,7 +147,7 @@ size_t job_bytes(const JobShape &s)
     const size_t H = s.H, Wp = s.Wp(), W = s.W, nb = s.nb(), kc = s.kcap(), lc = s.logcap();
     size_t b = 0;
     b += 2 * align_up(H * Wp * 2);       // M0, M1
-    b += 2 * align_up((H + 1) * (size_t)s.Kp() * 4);  // K0, K1
+    b += 2 * align_up((H + 1) * (size_t)s.Kp() * 2);  // K0, K1
     b += align_up(H * Wp);               // dir
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
@@ -171,8 +177,8 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.logcap = (int32_t)lc;
     J.M0 = bp.take<int16_t>(H * Wp);
     J.M1 = bp.take<int16_t>(H * Wp);
-    J.K0 = bp.take<uint32_t>((H + 1) * (size_t)J.Kp);
-    J.K1 = bp.take<uint32_t>((H + 1) * (size_t)J.Kp);
+    J.K0 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
+    J.K1 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
     J.dir = bp.take<uint8_t>(H * Wp);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
@@ -214,6 +220,24 @@ scpl_status ensure_pinned(scpl_ctx *ctx, size_t bytes)
     size_t want = align_up(bytes, (size_t)1 << 16);
     SCPL_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
     ctx->pinned_size = want;
+    return SCPL_OK;
+}
+
+// Streams and events for n job groups (streams only when n > 1: a single
+// group runs on the caller's stream).
+scpl_status ensure_groups(scpl_ctx *ctx, int n)
+{
+    if (!ctx->fork) SCPL_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    while ((int)ctx->gevents.size() < n) {
+        hipEvent_t e;
+        SCPL_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->gevents.push_back(e);
+    }
+    while (n > 1 && (int)ctx->gstreams.size() < n) {
+        hipStream_t st;
+        SCPL_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->gstreams.push_back(st);
+    }
     return SCPL_OK;
 }
 
@@ -287,6 +311,7 @@ struct SegClip {
     int32_t nbuf = 0;
     // controller
     int t0 = 0, n = 1, nb = 0, t = 1, te = 0;
+    int win = kSegWindow / 2;  // candidates per scan: halved after a rejection, doubled after none
     bool valid = false, done = false, launched = false;
 };
 
@@ -337,7 +362,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
                 c.done = true;
                 continue;
             }
-            c.te = std::min(N, c.t + kSegWindow);
+            c.te = std::min(N, c.t + c.win);
             if (p->max_buffer > 0) c.te = std::min(c.te, c.t + (p->max_buffer - c.n));
             const int64_t HW = (int64_t)p->height * p->width;
             Bump bp{static_cast<char *>(c.state)};
@@ -384,6 +409,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
                     c.n = 1;
                     c.valid = false;
                     c.t = tt + 1;
+                    c.win = std::max(8, c.win / 2);
                     rejected = true;
                     break;
                 }
@@ -393,6 +419,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
             if (!rejected) {
                 c.valid = true;
                 c.t = c.te;
+                c.win = std::min(kSegWindow, 2 * c.win);
             }
         }
     }
@@ -403,9 +430,11 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
 
 struct LaunchShape {
     int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0;
-    DpGeom g{0, 0, 0};
-    void add(const JobShape &s)
+    size_t gather_lds = 0;
+    DpGeom g{0, 0, 0, 0, 0};
+    void add(const JobShape &s, int C = 1)
     {
+        gather_lds = std::max(gather_lds, gather_lds_bytes(s.W, s.Wt, C));
         Hmax = std::max(Hmax, s.H);
         Wmax = std::max(Wmax, s.W);
         nbmax = std::max(nbmax, s.nb());
@@ -443,77 +472,144 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const La
     }
 }
 
-// Runs every SCPL iteration of jobs [0, nj) until all reach their target
-// width, then gathers the outputs.  r_first_batch iterations are enqueued
-// (captured into a graph when use_graph) before the first look at the
-// per-job states; stragglers (iterations that found fewer parents than k)
-// get further iterations.
-scpl_status run_jobs(scpl_ctx *ctx, const Job *d_jobs, const Job *h_jobs, int32_t *d_states, int32_t *h_states,
-                     int nj, const LaunchShape &ls, int r_first_batch, bool use_graph, hipStream_t s)
+// A group of jobs that advances in lock-step on one stream: every stage of
+// an iteration is one launch over the group's jobs.  Groups on different
+// streams advance independently, so one group's bandwidth-bound stages run
+// beside another's latency-bound DP.
+struct Group {
+    const Job *d_jobs = nullptr;
+    const Job *h_jobs = nullptr;
+    int32_t *d_states = nullptr;
+    int32_t *h_states = nullptr;  // pinned
+    int nj = 0;
+    LaunchShape ls;
+    int rfirst = 0;               // iterations enqueued before the first look at the states
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;      // completes with the group's latest state read-back
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    int r = 0;                    // iterations enqueued so far
+    bool done = false;
+    void release()
+    {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        ge = nullptr;
+        g = nullptr;
+    }
+};
+
+scpl_status group_readback(Group &G)
 {
+    SCPL_TRY(hipMemcpyAsync(G.h_states, G.d_states, (size_t)G.nj * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, G.st));
+    SCPL_TRY(hipEventRecord(G.ev, G.st));
+    return SCPL_OK;
+}
+
+// Initial key rows, then the first rfirst iterations (captured into a graph
+// when use_graph), then a state read-back.
+scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
+{
+    const hipStream_t s = G.st;
     {
         ProfScope ps(ctx, SCPL_KERNEL_INIT, s);
-        launch_init_jobs(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+        launch_init_jobs(G.d_jobs, G.nj, G.ls.Hmax, G.ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_ENERGY, s);
-        launch_energy(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+        launch_energy(G.d_jobs, G.nj, G.ls.Hmax, G.ls.Wmax, s);
     }
     SCPL_CHECK_LAUNCH();
-    int r = 0;
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    if (use_graph && !ctx->profiling && s != nullptr && r_first_batch > 0) {
+    if (use_graph && !ctx->profiling && s != nullptr && G.rfirst > 0) {
         SCPL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (; r < r_first_batch; ++r) enqueue_iteration(ctx, d_jobs, nj, r, ls, s);
+        for (; G.r < G.rfirst; ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, s);
         hipError_t le = hipGetLastError();
-        hipError_t ce = hipStreamEndCapture(s, &g);
+        hipError_t ce = hipStreamEndCapture(s, &G.g);
         SCPL_TRY(le);
         SCPL_TRY(ce);
-        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
-        if (ie != hipSuccess) {
-            if (ge) (void)hipGraphExecDestroy(ge);
-            (void)hipGraphDestroy(g);
-            return dev_status(ie);
-        }
+        SCPL_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
+        SCPL_TRY(hipGraphLaunch(G.ge, s));
     } else {
-        for (; r < r_first_batch; ++r) enqueue_iteration(ctx, d_jobs, nj, r, ls, s);
+        for (; G.r < G.rfirst; ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, s);
         SCPL_CHECK_LAUNCH();
     }
-    // the graph is released once the first state read-back has synchronised
-    struct GraphGuard {
-        hipGraph_t &g;
-        hipGraphExec_t &ge;
-        ~GraphGuard()
+    return group_readback(G);
+}
+
+// After the group's read-back has completed: either every job has reached
+// its target width (the outputs are gathered) or the jobs still carving
+// (iterations that found fewer parents than k) get the iterations their
+// width and last k_iter call for.
+scpl_status group_advance(scpl_ctx *ctx, Group &G)
+{
+    G.release();  // the graph's launch precedes the completed read-back
+    bool all = true;
+    int more = 1;
+    for (int j = 0; j < G.nj; ++j) {
+        if (G.h_states[4 * j] >= 0) continue;
+        all = false;
+        const int rem = G.h_states[4 * j + 1] - G.h_jobs[j].Wt;
+        const int last = std::max(1, G.h_states[4 * j + 2]);
+        more = std::max(more, (rem + last - 1) / last);
+    }
+    if (all) {
         {
-            if (ge) (void)hipGraphExecDestroy(ge);
-            if (g) (void)hipGraphDestroy(g);
+            ProfScope ps(ctx, SCPL_KERNEL_GATHER, G.st);
+            launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gather_lds, G.st);
         }
-    } guard{g, ge};
-    for (;;) {
-        SCPL_TRY(hipMemcpyAsync(h_states, d_states, (size_t)nj * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        SCPL_TRY(hipStreamSynchronize(s));
-        bool all = true;
-        int more = 1;
-        for (int j = 0; j < nj; ++j) {
-            if (h_states[4 * j] >= 0) continue;
-            all = false;
-            // the job's width and last k_iter bound the iterations it still needs
-            const int rem = h_states[4 * j + 1] - h_jobs[j].Wt;
-            const int last = std::max(1, h_states[4 * j + 2]);
-            more = std::max(more, (rem + last - 1) / last);
-        }
-        if (all) break;
-        if (r > ls.Wmax + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
-        for (int q = 0; q < more; ++q, ++r) enqueue_iteration(ctx, d_jobs, nj, r, ls, s);
         SCPL_CHECK_LAUNCH();
+        SCPL_TRY(hipEventRecord(G.ev, G.st));
+        G.done = true;
+        return SCPL_OK;
     }
-    {
-        ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
-        launch_gather(d_jobs, nj, ls.Hmax, s);
-    }
+    if (G.r > G.ls.Wmax + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
+    for (int q = 0; q < more; ++q, ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, G.st);
     SCPL_CHECK_LAUNCH();
+    return group_readback(G);
+}
+
+// Runs the groups to completion after the work already on stream s, and
+// makes s wait for all of them.  The host polls the groups' read-backs and
+// feeds whichever is ready.
+scpl_status run_groups(scpl_ctx *ctx, std::vector<Group> &gs, bool use_graph, hipStream_t s)
+{
+    struct Cleanup {
+        std::vector<Group> &gs;
+        bool ok = false;
+        ~Cleanup()
+        {
+            for (Group &G : gs) {
+                if (!ok) (void)hipStreamSynchronize(G.st);  // no graph is freed while it may run
+                G.release();
+            }
+        }
+    } cleanup{gs};
+    bool forked = false;
+    for (Group &G : gs)
+        if (G.st != s) forked = true;
+    if (forked) {
+        SCPL_TRY(hipEventRecord(ctx->fork, s));
+        for (Group &G : gs)
+            if (G.st != s) SCPL_TRY(hipStreamWaitEvent(G.st, ctx->fork, 0));
+    }
+    for (Group &G : gs) SCPL_TRY(group_start(ctx, G, use_graph));
+    int open = (int)gs.size();
+    while (open > 0) {
+        bool progressed = false;
+        for (Group &G : gs) {
+            if (G.done) continue;
+            hipError_t q = open == 1 ? hipEventSynchronize(G.ev) : hipEventQuery(G.ev);
+            if (q == hipErrorNotReady) continue;
+            SCPL_TRY(q);
+            SCPL_TRY(group_advance(ctx, G));
+            if (G.done) --open;
+            progressed = true;
+        }
+        if (!progressed) std::this_thread::yield();
+    }
+    for (Group &G : gs)
+        if (G.st != s) SCPL_TRY(hipStreamWaitEvent(s, G.ev, 0));
+    cleanup.ok = true;
     return SCPL_OK;
 }
 
@@ -625,6 +721,9 @@ void scpl_destroy(scpl_ctx *ctx)
         (void)hipEventDestroy(pp.a);
         (void)hipEventDestroy(pp.b);
     }
+    for (hipStream_t st : ctx->gstreams) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : ctx->gevents) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->jws) (void)hipFree(ctx->jws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -729,9 +828,20 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
     char *job_ws = jdev.take<char>(job_area);
     Job *d_jobs = jdev.take<Job>((size_t)nj);
     int32_t *d_states = jdev.take<int32_t>(4 * (size_t)nj);
+    // batched: the jobs are dealt to the groups in order of decreasing
+    // length, so that every group gets a share of the heavy buffers; a
+    // group's jobs are consecutive in the job table
+    const int ng = batched ? std::max(1, std::min(ctx->nstreams, nj)) : 1;
+    std::vector<int> order(nj), slot(nj), gsize(ng, 0), gfirst(ng, 0);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pend[a].T > pend[b].T; });
+    for (int i = 0; i < nj; ++i) ++gsize[i % ng];
+    for (int g = 1; g < ng; ++g) gfirst[g] = gfirst[g - 1] + gsize[g - 1];
+    {
+        std::vector<int> fill(ng, 0);
+        for (int i = 0; i < nj; ++i) slot[order[i]] = gfirst[i % ng] + fill[i % ng]++;
+    }
     Bump jb{job_ws};
-    LaunchShape ls;
-    int rfirst = 0;
     std::vector<Job> jobs;
     for (int q = 0; q < nj; ++q) {
         const scpl_clip &cl = clips[pend[q].clip];
@@ -739,24 +849,40 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
         Job J = clip_job(&cl.p, cl.d_frames, seg[pend[q].clip].tiled, cl.d_out, cl.d_masks, pend[q].t0, pend[q].T,
                          pend[q].bindex);
         if (!batched) jb.off = 0;  // plain: every buffer reuses the same area
-        carve_job(J, js, jb, d_states + 4 * q);
-        h_jobs[q] = J;
+        carve_job(J, js, jb, d_states + 4 * slot[q]);
+        h_jobs[slot[q]] = J;
         jobs.push_back(J);
-        ls.add(js);
-        rfirst = std::max(rfirst, first_batch_iterations(&cl.p));
     }
     SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)nj, hipMemcpyHostToDevice, s));
+    SCPL_TRY(ensure_groups(ctx, ng));
     ctx->last_log.clear();
+    auto make_group = [&](int first, int n, hipStream_t st, hipEvent_t ev) {
+        Group G;
+        G.d_jobs = d_jobs + first;
+        G.h_jobs = h_jobs + first;
+        G.d_states = d_states + 4 * first;
+        G.h_states = h_states + 4 * first;
+        G.nj = n;
+        G.st = st;
+        G.ev = ev;
+        for (int q = 0; q < nj; ++q)
+            if (slot[q] >= first && slot[q] < first + n) {
+                G.ls.add(shape_of(pend[q]), clips[pend[q].clip].p.channels);
+                G.rfirst = std::max(G.rfirst, first_batch_iterations(&clips[pend[q].clip].p));
+            }
+        return G;
+    };
     if (batched) {
-        st = run_jobs(ctx, d_jobs, h_jobs, d_states, h_states, nj, ls, rfirst, true, s);
+        std::vector<Group> gs;
+        for (int g = 0; g < ng; ++g)
+            gs.push_back(make_group(gfirst[g], gsize[g], ng > 1 ? ctx->gstreams[g] : s, ctx->gevents[g]));
+        st = run_groups(ctx, gs, true, s);
         if (st != SCPL_OK) return st;
         return collect_logs(ctx, jobs, s);
     }
     for (int q = 0; q < nj; ++q) {
-        LaunchShape one;
-        one.add(shape_of(pend[q]));
-        st = run_jobs(ctx, d_jobs + q, h_jobs + q, d_states + 4 * q, h_states + 4 * q, 1, one,
-                      first_batch_iterations(&clips[pend[q].clip].p), false, s);
+        std::vector<Group> gs(1, make_group(slot[q], 1, s, ctx->gevents[0]));
+        st = run_groups(ctx, gs, false, s);
         if (st != SCPL_OK) return st;
         std::vector<Job> single(1, jobs[q]);
         st = collect_logs(ctx, single, s);
@@ -786,6 +912,13 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     }
     SCPL_TRY(hipSetDevice(ctx->device));
     return run_clips(ctx, clips, n_clips, true, nullptr, static_cast<hipStream_t>(stream));
+}
+
+scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n)
+{
+    if (!ctx || n < 1 || n > SCPL_MAX_STREAMS) return SCPL_ERR_INVALID_ARG;
+    ctx->nstreams = n;
+    return SCPL_OK;
 }
 
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on)
@@ -991,35 +1124,48 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     return SCPL_OK;
 }
 
-scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB)
+scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, int32_t EX)
 {
-    if (!ctx) return SCPL_ERR_INVALID_ARG;
+    if (!ctx || (EX != 0 && EX != 1)) return SCPL_ERR_INVALID_ARG;
     if (Q == 0) {
-        ctx->forced = DpGeom{0, 0, 0};
+        ctx->forced = DpGeom{0, 0, 0, 0, 0};
         return SCPL_OK;
     }
     for (int v = 0; v < kNumDpVariants; ++v)
-        if (kDpVariants[v].Q == Q && kDpVariants[v].HB == HB) {
+        if (kDpVariants[v].Q == Q && kDpVariants[v].HB == HB && (PF == 0 || kDpVariants[v].PF == PF)) {
             ctx->forced = kDpVariants[v];
+            ctx->forced.EX = EX;
             return SCPL_OK;
         }
-    if (Q == 32 && HB == 0) {
-        ctx->forced = DpGeom{32, 0, 0};
+    if (Q == 32 && HB == 0 && (PF == 0 || PF == 2)) {
+        ctx->forced = DpGeom{32, 0, 0, 2, EX};
         return SCPL_OK;
     }
     return SCPL_ERR_INVALID_ARG;
 }
 
-scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, int32_t *h_HB, double *h_us)
+scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
+                             int32_t *h_PF, int32_t *h_EX, double *h_us)
 {
-    if (!ctx || H < 2 || W < 1 || H > SCPL_MAX_HEIGHT || W > SCPL_MAX_WIDTH || (int64_t)H * W > SCPL_MAX_PIXELS)
+    if (!ctx || H < 2 || W < 1 || H > SCPL_MAX_HEIGHT || W > SCPL_MAX_WIDTH || (int64_t)H * W > SCPL_MAX_PIXELS ||
+        n_jobs < 1 || n_jobs > 1024)
         return SCPL_ERR_INVALID_ARG;
     SCPL_TRY(hipSetDevice(ctx->device));
     hipStream_t s = nullptr;
     std::vector<DpGeom> cand;
     for (int v = 0; v < kNumDpVariants; ++v)
-        if (dp_geom_fits(kDpVariants[v], W)) cand.push_back(kDpVariants[v]);
-    if (cand.empty()) cand.push_back(dp_geom(W));
+        if (dp_geom_fits(kDpVariants[v], W))
+            for (int ex = 0; ex < 2; ++ex) {
+                DpGeom g = kDpVariants[v];
+                g.EX = ex;
+                cand.push_back(g);
+            }
+    if (cand.empty()) {
+        DpGeom g = dp_geom(W);
+        cand.push_back(g);
+        g.EX = 1;
+        cand.push_back(g);
+    }
     hipEvent_t e0, e1;
     SCPL_TRY(hipEventCreate(&e0));
     SCPL_TRY(hipEventCreate(&e1));
@@ -1027,28 +1173,32 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, 
     double best_us = 1e30;
     scpl_status st = SCPL_OK;
     for (const DpGeom &g : cand) {
+        // n_jobs concurrent jobs of the same shape, each with its own workspace
         JobShape js{H, W, 0, 1, g};
-        const size_t total = job_bytes(js) + align_up(sizeof(Job)) + align_up(16);
+        const size_t jb = job_bytes(js);
+        const size_t total = jb * (size_t)n_jobs + align_up(sizeof(Job) * (size_t)n_jobs) + align_up(16 * (size_t)n_jobs);
         st = ensure_ws(ctx, total);
         if (st != SCPL_OK) break;
-        st = ensure_pinned(ctx, align_up(sizeof(Job)));
+        st = ensure_pinned(ctx, align_up(sizeof(Job) * (size_t)n_jobs));
         if (st != SCPL_OK) break;
         Bump dev{static_cast<char *>(ctx->ws)};
-        char *job_ws = dev.take<char>(job_bytes(js));
-        Job *d_job = dev.take<Job>(1);
-        int32_t *d_state = dev.take<int32_t>(4);
-        Job J{};
-        Bump jb{job_ws};
-        carve_job(J, js, jb, d_state);
+        char *job_ws = dev.take<char>(jb * (size_t)n_jobs);
+        Job *d_job = dev.take<Job>((size_t)n_jobs);
+        int32_t *d_state = dev.take<int32_t>(4 * (size_t)n_jobs);
         Job *h = static_cast<Job *>(ctx->pinned);
-        *h = J;
-        SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job), hipMemcpyHostToDevice, s));
-        launch_init_jobs(d_job, 1, H, W, s);
-        launch_tune_fill(J.K0, H, W, J.Kp, J.KL, s);
-        launch_dp(d_job, 1, 0, g, W, s);  // warm-up
+        Bump bjb{job_ws};
+        for (int q = 0; q < n_jobs; ++q) {
+            Job J{};
+            carve_job(J, js, bjb, d_state + 4 * q);
+            h[q] = J;
+        }
+        SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
+        launch_init_jobs(d_job, n_jobs, H, W, s);
+        for (int q = 0; q < n_jobs; ++q) launch_tune_fill(h[q].K0, H, W, h[q].Kp, h[q].KL, s);
+        launch_dp(d_job, n_jobs, 0, g, W, s);  // warm-up
         const int reps = 5;
         SCPL_TRY(hipEventRecord(e0, s));
-        for (int q = 0; q < reps; ++q) launch_dp(d_job, 1, 0, g, W, s);
+        for (int q = 0; q < reps; ++q) launch_dp(d_job, n_jobs, 0, g, W, s);
         SCPL_TRY(hipEventRecord(e1, s));
         SCPL_TRY(hipEventSynchronize(e1));
         SCPL_CHECK_LAUNCH();
@@ -1066,13 +1216,15 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t *h_Q, 
     for (auto &t : ctx->tuned)
         if (t.first == W) {
             t.second = best;
-            best = DpGeom{-1, 0, 0};
+            best = DpGeom{-1, 0, 0, 0, 0};
             break;
         }
     if (best.Q != -1) ctx->tuned.emplace_back(W, best);
     const DpGeom chosen = select_geom(ctx, W);
     if (h_Q) *h_Q = chosen.Q;
     if (h_HB) *h_HB = chosen.HB;
+    if (h_PF) *h_PF = chosen.PF;
+    if (h_EX) *h_EX = chosen.EX;
     if (h_us) *h_us = best_us;
     return SCPL_OK;
 }

@@ -56,9 +56,9 @@ struct Job {
     int32_t buffer_index;   // index of the buffer within its clip
     // workspace (device)
     int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
-    uint32_t *K0, *K1;      // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
-                            // all ones left of column 0 and at and beyond W_r; (H + 1) rows,
-                            // the extra row all ones
+    uint16_t *K0, *K1;      // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
+                            // 0xffff left of column 0 and at and beyond W_r; (H + 1) rows, the
+                            // extra row all 0xffff
     uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
@@ -97,9 +97,11 @@ void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStrea
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 // DP geometry of a launch, chosen from its widest job: Q columns per
 // thread; banded kernels give each wavefront C = 64 Q - 2 HB owned columns
-// plus HB halo columns on each side and synchronise every HB rows.
+// plus HB halo columns on each side and synchronise every HB rows; key rows
+// are requested PF rows ahead.  EX = 1: the workgroup reserves the whole
+// LDS of its compute unit, so no other workgroup shares that unit.
 struct DpGeom {
-    int Q, HB, banded;
+    int Q, HB, banded, PF, EX;
     int C() const { return 64 * Q - 2 * HB; }
     int waves(int W) const { return (W + C() - 1) / C(); }
     // columns at or right of column 0 the DP may read for a job of width W
@@ -112,7 +114,7 @@ extern const DpGeom kDpVariants[];
 extern const int kNumDpVariants;
 constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
 void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s);
-void launch_tune_fill(uint32_t *K, int H, int W, int Kp, int KL, hipStream_t s);
+void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s);
 void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s);
 void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s);
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
@@ -120,9 +122,11 @@ void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s);
 void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s);
 void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
 void launch_refresh(const Job *d_jobs, int njobs, int r, int kmax, int Hmax, hipStream_t s);
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s);
-void launch_u_to_keys(const int32_t *src, uint32_t *dst, int H, int W, int pitch, hipStream_t s);
-void launch_keys_to_u(const uint32_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
+// LDS of the gather for a job (0: the job gathers directly from global memory)
+size_t gather_lds_bytes(int W, int Wt, int C);
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);
+void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
+void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
 void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s);
 // indicator codes <-> int8 {-1, 0, 1} with pitch change (stage entry points)
 void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s);

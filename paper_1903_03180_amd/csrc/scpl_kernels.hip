@@ -55,9 +55,16 @@ __device__ __forceinline__ int sobel9(int a0, int a1, int a2, int b0, int b2, in
     return abs(gx) + abs(gy);
 }
 
+// floor(sqrt(q)): the hardware reciprocal square root in double precision
+// (coarse), one Newton step (relative error then far below 2^-40, so the
+// estimate is within 1 of the root for every q < 2^64), then integer steps
+// until exact -- the steps also guarantee exactness whatever the estimate.
 __device__ __forceinline__ uint32_t isqrt_u64(uint64_t q)
 {
-    uint64_t r = (uint64_t)sqrt((double)q);
+    const double qd = (double)(uint32_t)(q >> 32) * 4294967296.0 + (double)(uint32_t)q;
+    double y = __builtin_amdgcn_rsq(q ? qd : 1.0);
+    y = y * (1.5 - 0.5 * qd * y * y);
+    uint64_t r = q ? (uint64_t)(uint32_t)min(qd * y, 4294967295.0) : 0u;
     while (r * r > q) --r;
     while ((r + 1) * (r + 1) <= q) ++r;
     return (uint32_t)r;
@@ -201,14 +208,92 @@ __global__ __launch_bounds__(256) void untile_kernel(const uint8_t *__restrict__
     dst[p] = src[(size_t)n * tiled_frame_bytes(H, W) + tofs(r, c, tiles_across(W))];
 }
 
+// ---------------------------------------------- tile-row energy helpers
+//
+// A thread works on one tile row: 8 consecutive columns of one row of a
+// tiled luma frame.  row10 loads the 8 bytes with one 64-bit load plus the
+// column on each side (replicated at the frame borders, as are rows above
+// and below the frame); sobel8 then gives |Gx| + |Gy| of the 8 pixels from
+// three such rows.  Columns of the last tile past the frame's width are
+// filled with the last column, so every pixel's stencil is the replicated
+// one.
+
+// b[k] = luma of column 8 tc + k - 1 of row r (clamped into the frame).
+__device__ __forceinline__ void row10(const GLOBAL uint8_t *f, int r, int H, int tc, int ntc, int W, int (&b)[10])
+{
+    r = min(max(r, 0), H - 1);
+    const GLOBAL uint8_t *t = f + ((size_t)((r >> 4) * ntc + tc) << 7) + ((r & 15) << 3);
+    const u32x2 v = *reinterpret_cast<const GLOBAL u32x2 *>(t);
+    const int nv = W - 8 * tc;  // columns of this tile inside the frame (>= 1)
+    // neighbours in the tiles left and right (same row); clamped addresses so
+    // that every lane loads
+    const int left = t[tc > 0 ? -121 : 0];
+    const int right = t[nv > 8 ? 128 : 0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b[1 + k] = (int)((v.x >> (8 * k)) & 255u);
+        b[5 + k] = (int)((v.y >> (8 * k)) & 255u);
+    }
+    b[0] = tc > 0 ? left : b[1];
+    b[9] = right;
+#pragma unroll
+    for (int k = 2; k <= 9; ++k)
+        if (k - 1 >= nv) b[k] = b[k - 1];  // past the last column: replicate it
+}
+
+// |Gx| + |Gy| of the 8 pixels of row b (rows a above, c below).
+__device__ __forceinline__ void sobel8(const int (&a)[10], const int (&b)[10], const int (&c)[10], int (&g)[8])
+{
+    int v[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = a[k] + 2 * b[k] + c[k];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const int gx = v[x + 2] - v[x];
+        const int gy = (c[x] + 2 * c[x + 1] + c[x + 2]) - (a[x] + 2 * a[x + 1] + a[x + 2]);
+        g[x] = abs(gx) + abs(gy);
+    }
+}
+
+// 8 bytes of row r (clamped) of a tiled frame at tile column tc.
+__device__ __forceinline__ u32x2 row8(const GLOBAL uint8_t *f, int r, int H, int tc, int ntc)
+{
+    r = min(max(r, 0), H - 1);
+    return *reinterpret_cast<const GLOBAL u32x2 *>(f + ((size_t)((r >> 4) * ntc + tc) << 7) + ((r & 15) << 3));
+}
+
+__device__ __forceinline__ int byte_of(const u32x2 &v, int x) { return (int)(((x < 4 ? v.x : v.y) >> (8 * (x & 3))) & 255u); }
+
+// Energies of the 8 pixels of row r of frame f (Sec. 3.3); pf is the
+// predecessor frame or null.  a, b, c: rows r - 1, r, r + 1 from row10.
+__device__ __forceinline__ void energy8(const int (&a)[10], const int (&b)[10], const int (&c)[10],
+                                        const GLOBAL uint8_t *pf, int r, int H, int tc, int ntc, int mode,
+                                        uint32_t (&e)[8])
+{
+    int g[8];
+    sobel8(a, b, c, g);
+    if (mode != 1) {
+#pragma unroll
+        for (int x = 0; x < 8; ++x) e[x] = (uint32_t)g[x];
+        return;
+    }
+    u32x2 p{0u, 0u};
+    if (pf) p = row8(pf, r, H, tc, ntc);
+#pragma unroll
+    for (int x = 0; x < 8; ++x) e[x] = (uint32_t)(2 * g[x] + (pf ? 18 * abs(b[x + 1] - byte_of(p, x)) : 0));
+}
+
 // ------------------------------------------------------- ASDE window scan
 //
-// One thread per pixel of the original frame.  For a buffer starting at t0
-// whose moments S1 = sum e, S2 = sum e^2 cover frames [t0, tb), frames
-// [tb, te) are appended one at a time; after each one the per-pixel
+// A thread holds 8 columns x 2 rows of the original frame (one tile row in
+// each of two consecutive rows).  For a buffer starting at t0 whose moments
+// S1 = sum e, S2 = sum e^2 cover frames [t0, tb), frames [tb, te) are
+// appended one at a time; after each one the per-pixel
 // floor(sqrt(n S2 - S1^2)) (n times the population deviation of eq. 8) is
 // summed into sout[t - tb].  The host then decides every candidate in order
 // (eq. 9) and discards the tail after the first rejection.
+
+constexpr int kSegRows = 2;
 
 __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
 {
@@ -216,54 +301,84 @@ __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
     const int tid = threadIdx.x;
     if (tid < kSegWindow) part[tid] = 0;
     __syncthreads();
-    // a block covers 16 x 16 pixels; each wavefront an 8 x 8 half tile, so
-    // that a load instruction reads 64 contiguous bytes
-    const int wv = tid >> 6, ln = tid & 63;
-    const int i = blockIdx.y * 16 + (wv >> 1) * 8 + (ln >> 3);
-    const int j = blockIdx.x * 16 + (wv & 1) * 8 + (ln & 7);
-    const bool valid = i < a.H && j < a.W;
-    const int ii = valid ? i : 0, jj = valid ? j : 0;
-    const int im = max(ii - 1, 0), ip = min(ii + 1, a.H - 1), jm = max(jj - 1, 0), jp = min(jj + 1, a.W - 1);
     const int n = a.ntc;
-    const int o00 = tofs(im, jm, n), o01 = tofs(im, jj, n), o02 = tofs(im, jp, n);
-    const int o10 = tofs(ii, jm, n), o11 = tofs(ii, jj, n), o12 = tofs(ii, jp, n);
-    const int o20 = tofs(ip, jm, n), o21 = tofs(ip, jj, n), o22 = tofs(ip, jp, n);
+    const int tc = blockIdx.x * 64 + (tid >> 2);
+    const int r0 = (blockIdx.y * 4 + (tid & 3)) * kSegRows;
+    const bool valid = tc < n && r0 < a.H;
+    const int tcc = valid ? tc : 0;
+    const int nv = min(a.W - 8 * tcc, 8);
     const int64_t FS = a.FS;
-    uint32_t s1 = 0;
-    uint64_t s2 = 0;
-    const int64_t p = (int64_t)ii * a.W + jj;
+    uint32_t s1[kSegRows][8];
+    uint64_t s2[kSegRows][8];
+    auto energies = [&](int t, bool diff, uint32_t (&e)[kSegRows][8]) {
+        const GLOBAL uint8_t *f = gp(a.luma) + (size_t)t * FS;
+        const GLOBAL uint8_t *pf = diff ? f - FS : nullptr;
+        int ra[10], rb[10], rc[10];
+        row10(f, r0 - 1, a.H, tcc, n, a.W, ra);
+        row10(f, r0, a.H, tcc, n, a.W, rb);
+#pragma unroll
+        for (int q = 0; q < kSegRows; ++q) {
+            row10(f, r0 + q + 1, a.H, tcc, n, a.W, rc);
+            energy8(ra, rb, rc, pf, r0 + q, a.H, tcc, n, a.mode, e[q]);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                ra[k] = rb[k];
+                rb[k] = rc[k];
+            }
+        }
+    };
     if (valid) {
         if (a.init) {
-            const GLOBAL uint8_t *f = gp(a.luma) + (size_t)a.t0 * FS;
-            const int g = sobel9(f[o00], f[o01], f[o02], f[o10], f[o12], f[o20], f[o21], f[o22]);
-            uint32_t e = (uint32_t)g;
-            if (a.mode == 1) e = 2u * g + (a.t0 > 0 ? 18u * (uint32_t)abs((int)f[o11] - (int)f[(ptrdiff_t)o11 - FS]) : 0u);
-            s1 = e;
-            s2 = (uint64_t)e * e;
+            uint32_t e[kSegRows][8];
+            energies(a.t0, a.mode == 1 && a.t0 > 0, e);
+#pragma unroll
+            for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    s1[q][x] = e[q][x];
+                    s2[q][x] = (uint64_t)e[q][x] * e[q][x];
+                }
         } else {
-            s1 = a.s1[p];
-            s2 = a.s2[p];
+#pragma unroll
+            for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    const int i = min(r0 + q, a.H - 1), j = 8 * tcc + min(x, nv - 1);
+                    s1[q][x] = a.s1[(int64_t)i * a.W + j];
+                    s2[q][x] = a.s2[(int64_t)i * a.W + j];
+                }
         }
     }
     for (int t = a.tb; t < a.te; ++t) {
         unsigned long long v = 0;
         if (valid) {
-            const GLOBAL uint8_t *f = gp(a.luma) + (size_t)t * FS;
-            const int g = sobel9(f[o00], f[o01], f[o02], f[o10], f[o12], f[o20], f[o21], f[o22]);
-            uint32_t e = (uint32_t)g;
-            if (a.mode == 1) e = 2u * g + 18u * (uint32_t)abs((int)f[o11] - (int)f[(ptrdiff_t)o11 - FS]);
-            s1 += e;
-            s2 += (uint64_t)e * e;
+            uint32_t e[kSegRows][8];
+            energies(t, a.mode == 1, e);
             const uint64_t nn = (uint64_t)(t - a.t0 + 1);
-            v = isqrt_u64(nn * s2 - (uint64_t)s1 * s1);
+#pragma unroll
+            for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    s1[q][x] += e[q][x];
+                    s2[q][x] += (uint64_t)e[q][x] * e[q][x];
+                    const bool in = r0 + q < a.H && x < nv;
+                    v += in ? isqrt_u64(nn * s2[q][x] - (uint64_t)s1[q][x] * s1[q][x]) : 0u;
+                }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if ((tid & 63) == 0) atomicAdd(&part[t - a.tb], v);
     }
     if (valid) {
-        a.s1[p] = s1;
-        a.s2[p] = s2;
+#pragma unroll
+        for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+                if (r0 + q < a.H && x < nv) {
+                    const int64_t p = (int64_t)(r0 + q) * a.W + 8 * tcc + x;
+                    a.s1[p] = s1[q][x];
+                    a.s2[p] = s2[q][x];
+                }
     }
     __syncthreads();
     if (tid < a.te - a.tb) atomicAdd(&a.sout[tid], part[tid]);
@@ -271,7 +386,13 @@ __global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
 
 // ------------------------------------------------------------ job set-up
 
+// Keys in registers: all ones is "no path".  Key rows in memory hold 16 bits
+// per column, 0xffff beyond the width: 65535 per row exceeds what any real
+// column can add in a row (4 x 7650 + 2, U <= 16382 in general), so by
+// induction over the rows such a column's cumulative key always exceeds its
+// real neighbour's and it never becomes anyone's predecessor.
 constexpr uint32_t kKeyInf = 0xffffffffu;
+constexpr uint16_t kRowInf = 0xffffu;
 
 __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
 {
@@ -280,8 +401,8 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
     if (i > J.H) return;
     if (i == J.H) {  // the all-ones row read by DP lanes past the job's width
         for (int j = threadIdx.x; j < J.Kp; j += 256) {
-            J.K0[(size_t)i * J.Kp + j] = kKeyInf;
-            J.K1[(size_t)i * J.Kp + j] = kKeyInf;
+            J.K0[(size_t)i * J.Kp + j] = kRowInf;
+            J.K1[(size_t)i * J.Kp + j] = kRowInf;
         }
         return;
     }
@@ -291,8 +412,8 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
     }
     for (int x = threadIdx.x; x < J.Kp; x += 256) {
         if (x >= J.KL && x < J.KL + J.W) continue;
-        J.K0[(size_t)i * J.Kp + x] = kKeyInf;
-        J.K1[(size_t)i * J.Kp + x] = kKeyInf;
+        J.K0[(size_t)i * J.Kp + x] = kRowInf;
+        J.K1[(size_t)i * J.Kp + x] = kRowInf;
     }
     if (i == 0 && threadIdx.x == 0) {
         J.log[0] = J.W;
@@ -350,30 +471,61 @@ __device__ __forceinline__ int energy_one(const Job &J, const Stencil &s, int t)
 
 // Iteration 0 of every job: the DP key row 4 floor(sum of the T energy
 // maps / T) over the uncarved frames (the column map is the identity).  A
-// block covers 16 x 16 pixels.
+// thread sums 8 columns x 4 rows (one tile row in each of 4 consecutive
+// rows) over the buffer's frames; a block covers 512 columns x 16 rows.
 __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
 {
     const Job &J = jobs[blockIdx.z];
     if (J.W <= J.Wt) return;
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;  // 8 x 8 half tile per wavefront
-    const int i = blockIdx.y * 16 + (wv >> 1) * 8 + (ln >> 3);
-    const int j = blockIdx.x * 16 + (wv & 1) * 8 + (ln & 7);
-    if (i >= J.H || j >= J.W) return;
-    const int W = J.W, H = J.H, n = J.ntc;
-    const int im = max(i - 1, 0), ip = min(i + 1, H - 1), jm = max(j - 1, 0), jp = min(j + 1, W - 1);
-    Stencil st;
-    st.oa0 = tofs(im, jm, n);
-    st.oa1 = tofs(im, j, n);
-    st.oa2 = tofs(im, jp, n);
-    st.ob0 = tofs(i, jm, n);
-    st.ob1 = tofs(i, j, n);
-    st.ob2 = tofs(i, jp, n);
-    st.oc0 = tofs(ip, jm, n);
-    st.oc1 = tofs(ip, j, n);
-    st.oc2 = tofs(ip, jp, n);
-    uint32_t acc = 0;
-    for (int t = 0; t < J.T; ++t) acc += (uint32_t)energy_one(J, st, t);
-    J.K0[(size_t)i * J.Kp + J.KL + j] = (acc / (uint32_t)J.T) << 2;
+    const int tid = threadIdx.x;
+    const int n = J.ntc, H = J.H, W = J.W;
+    const int tc = blockIdx.x * 64 + (tid >> 2);
+    const int r0 = blockIdx.y * 16 + (tid & 3) * 4;
+    if (tc >= n || r0 >= H) return;
+    const int nv = min(W - 8 * tc, 8);
+    uint32_t acc[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int x = 0; x < 8; ++x) acc[q][x] = 0;
+    for (int t = 0; t < J.T; ++t) {
+        const GLOBAL uint8_t *f = gp(J.luma) + (size_t)(J.t0 + t) * J.FS;
+        const GLOBAL uint8_t *pf = (J.mode == 1 && (t > 0 || J.has_prev)) ? f - J.FS : nullptr;
+        int ra[10], rb[10], rc[10];
+        row10(f, r0 - 1, H, tc, n, W, ra);
+        row10(f, r0, H, tc, n, W, rb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            row10(f, r0 + q + 1, H, tc, n, W, rc);
+            uint32_t e[8];
+            energy8(ra, rb, rc, pf, r0 + q, H, tc, n, J.mode, e);
+#pragma unroll
+            for (int x = 0; x < 8; ++x) acc[q][x] += e[x];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                ra[k] = rb[k];
+                rb[k] = rc[k];
+            }
+        }
+    }
+    const uint32_t T = (uint32_t)J.T;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = r0 + q;
+        if (i >= H) break;
+        uint32_t k8[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) k8[x] = (acc[q][x] / T) << 2;
+        uint16_t *dst = J.K0 + (size_t)i * J.Kp + J.KL + 8 * tc;  // 16-byte aligned
+        if (nv == 8) {
+            *gp(reinterpret_cast<u32x4 *>(dst)) =
+                u32x4{k8[0] | (k8[1] << 16), k8[2] | (k8[3] << 16), k8[4] | (k8[5] << 16), k8[6] | (k8[7] << 16)};
+        } else {
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+                if (x < nv) dst[x] = (uint16_t)k8[x];
+        }
+    }
 }
 
 // ------------------------------------------------------------------- DP
@@ -383,32 +535,41 @@ __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
 // candidates of a pixel get the offsets 0 (left), 1 (above), 2 (right), so
 // one unsigned min3 picks the least cumulative energy and, among equal
 // ones, the leftmost; the offset left in the two low bits is the indicator
-// code (predecessor column - column + 1).  Key rows hold 4 U and all ones
-// at and beyond the current width; saturating adds keep those columns at
-// all ones, so they never win.  Neighbours inside a wavefront come through
+// code (predecessor column - column + 1).  Key rows hold 4 U in 16 bits and
+// 0xffff at and beyond the current width (such columns never win, see
+// kRowInf); values all ones in registers (no neighbour) stay all ones
+// through saturating adds.  Neighbours inside a wavefront come through
 // DPP wave shifts; the two wavefront-edge values cross through LDS, one
 // barrier per row.  Key rows are requested a group of PF rows ahead.
 // Parent labels are not carried here: they follow from the band origins.
 
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
+// Q consecutive 16-bit keys of one row, as loaded (two per word).
 template <int Q>
 struct KRow {
-    uint32_t w[Q];
+    uint32_t w[(Q + 1) / 2];
+    __device__ __forceinline__ uint32_t at(int c) const
+    {
+        if constexpr (Q == 1) return w[0];
+        return (c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu);
+    }
 };
 
 template <int Q>
-__device__ __forceinline__ void load_krow(KRow<Q> &dst, const uint32_t *p)
+__device__ __forceinline__ void load_krow(KRow<Q> &dst, const uint16_t *p)
 {
     if constexpr (Q == 1) {
         dst.w[0] = *gp(p);
     } else if constexpr (Q == 2) {
+        dst.w[0] = *gp(reinterpret_cast<const uint32_t *>(p));
+    } else if constexpr (Q == 4) {
         const u32x2 v = *gp(reinterpret_cast<const u32x2 *>(p));
         dst.w[0] = v.x;
         dst.w[1] = v.y;
     } else {
 #pragma unroll
-        for (int q = 0; q < Q / 4; ++q) {
+        for (int q = 0; q < Q / 8; ++q) {
             const u32x4 v = gp(reinterpret_cast<const u32x4 *>(p))[q];
             dst.w[4 * q] = v.x;
             dst.w[4 * q + 1] = v.y;
@@ -438,7 +599,7 @@ __device__ __forceinline__ void store_codes(uint8_t *p, const uint32_t (&b)[Q])
 
 template <int Q>
 struct DpPrefetch {
-    static constexpr int PF = Q <= 4 ? 8 : (Q == 8 ? 4 : 2);
+    static constexpr int PF = Q <= 4 ? 8 : (Q == 8 ? 4 : 2);  // row-synchronous kernel
 };
 
 // One DP row step of a lane holding Q consecutive columns: lnb / rnb are the
@@ -455,7 +616,7 @@ __device__ __forceinline__ void dp_step(uint32_t (&key)[Q], uint32_t lnb, uint32
         best[c] = min(min(kl, kc), kr);
     }
 #pragma unroll
-    for (int c = 0; c < Q; ++c) key[c] = sat_add(nxt.w[c], best[c] & ~3u);
+    for (int c = 0; c < Q; ++c) key[c] = sat_add(nxt.at(c), best[c] & ~3u);
 }
 
 // Row-synchronous DP for the widest frames: every row, the two
@@ -473,9 +634,9 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
     const int j0 = tid * Q;
     const int H = J.H, Kp = J.Kp, Wp = J.Wp;
     const bool owns = J.KL + j0 + Q <= Kp;
-    const uint32_t *K = (r & 1) ? J.K1 : J.K0;
+    const uint16_t *K = (r & 1) ? J.K1 : J.K0;
     // lanes past the job's key rows read the all-ones row at stride 0
-    const uint32_t *kp = owns ? K + J.KL + j0 : K + (size_t)H * Kp;
+    const uint16_t *kp = owns ? K + J.KL + j0 : K + (size_t)H * Kp;
     const size_t kstride = owns ? (size_t)Kp : 0;
     uint8_t *__restrict__ dir = J.dir;
     const bool stores = j0 < Wp;
@@ -487,7 +648,7 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
         uint32_t code[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-            key[c] = k0.w[c];
+            key[c] = k0.at(c);
             code[c] = 1;
         }
         if (stores) store_codes<Q>(dir + j0, code);
@@ -543,10 +704,9 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
 // owners publish their keys of the band's last row in LDS (ping-pong), the
 // block meets at one barrier, and the halo lanes take the neighbours' keys.
 // Only owned columns store indicator codes.
-template <int Q, int HB>
+template <int Q, int HB, int PF>
 __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
 {
-    constexpr int PF = DpPrefetch<Q>::PF;
     constexpr int C = 64 * Q - 2 * HB;
     static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
     extern __shared__ uint32_t rowbuf[];  // 2 x (Kp - KL) keys
@@ -560,8 +720,8 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
     const bool live = wid < J.dpnw;
     const bool owner = live && lane * Q >= HB && lane * Q < HB + C;
     const bool stores = owner && jl < Wp;
-    const uint32_t *K = (r & 1) ? J.K1 : J.K0;
-    const uint32_t *kp = live ? K + J.KL + jl : K + (size_t)H * Kp;
+    const uint16_t *K = (r & 1) ? J.K1 : J.K0;
+    const uint16_t *kp = live ? K + J.KL + jl : K + (size_t)H * Kp;
     const size_t kstride = live ? (size_t)Kp : 0;
     uint8_t *__restrict__ dir = J.dir;
 
@@ -572,7 +732,7 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
         uint32_t code[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-            key[c] = k0.w[c];
+            key[c] = k0.at(c);
             code[c] = 1;
         }
         if (stores) store_codes<Q>(dir + jl, code);
@@ -638,7 +798,7 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
 // column - j, |.| <= B.  The band's indicator rows around the block's 128
 // columns are staged in LDS with 32-bit loads.
 
-constexpr int kBorgCols = 128;
+constexpr int kBorgCols = 256;
 
 __device__ __forceinline__ int code_step(uint8_t c) { return (int)(c & 3u) - 1; }
 
@@ -650,10 +810,20 @@ __device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *
 {
     const int a0 = c0 & ~3;
     const int nw = (c1 - a0 + 3) >> 2;  // words per row
-    for (int idx = tid; idx < nrows * nw; idx += nthreads) {
-        const int rr = idx / nw, w = idx - rr * nw;
-        const uint32_t v = *gp(reinterpret_cast<const uint32_t *>(src + (size_t)(r0 + rr) * pitch + a0) + w);
+    if (nw <= 0 || nrows <= 0) return c0 - a0;
+    // (row, word) of this thread, advanced by nthreads words per step
+    int rr = tid / nw, w = tid - rr * nw;
+    const int drr = nthreads / nw, dw = nthreads - drr * nw;
+    const GLOBAL uint8_t *g = gp(src) + (size_t)r0 * pitch + a0;
+    while (rr < nrows) {
+        const uint32_t v = *reinterpret_cast<const GLOBAL uint32_t *>(g + (size_t)rr * pitch + 4 * w);
         *reinterpret_cast<uint32_t *>(lds + rr * lp + 4 * w) = v;
+        rr += drr;
+        w += dw;
+        if (w >= nw) {
+            w -= nw;
+            ++rr;
+        }
     }
     return c0 - a0;
 }
@@ -828,11 +998,9 @@ __global__ __launch_bounds__(256) void jump_kernel(const Job *jobs, int r)
 // marks the removed pixels (original columns, via the column map) in the
 // buffer mask with the iteration number + 1.
 
-constexpr int kFillPitch = 2 * kBandMax + 8;
-
 __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
 {
-    __shared__ uint8_t tile[kBandMax * kFillPitch];
+    extern __shared__ uint8_t tile[];  // B - 1 rows x (2 B + 8) bytes of the launch's largest B
     __shared__ int16_t path[kBandMax];
     const Job &J = jobs[blockIdx.z];
     const int Wr = job_width(J, r);
@@ -841,19 +1009,20 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
     const int b = blockIdx.y;
     if (b >= J.nb) return;
     const int H = J.H, nb = J.nb, lane = threadIdx.x;
+    const int fp = 2 * J.B + 8;  // LDS pitch: the window of a seam is at most 2 B - 1 wide, staged from a word
     const int16_t *__restrict__ M = (r & 1) ? J.M1 : J.M0;
     const int lo = b * J.B, hi = min(lo + J.B, H) - 1;
     const int span = hi - lo;  // < B <= kBandMax
     for (int s = blockIdx.x; s < kk; s += gridDim.x) {
         const int c_end = J.bcol[s * nb + b];
         const int wlo = max(c_end - span, 0), whi = min(c_end + span + 1, Wr);
-        const int sh = stage_bytes(tile, kFillPitch, J.dir, J.Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
+        const int sh = stage_bytes(tile, fp, J.dir, J.Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
         __syncthreads();
         if (lane == 0) {
             int c = c_end;
             path[span] = (int16_t)c;
             for (int i = hi; i > lo; --i) {
-                c += code_step(tile[(i - lo - 1) * kFillPitch + c + sh]);
+                c += code_step(tile[(i - lo - 1) * fp + c + sh]);
                 path[i - 1 - lo] = (int16_t)c;
             }
         }
@@ -900,9 +1069,16 @@ __device__ __forceinline__ int source_column(int j, int kk, const int *R, const 
     return j + a;
 }
 
+// Output columns per pass of the staged compaction, and the seams a row may
+// lose for the staged form (more take the direct form).
+constexpr int kUpdChunk = 2048;
+constexpr int kUpdSeams = 256;
+
 __global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
 {
-    __shared__ int R[256];  // seams of row i: old column - s (when k_iter <= 256)
+    __shared__ int R[kUpdSeams];  // seams of row i: old column - s (when k_iter <= kUpdSeams)
+    __shared__ __align__(16) uint16_t Ks[kUpdChunk + kUpdSeams + 2];
+    __shared__ __align__(16) int16_t Ms[kUpdChunk + kUpdSeams + 2];
     const Job &J = jobs[blockIdx.y];
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
@@ -911,29 +1087,78 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
     const int H = J.H, Wp = J.Wp;
-    const int16_t *__restrict__ Mo = (r & 1) ? J.M1 : J.M0;
-    int16_t *__restrict__ Mw = (r & 1) ? J.M0 : J.M1;
-    const uint32_t *__restrict__ Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
-    uint32_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
-    const bool rl = kk <= 256;
+    const int16_t *__restrict__ Mo = ((r & 1) ? J.M1 : J.M0) + (size_t)i * Wp;
+    int16_t *__restrict__ Mw = ((r & 1) ? J.M0 : J.M1) + (size_t)i * Wp;
+    const uint16_t *__restrict__ Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
+    uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
     const bool keys = Wn > J.Wt;  // a further iteration reads the keys
     const int tid = threadIdx.x;
-    if (rl) {
+    if (kk > kUpdSeams) {
+        // direct form: every pixel of the row moves to its new column with its key
+        for (int j = tid; j < Wn; j += 256) {
+            const int src = source_column(j, kk, nullptr, J.seams + i, H);
+            Mw[j] = Mo[src];
+            if (keys) Kn[j] = Ko[src];
+        }
+    } else {
         for (int s = tid; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
-        __syncthreads();
-    }
-    // every pixel of the row moves to its new column with its key (the
-    // refresh kernel then recomputes the keys whose neighbourhood changed)
-    for (int j = tid; j < Wn; j += 256) {
-        const int src = source_column(j, kk, rl ? R : nullptr, J.seams + i, H);
-        Mw[(size_t)i * Wp + j] = Mo[(size_t)i * Wp + src];
-        if (keys) Kn[j] = Ko[src];
+        // staged form: per chunk of output columns [j0, j1), the old columns
+        // [s0, s1) they come from are loaded into LDS with coalesced loads,
+        // then each thread builds 8 consecutive new columns and stores them
+        // with vector stores
+        for (int j0 = 0; j0 < Wn; j0 += kUpdChunk) {
+            const int j1 = min(j0 + kUpdChunk, Wn);
+            __syncthreads();  // R ready; the previous chunk's LDS reads are done
+            const int s0 = source_column(j0, kk, R, nullptr, H);
+            const int s1 = source_column(j1 - 1, kk, R, nullptr, H) + 1;  // <= s0 + kUpdChunk + kk
+            const int m0 = s0 & ~1;  // staged from an even column: 32-bit loads of column pairs
+            const int mw = (s1 - m0) >> 1;  // whole pairs inside [m0, s1)
+            for (int x = tid; x < mw; x += 256) {
+                reinterpret_cast<uint32_t *>(Ms)[x] = gp(reinterpret_cast<const uint32_t *>(Mo + m0))[x];
+                if (keys) reinterpret_cast<uint32_t *>(Ks)[x] = gp(reinterpret_cast<const uint32_t *>(Ko + m0))[x];
+            }
+            if (tid == 0 && ((s1 - m0) & 1)) {
+                Ms[s1 - 1 - m0] = Mo[s1 - 1];
+                if (keys) Ks[s1 - 1 - m0] = Ko[s1 - 1];
+            }
+            __syncthreads();
+            const int jb = j0 + 8 * tid;
+            if (jb < j1) {
+                int a = source_column(jb, kk, R, nullptr, H) - jb;
+                int16_t mv[8];
+                uint16_t kv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = jb + q;
+                    while (a < kk && R[a] <= j) ++a;
+                    const int src = min(j + a, s1 - 1);  // lanes past j1 read a valid slot, never stored
+                    mv[q] = Ms[src - m0];
+                    kv[q] = Ks[src - m0];
+                }
+                if (jb + 8 <= j1) {
+                    const u32x4 mo{(uint16_t)mv[0] | ((uint32_t)(uint16_t)mv[1] << 16),
+                                   (uint16_t)mv[2] | ((uint32_t)(uint16_t)mv[3] << 16),
+                                   (uint16_t)mv[4] | ((uint32_t)(uint16_t)mv[5] << 16),
+                                   (uint16_t)mv[6] | ((uint32_t)(uint16_t)mv[7] << 16)};
+                    *gp(reinterpret_cast<u32x4 *>(Mw + jb)) = mo;
+                    if (keys)
+                        *gp(reinterpret_cast<u32x4 *>(Kn + jb)) =
+                            u32x4{kv[0] | ((uint32_t)kv[1] << 16), kv[2] | ((uint32_t)kv[3] << 16),
+                                  kv[4] | ((uint32_t)kv[5] << 16), kv[6] | ((uint32_t)kv[7] << 16)};
+                } else {
+                    for (int q = 0; q < 8 && jb + q < j1; ++q) {
+                        Mw[jb + q] = mv[q];
+                        if (keys) Kn[jb + q] = kv[q];
+                    }
+                }
+            }
+        }
     }
     if (!keys) return;
     // the keys of the vacated columns become all ones; columns beyond the
     // previous width of this buffer already are
     const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
-    for (int j = Wn + tid; j < wprev; j += 256) Kn[j] = kKeyInf;
+    for (int j = Wn + tid; j < wprev; j += 256) Kn[j] = kRowInf;
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -977,7 +1202,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
     if (i0 >= H) return;
     const int nrows = min(kRefreshRows, H - i0);
     const int16_t *__restrict__ Mn = (r & 1) ? J.M0 : J.M1;
-    uint32_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + J.KL;
+    uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + J.KL;
     const int tid = threadIdx.x;
     const bool rl = kk <= kRefreshSeams;
     if (tid == 0) nf = 0;
@@ -1046,7 +1271,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
                 const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
                 const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
                                                      Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W, ntc);
-                Kn[(size_t)i * Kp + c] = (full_sum(st) / (uint32_t)T) << 2;
+                Kn[(size_t)i * Kp + c] = (uint16_t)((full_sum(st) / (uint32_t)T) << 2);
             }
         }
     }
@@ -1079,7 +1304,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
     __syncthreads();
     for (int p = tid; p < n; p += 256) {
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
-        Kn[(size_t)i * Kp + c] = (fsum[p] / (uint32_t)T) << 2;
+        Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
     }
 }
 
@@ -1088,44 +1313,102 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
 // Carved output of every frame of the buffer: out(t, i, j) = frame(t, i,
 // M(i, j)) for j < Wt, all channels; masks of every frame = buffer mask.
 
+// Staged form, for rows of at most kGatherIn source and kGatherOut output
+// bytes: the byte offsets of the output row within the source row are
+// computed once per row, then for every frame of the buffer the source row
+// is loaded into LDS with coalesced loads and the output row is assembled
+// from it and written with 16-byte stores.  Wider rows gather directly.
+constexpr int kGatherIn = 32768;
+constexpr int kGatherOut = 16384;
+
+__device__ __forceinline__ uint32_t div3(uint32_t x) { return __umulhi(x, 0xAAAAAAABu) >> 1; }
+
 __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
 {
+    extern __shared__ __align__(16) uint8_t gsm[];
     const Job &J = jobs[blockIdx.y];
     const int i = blockIdx.x;
     if (i >= J.H) return;
     const int rd = J.state[0];
     const int16_t *__restrict__ M = ((rd & 1) ? J.M1 : J.M0) + (size_t)i * J.Wp;
     const int C = J.C, W = J.W, Wt = J.Wt, H = J.H;
-    for (int t = J.t0; t < J.t0 + J.T; ++t) {
-        const uint8_t *src = J.frames + ((size_t)t * H + i) * W * C;
-        uint8_t *dst = J.out + ((size_t)t * H + i) * Wt * C;
-        if (C == 1) {
-            for (int j = threadIdx.x; j < Wt; j += 256) dst[j] = src[mcol(M, j, W)];
+    const int inb = W * C, outb = Wt * C;
+    const int tid = threadIdx.x;
+    const uint16_t *msrc = J.bmask + (size_t)i * W;
+    const bool vmask = J.masks && ((((uintptr_t)J.masks) | (uintptr_t)(2 * W)) & 15) == 0;
+    auto copy_mask = [&](int t) {
+        uint16_t *mdst = J.masks + ((size_t)t * H + i) * W;
+        if (vmask) {
+            for (int q = tid; q < W / 8; q += 256)
+                gp(reinterpret_cast<u32x4 *>(mdst))[q] = gp(reinterpret_cast<const u32x4 *>(msrc))[q];
         } else {
-            for (int idx = threadIdx.x; idx < Wt * C; idx += 256) {
-                const int j = idx / C, c = idx - j * C;
-                dst[idx] = src[mcol(M, j, W) * C + c];
+            for (int j = tid; j < W; j += 256) mdst[j] = msrc[j];
+        }
+    };
+    if (inb > kGatherIn || outb > kGatherOut) {
+        for (int t = J.t0; t < J.t0 + J.T; ++t) {
+            const uint8_t *src = J.frames + ((size_t)t * H + i) * inb;
+            uint8_t *dst = J.out + ((size_t)t * H + i) * outb;
+            for (int b = tid; b < outb; b += 256) {
+                const int j = C == 1 ? b : (int)div3((uint32_t)b);
+                dst[b] = src[mcol(M, j, W) * C + (b - j * C)];
             }
+            if (J.masks) copy_mask(t);
         }
-        if (J.masks) {
-            uint16_t *mdst = J.masks + ((size_t)t * H + i) * W;
-            const uint16_t *msrc = J.bmask + (size_t)i * W;
-            for (int j = threadIdx.x; j < W; j += 256) mdst[j] = msrc[j];
+        return;
+    }
+    uint8_t *srow = gsm;
+    uint16_t *ofs = reinterpret_cast<uint16_t *>(gsm + ((inb + 15) & ~15));
+    for (int b = tid; b < outb; b += 256) {
+        const int j = C == 1 ? b : (int)div3((uint32_t)b);
+        ofs[b] = (uint16_t)(mcol(M, j, W) * C + (b - j * C));
+    }
+    const bool vin = ((((uintptr_t)J.frames) | (uintptr_t)inb) & 15) == 0;
+    const bool vout = ((((uintptr_t)J.out) | (uintptr_t)outb) & 15) == 0;
+    for (int t = J.t0; t < J.t0 + J.T; ++t) {
+        const uint8_t *src = J.frames + ((size_t)t * H + i) * inb;
+        uint8_t *dst = J.out + ((size_t)t * H + i) * outb;
+        __syncthreads();  // offsets written; the previous frame's reads of srow done
+        if (vin) {
+            for (int q = tid; q < inb / 16; q += 256)
+                reinterpret_cast<u32x4 *>(srow)[q] = gp(reinterpret_cast<const u32x4 *>(src))[q];
+        } else {
+            for (int b = tid; b < inb; b += 256) srow[b] = gp(src)[b];
         }
+        __syncthreads();
+        if (vout) {
+            for (int q = tid; q < outb / 16; q += 256) {
+                const u32x4 oa = reinterpret_cast<const u32x4 *>(ofs)[2 * q];
+                const u32x4 ob = reinterpret_cast<const u32x4 *>(ofs)[2 * q + 1];
+                const uint32_t o[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
+                uint32_t w[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t p0 = o[2 * k], p1 = o[2 * k + 1];
+                    w[k] = (uint32_t)srow[p0 & 0xffff] | ((uint32_t)srow[p0 >> 16] << 8) |
+                           ((uint32_t)srow[p1 & 0xffff] << 16) | ((uint32_t)srow[p1 >> 16] << 24);
+                }
+                gp(reinterpret_cast<u32x4 *>(dst))[q] = u32x4{w[0], w[1], w[2], w[3]};
+            }
+        } else {
+            for (int b = tid; b < outb; b += 256) dst[b] = srow[ofs[b]];
+        }
+        if (J.masks) copy_mask(t);
     }
 }
 
 // ------------------------------------------------- stage-API conversions
 
-__global__ void u_to_keys_kernel(const int32_t *src, uint32_t *dst, int H, int W, int pitch)
+// U -> key row entry; U outside [0, 16382] is clamped into it
+__global__ void u_to_keys_kernel(const int32_t *src, uint16_t *dst, int H, int W, int pitch)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
     const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
-    dst[(size_t)i * pitch + j] = (uint32_t)src[p] << 2;
+    dst[(size_t)i * pitch + j] = (uint16_t)(min(max(src[p], 0), 16382) << 2);
 }
 
-__global__ void keys_to_u_kernel(const uint32_t *src, int32_t *dst, int H, int W, int pitch)
+__global__ void keys_to_u_kernel(const uint16_t *src, int32_t *dst, int H, int W, int pitch)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
@@ -1185,7 +1468,8 @@ void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s)
 
 void launch_seg_window(const SegArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(a.W, 16), blocks_for(a.H, 16)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(tiles_across(a.W), 64), blocks_for(a.H, 4 * kSegRows)),
+                       dim3(256), 0, s, a);
 }
 
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
@@ -1195,8 +1479,8 @@ void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s
 
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(Wmax, 16), blocks_for(Hmax, 16), njobs), dim3(256), 0, s,
-                       d_jobs);
+    hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(tiles_across(Wmax), 64), blocks_for(Hmax, 16), njobs),
+                       dim3(256), 0, s, d_jobs);
 }
 
 int DpGeom::cover(int W) const
@@ -1213,8 +1497,11 @@ int DpGeom::threads(int Wmax) const
     return ((t + 63) / 64) * 64;
 }
 
-// Banded variants (Q columns per lane, HB halo columns = rows per band).
-const DpGeom kDpVariants[] = {{2, 8, 1}, {4, 8, 1}, {4, 16, 1}, {8, 16, 1}, {8, 32, 1}, {16, 32, 1}, {16, 64, 1}};
+// Banded variants (Q columns per lane, HB halo columns = rows per band, PF
+// rows of key prefetch); for each (Q, HB) the first listed PF is the default.
+const DpGeom kDpVariants[] = {{2, 8, 1, 8, 0},  {2, 8, 1, 16, 0},  {4, 8, 1, 8, 0},   {4, 8, 1, 16, 0},
+                              {4, 16, 1, 8, 0}, {4, 16, 1, 16, 0}, {8, 16, 1, 4, 0},  {8, 16, 1, 8, 0},
+                              {8, 32, 1, 4, 0}, {16, 32, 1, 2, 0}, {16, 64, 1, 2, 0}};
 const int kNumDpVariants = (int)(sizeof(kDpVariants) / sizeof(kDpVariants[0]));
 
 bool dp_geom_fits(const DpGeom &g, int Wmax)
@@ -1227,42 +1514,49 @@ DpGeom dp_geom(int Wmax)
 {
     // defaults: the fewest wavefronts that cover the width with balanced
     // SIMDs; the autotuner may replace them
-    if (Wmax <= 448) return DpGeom{2, 8, 1};
-    if (Wmax <= 1920) return DpGeom{4, 8, 1};
-    if (Wmax <= 3840) return DpGeom{8, 16, 1};
-    if (Wmax <= 7680) return DpGeom{16, 32, 1};
-    if (Wmax <= 8960) return DpGeom{16, 64, 1};
-    return DpGeom{32, 0, 0};
+    if (Wmax <= 448) return DpGeom{2, 8, 1, 8, 0};
+    if (Wmax <= 1920) return DpGeom{4, 8, 1, 8, 0};
+    if (Wmax <= 3840) return DpGeom{8, 16, 1, 4, 0};
+    if (Wmax <= 7680) return DpGeom{16, 32, 1, 2, 0};
+    if (Wmax <= 8960) return DpGeom{16, 64, 1, 2, 0};
+    return DpGeom{32, 0, 0, 2, 0};
 }
+
+size_t g_dp_lds_cap = 65536;  // LDS of one compute unit as a workgroup may request it
 
 void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s)
 {
     const dim3 grid(njobs), block(g.threads(Wmax));
     // two ping-pong rows of keys: the widest job's key row less its left pad
-    const size_t lds = (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t);
+    size_t lds = g.banded ? (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t) : 0;
+    if (g.EX && lds < g_dp_lds_cap) lds = g_dp_lds_cap;
     if (!g.banded) {
-        hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);
+        hipLaunchKernelGGL(dp_kernel<32>, grid, block, lds, s, d_jobs, r);
         return;
     }
-#define SCPL_DP_CASE(q, hb)                                                                 \
-    if (g.Q == q && g.HB == hb) {                                                           \
-        hipLaunchKernelGGL((dp_band_kernel<q, hb>), grid, block, lds, s, d_jobs, r);        \
+#define SCPL_DP_CASE(q, hb, pf)                                                             \
+    if (g.Q == q && g.HB == hb && g.PF == pf) {                                             \
+        hipLaunchKernelGGL((dp_band_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, r);    \
         return;                                                                             \
     }
-    SCPL_DP_CASE(2, 8)
-    SCPL_DP_CASE(4, 8)
-    SCPL_DP_CASE(4, 16)
-    SCPL_DP_CASE(8, 16)
-    SCPL_DP_CASE(8, 32)
-    SCPL_DP_CASE(16, 32)
-    SCPL_DP_CASE(16, 64)
+    SCPL_DP_CASE(2, 8, 8)
+    SCPL_DP_CASE(2, 8, 16)
+    SCPL_DP_CASE(4, 8, 8)
+    SCPL_DP_CASE(4, 8, 16)
+    SCPL_DP_CASE(4, 16, 8)
+    SCPL_DP_CASE(4, 16, 16)
+    SCPL_DP_CASE(8, 16, 4)
+    SCPL_DP_CASE(8, 16, 8)
+    SCPL_DP_CASE(8, 32, 4)
+    SCPL_DP_CASE(16, 32, 2)
+    SCPL_DP_CASE(16, 64, 2)
 #undef SCPL_DP_CASE
     hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);  // unreachable for valid geometries
 }
 
 // Deterministic pseudo-random key rows for the autotuner (xorshift of the
 // position; values 0..7650).
-__global__ void tune_fill_kernel(uint32_t *K, int H, int W, int Kp, int KL)
+__global__ void tune_fill_kernel(uint16_t *K, int H, int W, int Kp, int KL)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
@@ -1271,10 +1565,10 @@ __global__ void tune_fill_kernel(uint32_t *K, int H, int W, int Kp, int KL)
     x ^= x << 13;
     x ^= x >> 17;
     x ^= x << 5;
-    K[(size_t)i * Kp + KL + j] = (x % 7651u) << 2;
+    K[(size_t)i * Kp + KL + j] = (uint16_t)((x % 7651u) << 2);
 }
 
-void launch_tune_fill(uint32_t *K, int H, int W, int Kp, int KL, hipStream_t s)
+void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s)
 {
     hipLaunchKernelGGL(tune_fill_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, K, H, W, Kp, KL);
 }
@@ -1295,6 +1589,15 @@ size_t select_lds_bytes(size_t lds_cap) { return lds_cap; }
 
 void set_kernel_attributes(size_t lds_cap)
 {
+    g_dp_lds_cap = lds_cap;
+    const void *dps[] = {
+        reinterpret_cast<const void *>(&dp_kernel<32>),          reinterpret_cast<const void *>(&dp_band_kernel<2, 8, 8>),
+        reinterpret_cast<const void *>(&dp_band_kernel<2, 8, 16>), reinterpret_cast<const void *>(&dp_band_kernel<4, 8, 8>),
+        reinterpret_cast<const void *>(&dp_band_kernel<4, 8, 16>), reinterpret_cast<const void *>(&dp_band_kernel<4, 16, 8>),
+        reinterpret_cast<const void *>(&dp_band_kernel<4, 16, 16>), reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 4>),
+        reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 8>), reinterpret_cast<const void *>(&dp_band_kernel<8, 32, 4>),
+        reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 2>), reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 2>)};
+    for (const void *f : dps) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
 }
@@ -1309,10 +1612,11 @@ void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s)
     hipLaunchKernelGGL(jump_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, r);
 }
 
-void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int, hipStream_t s)
+void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s)
 {
     const int gx = kmax < 1024 ? kmax : 1024;
-    hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), 0, s, d_jobs, r);
+    const size_t lds = (size_t)Bmax * (2 * Bmax + 8);
+    hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), lds, s, d_jobs, r);
 }
 
 void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int, hipStream_t s)
@@ -1325,18 +1629,25 @@ void launch_refresh(const Job *d_jobs, int njobs, int r, int, int Hmax, hipStrea
     hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for(Hmax, kRefreshRows), njobs), dim3(256), 0, s, d_jobs, r);
 }
 
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, hipStream_t s)
+size_t gather_lds_bytes(int W, int Wt, int C)
 {
-    hipLaunchKernelGGL(gather_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs);
+    const size_t inb = (size_t)W * C, outb = (size_t)Wt * C;
+    if (inb > (size_t)kGatherIn || outb > (size_t)kGatherOut) return 0;
+    return ((inb + 15) & ~(size_t)15) + 2 * outb;
 }
 
-void launch_u_to_keys(const int32_t *src, uint32_t *dst, int H, int W, int pitch, hipStream_t s)
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_kernel, dim3(Hmax, njobs), dim3(256), lds, s, d_jobs);
+}
+
+void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s)
 {
     hipLaunchKernelGGL(u_to_keys_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);
 }
 
-void launch_keys_to_u(const uint32_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s)
+void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s)
 {
     hipLaunchKernelGGL(keys_to_u_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);

@@ -36,10 +36,11 @@ EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_dp_geometry",
-    "scpl_autotune_dp",
+    "scpl_autotune_dp", "scpl_batch_streams",
 ]
 
-DP_GEOMETRIES = [(2, 8), (4, 8), (4, 16), (8, 16), (8, 32), (16, 32), (16, 64), (32, 0)]
+DP_GEOMETRIES = [(2, 8, 8), (2, 8, 16), (4, 8, 8), (4, 8, 16), (4, 16, 8), (4, 16, 16), (8, 16, 4), (8, 16, 8),
+                 (8, 32, 4), (16, 32, 2), (16, 64, 2), (32, 0, 2)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
@@ -72,8 +73,10 @@ _sig = {
     "scpl_segment": ([_P, C.POINTER(scpl_params), _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_profile_enable": ([_P, _I32], C.c_int),
     "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
-    "scpl_dp_geometry": ([_P, _I32, _I32], C.c_int),
-    "scpl_autotune_dp": ([_P, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(C.c_double)], C.c_int),
+    "scpl_dp_geometry": ([_P, _I32, _I32, _I32, _I32], C.c_int),
+    "scpl_batch_streams": ([_P, _I32], C.c_int),
+    "scpl_autotune_dp": ([_P, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
+                          C.POINTER(_I32), C.POINTER(C.c_double)], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -208,6 +211,11 @@ class Context:
         _check(scpl_last_log(self.h, a.ctypes.data, n.value, C.byref(n)), "scpl_last_log")
         return a[:n.value]
 
+    def batch_streams(self, n: int) -> None:
+        """Number of independently advancing job groups (streams) of the
+        batched path."""
+        _check(scpl_batch_streams(self.h, n), "scpl_batch_streams")
+
     # ---------------------------------------------------------- timing
     def profile(self, on: bool = True) -> None:
         """Start (and reset) or stop per-kernel event timing."""
@@ -223,16 +231,19 @@ class Context:
         return out
 
     # ---------------------------------------------------------- DP geometry
-    def dp_geometry(self, Q: int = 0, HB: int = 0) -> None:
-        """Force the DP geometry (Q columns per lane, HB halo); Q = 0: automatic."""
-        _check(scpl_dp_geometry(self.h, Q, HB), "scpl_dp_geometry")
+    def dp_geometry(self, Q: int = 0, HB: int = 0, PF: int = 0, EX: int = 0) -> None:
+        """Force the DP geometry (Q columns per lane, HB halo, PF prefetch
+        rows, PF = 0: default depth; EX = 1: one DP workgroup per compute
+        unit and nothing beside it); Q = 0: automatic."""
+        _check(scpl_dp_geometry(self.h, Q, HB, PF, EX), "scpl_dp_geometry")
 
-    def autotune_dp(self, H: int, W: int):
-        """Time every DP geometry for an H x W frame; keep the fastest.
-        Returns (Q, HB, microseconds per launch)."""
-        q, hb, us = C.c_int32(0), C.c_int32(0), C.c_double(0)
-        _check(scpl_autotune_dp(self.h, H, W, C.byref(q), C.byref(hb), C.byref(us)), "scpl_autotune_dp")
-        return int(q.value), int(hb.value), float(us.value)
+    def autotune_dp(self, H: int, W: int, n_jobs: int = 1):
+        """Time every DP geometry on launches of n_jobs H x W jobs; keep the
+        fastest.  Returns (Q, HB, PF, EX, microseconds per launch)."""
+        q, hb, pf, ex, us = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_double(0)
+        _check(scpl_autotune_dp(self.h, H, W, n_jobs, C.byref(q), C.byref(hb), C.byref(pf), C.byref(ex),
+                                C.byref(us)), "scpl_autotune_dp")
+        return int(q.value), int(hb.value), int(pf.value), int(ex.value), float(us.value)
 
     # ---------------------------------------------------------- stages
     def luma(self, rgb, stream=None):

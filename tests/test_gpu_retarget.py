@@ -85,7 +85,8 @@ def test_degenerate(ctx, orc, shape, Wt, k):
     compare(ctx, orc, clip, Wt, k)
 
 
-def test_batch_equals_oracle_and_plain(ctx, orc):
+@pytest.mark.parametrize("nstreams", [1, 2, 3, 8])
+def test_batch_equals_oracle_and_plain(ctx, orc, nstreams):
     clips = [
         dict(frames=synth.make_clip(500, 12, 40, 90, C=3, n_obj=3, cut_at=6, lattice=8), target_width=70,
              seams_per_iter=4),
@@ -98,8 +99,12 @@ def test_batch_equals_oracle_and_plain(ctx, orc):
     for c in clips:
         c["frames"] = dev(c["frames"])
         c["want_masks"] = True
-    ctx.retarget_batch(clips)
-    torch.cuda.synchronize()
+    ctx.batch_streams(nstreams)
+    try:
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+    finally:
+        ctx.batch_streams(2)
     for c, fr in zip(clips, host):
         kw = dict(mode=c.get("energy_mode", 1), use_buffer=c.get("use_buffer", 1), anum=c.get("alpha_num", 1),
                   aden=c.get("alpha_den", 5))
@@ -189,7 +194,7 @@ def test_4k_clip_full_size(ctx, orc, alpha):
     check_full_size(orc, frames, res, 2880, 32, 1, alpha[0], alpha[1], n_first=1)
 
 
-@pytest.mark.parametrize("geom", [(4, 16), (8, 16), (8, 32), (32, 0)])
+@pytest.mark.parametrize("geom", [(4, 8, 16, 1), (4, 16, 8, 0), (8, 16, 8, 1), (8, 32, 4, 0), (32, 0, 2, 1)])
 def test_forced_geometry_retarget(ctx, orc, geom):
     clip = synth.make_clip(610, 8, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
     ctx.dp_geometry(*geom)

@@ -55,8 +55,10 @@ DP_SHAPES = [(1, 1), (1, 7), (7, 1), (3, 2), (37, 1100), (70, 2500), (130, 65), 
              (65, 129), (64, 64), (129, 3), (33, 513), (17, 2240), (45, 4480), (70, 8960), (4, 9500), (3, 20000)]
 
 
+# hi: tie-heavy energies, the motion energy's maximum, and the largest U the
+# 16-bit key rows hold (columns past the width must still never win)
 @pytest.mark.parametrize("shape", DP_SHAPES)
-@pytest.mark.parametrize("hi", [3, 7650])
+@pytest.mark.parametrize("hi", [3, 7650, 16382])
 def test_dp(ctx, orc, shape, hi):
     rng = np.random.default_rng(shape[0] * 7 + shape[1] + hi)
     u = rng.integers(0, hi + 1, size=shape).astype(np.int32)
@@ -117,12 +119,24 @@ def test_segment_max_buffer_and_off(ctx, orc):
     assert bid.tolist() == list(range(40))
 
 
-GEOMETRIES = [(2, 8), (4, 8), (4, 16), (8, 16), (8, 32), (16, 32), (16, 64), (32, 0)]
+from paper_1903_03180_amd.scpl import DP_GEOMETRIES as GEOMETRIES  # noqa: E402
 
 
-@pytest.mark.parametrize("geom", GEOMETRIES)
+def test_dp_extreme_values_at_the_border(ctx, orc):
+    """U at its maximum next to the right border and zero elsewhere: the
+    0xffff columns past the width sit beside the costliest real column."""
+    for shape in [(50, 1920), (200, 77), (9, 6001)]:
+        u = np.zeros(shape, dtype=np.int32)
+        u[:, -1] = 16382
+        u[::3, -2] = 16382
+        ce, lab, d = ctx.dp(dev(u))
+        oce, olab, od = orc.dp(u)
+        assert np.array_equal(host(ce), oce[-1]) and np.array_equal(host(d), od), shape
+
+
+@pytest.mark.parametrize("geom", [g + (ex,) for g in GEOMETRIES for ex in (0, 1)])
 def test_dp_every_geometry(ctx, orc, geom):
-    """Every DP geometry (columns per lane, halo / band rows) gives the
+    """Every DP geometry (columns per lane, halo / band rows, prefetch) gives the
     oracle's result; widths a geometry cannot hold fall back to the default
     and must agree too."""
     ctx.dp_geometry(*geom)
@@ -140,8 +154,8 @@ def test_dp_every_geometry(ctx, orc, geom):
 
 
 def test_autotune_then_parity(ctx, orc):
-    q, hb, us = ctx.autotune_dp(256, 1920)
-    assert (q, hb) in GEOMETRIES and us > 0
+    q, hb, pf, ex, us = ctx.autotune_dp(256, 1920, n_jobs=3)
+    assert (q, hb, pf) in GEOMETRIES and ex in (0, 1) and us > 0
     rng = np.random.default_rng(3)
     u = rng.integers(0, 7651, size=(90, 1920)).astype(np.int32)
     ce, lab, d = ctx.dp(dev(u))
