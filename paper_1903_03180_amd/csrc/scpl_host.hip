@@ -444,33 +444,39 @@ struct LaunchShape {
     }
 };
 
-void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, int r, const LaunchShape &ls, hipStream_t s)
+// One SCPL iteration of every job of a launch (each job at its own
+// iteration, kept on the device).
+void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchShape &ls, hipStream_t s)
 {
     {
         ProfScope ps(ctx, SCPL_KERNEL_DP, s);
-        launch_dp(d_jobs, nj, r, ls.g, ls.Wmax, s);
+        launch_dp(d_jobs, nj, ls.g, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
-        launch_borg(d_jobs, nj, r, ls.nbmax, ls.Bmax, ls.Wmax, s);
+        launch_borg(d_jobs, nj, ls.nbmax, ls.Bmax, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_SELECT, s);
-        launch_select(d_jobs, nj, r, 0, ctx->lds_cap, s);
+        launch_select(d_jobs, nj, 0, ctx->lds_cap, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_FILL, s);
-        launch_fill(d_jobs, nj, r, ls.kmax, ls.nbmax, ls.Bmax, s);
+        launch_fill(d_jobs, nj, ls.kmax, ls.nbmax, ls.Bmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
-        launch_update(d_jobs, nj, r, ls.Hmax, ls.Wmax, s);
+        launch_update(d_jobs, nj, ls.Hmax, ls.Wmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_REFRESH, s);
-        launch_refresh(d_jobs, nj, r, ls.kmax, ls.Hmax, s);
+        launch_refresh(d_jobs, nj, ls.kmax, ls.Hmax, s);
     }
+    launch_advance(d_jobs, nj, s);
 }
+
+// Iterations per replay of a group's graph.
+constexpr int kGraphIters = 8;
 
 // A group of jobs that advances in lock-step on one stream: every stage of
 // an iteration is one launch over the group's jobs.  Groups on different
@@ -506,8 +512,22 @@ scpl_status group_readback(Group &G)
     return SCPL_OK;
 }
 
-// Initial key rows, then the first rfirst iterations (captured into a graph
-// when use_graph), then a state read-back.
+// Enqueues at least n more iterations of the group: whole replays of its
+// graph, or single launches when there is none (profiling, or a stream that
+// cannot be captured).
+scpl_status group_iterate(scpl_ctx *ctx, Group &G, int n)
+{
+    if (G.ge) {
+        for (int q = 0; q < n; q += kGraphIters, G.r += kGraphIters) SCPL_TRY(hipGraphLaunch(G.ge, G.st));
+        return SCPL_OK;
+    }
+    for (int q = 0; q < n; ++q, ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.ls, G.st);
+    SCPL_CHECK_LAUNCH();
+    return SCPL_OK;
+}
+
+// Initial key rows, a graph of kGraphIters iterations (when use_graph), the
+// first rfirst iterations, then a state read-back.
 scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
 {
     const hipStream_t s = G.st;
@@ -522,17 +542,14 @@ scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
     SCPL_CHECK_LAUNCH();
     if (use_graph && !ctx->profiling && s != nullptr && G.rfirst > 0) {
         SCPL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (; G.r < G.rfirst; ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, s);
+        for (int q = 0; q < kGraphIters; ++q) enqueue_iteration(ctx, G.d_jobs, G.nj, G.ls, s);
         hipError_t le = hipGetLastError();
         hipError_t ce = hipStreamEndCapture(s, &G.g);
         SCPL_TRY(le);
         SCPL_TRY(ce);
         SCPL_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
-        SCPL_TRY(hipGraphLaunch(G.ge, s));
-    } else {
-        for (; G.r < G.rfirst; ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, s);
-        SCPL_CHECK_LAUNCH();
     }
+    SCPL_TRY(group_iterate(ctx, G, G.rfirst));
     return group_readback(G);
 }
 
@@ -542,7 +559,6 @@ scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
 // width and last k_iter call for.
 scpl_status group_advance(scpl_ctx *ctx, Group &G)
 {
-    G.release();  // the graph's launch precedes the completed read-back
     bool all = true;
     int more = 1;
     for (int j = 0; j < G.nj; ++j) {
@@ -562,9 +578,8 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
         G.done = true;
         return SCPL_OK;
     }
-    if (G.r > G.ls.Wmax + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
-    for (int q = 0; q < more; ++q, ++G.r) enqueue_iteration(ctx, G.d_jobs, G.nj, G.r, G.ls, G.st);
-    SCPL_CHECK_LAUNCH();
+    if (G.r > G.ls.Wmax + kGraphIters + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
+    SCPL_TRY(group_iterate(ctx, G, more));
     return group_readback(G);
 }
 
@@ -1048,8 +1063,8 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, H, W, s);
     launch_u_to_keys(d_u, J.K0 + J.KL, H, W, J.Kp, s);
-    launch_dp(d_job, 1, 0, ls.g, W, s);
-    launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
+    launch_dp(d_job, 1, ls.g, W, s);
+    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);
     launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);
     SCPL_CHECK_LAUNCH();
@@ -1077,7 +1092,7 @@ scpl_status scpl_select(scpl_ctx *ctx, int32_t W, const int32_t *d_ce_last, cons
     launch_init_jobs(d_job, 1, H, W, s);
     SCPL_TRY(hipMemcpyAsync(J.ce_last, d_ce_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
     SCPL_TRY(hipMemcpyAsync(J.lab_last, d_label_last, (size_t)W * 4, hipMemcpyDeviceToDevice, s));
-    launch_select(d_job, 1, 0, 1, ctx->lds_cap, s);
+    launch_select(d_job, 1, 1, ctx->lds_cap, s);
     SCPL_CHECK_LAUNCH();
     int32_t rec[4];
     SCPL_TRY(hipMemcpyAsync(rec, J.log, 16, hipMemcpyDeviceToHost, s));
@@ -1115,10 +1130,10 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     SCPL_TRY(hipMemcpyAsync(J.log, h, 16, hipMemcpyHostToDevice, s));
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, kk, select_geom(ctx, W)});
-    launch_borg(d_job, 1, 0, ls.nbmax, ls.Bmax, W, s);
-    launch_jump_only(d_job, 1, 0, s);
-    launch_fill(d_job, 1, 0, kk, ls.nbmax, ls.Bmax, s);
-    launch_i16_to_i32(J.seams, d_seams, (int64_t)kk * H, s);
+    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
+    launch_jump_only(d_job, 1, s);
+    launch_fill(d_job, 1, kk, ls.nbmax, ls.Bmax, s);
+    launch_seams_out(J.seams, J.kcap, d_seams, kk, H, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));
     return SCPL_OK;
@@ -1195,10 +1210,10 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
         SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
         launch_init_jobs(d_job, n_jobs, H, W, s);
         for (int q = 0; q < n_jobs; ++q) launch_tune_fill(h[q].K0, H, W, h[q].Kp, h[q].KL, s);
-        launch_dp(d_job, n_jobs, 0, g, W, s);  // warm-up
+        launch_dp(d_job, n_jobs, g, W, s);  // warm-up
         const int reps = 5;
         SCPL_TRY(hipEventRecord(e0, s));
-        for (int q = 0; q < reps; ++q) launch_dp(d_job, n_jobs, 0, g, W, s);
+        for (int q = 0; q < reps; ++q) launch_dp(d_job, n_jobs, g, W, s);
         SCPL_TRY(hipEventRecord(e1, s));
         SCPL_TRY(hipEventSynchronize(e1));
         SCPL_CHECK_LAUNCH();

@@ -67,10 +67,10 @@ struct Job {
     uint64_t *keys;         // 2 x Wp scratch for the selection
     int32_t *children;      // kcap
     int32_t *bcol;          // kcap x nb: seam column at the last row of each band
-    int16_t *seams;         // kcap x H
+    int16_t *seams;         // H x kcap: columns of the seams in each row, increasing
     int32_t *log;           // logcap x 4: (W_r, P_eff, k_iter, 0)
     int32_t *state;         // [0]: iteration at which W_r reached Wt (-1 while running),
-                            // [1]: current W_r, [2]: last k_iter
+                            // [1]: current W_r, [2]: last k_iter, [3]: current iteration
 };
 
 struct SegArgs {
@@ -113,21 +113,24 @@ bool dp_geom_fits(const DpGeom &g, int Wmax);
 extern const DpGeom kDpVariants[];
 extern const int kNumDpVariants;
 constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
-void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s);
+void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStream_t s);
 void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s);
-void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s);
-void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s);
+void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s);
+void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s);
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
-void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s);
-void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s);
-void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int Wmax, hipStream_t s);
-void launch_refresh(const Job *d_jobs, int njobs, int r, int kmax, int Hmax, hipStream_t s);
+void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s);
+void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s);
+void launch_update(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
+void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, hipStream_t s);
+// end of an iteration: each job still carving moves to its next iteration
+void launch_advance(const Job *d_jobs, int njobs, hipStream_t s);
 // LDS of the gather for a job (0: the job gathers directly from global memory)
 size_t gather_lds_bytes(int W, int Wt, int C);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
-void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s);
+// row-major seams (H x pitch int16) -> kk x H int32
+void launch_seams_out(const int16_t *src, int pitch, int32_t *dst, int kk, int H, hipStream_t s);
 // indicator codes <-> int8 {-1, 0, 1} with pitch change (stage entry points)
 void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s);
 void launch_dir_in(const int8_t *src, uint8_t *codes, int pitch, int H, int W, hipStream_t s);

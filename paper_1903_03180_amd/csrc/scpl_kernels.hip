@@ -27,6 +27,12 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int job_width(const Job &J, int r) { return r < J.logcap ? J.log[4 * r] : J.Wt; }
 
+// The job's current iteration: every kernel of an iteration reads it from
+// the job's state, and advance_kernel moves it on after the iteration's last
+// kernel, so that each job advances at its own pace and a fixed sequence of
+// launches (a graph) can be replayed for any number of iterations.
+__device__ __forceinline__ int job_iter(const Job &J) { return J.state[3]; }
+
 // Global-address-space views of pointers held in job descriptors.  Loads
 // through generic pointers compile to flat instructions, which also count
 // against the LDS wait counter, so every wait for an LDS access would drain
@@ -423,6 +429,7 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
         J.state[0] = J.W <= J.Wt ? 0 : -1;
         J.state[1] = J.W;
         J.state[2] = 0;
+        J.state[3] = 0;
     }
 }
 
@@ -622,10 +629,11 @@ __device__ __forceinline__ void dp_step(uint32_t (&key)[Q], uint32_t lnb, uint32
 // Row-synchronous DP for the widest frames: every row, the two
 // wavefront-edge keys cross through LDS and the block meets at a barrier.
 template <int Q>
-__global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs)
 {
     constexpr int PF = DpPrefetch<Q>::PF;
     const Job &J = jobs[blockIdx.x];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     __shared__ uint32_t eL[2][16], eR[2][16];
@@ -705,12 +713,13 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs, int r)
 // block meets at one barrier, and the halo lanes take the neighbours' keys.
 // Only owned columns store indicator codes.
 template <int Q, int HB, int PF>
-__global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs)
 {
     constexpr int C = 64 * Q - 2 * HB;
     static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
     extern __shared__ uint32_t rowbuf[];  // 2 x (Kp - KL) keys
     const Job &J = jobs[blockIdx.x];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -828,10 +837,11 @@ __device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *
     return c0 - a0;
 }
 
-__global__ __launch_bounds__(kBorgCols) void borg_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(kBorgCols) void borg_kernel(const Job *jobs)
 {
     extern __shared__ uint8_t tile[];  // B rows x (kBorgCols + 2B + 8) bytes
     const Job &J = jobs[blockIdx.z];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int b = blockIdx.y;
@@ -891,11 +901,12 @@ __device__ void band_jumps(const Job &J, int kk, const int8_t *bo, int bo_pitch,
     }
 }
 
-__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, int lds_bytes, int use_lab_array)
+__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_bytes, int use_lab_array)
 {
     extern __shared__ uint64_t dsm[];
     __shared__ int scan_tmp[16];
     const Job &J = jobs[blockIdx.x];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     const int tid = threadIdx.x;
     if (Wr <= J.Wt) {
@@ -984,9 +995,10 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int r, in
 
 // Band jumps alone, for the backtrack stage entry point (children and
 // k_iter already in place).
-__global__ __launch_bounds__(256) void jump_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(256) void jump_kernel(const Job *jobs)
 {
     const Job &J = jobs[blockIdx.x];
+    const int r = job_iter(J);
     band_jumps(J, J.log[4 * r + 2], J.borg, J.Wp, threadIdx.x, 256);
 }
 
@@ -998,11 +1010,12 @@ __global__ __launch_bounds__(256) void jump_kernel(const Job *jobs, int r)
 // marks the removed pixels (original columns, via the column map) in the
 // buffer mask with the iteration number + 1.
 
-__global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 {
     extern __shared__ uint8_t tile[];  // B - 1 rows x (2 B + 8) bytes of the launch's largest B
     __shared__ int16_t path[kBandMax];
     const Job &J = jobs[blockIdx.z];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int kk = J.log[4 * r + 2];
@@ -1030,7 +1043,7 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
         for (int rr = lane; rr <= span; rr += 64) {
             const int i = lo + rr;
             const int x = path[rr];
-            J.seams[(size_t)s * H + i] = (int16_t)x;
+            J.seams[(size_t)i * J.kcap + s] = (int16_t)x;
             J.bmask[(size_t)i * J.W + mcol(M + (size_t)i * J.Wp, x, J.W)] = (uint16_t)(r + 1);
         }
         __syncthreads();
@@ -1051,114 +1064,78 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs, int r)
 // neighbourhood around its new position holds the same original pixels as
 // the one around its old position, all its energies -- hence its key -- are
 // unchanged and move with it; otherwise they are recomputed from the T
-// frames.  This is exact: the result equals a full recomputation.  One
-// block per row: the old maps of rows i-1..i+1 are staged in LDS and their
-// new maps built there; the affected pixels of the row (a few per seam) are
-// collected and each gets a share of the block's threads, which split the
-// T frames between them.
+// frames (refresh_kernel).  This is exact: the result equals a full
+// recomputation.
 
-__device__ __forceinline__ int source_column(int j, int kk, const int *R, const int16_t *seams_row_major, int H)
+// One wavefront per row, four rows per block, no block barriers: each lane
+// builds 8 consecutive new columns (the count of seams left of them found
+// once, then stepped), gathers their old entries straight from global memory
+// (neighbouring lanes read neighbouring columns) and writes them with two
+// 16-byte stores.
+constexpr int kUpdRows = 4;
+
+__global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
 {
-    int a = 0, b = kk;
-    while (a < b) {
-        const int m = (a + b) >> 1;
-        const int v = R ? R[m] : (seams_row_major[(size_t)m * H] - m);
-        if (v <= j) a = m + 1;
-        else b = m;
-    }
-    return j + a;
-}
-
-// Output columns per pass of the staged compaction, and the seams a row may
-// lose for the staged form (more take the direct form).
-constexpr int kUpdChunk = 2048;
-constexpr int kUpdSeams = 256;
-
-__global__ __launch_bounds__(256) void update_kernel(const Job *jobs, int r)
-{
-    __shared__ int R[kUpdSeams];  // seams of row i: old column - s (when k_iter <= kUpdSeams)
-    __shared__ __align__(16) uint16_t Ks[kUpdChunk + kUpdSeams + 2];
-    __shared__ __align__(16) int16_t Ms[kUpdChunk + kUpdSeams + 2];
     const Job &J = jobs[blockIdx.y];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
-    const int i = blockIdx.x;
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kUpdRows + (int)(threadIdx.x >> 6));
     if (i >= J.H) return;
+    const int lane = threadIdx.x & 63;
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
-    const int H = J.H, Wp = J.Wp;
+    const int Wp = J.Wp;
     const int16_t *__restrict__ Mo = ((r & 1) ? J.M1 : J.M0) + (size_t)i * Wp;
     int16_t *__restrict__ Mw = ((r & 1) ? J.M0 : J.M1) + (size_t)i * Wp;
     const uint16_t *__restrict__ Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
     uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
     const bool keys = Wn > J.Wt;  // a further iteration reads the keys
-    const int tid = threadIdx.x;
-    if (kk > kUpdSeams) {
-        // direct form: every pixel of the row moves to its new column with its key
-        for (int j = tid; j < Wn; j += 256) {
-            const int src = source_column(j, kk, nullptr, J.seams + i, H);
-            Mw[j] = Mo[src];
-            if (keys) Kn[j] = Ko[src];
+    const int16_t *__restrict__ R = J.seams + (size_t)i * J.kcap;  // removed columns of row i, increasing
+    // seam s removed old column R[s]; new column j reads old column j + #{s : R[s] - s <= j}
+    auto rs = [&](int s) -> int { return s < kk ? (int)R[s] - s : 0x7fffffff; };
+    for (int j0 = 0; j0 < Wn; j0 += 512) {
+        const int jb = j0 + 8 * lane;
+        int a = 0;
+        if (kk <= 32) {
+            for (int s = 0; s < kk; ++s) a += rs(s) <= jb ? 1 : 0;  // uniform loads
+        } else {
+            int hi = kk;
+            while (a < hi) {
+                const int m = (a + hi) >> 1;
+                if (rs(m) <= jb) a = m + 1;
+                else hi = m;
+            }
         }
-    } else {
-        for (int s = tid; s < kk; s += 256) R[s] = J.seams[(size_t)s * H + i] - s;
-        // staged form: per chunk of output columns [j0, j1), the old columns
-        // [s0, s1) they come from are loaded into LDS with coalesced loads,
-        // then each thread builds 8 consecutive new columns and stores them
-        // with vector stores
-        for (int j0 = 0; j0 < Wn; j0 += kUpdChunk) {
-            const int j1 = min(j0 + kUpdChunk, Wn);
-            __syncthreads();  // R ready; the previous chunk's LDS reads are done
-            const int s0 = source_column(j0, kk, R, nullptr, H);
-            const int s1 = source_column(j1 - 1, kk, R, nullptr, H) + 1;  // <= s0 + kUpdChunk + kk
-            const int m0 = s0 & ~1;  // staged from an even column: 32-bit loads of column pairs
-            const int mw = (s1 - m0) >> 1;  // whole pairs inside [m0, s1)
-            for (int x = tid; x < mw; x += 256) {
-                reinterpret_cast<uint32_t *>(Ms)[x] = gp(reinterpret_cast<const uint32_t *>(Mo + m0))[x];
-                if (keys) reinterpret_cast<uint32_t *>(Ks)[x] = gp(reinterpret_cast<const uint32_t *>(Ko + m0))[x];
-            }
-            if (tid == 0 && ((s1 - m0) & 1)) {
-                Ms[s1 - 1 - m0] = Mo[s1 - 1];
-                if (keys) Ks[s1 - 1 - m0] = Ko[s1 - 1];
-            }
-            __syncthreads();
-            const int jb = j0 + 8 * tid;
-            if (jb < j1) {
-                int a = source_column(jb, kk, R, nullptr, H) - jb;
-                int16_t mv[8];
-                uint16_t kv[8];
+        if (jb >= Wn) continue;
+        int nxt = rs(a);
+        uint32_t mv[8], kv[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int j = jb + q;
-                    while (a < kk && R[a] <= j) ++a;
-                    const int src = min(j + a, s1 - 1);  // lanes past j1 read a valid slot, never stored
-                    mv[q] = Ms[src - m0];
-                    kv[q] = Ks[src - m0];
-                }
-                if (jb + 8 <= j1) {
-                    const u32x4 mo{(uint16_t)mv[0] | ((uint32_t)(uint16_t)mv[1] << 16),
-                                   (uint16_t)mv[2] | ((uint32_t)(uint16_t)mv[3] << 16),
-                                   (uint16_t)mv[4] | ((uint32_t)(uint16_t)mv[5] << 16),
-                                   (uint16_t)mv[6] | ((uint32_t)(uint16_t)mv[7] << 16)};
-                    *gp(reinterpret_cast<u32x4 *>(Mw + jb)) = mo;
-                    if (keys)
-                        *gp(reinterpret_cast<u32x4 *>(Kn + jb)) =
-                            u32x4{kv[0] | ((uint32_t)kv[1] << 16), kv[2] | ((uint32_t)kv[3] << 16),
-                                  kv[4] | ((uint32_t)kv[5] << 16), kv[6] | ((uint32_t)kv[7] << 16)};
-                } else {
-                    for (int q = 0; q < 8 && jb + q < j1; ++q) {
-                        Mw[jb + q] = mv[q];
-                        if (keys) Kn[jb + q] = kv[q];
-                    }
-                }
+        for (int q = 0; q < 8; ++q) {
+            const int j = jb + q;
+            while (nxt <= j) nxt = rs(++a);
+            const int src = min(j + a, Wr - 1);  // columns past Wn read a valid entry, never stored
+            mv[q] = (uint16_t)Mo[src];
+            kv[q] = keys ? Ko[src] : 0u;
+        }
+        if (jb + 8 <= Wn) {
+            *gp(reinterpret_cast<u32x4 *>(Mw + jb)) =
+                u32x4{mv[0] | (mv[1] << 16), mv[2] | (mv[3] << 16), mv[4] | (mv[5] << 16), mv[6] | (mv[7] << 16)};
+            if (keys)
+                *gp(reinterpret_cast<u32x4 *>(Kn + jb)) = u32x4{kv[0] | (kv[1] << 16), kv[2] | (kv[3] << 16),
+                                                                kv[4] | (kv[5] << 16), kv[6] | (kv[7] << 16)};
+        } else {
+            for (int q = 0; q < 8 && jb + q < Wn; ++q) {
+                Mw[jb + q] = (int16_t)mv[q];
+                if (keys) Kn[jb + q] = (uint16_t)kv[q];
             }
         }
     }
     if (!keys) return;
-    // the keys of the vacated columns become all ones; columns beyond the
+    // the keys of the vacated columns become 0xffff; columns beyond the
     // previous width of this buffer already are
     const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
-    for (int j = Wn + tid; j < wprev; j += 256) Kn[j] = kRowInf;
+    for (int j = Wn + lane; j < wprev; j += 64) Kn[j] = kRowInf;
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -1183,7 +1160,7 @@ constexpr int kRefreshRows = 16;
 constexpr int kRefreshList = 512;
 constexpr int kRefreshSeams = 64;  // seams whose positions are staged in LDS
 
-__global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
+__global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
 {
     __shared__ int R[kRefreshRows + 2][kRefreshSeams];  // rows i0-1 .. i0+16 (clamped): old column - s
     __shared__ int flist[kRefreshList];                 // (row in band << 16) | new column
@@ -1191,6 +1168,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
     __shared__ uint32_t fsum[kRefreshList];
     __shared__ int nf;
     const Job &J = jobs[blockIdx.y];
+    const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int kk = J.log[4 * r + 2];
@@ -1210,13 +1188,13 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
         for (int idx = tid; idx < (nrows + 2) * kk; idx += 256) {
             const int ss = idx / (nrows + 2), rr = idx - ss * (nrows + 2);  // consecutive threads: same seam
             const int row = min(max(i0 - 1 + rr, 0), H - 1);
-            R[rr][ss] = J.seams[(size_t)ss * H + row] - ss;
+            R[rr][ss] = J.seams[(size_t)row * J.kcap + ss] - ss;
         }
     __syncthreads();
     // seam positions (old column - rank) of row `row` (absolute, clamped)
     auto rsd = [&](int row, int ss) -> int {
         row = min(max(row, 0), H - 1);
-        return rl ? R[row - (i0 - 1)][ss] : (int)J.seams[(size_t)ss * H + row] - ss;
+        return rl ? R[row - (i0 - 1)][ss] : (int)J.seams[(size_t)row * J.kcap + ss] - ss;
     };
     // old column of new column c in row `row`
     auto oldcol = [&](int row, int c) -> int {
@@ -1306,6 +1284,17 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs, int r)
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
         Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
     }
+}
+
+// End of an iteration: every job still carving moves on to its next
+// iteration.
+__global__ __launch_bounds__(256) void advance_kernel(const Job *jobs, int njobs)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= njobs) return;
+    const Job &J = jobs[q];
+    const int r = job_iter(J);
+    if (job_width(J, r) > J.Wt) J.state[3] = r + 1;
 }
 
 // ----------------------------------------------------------------- gather
@@ -1416,10 +1405,13 @@ __global__ void keys_to_u_kernel(const uint16_t *src, int32_t *dst, int H, int W
     dst[p] = (int32_t)(src[(size_t)i * pitch + j] >> 2);
 }
 
-__global__ void i16_to_i32_kernel(const int16_t *src, int32_t *dst, int64_t n)
+// seams (row-major, H x pitch) -> kk x H int32
+__global__ void seams_out_kernel(const int16_t *src, int pitch, int32_t *dst, int kk, int H)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p < n) dst[p] = src[p];
+    if (p >= (int64_t)kk * H) return;
+    const int s = (int)(p / H), i = (int)(p - (int64_t)s * H);
+    dst[p] = src[(size_t)i * pitch + s];
 }
 
 __global__ void dir_out_kernel(const uint8_t *codes, int pitch, int8_t *dst, int H, int W)
@@ -1524,19 +1516,19 @@ DpGeom dp_geom(int Wmax)
 
 size_t g_dp_lds_cap = 65536;  // LDS of one compute unit as a workgroup may request it
 
-void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, hipStream_t s)
+void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStream_t s)
 {
     const dim3 grid(njobs), block(g.threads(Wmax));
     // two ping-pong rows of keys: the widest job's key row less its left pad
     size_t lds = g.banded ? (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t) : 0;
     if (g.EX && lds < g_dp_lds_cap) lds = g_dp_lds_cap;
     if (!g.banded) {
-        hipLaunchKernelGGL(dp_kernel<32>, grid, block, lds, s, d_jobs, r);
+        hipLaunchKernelGGL(dp_kernel<32>, grid, block, lds, s, d_jobs);
         return;
     }
 #define SCPL_DP_CASE(q, hb, pf)                                                             \
     if (g.Q == q && g.HB == hb && g.PF == pf) {                                             \
-        hipLaunchKernelGGL((dp_band_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, r);    \
+        hipLaunchKernelGGL((dp_band_kernel<q, hb, pf>), grid, block, lds, s, d_jobs);    \
         return;                                                                             \
     }
     SCPL_DP_CASE(2, 8, 8)
@@ -1551,7 +1543,7 @@ void launch_dp(const Job *d_jobs, int njobs, int r, const DpGeom &g, int Wmax, h
     SCPL_DP_CASE(16, 32, 2)
     SCPL_DP_CASE(16, 64, 2)
 #undef SCPL_DP_CASE
-    hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs, r);  // unreachable for valid geometries
+    hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs);  // unreachable for valid geometries
 }
 
 // Deterministic pseudo-random key rows for the autotuner (xorshift of the
@@ -1573,11 +1565,11 @@ void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s)
     hipLaunchKernelGGL(tune_fill_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, K, H, W, Kp, KL);
 }
 
-void launch_borg(const Job *d_jobs, int njobs, int r, int nbmax, int Bmax, int Wmax, hipStream_t s)
+void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s)
 {
     const size_t lds = (size_t)Bmax * (kBorgCols + 2 * Bmax + 8);
     hipLaunchKernelGGL(borg_kernel, dim3(blocks_for(Wmax, kBorgCols), nbmax, njobs), dim3(kBorgCols), lds, s,
-                       d_jobs, r);
+                       d_jobs);
 }
 
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s)
@@ -1602,31 +1594,36 @@ void set_kernel_attributes(size_t lds_cap)
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
 }
 
-void launch_select(const Job *d_jobs, int njobs, int r, int use_lab_array, size_t lds_cap, hipStream_t s)
+void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(select_kernel, dim3(njobs), dim3(1024), lds_cap, s, d_jobs, r, (int)lds_cap, use_lab_array);
+    hipLaunchKernelGGL(select_kernel, dim3(njobs), dim3(1024), lds_cap, s, d_jobs, (int)lds_cap, use_lab_array);
 }
 
-void launch_jump_only(const Job *d_jobs, int njobs, int r, hipStream_t s)
+void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s)
 {
-    hipLaunchKernelGGL(jump_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, r);
+    hipLaunchKernelGGL(jump_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
 }
 
-void launch_fill(const Job *d_jobs, int njobs, int r, int kmax, int nbmax, int Bmax, hipStream_t s)
+void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s)
 {
     const int gx = kmax < 1024 ? kmax : 1024;
     const size_t lds = (size_t)Bmax * (2 * Bmax + 8);
-    hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), lds, s, d_jobs, r);
+    hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), lds, s, d_jobs);
 }
 
-void launch_update(const Job *d_jobs, int njobs, int r, int Hmax, int, hipStream_t s)
+void launch_update(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(Hmax, njobs), dim3(256), 0, s, d_jobs, r);
+    hipLaunchKernelGGL(update_kernel, dim3(blocks_for(Hmax, kUpdRows), njobs), dim3(256), 0, s, d_jobs);
 }
 
-void launch_refresh(const Job *d_jobs, int njobs, int r, int, int Hmax, hipStream_t s)
+void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for(Hmax, kRefreshRows), njobs), dim3(256), 0, s, d_jobs, r);
+    hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for(Hmax, kRefreshRows), njobs), dim3(256), 0, s, d_jobs);
+}
+
+void launch_advance(const Job *d_jobs, int njobs, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_kernel, dim3(blocks_for(njobs, 256)), dim3(256), 0, s, d_jobs, njobs);
 }
 
 size_t gather_lds_bytes(int W, int Wt, int C)
@@ -1653,9 +1650,10 @@ void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch
                        pitch);
 }
 
-void launch_i16_to_i32(const int16_t *src, int32_t *dst, int64_t n, hipStream_t s)
+void launch_seams_out(const int16_t *src, int pitch, int32_t *dst, int kk, int H, hipStream_t s)
 {
-    hipLaunchKernelGGL(i16_to_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    hipLaunchKernelGGL(seams_out_kernel, dim3(blocks_for((int64_t)kk * H, 256)), dim3(256), 0, s, src, pitch, dst,
+                       kk, H);
 }
 
 void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s)
