@@ -44,25 +44,201 @@ def _gen(args):
 
 
 def make_workload(name):
+    """[(clip, target width, seams per iteration)], description."""
     from multiprocessing import Pool
     if name == "1080p-batch16":
         seeds = list(range(2000, 2016))
         with Pool(8) as pool:
             clips = pool.map(_gen, [("1080p", s) for s in seeds])
-        return clips, 1440, 16, ("16 clips x 120 frames 1920x1080 RGB (1080p generator, seeds 2000-2015) -> 1440 "
-                                 "wide, k=16 seams/iteration, alpha=1/5, motion energy")
+        return [(c, 1440, 16) for c in clips], (
+            "16 clips x 120 frames 1920x1080 RGB (1080p generator, seeds 2000-2015) -> 1440 wide, k=16 "
+            "seams/iteration, alpha=1/5, motion energy")
     if name == "1080p":
-        return [_gen(("1080p", 2))], 1440, 16, ("1080p RGB clip: 120 frames 1920x1080 -> 1440 wide, k=16 "
-                                                "seams/iteration, alpha=1/5, motion energy")
-    return [_gen(("4k", 3))], 2880, 32, ("4K luma clip: 60 frames 3840x2160 -> 2880 wide, k=32 seams/iteration, "
-                                         "alpha=1/5, motion energy")
+        return [(_gen(("1080p", 2)), 1440, 16)], ("1080p RGB clip: 120 frames 1920x1080 -> 1440 wide, k=16 "
+                                                  "seams/iteration, alpha=1/5, motion energy")
+    if name == "mix64":
+        from paper_1903_03180_amd import synth
+        specs = synth.batch_mix_specs(64)
+        with Pool(8) as pool:
+            clips = pool.map(_gen_spec, specs)
+        return [(c, s.Wt, 16) for c, s in zip(clips, specs)], (
+            "64 clips of uneven size (luma, widths 480-2560, heights 360-1440, aspect 1:1-21:9, 30-240 frames, "
+            "seeds 4000-4063) -> 3/4 of the width, k=16 seams/iteration, alpha=1/5, motion energy")
+    return [(_gen(("4k", 3)), 2880, 32)], ("4K luma clip: 60 frames 3840x2160 -> 2880 wide, k=32 seams/iteration, "
+                                           "alpha=1/5, motion energy")
 
 
-def dp_bytes(log_rows, H):
+def _gen_spec(spec):
+    from paper_1903_03180_amd import synth
+    if spec is None:
+        return None
+    if isinstance(spec, tuple):  # ("4k", seed)
+        return synth.clip_4k(spec[1])
+    return synth.clip_from_spec(spec)
+
+
+def serving_pool(n_mix, n_4k):
+    """Requests drawn from the uneven batch mix (luma, widths 480-2560,
+    heights 360-1440, 30-240 frames, target 3/4 of the width) plus 4K jobs
+    (60 frames 3840x2160 luma)."""
+    import multiprocessing as mp
+    from paper_1903_03180_amd import synth
+    specs = synth.batch_mix_specs(n_mix)
+    jobs = list(specs) + [("4k", 5000 + j) for j in range(n_4k)]
+    with mp.get_context("spawn").Pool(8) as pool:  # this process already uses the GPU: fresh workers
+        clips = pool.map(_gen_spec, jobs)
+    wt = [s.Wt for s in specs] + [2880] * n_4k
+    k = [16] * n_mix + [32] * n_4k
+    return clips, wt, k
+
+
+def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=32, fracs=(0.5, 0.8, 0.95), lanes=4, seed=5):
+    """Poisson arrivals of retarget requests at fractions of the measured
+    capacity; p50 / p99 of completion minus arrival, and frames/s."""
+    import time as _t
+    clips_np, wts, ks = serving_pool(n_mix, n_4k)
+    dev = [torch.from_numpy(c).cuda() for c in clips_np]
+    torch.cuda.synchronize()
+    srv = scpl.Server(0, lanes=lanes, max_batch=8)
+
+    def req(q):
+        return dict(frames=dev[q], target_width=wts[q], seams_per_iter=ks[q])
+
+    # capacity: the whole pool submitted at once
+    t0 = _t.perf_counter()
+    ts = [srv.submit(req(q)) for q in range(len(dev))]
+    for t in ts:
+        srv.wait(t)
+        srv.release(t)
+    cap = len(dev) / (_t.perf_counter() - t0)
+    log(f"serving capacity on the pool ({len(dev)} requests): {cap:.2f} requests/s")
+    rng = np.random.default_rng(seed)
+    out = {"capacity_req_per_s": round(cap, 3), "pool": f"{n_mix} clips of the uneven mix + {n_4k} 4K clips",
+           "requests_per_rate": n_req, "lanes": lanes, "rates": []}
+    for f in fracs:
+        lam = f * cap
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+        picks = rng.integers(0, len(dev), size=n_req)
+        tickets = []
+        start = _t.perf_counter()
+        for a, q in zip(arrivals, picks):
+            now = _t.perf_counter() - start
+            if a > now:
+                _t.sleep(a - now)
+            lag = max(0.0, (_t.perf_counter() - start) - a)
+            tickets.append((srv.submit(req(int(q))), lag, int(q)))
+        lat, frames = [], 0
+        for t, lag, q in tickets:
+            srv.wait(t)
+            _, total_ms = srv.times(t)
+            lat.append(total_ms + 1e3 * lag)
+            frames += dev[q].shape[0]
+            srv.release(t)
+        span = _t.perf_counter() - start
+        lat = np.array(lat)
+        rec = {"load": f, "arrival_req_per_s": round(lam, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+               "p99_ms": round(float(np.percentile(lat, 99)), 2), "frames_per_s": round(frames / span, 1)}
+        log(f"serving at {f:.2f} x capacity: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
+            f"{rec['frames_per_s']} frames/s")
+        out["rates"].append(rec)
+    srv.close()
+    del dev
+    torch.cuda.synchronize()
+    return out
+
+
+# Table 1 of the paper (Sec. 4): clip, width x height, frames, target width,
+# and the paper's CPU seconds for its method ("Proposed") and for seam
+# carving run on every frame ("Raw").  Frames of the rows whose cells are
+# garbled are read as Helicopter's 178.
+TABLE1 = [("Big Belly", 640, 480, 377, 512, 124.36, 1255.19), ("Big Belly", 640, 480, 377, 384, 214.24, 2484.91),
+          ("Lion", 640, 480, 117, 512, 80.72, 600.90), ("Lion", 640, 480, 117, 384, 140.88, 1225.60),
+          ("Lego", 560, 320, 164, 448, 32.28, 263.89), ("Lego", 560, 320, 164, 336, 56.21, 532.16),
+          ("Helicopter", 720, 576, 178, 576, 143.31, 1594.19), ("Helicopter", 720, 576, 178, 432, 282.70, 3096.67),
+          ("Helicopter", 320, 240, 178, 256, 16.32, 201.71), ("Helicopter", 320, 240, 178, 192, 31.44, 426.67),
+          ("Helicopter", 176, 144, 178, 140, 3.43, 52.65), ("Helicopter", 176, 144, 178, 105, 6.73, 108.34)]
+
+
+def _gen_table1(row):
+    from paper_1903_03180_amd import synth
+    q, (_n, W, H, N, _wt, _p, _r) = row
+    return synth.make_clip(6000 + q, N, H, W, C=3, n_obj=3, max_speed=4, cut_at=N // 2, lattice=32)
+
+
+def run_table1(np, torch, scpl, ctx):
+    """Proposed (SCPL, one seam per parent per iteration, dynamic buffer,
+    motion energy) against Raw (classic seam carving of every frame: one
+    seam per iteration, no buffer, gradient energy) on synthetic RGB clips
+    of Table 1's shapes, lengths and target widths, both on this GPU."""
+    import multiprocessing as mp
+    import time as _t
+    with mp.get_context("spawn").Pool(8) as pool:
+        clips = pool.map(_gen_table1, list(enumerate(TABLE1)))
+    rows = []
+    for (name, W, H, N, Wt, p_s, r_s), c in zip(TABLE1, clips):
+        fr = torch.from_numpy(c).cuda()
+        res = {}
+        for method, kw in (("proposed", dict(seams_per_iter=W)),
+                           ("raw", dict(seams_per_iter=1, use_buffer=0, energy_mode=0))):
+            job = [dict(frames=fr, target_width=Wt, **kw)]
+            ctx.retarget_batch(job)  # warm-up (workspace, graphs)
+            torch.cuda.synchronize()
+            t0 = _t.perf_counter()
+            ctx.retarget_batch(job)
+            torch.cuda.synchronize()
+            res[method] = _t.perf_counter() - t0
+        rows.append({"clip": name, "size": f"{W}x{H}", "frames": N, "target_width": Wt,
+                     "proposed_ms": round(1e3 * res["proposed"], 2), "raw_ms": round(1e3 * res["raw"], 2),
+                     "reduction": round(1 - res["proposed"] / res["raw"], 4),
+                     "paper_reduction": round(1 - p_s / r_s, 4)})
+        del fr
+    red = [r["reduction"] for r in rows]
+    log("Table 1 shapes: mean reduction Proposed vs Raw on this GPU " + f"{100 * np.mean(red):.1f}% "
+        f"(paper, CPU: {100 * np.mean([r['paper_reduction'] for r in rows]):.1f}%)")
+    return {"rows": rows, "mean_reduction": round(float(np.mean(red)), 4),
+            "paper_mean_reduction": round(float(np.mean([r["paper_reduction"] for r in rows])), 4),
+            "inputs": "synthetic RGB clips of each row's size, length and target (seeds 6000-6011)"}
+
+
+def _oracle_sample(args):
+    clip, Wt, k, nf = args
+    import oracle
+    oracle.retarget(clip[:nf], Wt, k, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
+    return nf
+
+
+def job_rows(log_rows, jobs):
+    """Splits the per-iteration log into the jobs (buffers, in order): a
+    job's records continue while its width minus the seams of its previous
+    iteration stays above its target."""
+    out, j, prev = [[] for _ in jobs], -1, None
+    for row in log_rows.tolist():
+        _b, Wr, _p, kk = row
+        if prev is None or prev[1] - prev[3] <= jobs[j]["Wt"]:
+            j += 1
+        out[j].append(row)
+        prev = row
+    return out
+
+
+def balg_bytes(per_job, jobs):
+    """Algorithmic HBM bytes of one step by the paper-literal accounting:
+    every input frame read and every output frame written once (plus the
+    luma of colour frames), and for every iteration r >= 1 of a buffer each
+    of its frames' carved luma re-read for the energy recompute."""
+    total = 0
+    for rows, jb in zip(per_job, jobs):
+        H, W, Wt, C, T = jb["H"], jb["W"], jb["Wt"], jb["C"], jb["T"]
+        total += T * (H * W * C + H * Wt * C + (H * W if C == 3 else 0))
+        total += T * sum(H * int(r[1]) for r in rows[1:])
+    return total
+
+
+def dp_bytes(per_job, jobs):
     """Algorithmic bytes of the DP over one retarget: per iteration of a
-    buffer at width W_r, the 4-byte key row of every carved pixel is read
-    once and its 1-byte indicator written once."""
-    return sum(5 * H * int(Wr) for _b, Wr, _p, _k in log_rows.tolist())
+    buffer at width W_r, the 2-byte key of every carved pixel is read once
+    and its 1-byte indicator code written once."""
+    return sum(3 * jb["H"] * int(r[1]) for rows, jb in zip(per_job, jobs) for r in rows)
 
 
 def main() -> int:
@@ -70,9 +246,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k"])
+    ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k", "mix64"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--streams", type=int, default=2, help="job groups (streams) of the batched path")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests per arrival rate (0: no serving run)")
+    ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -89,23 +267,26 @@ def main() -> int:
     from paper_1903_03180_amd import scpl
 
     t_gen = time.perf_counter()
-    clips_np, Wt, k, wname = make_workload(args.workload)
-    N, H, W = clips_np[0].shape[:3]
+    work, wname = make_workload(args.workload)
+    clips_np = [w[0] for w in work]
     n_frames = sum(c.shape[0] for c in clips_np)
+    Hmax = max(c.shape[1] for c in clips_np)
+    Wmax = max(c.shape[2] for c in clips_np)
     log(f"workload {wname}; generated {sum(c.nbytes for c in clips_np) / 1e9:.2f} GB in "
         f"{time.perf_counter() - t_gen:.1f} s")
     ctx = scpl.Context(0)
     ctx.batch_streams(args.streams)
     clips = []
-    for c in clips_np:
+    for c, wt, kk in work:
         fr = torch.from_numpy(c).cuda()
-        clips.append(dict(frames=fr, target_width=Wt, seams_per_iter=k, alpha_num=1, alpha_den=5,
-                          out=torch.empty((c.shape[0], H, Wt) + c.shape[3:], dtype=torch.uint8, device="cuda"),
+        clips.append(dict(frames=fr, target_width=wt, seams_per_iter=kk, alpha_num=1, alpha_den=5,
+                          out=torch.empty((c.shape[0], c.shape[1], wt) + c.shape[3:], dtype=torch.uint8,
+                                          device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
-    dpq, dphb, dppf, dpex, dpus = ctx.autotune_dp(H, W, n_jobs=3 * len(clips))
-    log(f"DP autotune for {len(clips) * 3} jobs of {H}x{W}: {dpq} columns per lane, halo {dphb}, prefetch {dppf}, "
-        f"exclusive {dpex}: {dpus:.1f} us per launch")
+    dpq, dphb, dppf, dpex, dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))
+    log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpq} columns per lane, halo {dphb}, "
+        f"prefetch {dppf}, exclusive {dpex}: {dpus:.1f} us per launch")
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -147,7 +328,12 @@ def main() -> int:
     dom = max(ktime, key=ktime.get)
     dp_ms, dp_n = prof["dp"]
     dp_launch_ms = dp_ms / max(dp_n, 1)
-    dp_bytes_launch = dp_bytes(log_rows, H) * args.steps / max(dp_n, 1)
+    jobs = []
+    for c, (cnp, wt, kk) in zip(clips, work):
+        for T in np.bincount(c["buffer_id"].cpu().numpy()).tolist():
+            jobs.append(dict(H=cnp.shape[1], W=cnp.shape[2], Wt=wt, C=cnp.shape[3] if cnp.ndim == 4 else 1, T=T))
+    per_job = job_rows(log_rows, jobs)
+    dp_bytes_launch = dp_bytes(per_job, jobs) * args.steps / max(dp_n, 1)
     achieved = dp_bytes_launch / (dp_launch_ms * 1e-3) / 1e9
 
     # plain path: clips one after another, buffers one after another
@@ -156,7 +342,8 @@ def main() -> int:
         p0 = time.perf_counter()
         for _ in range(args.plain_steps):
             for c in clips:
-                ctx.retarget(c["frames"], Wt, k, want_masks=False, alpha_num=1, alpha_den=5)
+                ctx.retarget(c["frames"], c["target_width"], c["seams_per_iter"], want_masks=False, alpha_num=1,
+                             alpha_den=5)
         torch.cuda.synchronize()
         p1 = time.perf_counter()
         plain_fps = n_frames * args.plain_steps / (p1 - p0)
@@ -172,19 +359,46 @@ def main() -> int:
         log(f"calibration copy: {args.copy_calibration} MiB read and written")
         del a, b
 
+    # paper-literal algorithmic bytes per step
+    balg = balg_bytes(per_job, jobs)
+
     cpu = None
+    cpu_all = None
     if not args.no_cpu:
         import oracle
-        nf = min(args.cpu_frames, N)
+        Wt0, k0 = work[0][1], work[0][2]
+        nf = min(args.cpu_frames, clips_np[0].shape[0])
         c0 = time.perf_counter()
-        oracle.retarget(clips_np[0][:nf], Wt, k, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
+        oracle.retarget(clips_np[0][:nf], Wt0, k0, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
         c1 = time.perf_counter()
         cpu = {"value": round(nf / (c1 - c0), 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
                "sample": f"first {nf} frames of the first clip, whole retarget (segmentation and every "
                          f"iteration of the sample's buffers), {c1 - c0:.1f} s on one core"}
         log(f"oracle: {nf} frames in {c1 - c0:.1f} s")
+        # all host cores: the same sample of every clip, one process per clip
+        import multiprocessing as mp
+        procs = min(len(clips_np), os.cpu_count() or 1, 16)
+        samples = [(np.ascontiguousarray(w[0][:nf]), w[1], w[2], min(nf, w[0].shape[0])) for w in work[:procs]]
+        with mp.get_context("spawn").Pool(procs) as pool:  # fresh workers: this process uses the GPU
+            pool.map(_oracle_sample, [(samples[0][0][:1], Wt0, k0, 1)] * procs)  # start-up and oracle load
+            c0 = time.perf_counter()
+            done = sum(pool.map(_oracle_sample, samples))
+        c1 = time.perf_counter()
+        cpu_all = {"value": round(done / (c1 - c0), 4), "unit": "frames/s", "cores": procs, "kind": "oracle",
+                   "sample": f"first {nf} frames of each of {procs} clips, one process per clip, {c1 - c0:.1f} s"}
+        log(f"oracle on {procs} cores: {done} frames in {c1 - c0:.1f} s")
 
-    b_alg_frame = (H * W * clips_np[0].shape[-1] if clips_np[0].ndim == 4 else H * W)
+    table1 = None if args.no_table1 else run_table1(np, torch, scpl, ctx)
+
+    serving = None
+    n_clips = len(clips)
+    shape = {"height": Hmax, "width": Wmax, "target_width": work[0][1], "seams_per_iter": work[0][2]} \
+        if len({(c.shape[1:], w, kk) for c, w, kk in work}) == 1 else {"uneven": True}
+    if args.serve_requests > 0:
+        del clips, clips_np, work
+        torch.cuda.empty_cache()
+        serving = run_serving(np, torch, scpl, n_req=args.serve_requests)
+
     line = {
         "metric": METRIC,
         "value": round(fps, 2),
@@ -199,8 +413,8 @@ def main() -> int:
         "dtype": "u8/int32",
         "data": "synthetic",
         "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
-                   "clips": len(clips), "frames": n_frames, "height": H, "width": W, "target_width": Wt,
-                   "seams_per_iter": k, "buffers": nbuf, "buffer_iterations": int(len(log_rows)),
+                   "clips": n_clips, "frames": n_frames, **shape, "buffers": nbuf,
+                   "buffer_iterations": int(len(log_rows)),
                    "dp_geometry": {"cols_per_lane": dpq, "halo_rows": dphb, "prefetch_rows": dppf,
                                                         "exclusive_cu": dpex}, "streams": args.streams},
         "value_graph_no_events": round(fps_graph, 2),
@@ -211,8 +425,14 @@ def main() -> int:
         "roofline": {"kernel": "dp", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(dp_bytes_launch), "launch_ms": round(dp_launch_ms, 4)},
-        "input_bytes_per_frame": b_alg_frame,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "effective_hbm": {"accounting": "paper-literal B_alg: input read, output written, colour luma written, "
+                                        "carved luma re-read by every frame of a buffer at every iteration >= 1",
+                          "bytes_per_step": int(balg), "GBps": round(balg / (ms_per_step * 1e-3) / 1e9, 1),
+                          "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "serving": serving,
+        "raw_vs_proposed": table1,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

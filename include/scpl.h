@@ -138,6 +138,50 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
 #define SCPL_MAX_STREAMS 8
 scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
 
+/* ---- request server (continuous batching) ----
+ * Retarget requests are queued in arrival order.  Each of `lanes` worker
+ * threads owns a context and a stream; whenever a lane is free it takes the
+ * queued requests that fit the device-memory budget (in order, at most
+ * max_batch) and retargets them as one batch (as scpl_retarget_batch).
+ * A request is admitted by an upper bound of the device memory its batch
+ * share can claim (its tiled luma and buffer controller plus one carving
+ * job per frame); the admitted requests' bounds never exceed hbm_budget.
+ * Requests that arrive while batches run are admitted as lanes and memory
+ * free up, and their work overlaps on the device with the batches in
+ * flight.  Results are bit-identical to scpl_retarget on each clip alone.
+ *
+ * scpl_server_create: lanes in [1, SCPL_MAX_LANES], max_batch >= 1,
+ *   hbm_budget in bytes (0: half the device memory free at creation).
+ * scpl_server_submit: the clip's frames must be complete on the device and
+ *   every buffer of the clip stays owned by the caller, untouched by the
+ *   caller until the request is done.  Returns a ticket; SCPL_ERR_CAPACITY
+ *   if the request's bound exceeds the whole budget (nothing is queued).
+ * scpl_server_poll: *h_done = 1 once the outputs are complete on the device;
+ *   *h_result (nullable) is then the request's status (SCPL_ERR_NOT_READY
+ *   before, or for a request dropped by scpl_server_destroy).
+ * scpl_server_wait: blocks until the request is done.
+ * scpl_server_ticket_times: host steady-clock milliseconds from submission
+ *   to the start of the request's batch and to its completion (done only).
+ * scpl_server_release: forgets a done ticket.
+ * scpl_server_destroy: requests already running finish; queued ones are
+ *   dropped; then the lanes' contexts are destroyed. */
+#define SCPL_MAX_LANES 16
+typedef struct scpl_server scpl_server;
+typedef struct {
+    int32_t lanes;
+    int32_t max_batch;
+    uint64_t hbm_budget;
+} scpl_server_config;
+scpl_status scpl_server_create(int32_t hip_device, const scpl_server_config *cfg, scpl_server **out);
+scpl_status scpl_server_submit(scpl_server *srv, const scpl_clip *clip, int64_t *h_ticket);
+scpl_status scpl_server_poll(scpl_server *srv, int64_t ticket, int32_t *h_done, scpl_status *h_result);
+scpl_status scpl_server_wait(scpl_server *srv, int64_t ticket, scpl_status *h_result);
+scpl_status scpl_server_ticket_times(scpl_server *srv, int64_t ticket, double *h_queue_ms, double *h_total_ms);
+scpl_status scpl_server_release(scpl_server *srv, int64_t ticket);
+void scpl_server_destroy(scpl_server *srv);
+/* The admission bound of a request with params p (bytes; host arithmetic). */
+scpl_status scpl_server_footprint(const scpl_params *p, uint64_t *h_bytes);
+
 /* Per-iteration record of the last scpl_retarget / scpl_retarget_batch call:
  * for every buffer in order, for every iteration, four int32
  * (buffer index within its clip, W_r, P_eff, k_iter); clips in order.
@@ -222,6 +266,26 @@ scpl_status scpl_select(scpl_ctx *ctx, int32_t W, const int32_t *d_ce_last, cons
  * d_seams: kk x H int32, d_seams[s*H + i] = column of seam s in row i. */
 scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_dir, const int32_t *d_children,
                            int32_t kk, int32_t *d_seams, void *stream);
+
+/* ASDE test of one candidate buffer (Sec. 3.2, eqs. 7-9): the n frames of
+ * d_luma (n x H x W luma) with d_prev (nullable, H x W: the frame before
+ * them, for the difference term of the first; motion energy only).
+ * *h_S = sum over pixels of floor(sqrt(n S2 - S1^2)) (S1, S2: sums of the n
+ * energies and of their squares; n times the population deviation of
+ * eq. 8); *h_reject = 1 iff ASDE = S / (n H W) exceeds phi(n) of eq. (9)
+ * with alpha = alpha_num / alpha_den (decided exactly in integers).
+ * Synchronises `stream`. */
+scpl_status scpl_asde(scpl_ctx *ctx, int32_t n, int32_t H, int32_t W, int32_t mode, const uint8_t *d_luma,
+                      const uint8_t *d_prev, int32_t alpha_num, int32_t alpha_den, int64_t *h_S, int32_t *h_reject,
+                      void *stream);
+
+/* One-pass removal of kk seams from one frame (Sec. 3.1): d_in H x W x C
+ * uint8 (C = 1 or 3), d_seams kk x H int32 with d_seams[s*H + i] the column
+ * of seam s in row i (strictly increasing in s in every row, as
+ * scpl_backtrack returns them; entries that break this give an undefined
+ * but in-bounds result), 0 <= kk < W.  d_out: H x (W - kk) x C. */
+scpl_status scpl_compact(scpl_ctx *ctx, int32_t H, int32_t W, int32_t C, const uint8_t *d_in, const int32_t *d_seams,
+                         int32_t kk, uint8_t *d_out, void *stream);
 
 /* Buffer segmentation alone (Sec. 3.2) on N x H x W luma.
  * h_buffer_id: N int32 (host).  h_s_trace (nullable, host): N int64, the

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libscpl.so")
-SOURCES = ["scpl_kernels.hip", "scpl_host.hip"]
+SOURCES = ["scpl_kernels.hip", "scpl_host.hip", "scpl_server.hip"]
 ARCH = "gfx950"
 
 

@@ -13,6 +13,7 @@
 
 #include "../../include/scpl.h"
 #include "scpl_internal.h"
+#include "scpl_runtime.h"
 
 using namespace scpl;
 
@@ -759,11 +760,37 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
     return SCPL_OK;
 }
 
+}  // extern "C"
+
+scpl_status scpl::trim_workspace(scpl_ctx *ctx, uint64_t keep)
+{
+    if ((uint64_t)ctx->ws_size + ctx->jws_size <= keep) return SCPL_OK;
+    SCPL_TRY(hipSetDevice(ctx->device));
+    if (ctx->ws) SCPL_TRY(hipFree(ctx->ws));  // waits for work that uses it
+    if (ctx->jws) SCPL_TRY(hipFree(ctx->jws));
+    ctx->ws = ctx->jws = nullptr;
+    ctx->ws_size = ctx->jws_size = 0;
+    return SCPL_OK;
+}
+
+// Upper bound of the device bytes a batched retarget of this clip can
+// claim: its tiled luma and controller state, and one job per frame (the
+// most buffers a clip can have) with its table entries.
+uint64_t scpl::clip_footprint(const scpl_params &p)
+{
+    JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, dp_geom(p.width)};
+    const uint64_t N = (uint64_t)p.n_frames;
+    uint64_t b = align_up((size_t)N * tiled_frame_bytes(p.height, p.width));
+    b += seg_bytes((int64_t)p.height * p.width) + align_up(kSegWindow * 8);
+    b += N * (job_bytes(js) + sizeof(Job) + 16) + 2 * kAlign;
+    return b;
+}
+
 // Retargets clips: tiled luma of every clip, buffer segmentation of all
 // clips together, then the carving jobs (one per buffer) -- all at once
 // (batched) or one buffer after another (plain).
-static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
-                             hipStream_t s)
+scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
+                            hipStream_t s, bool use_graph)
 {
     // area A: tiled lumas, controller states, window sums
     size_t a_bytes = align_up((size_t)nc * kSegWindow * 8);
@@ -891,7 +918,7 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
         std::vector<Group> gs;
         for (int g = 0; g < ng; ++g)
             gs.push_back(make_group(gfirst[g], gsize[g], ng > 1 ? ctx->gstreams[g] : s, ctx->gevents[g]));
-        st = run_groups(ctx, gs, true, s);
+        st = run_groups(ctx, gs, use_graph, s);
         if (st != SCPL_OK) return st;
         return collect_logs(ctx, jobs, s);
     }
@@ -905,6 +932,8 @@ static scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool
     }
     return SCPL_OK;
 }
+
+extern "C" {
 
 scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
                           uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream)
@@ -1272,6 +1301,75 @@ scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
     st = segment_clips(ctx, seg, d_sums, static_cast<unsigned long long *>(ctx->pinned), s);
     if (h_n_buffers) *h_n_buffers = seg[0].nbuf;
     return st;
+}
+
+scpl_status scpl_asde(scpl_ctx *ctx, int32_t n, int32_t H, int32_t W, int32_t mode, const uint8_t *d_luma,
+                      const uint8_t *d_prev, int32_t alpha_num, int32_t alpha_den, int64_t *h_S, int32_t *h_reject,
+                      void *stream)
+{
+    if (!ctx || !d_luma || !h_S || !h_reject || n < 1 || n > SCPL_MAX_FRAMES || H < 1 || W < 1 ||
+        H > SCPL_MAX_HEIGHT || W > SCPL_MAX_WIDTH || (int64_t)H * W > SCPL_MAX_PIXELS || (mode != 0 && mode != 1) ||
+        alpha_num < 0 || alpha_num > SCPL_MAX_ALPHA_TERM || alpha_den < 1 || alpha_den > SCPL_MAX_ALPHA_TERM)
+        return SCPL_ERR_INVALID_ARG;
+    SCPL_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t HW = (int64_t)H * W;
+    const int64_t FS = tiled_frame_bytes(H, W);
+    const int pre = (d_prev && mode == SCPL_ENERGY_MOTION) ? 1 : 0;  // tiled frame 0 is the predecessor
+    const int nt = n + pre;
+    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up((size_t)nt * FS) + seg_bytes(HW)));
+    SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8)));
+    Bump dev{static_cast<char *>(ctx->ws)};
+    unsigned long long *d_sums = dev.take<unsigned long long>(kSegWindow);
+    uint8_t *tiled = dev.take<uint8_t>((size_t)nt * FS);
+    char *state = dev.take<char>(seg_bytes(HW));
+    if (pre) launch_tile_luma(d_prev, 1, 1, H, W, tiled, s);
+    launch_tile_luma(d_luma, 1, n, H, W, tiled + (size_t)pre * FS, s);
+    SCPL_CHECK_LAUNCH();
+    // the moments start from the first frame and take the others in windows
+    // of candidates; the sum after the last one is S of the whole buffer
+    uint64_t S = 0;  // a single frame has no deviation
+    unsigned long long *h_sums = static_cast<unsigned long long *>(ctx->pinned);
+    for (int tb = pre + 1; tb < nt; tb += kSegWindow) {
+        SegArgs a{};
+        Bump bp{state};
+        a.luma = tiled;
+        a.FS = FS;
+        a.ntc = tiles_across(W);
+        a.s1 = bp.take<uint32_t>(HW);
+        a.s2 = bp.take<uint64_t>(HW);
+        a.sout = d_sums;
+        a.H = H;
+        a.W = W;
+        a.mode = mode;
+        a.t0 = pre;
+        a.tb = tb;
+        a.te = std::min(nt, tb + kSegWindow);
+        a.init = tb == pre + 1 ? 1 : 0;
+        SCPL_TRY(hipMemsetAsync(d_sums, 0, kSegWindow * 8, s));
+        launch_seg_window(a, s);
+        SCPL_CHECK_LAUNCH();
+        if (a.te == nt) {
+            SCPL_TRY(hipMemcpyAsync(h_sums, d_sums, kSegWindow * 8, hipMemcpyDeviceToHost, s));
+            SCPL_TRY(hipStreamSynchronize(s));
+            S = h_sums[a.te - a.tb - 1];
+        }
+    }
+    *h_S = (int64_t)S;
+    *h_reject = asde_rejects(S, n, HW, energy_max(mode), alpha_num, alpha_den) ? 1 : 0;
+    return SCPL_OK;
+}
+
+scpl_status scpl_compact(scpl_ctx *ctx, int32_t H, int32_t W, int32_t C, const uint8_t *d_in, const int32_t *d_seams,
+                         int32_t kk, uint8_t *d_out, void *stream)
+{
+    if (!ctx || !d_in || !d_out || H < 1 || W < 1 || H > SCPL_MAX_HEIGHT || W > SCPL_MAX_WIDTH ||
+        (int64_t)H * W > SCPL_MAX_PIXELS || (C != 1 && C != 3) || kk < 0 || kk >= W || (kk > 0 && !d_seams))
+        return SCPL_ERR_INVALID_ARG;
+    SCPL_TRY(hipSetDevice(ctx->device));
+    launch_compact_frame(d_in, H, W, C, d_seams, kk, d_out, static_cast<hipStream_t>(stream));
+    SCPL_CHECK_LAUNCH();
+    return SCPL_OK;
 }
 
 }  // extern "C"

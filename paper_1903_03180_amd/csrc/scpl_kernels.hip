@@ -1386,6 +1386,40 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
     }
 }
 
+// -------------------------------------------------- one-frame compaction
+//
+// Stage entry point of the one-pass removal (Sec. 3.1): row i of an H x W x
+// C frame loses the kk columns seams[s * H + i] (increasing in s); new
+// column j reads old column j + #{s : seams[s] - s <= j}.  One block per
+// row; the row's seam positions are staged in LDS when there are few.
+
+constexpr int kCompactSeams = 1024;
+
+__global__ __launch_bounds__(256) void compact_frame_kernel(const uint8_t *in, int H, int W, int C, const int32_t *seams,
+                                                            int kk, uint8_t *out)
+{
+    __shared__ int R[kCompactSeams];
+    const int i = blockIdx.x;
+    const bool lds = kk <= kCompactSeams;
+    if (lds)
+        for (int s = threadIdx.x; s < kk; s += 256) R[s] = seams[(size_t)s * H + i] - s;
+    __syncthreads();
+    auto rs = [&](int s) { return lds ? R[s] : seams[(size_t)s * H + i] - s; };
+    const int Wn = W - kk;
+    const uint8_t *src = in + (size_t)i * W * C;
+    uint8_t *dst = out + (size_t)i * Wn * C;
+    for (int j = threadIdx.x; j < Wn; j += 256) {
+        int a = 0, b = kk;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (rs(m) <= j) a = m + 1;
+            else b = m;
+        }
+        const int o = min(max(j + a, 0), W - 1);
+        for (int c = 0; c < C; ++c) dst[(size_t)j * C + c] = src[(size_t)o * C + c];
+    }
+}
+
 // ------------------------------------------------- stage-API conversions
 
 // U -> key row entry; U outside [0, 16382] is clamped into it
@@ -1648,6 +1682,12 @@ void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch
 {
     hipLaunchKernelGGL(keys_to_u_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);
+}
+
+void launch_compact_frame(const uint8_t *in, int H, int W, int C, const int32_t *seams, int kk, uint8_t *out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(compact_frame_kernel, dim3(H), dim3(256), 0, s, in, H, W, C, seams, kk, out);
 }
 
 void launch_seams_out(const int16_t *src, int pitch, int32_t *dst, int kk, int H, hipStream_t s)

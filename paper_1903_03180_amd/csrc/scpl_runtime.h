@@ -1,0 +1,28 @@
+// Host-runtime functions shared by the C ABI entry points of libscpl.so
+// (scpl_host.hip) and the request server (scpl_server.hip).  Not part of
+// the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/scpl.h"
+
+namespace scpl {
+
+// Retargets nc clips on stream s: tiled luma, buffer segmentation, then the
+// carving jobs (one per buffer) all at once (batched) or one buffer after
+// another (plain).  h_nbuf_first (nullable) receives the first clip's
+// number of buffers.  use_graph: the batched iterations are replayed from
+// HIP graphs (no other host thread may then synchronise the device while
+// the graphs are captured).
+scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
+                      hipStream_t s, bool use_graph = true);
+
+// Upper bound of the device bytes a batched retarget of one clip claims.
+uint64_t clip_footprint(const scpl_params &p);
+
+// Frees the context's device workspaces if together they exceed keep bytes.
+scpl_status trim_workspace(scpl_ctx *ctx, uint64_t keep);
+
+}  // namespace scpl

@@ -36,7 +36,9 @@ EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_dp_geometry",
-    "scpl_autotune_dp", "scpl_batch_streams",
+    "scpl_autotune_dp", "scpl_batch_streams", "scpl_server_create", "scpl_server_submit", "scpl_server_poll",
+    "scpl_server_wait", "scpl_server_ticket_times", "scpl_server_release", "scpl_server_destroy",
+    "scpl_server_footprint", "scpl_asde", "scpl_compact",
 ]
 
 DP_GEOMETRIES = [(2, 8, 8), (2, 8, 16), (4, 8, 8), (4, 8, 16), (4, 16, 8), (4, 16, 16), (8, 16, 4), (8, 16, 8),
@@ -54,6 +56,10 @@ class scpl_params(C.Structure):
 class scpl_clip(C.Structure):
     _fields_ = [("p", scpl_params), ("d_frames", C.c_void_p), ("d_out", C.c_void_p), ("d_masks", C.c_void_p),
                 ("d_buffer_id", C.c_void_p)]
+
+
+class scpl_server_config(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("hbm_budget", C.c_uint64)]
 
 
 _P, _I32, _I64 = C.c_void_p, C.c_int32, C.c_int64
@@ -75,6 +81,16 @@ _sig = {
     "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
     "scpl_dp_geometry": ([_P, _I32, _I32, _I32, _I32], C.c_int),
     "scpl_batch_streams": ([_P, _I32], C.c_int),
+    "scpl_server_create": ([_I32, C.POINTER(scpl_server_config), C.POINTER(C.c_void_p)], C.c_int),
+    "scpl_server_submit": ([_P, C.POINTER(scpl_clip), C.POINTER(_I64)], C.c_int),
+    "scpl_server_poll": ([_P, _I64, C.POINTER(_I32), C.POINTER(C.c_int)], C.c_int),
+    "scpl_server_wait": ([_P, _I64, C.POINTER(C.c_int)], C.c_int),
+    "scpl_server_ticket_times": ([_P, _I64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "scpl_server_release": ([_P, _I64], C.c_int),
+    "scpl_server_destroy": ([_P], None),
+    "scpl_server_footprint": ([C.POINTER(scpl_params), C.POINTER(C.c_uint64)], C.c_int),
+    "scpl_asde": ([_P, _I32, _I32, _I32, _I32, _P, _P, _I32, _I32, C.POINTER(_I64), C.POINTER(_I32), _P], C.c_int),
+    "scpl_compact": ([_P, _I32, _I32, _I32, _P, _P, _I32, _P, _P], C.c_int),
     "scpl_autotune_dp": ([_P, _I32, _I32, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                           C.POINTER(_I32), C.POINTER(C.c_double)], C.c_int),
 }
@@ -288,6 +304,25 @@ class Context:
                "scpl_backtrack")
         return seams[:kk]
 
+    def asde(self, luma, prev=None, energy_mode=SCPL_ENERGY_MOTION, alpha_num=1, alpha_den=5, stream=None):
+        """(S, reject) of the candidate buffer luma (n x H x W)."""
+        n, H, W = luma.shape
+        S, rj = C.c_int64(0), C.c_int32(0)
+        _check(scpl_asde(self.h, n, H, W, energy_mode, _ptr(luma), _ptr(prev), alpha_num, alpha_den, C.byref(S),
+                         C.byref(rj), _stream(stream)), "scpl_asde")
+        return int(S.value), bool(rj.value)
+
+    def compact(self, frame, seams, stream=None):
+        """frame H x W (x 3) uint8 minus the seams (kk x H int32 columns)."""
+        import torch
+        H, W = frame.shape[:2]
+        Cc = frame.shape[2] if frame.dim() == 3 else 1
+        kk = seams.shape[0]
+        out = torch.empty((H, W - kk) + tuple(frame.shape[2:]), dtype=torch.uint8, device=frame.device)
+        _check(scpl_compact(self.h, H, W, Cc, _ptr(frame), _ptr(seams) if kk else None, kk, _ptr(out),
+                            _stream(stream)), "scpl_compact")
+        return out
+
     def segment(self, luma, energy_mode=SCPL_ENERGY_MOTION, use_buffer=1, alpha_num=1, alpha_den=5, max_buffer=0,
                 stream=None):
         import numpy as np
@@ -299,3 +334,79 @@ class Context:
         _check(scpl_segment(self.h, C.byref(p), _ptr(luma), bid.ctypes.data, tr.ctypes.data, C.byref(nb),
                             _stream(stream)), "scpl_segment")
         return bid, tr
+
+
+class Server:
+    """Continuous-batching request server (scpl_server_* in include/scpl.h).
+
+    submit() takes the same dict as one entry of Context.retarget_batch
+    (frames must be complete on the device: synchronise first) and returns a
+    ticket; the dict's tensors must stay alive and untouched until the
+    ticket is done."""
+
+    def __init__(self, device: int = 0, lanes: int = 4, max_batch: int = 8, hbm_budget: int = 0):
+        h = C.c_void_p()
+        cfg = scpl_server_config(lanes, max_batch, hbm_budget)
+        _check(scpl_server_create(device, C.byref(cfg), C.byref(h)), "scpl_server_create")
+        self.h = h
+        self._live = {}
+
+    def close(self) -> None:
+        if self.h:
+            scpl_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, clip: dict) -> int:
+        import torch
+        fr = clip["frames"]
+        kw = {k: clip[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer") if k in clip}
+        p = params_for(fr, clip["target_width"], clip["seams_per_iter"], **kw)
+        shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
+        if clip.get("out") is None:
+            clip["out"] = torch.empty(shp, dtype=torch.uint8, device=fr.device)
+        if clip.get("masks") is None and clip.get("want_masks", False):
+            clip["masks"] = torch.empty((p.n_frames, p.height, p.width), dtype=torch.int16, device=fr.device)
+        if clip.get("buffer_id") is None:
+            clip["buffer_id"] = torch.empty(p.n_frames, dtype=torch.int32, device=fr.device)
+        c = scpl_clip(p.c(), _ptr(fr), _ptr(clip["out"]), _ptr(clip.get("masks")), _ptr(clip["buffer_id"]))
+        t = C.c_int64(0)
+        _check(scpl_server_submit(self.h, C.byref(c), C.byref(t)), "scpl_server_submit")
+        self._live[t.value] = clip  # keeps the tensors alive
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(done, status)"""
+        d, st = C.c_int32(0), C.c_int(0)
+        _check(scpl_server_poll(self.h, ticket, C.byref(d), C.byref(st)), "scpl_server_poll")
+        return bool(d.value), int(st.value)
+
+    def wait(self, ticket: int) -> dict:
+        st = C.c_int(0)
+        _check(scpl_server_wait(self.h, ticket, C.byref(st)), "scpl_server_wait")
+        _check(st.value, "retarget request")
+        return self._live[ticket]
+
+    def times(self, ticket: int):
+        """(queue_ms, total_ms) of a done request."""
+        q, t = C.c_double(0), C.c_double(0)
+        _check(scpl_server_ticket_times(self.h, ticket, C.byref(q), C.byref(t)), "scpl_server_ticket_times")
+        return q.value, t.value
+
+    def release(self, ticket: int) -> None:
+        _check(scpl_server_release(self.h, ticket), "scpl_server_release")
+        self._live.pop(ticket, None)
+
+    @staticmethod
+    def footprint(params: Params) -> int:
+        """Admission bound (device bytes) of a request."""
+        b = C.c_uint64(0)
+        cp = params.c()
+        _check(scpl_server_footprint(C.byref(cp), C.byref(b)), "scpl_server_footprint")
+        return int(b.value)

@@ -202,3 +202,20 @@ def test_forced_geometry_retarget(ctx, orc, geom):
         compare(ctx, orc, clip, 220, 6)
     finally:
         ctx.dp_geometry(0)
+
+
+@pytest.mark.parametrize("shape,Wt", [((3, 144, 176), 140), ((2, 144, 176), 105), ((2, 48, 64), 38)])
+def test_raw_baseline_matches_oracle(ctx, orc, shape, Wt):
+    """The paper's comparison "Raw": classic seam carving of every frame on
+    its own (one seam per iteration, gradient energy, no buffer), at Table 1
+    shapes and ratios."""
+    N, H, W = shape
+    clip = synth.make_clip(950 + W, N, H, W, C=3, n_obj=3, lattice=8)
+    compare(ctx, orc, clip, Wt, 1, energy_mode=0, use_buffer=0)
+
+
+def test_uncapped_one_seam_per_parent(ctx, orc):
+    """k >= W: every parent's least child leaves in each iteration (eq. 6
+    taken literally)."""
+    clip = synth.make_clip(960, 12, 40, 96, C=1, n_obj=3, cut_at=6, lattice=8)
+    compare(ctx, orc, clip, 60, 96)

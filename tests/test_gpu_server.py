@@ -1,0 +1,123 @@
+"""Request server (continuous batching): every request's result is
+bit-identical alone and inside a mix of uneven clips submitted while others
+are running, and admission follows the device-memory budget."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1903_03180_amd import synth  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# uneven sizes, aspect ratios, lengths, luma and RGB, gradient and motion
+MIX = [
+    dict(seed=900, N=14, H=40, W=90, C=3, Wt=67, k=4),
+    dict(seed=901, N=30, H=24, W=120, C=1, Wt=90, k=16),
+    dict(seed=902, N=6, H=64, W=64, C=1, Wt=48, k=8, energy_mode=0),
+    dict(seed=903, N=20, H=36, W=180, C=3, Wt=135, k=2, alpha_num=3, alpha_den=20),
+    dict(seed=904, N=9, H=90, W=50, C=1, Wt=37, k=1000),
+    dict(seed=905, N=25, H=18, W=256, C=1, Wt=192, k=16, use_buffer=0),
+    dict(seed=906, N=11, H=48, W=72, C=3, Wt=54, k=6, max_buffer=4),
+]
+
+
+def make(spec):
+    N, H, W, C = spec["N"], spec["H"], spec["W"], spec["C"]
+    return synth.make_clip(spec["seed"], N, H, W, C=C, n_obj=3, cut_at=N // 2, lattice=8)
+
+
+def kwargs(spec):
+    return {k: spec[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer") if k in spec}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1903_03180_amd import scpl
+    c = scpl.Context(0)
+    yield c
+    c.close()
+
+
+def test_server_results_alone_and_in_the_mix(ctx, orc):
+    from paper_1903_03180_amd import scpl
+    frames = [make(s) for s in MIX]
+    solo = [ctx.retarget(dev(f), s["Wt"], s["k"], **kwargs(s)) for f, s in zip(frames, MIX)]
+    torch.cuda.synchronize()
+    srv = scpl.Server(0, lanes=3, max_batch=2)
+    try:
+        tickets = []
+        for rep in range(2):  # every clip twice: more requests than lanes
+            for f, s in zip(frames, MIX):
+                clip = dict(frames=dev(f), target_width=s["Wt"], seams_per_iter=s["k"], want_masks=True, **kwargs(s))
+                torch.cuda.synchronize()
+                tickets.append(srv.submit(clip))
+                time.sleep(0.001)  # later requests arrive while earlier ones run
+        for q, t in enumerate(tickets):
+            r = srv.wait(t)
+            a = solo[q % len(MIX)]
+            assert torch.equal(r["out"], a["out"])
+            assert torch.equal(r["masks"], a["masks"])
+            assert torch.equal(r["buffer_id"], a["buffer_id"])
+            qms, tms = srv.times(t)
+            assert 0 <= qms <= tms
+            srv.release(t)
+    finally:
+        srv.close()
+    # and the solo results are the oracle's
+    for f, s, a in list(zip(frames, MIX, solo))[:3]:
+        okw = dict(mode=s.get("energy_mode", 1), use_buffer=s.get("use_buffer", 1), anum=s.get("alpha_num", 1),
+                   aden=s.get("alpha_den", 5), max_buffer=s.get("max_buffer", 0))
+        want = orc.retarget(f, s["Wt"], s["k"], **okw)
+        assert np.array_equal(a["out"].cpu().numpy(), want["out"])
+
+
+def test_server_admission_by_budget(ctx):
+    from paper_1903_03180_amd import scpl
+    spec = MIX[0]
+    f = make(spec)
+    p = scpl.params_for(dev(f), spec["Wt"], spec["k"])
+    need = scpl.Server.footprint(p)
+    assert need > 0
+    # a budget below one request: refused at submission, nothing queued
+    srv = scpl.Server(0, lanes=2, max_batch=4, hbm_budget=need - 1)
+    try:
+        with pytest.raises(scpl.ScplError) as ei:
+            srv.submit(dict(frames=dev(f), target_width=spec["Wt"], seams_per_iter=spec["k"]))
+        assert ei.value.status == scpl.SCPL_ERR_CAPACITY
+    finally:
+        srv.close()
+    # room for one request at a time: requests queue and all complete
+    solo = ctx.retarget(dev(f), spec["Wt"], spec["k"])
+    srv = scpl.Server(0, lanes=3, max_batch=4, hbm_budget=need + need // 2)
+    try:
+        ts = [srv.submit(dict(frames=dev(f), target_width=spec["Wt"], seams_per_iter=spec["k"])) for _ in range(4)]
+        spans = []
+        for t in ts:
+            r = srv.wait(t)
+            assert torch.equal(r["out"], solo["out"])
+            spans.append(srv.times(t))
+        # one at a time: the later requests waited in the queue
+        assert max(q for q, _ in spans) > 0
+    finally:
+        srv.close()
+
+
+def test_server_rejects_invalid_requests():
+    from paper_1903_03180_amd import scpl
+    srv = scpl.Server(0, lanes=1, max_batch=1)
+    try:
+        f = dev(make(MIX[1]))
+        with pytest.raises(scpl.ScplError):
+            srv.submit(dict(frames=f, target_width=0, seams_per_iter=4))
+        with pytest.raises(scpl.ScplError):
+            srv.poll(12345)
+    finally:
+        srv.close()

@@ -161,3 +161,41 @@ def test_autotune_then_parity(ctx, orc):
     ce, lab, d = ctx.dp(dev(u))
     oce, olab, od = orc.dp(u)
     assert np.array_equal(host(ce), oce[-1]) and np.array_equal(host(d), od)
+
+
+@pytest.mark.parametrize("n,H,W,mode,prev", [(1, 9, 13, 1, False), (2, 17, 30, 1, True), (5, 33, 65, 0, False),
+                                             (64, 20, 24, 1, False), (65, 20, 24, 1, True), (70, 16, 40, 0, True),
+                                             (12, 1, 1, 1, True)])
+@pytest.mark.parametrize("alpha", [(1, 5), (3, 20), (1, 50)])
+def test_asde(ctx, orc, n, H, W, mode, prev, alpha):
+    Y = _clip(81 + n, n + 1, H, W, cut=n // 2 + 1)
+    first = 1
+    frames, before = Y[first:], Y[0]
+    s1 = np.zeros((H, W), dtype=np.uint64)
+    s2 = np.zeros((H, W), dtype=np.uint64)
+    for t in range(n):
+        p = (frames[t - 1] if t else before) if mode == 1 and (t or prev) else None
+        e = orc.energy(frames[t], p, mode).astype(np.uint64)
+        s1 += e
+        s2 += e * e
+    S = orc.asde_sum(s1, s2, n)
+    rej = orc.reject(S, n, H * W, orc.energy_max(mode), alpha[0], alpha[1])
+    gS, grej = ctx.asde(dev(frames), dev(before) if prev else None, energy_mode=mode, alpha_num=alpha[0],
+                        alpha_den=alpha[1])
+    assert gS == S and grej == rej
+
+
+@pytest.mark.parametrize("shape,kk,C", [((1, 5), 2, 1), ((40, 70), 7, 3), ((130, 300), 60, 1), ((9, 2000), 1500, 3),
+                                        ((64, 64), 0, 1)])
+def test_compact(ctx, orc, shape, kk, C):
+    H, W = shape
+    rng = np.random.default_rng(H + W + kk)
+    u = rng.integers(0, 9, size=shape).astype(np.int32)
+    oce, olab, od = orc.dp(u)
+    och, _ = orc.select(oce[-1], olab[-1], max(kk, 1), max(kk, 1))
+    seams = orc.backtrack(od, och)[:kk] if kk else np.zeros((0, H), dtype=np.int32)
+    kk = seams.shape[0]
+    frame = rng.integers(0, 256, size=(H, W, C) if C == 3 else (H, W)).astype(np.uint8)
+    want = np.stack([np.delete(frame[i], seams[:, i], axis=0) for i in range(H)])
+    got = ctx.compact(dev(frame), dev(seams.astype(np.int32)))
+    assert np.array_equal(host(got), want)
