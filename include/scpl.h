@@ -75,7 +75,7 @@ enum {
 #define SCPL_MAX_PIXELS (1 << 27)  /* H * W, keeps the ASDE test in 128 bits */
 #define SCPL_MAX_FRAMES 16384      /* frames per call */
 #define SCPL_MAX_ALPHA_TERM 1024   /* alpha_num <= 1024, 1 <= alpha_den <= 1024 */
-#define SCPL_MAX_DP_STAGE_HEIGHT 16383 /* scpl_dp with energies up to 65535 */
+#define SCPL_MAX_DP_STAGE_HEIGHT 16383 /* scpl_dp: 4 x 16382 x H fits 32 bits */
 
 typedef struct {
     int32_t n_frames;       /* N >= 1 */
@@ -89,6 +89,7 @@ typedef struct {
     int32_t alpha_num;      /* alpha = alpha_num / alpha_den (paper: 0.15 .. 0.25) */
     int32_t alpha_den;
     int32_t max_buffer;     /* 0: unbounded (paper); > 0: force a new buffer at this length */
+    int32_t target_height;  /* 0 or H: height kept; 1 <= Ht < H: horizontal seams, see below */
 } scpl_params;
 
 typedef struct scpl_ctx scpl_ctx;
@@ -104,10 +105,18 @@ const char *scpl_status_str(scpl_status s);
 scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
 
 /* Whole retarget of one clip (Secs. 3.1-3.3).
- * d_frames: N x H x W x C uint8.  d_out: N x H x Wt x C uint8.
+ * d_frames: N x H x W x C uint8.  d_out: N x Ht x Wt x C uint8 (Ht = H
+ *   unless target_height is set).
  * d_masks (nullable): N x H x W uint16; 0 = kept, r + 1 = removed in
  *   iteration r of the frame's buffer (all frames of a buffer share a mask).
  * d_buffer_id (nullable): N int32, buffer index of each frame.
+ * Height (Sec. 2: horizontal seams are vertical seams of the transposed
+ * frames): with target_height Ht < H the clip is carved in width first (if
+ * Wt < W), then its frames are transposed, carved from H to Ht columns the
+ * same way (buffers, energies and seams of the transposed frames) and
+ * transposed back.  Masks and buffer ids then describe the height pass when
+ * Wt == W; when both dimensions shrink, buffer ids describe the width pass
+ * and d_masks must be null.
  * h_n_buffers (nullable): receives the number of buffers.
  * The segmentation step synchronises `stream` a few times; the carving is
  * asynchronous apart from one check of the iteration count per buffer.

@@ -172,3 +172,27 @@ def retarget(frames: np.ndarray, Wt: int, k: int, mode: int = MOTION, use_buffer
     if n < 0:
         raise ValueError(f"oracle_retarget failed with {n}")
     return dict(out=out, masks=masks, buffer_id=bid, log=log[:min(n, log_cap)].copy())
+
+
+def _t(a: np.ndarray) -> np.ndarray:
+    """Frames N x H x W (x C) -> N x W x H (x C)."""
+    return np.ascontiguousarray(np.swapaxes(a, 1, 2))
+
+
+def retarget_2d(frames: np.ndarray, Wt: int, Ht: int, k: int, **kw):
+    """Width, then height (Sec. 2: a horizontal seam is a vertical seam of
+    the transposed frame): the frames are carved to width Wt as by
+    retarget(), then transposed, carved to Ht columns, and transposed back.
+    Masks and buffer ids describe the height pass when only the height
+    shrinks; when both shrink, buffer ids are the width pass's and there are
+    no masks.  The log holds the width pass's rows, then the height pass's."""
+    H, W = frames.shape[1], frames.shape[2]
+    if Ht >= H:
+        return retarget(frames, Wt, k, **kw)
+    first = retarget(frames, Wt, k, **kw) if Wt < W else None
+    mid = first["out"] if first is not None else frames
+    second = retarget(_t(mid), Ht, k, **kw)
+    return dict(out=_t(second["out"]),
+                masks=None if first is not None else _t(second["masks"]) if second["masks"] is not None else None,
+                buffer_id=first["buffer_id"] if first is not None else second["buffer_id"],
+                log=np.concatenate([first["log"], second["log"]]) if first is not None else second["log"])

@@ -36,6 +36,8 @@ struct scpl_ctx {
     size_t ws_size = 0;
     void *jws = nullptr;       // device workspace of the carving jobs
     size_t jws_size = 0;
+    void *tws = nullptr;       // device temporaries of height retargeting
+    size_t tws_size = 0;
     void *pinned = nullptr;    // host staging (job tables, sums, states)
     size_t pinned_size = 0;
     std::vector<int32_t> last_log;
@@ -85,6 +87,7 @@ scpl_status validate(const scpl_params *p)
     if (p->alpha_num < 0 || p->alpha_num > SCPL_MAX_ALPHA_TERM) return SCPL_ERR_INVALID_ARG;
     if (p->alpha_den < 1 || p->alpha_den > SCPL_MAX_ALPHA_TERM) return SCPL_ERR_INVALID_ARG;
     if (p->max_buffer < 0) return SCPL_ERR_INVALID_ARG;
+    if (p->target_height < 0 || p->target_height > p->height) return SCPL_ERR_INVALID_ARG;
     return SCPL_OK;
 }
 
@@ -300,6 +303,48 @@ scpl_status prof_drain(scpl_ctx *ctx)
 // Device state of one clip's buffer controller: moments S1, S2 per pixel
 // and the window sums.
 size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8); }
+
+// ------------------------------------------------------- height retargeting
+
+bool height_pass(const scpl_params &p) { return p.target_height > 0 && p.target_height < p.height; }
+
+// Parameters of the height pass: the transposed frames (W_src x H) carved
+// from H to Ht columns; W_src is the width after the width pass.
+scpl_params transposed_params(const scpl_params &p)
+{
+    scpl_params q = p;
+    q.height = p.target_width;
+    q.width = p.height;
+    q.target_width = p.target_height;
+    q.target_height = 0;
+    return q;
+}
+
+// Temporaries of the height pass: the width-carved frames (when both
+// dimensions shrink), the transposed input and output, transposed masks.
+size_t height_temp_bytes(const scpl_params &p)
+{
+    if (!height_pass(p)) return 0;
+    const size_t N = p.n_frames, H = p.height, C = p.channels, Ws = p.target_width;
+    size_t b = 0;
+    if (p.target_width < p.width) b += align_up(N * H * Ws * C);
+    b += align_up(N * Ws * H * C) + align_up(N * Ws * p.target_height * C) + align_up(N * Ws * H * 2) +
+         align_up(N * 4);
+    return b;
+}
+
+// Workspace of the height pass run itself (plain path, one buffer at a time).
+size_t height_pass_bytes(const scpl_params &p)
+{
+    if (!height_pass(p)) return 0;
+    const scpl_params q = transposed_params(p);
+    JobShape js{q.height, q.width, q.target_width, q.seams_per_iter, dp_geom(q.width)};
+    size_t b = align_up((size_t)q.n_frames * tiled_frame_bytes(q.height, q.width));
+    b += seg_bytes((int64_t)q.height * q.width) + align_up(kSegWindow * 8);
+    b += job_bytes(js) + align_up(sizeof(Job) * (size_t)q.n_frames) + align_up(16 * (size_t)q.n_frames);
+    return b;
+}
+
 
 struct SegClip {
     const scpl_params *p;
@@ -742,6 +787,7 @@ void scpl_destroy(scpl_ctx *ctx)
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->jws) (void)hipFree(ctx->jws);
+    if (ctx->tws) (void)hipFree(ctx->tws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
@@ -756,6 +802,8 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
     size_t b = align_up((size_t)p->n_frames * tiled_frame_bytes(p->height, p->width));
     b += seg_bytes(HW) + align_up(kSegWindow * 8);
     b += job_bytes(js) + align_up(sizeof(Job) * (size_t)p->n_frames) + align_up(16 * (size_t)p->n_frames);
+    b = std::max<size_t>(b, height_pass_bytes(*p));
+    b += height_temp_bytes(*p);
     *device_bytes = b;
     return SCPL_OK;
 }
@@ -764,12 +812,13 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
 
 scpl_status scpl::trim_workspace(scpl_ctx *ctx, uint64_t keep)
 {
-    if ((uint64_t)ctx->ws_size + ctx->jws_size <= keep) return SCPL_OK;
+    if ((uint64_t)ctx->ws_size + ctx->jws_size + ctx->tws_size <= keep) return SCPL_OK;
     SCPL_TRY(hipSetDevice(ctx->device));
     if (ctx->ws) SCPL_TRY(hipFree(ctx->ws));  // waits for work that uses it
     if (ctx->jws) SCPL_TRY(hipFree(ctx->jws));
-    ctx->ws = ctx->jws = nullptr;
-    ctx->ws_size = ctx->jws_size = 0;
+    if (ctx->tws) SCPL_TRY(hipFree(ctx->tws));
+    ctx->ws = ctx->jws = ctx->tws = nullptr;
+    ctx->ws_size = ctx->jws_size = ctx->tws_size = 0;
     return SCPL_OK;
 }
 
@@ -783,6 +832,14 @@ uint64_t scpl::clip_footprint(const scpl_params &p)
     uint64_t b = align_up((size_t)N * tiled_frame_bytes(p.height, p.width));
     b += seg_bytes((int64_t)p.height * p.width) + align_up(kSegWindow * 8);
     b += N * (job_bytes(js) + sizeof(Job) + 16) + 2 * kAlign;
+    if (height_pass(p)) {
+        const scpl_params q = transposed_params(p);
+        JobShape jq{q.height, q.width, q.target_width, q.seams_per_iter, dp_geom(q.width)};
+        uint64_t b2 = align_up((size_t)N * tiled_frame_bytes(q.height, q.width));
+        b2 += seg_bytes((int64_t)q.height * q.width) + align_up(kSegWindow * 8);
+        b2 += N * (job_bytes(jq) + sizeof(Job) + 16) + 2 * kAlign;
+        b = std::max(b, b2) + height_temp_bytes(p);
+    }
     return b;
 }
 
@@ -935,6 +992,90 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
 
 extern "C" {
 
+}  // extern "C"
+
+// Width pass for every clip, then the height pass (transposed) for the clips
+// with a target height.  Each pass is one run of the clips it concerns.
+scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
+                               hipStream_t s, bool use_graph)
+{
+    bool any = false;
+    size_t tbytes = 0;
+    for (int c = 0; c < nc; ++c)
+        if (height_pass(clips[c].p)) {
+            any = true;
+            tbytes += height_temp_bytes(clips[c].p);
+            if (clips[c].p.target_width < clips[c].p.width && clips[c].d_masks) return SCPL_ERR_INVALID_ARG;
+        }
+    if (!any) return run_clips(ctx, clips, nc, batched, h_nbuf_first, s, use_graph);
+    SCPL_TRY(grow(ctx->tws, ctx->tws_size, tbytes));
+    std::vector<scpl_clip> pass1, pass2;
+    struct Back {
+        const scpl_clip *clip;
+        uint8_t *tout;
+        uint16_t *tmask;
+    };
+    std::vector<Back> back;
+    Bump tb{static_cast<char *>(ctx->tws)};
+    std::vector<uint8_t *> src2(nc, nullptr);
+    for (int c = 0; c < nc; ++c) {
+        const scpl_clip &cl = clips[c];
+        if (!height_pass(cl.p)) {
+            pass1.push_back(cl);
+            continue;
+        }
+        const size_t N = cl.p.n_frames, H = cl.p.height, C = cl.p.channels, Ws = cl.p.target_width;
+        if (cl.p.target_width < cl.p.width) {  // width first, into a temporary
+            scpl_clip w = cl;
+            w.p.target_height = 0;
+            w.d_out = tb.take<uint8_t>(N * H * Ws * C);
+            w.d_masks = nullptr;
+            src2[c] = w.d_out;
+            pass1.push_back(w);
+        }
+    }
+    int32_t nb1 = 0;
+    std::vector<int32_t> log1;
+    if (!pass1.empty()) {
+        SCPL_TRY(run_clips(ctx, pass1.data(), (int)pass1.size(), batched, &nb1, s, use_graph));
+        log1 = ctx->last_log;
+    }
+    for (int c = 0; c < nc; ++c) {
+        const scpl_clip &cl = clips[c];
+        if (!height_pass(cl.p)) continue;
+        const size_t N = cl.p.n_frames, H = cl.p.height, C = cl.p.channels, Ws = cl.p.target_width;
+        const size_t Ht = cl.p.target_height;
+        const bool both = cl.p.target_width < cl.p.width;
+        scpl_clip t{};
+        t.p = transposed_params(cl.p);
+        uint8_t *tin = tb.take<uint8_t>(N * Ws * H * C);
+        launch_transpose(both ? src2[c] : cl.d_frames, (int)N, (int)H, (int)Ws, (int)C, tin, s);
+        t.d_frames = tin;
+        t.d_out = tb.take<uint8_t>(N * Ws * Ht * C);
+        t.d_masks = (!both && cl.d_masks) ? tb.take<uint16_t>(N * Ws * H) : nullptr;
+        int32_t *tbid = tb.take<int32_t>(N);
+        t.d_buffer_id = both ? tbid : cl.d_buffer_id;
+        pass2.push_back(t);
+        back.push_back({&cl, t.d_out, t.d_masks});
+    }
+    SCPL_CHECK_LAUNCH();
+    int32_t nb2 = 0;
+    SCPL_TRY(run_clips(ctx, pass2.data(), (int)pass2.size(), batched, &nb2, s, use_graph));
+    for (const Back &b : back) {
+        const scpl_clip &cl = *b.clip;
+        const int N = cl.p.n_frames, H = cl.p.height, Ws = cl.p.target_width, Ht = cl.p.target_height;
+        launch_transpose(b.tout, N, Ws, Ht, cl.p.channels, cl.d_out, s);
+        if (b.tmask) launch_transpose16(b.tmask, N, Ws, H, cl.d_masks, s);
+    }
+    SCPL_CHECK_LAUNCH();
+    log1.insert(log1.end(), ctx->last_log.begin(), ctx->last_log.end());
+    ctx->last_log.swap(log1);
+    if (h_nbuf_first) *h_nbuf_first = height_pass(clips[0].p) && clips[0].p.target_width == clips[0].p.width ? nb2 : nb1;
+    return SCPL_OK;
+}
+
+extern "C" {
+
 scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
                           uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream)
 {
@@ -943,7 +1084,7 @@ scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_
     if (st != SCPL_OK) return st;
     SCPL_TRY(hipSetDevice(ctx->device));
     scpl_clip c{*p, d_frames, d_out, d_masks, d_buffer_id};
-    return run_clips(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
+    return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
 }
 
 scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, void *stream)
@@ -955,7 +1096,7 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         if (!clips[c].d_frames || !clips[c].d_out) return SCPL_ERR_INVALID_ARG;
     }
     SCPL_TRY(hipSetDevice(ctx->device));
-    return run_clips(ctx, clips, n_clips, true, nullptr, static_cast<hipStream_t>(stream));
+    return run_clips_2d(ctx, clips, n_clips, true, nullptr, static_cast<hipStream_t>(stream));
 }
 
 scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n)

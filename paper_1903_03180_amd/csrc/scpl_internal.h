@@ -129,6 +129,9 @@ size_t gather_lds_bytes(int W, int Wt, int C);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
+// N frames H x W of C-byte pixels -> N frames W x H (and of 16-bit entries)
+void launch_transpose(const uint8_t *src, int N, int H, int W, int C, uint8_t *dst, hipStream_t s);
+void launch_transpose16(const uint16_t *src, int N, int H, int W, uint16_t *dst, hipStream_t s);
 // one frame H x W x C minus kk seams (kk x H int32 columns) -> H x (W - kk) x C
 void launch_compact_frame(const uint8_t *in, int H, int W, int C, const int32_t *seams, int kk, uint8_t *out,
                           hipStream_t s);

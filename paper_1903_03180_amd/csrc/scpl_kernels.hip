@@ -1386,6 +1386,38 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
     }
 }
 
+// ---------------------------------------------------------- transposes
+//
+// Height retargeting carves the transposed frames.  dst[n][w][h] = src[n][h][w]
+// for elements of E bytes (a pixel of C channels, or a 16-bit mask entry);
+// a block moves a 32 x 32 tile through LDS so both sides are read and
+// written along rows.
+
+template <int E>
+__global__ __launch_bounds__(256) void transpose_kernel(const uint8_t *__restrict__ src, int H, int W,
+                                                        uint8_t *__restrict__ dst)
+{
+    __shared__ uint8_t tile[32][32 * E + 4];
+    const size_t n = blockIdx.z;
+    const int h0 = blockIdx.y * 32, w0 = blockIdx.x * 32;
+    const uint8_t *s = src + n * H * (size_t)W * E;
+    uint8_t *d = dst + n * H * (size_t)W * E;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int h = h0 + r, w = w0 + tx;
+        if (h < H && w < W)
+#pragma unroll
+            for (int e = 0; e < E; ++e) tile[r][tx * E + e] = s[((size_t)h * W + w) * E + e];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int w = w0 + r, h = h0 + tx;
+        if (h < H && w < W)
+#pragma unroll
+            for (int e = 0; e < E; ++e) d[((size_t)w * H + h) * E + e] = tile[tx][r * E + e];
+    }
+}
+
 // -------------------------------------------------- one-frame compaction
 //
 // Stage entry point of the one-pass removal (Sec. 3.1): row i of an H x W x
@@ -1682,6 +1714,20 @@ void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch
 {
     hipLaunchKernelGGL(keys_to_u_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
                        pitch);
+}
+
+void launch_transpose(const uint8_t *src, int N, int H, int W, int C, uint8_t *dst, hipStream_t s)
+{
+    const dim3 g(blocks_for(W, 32), blocks_for(H, 32), N);
+    if (C == 3) hipLaunchKernelGGL(transpose_kernel<3>, g, dim3(256), 0, s, src, H, W, dst);
+    else hipLaunchKernelGGL(transpose_kernel<1>, g, dim3(256), 0, s, src, H, W, dst);
+}
+
+void launch_transpose16(const uint16_t *src, int N, int H, int W, uint16_t *dst, hipStream_t s)
+{
+    const dim3 g(blocks_for(W, 32), blocks_for(H, 32), N);
+    hipLaunchKernelGGL(transpose_kernel<2>, g, dim3(256), 0, s, reinterpret_cast<const uint8_t *>(src), H, W,
+                       reinterpret_cast<uint8_t *>(dst));
 }
 
 void launch_compact_frame(const uint8_t *in, int H, int W, int C, const int32_t *seams, int kk, uint8_t *out,

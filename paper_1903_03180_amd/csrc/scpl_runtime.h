@@ -19,6 +19,11 @@ namespace scpl {
 scpl_status run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
                       hipStream_t s, bool use_graph = true);
 
+// run_clips with height retargeting: the width pass of every clip, then the
+// transposed height pass of the clips with a target height.
+scpl_status run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
+                         hipStream_t s, bool use_graph = true);
+
 // Upper bound of the device bytes a batched retarget of one clip claims.
 uint64_t clip_footprint(const scpl_params &p);
 

@@ -89,7 +89,7 @@ void lane_main(scpl_server *S, int li)
         }
         // no graph capture here: the caller's threads may synchronise the
         // device at any time
-        scpl_status res = scpl::run_clips(ctx, clips.data(), (int)clips.size(), true, nullptr, st, false);
+        scpl_status res = scpl::run_clips_2d(ctx, clips.data(), (int)clips.size(), true, nullptr, st, false);
         if (res == SCPL_OK && hipStreamSynchronize(st) != hipSuccess) res = SCPL_ERR_DEVICE;
         if (res == SCPL_OK) res = scpl::trim_workspace(ctx, kLaneKeep);
         {

@@ -50,7 +50,7 @@ KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update"
 class scpl_params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "n_frames", "height", "width", "channels", "target_width", "seams_per_iter", "energy_mode",
-        "use_buffer", "alpha_num", "alpha_den", "max_buffer")]
+        "use_buffer", "alpha_num", "alpha_den", "max_buffer", "target_height")]
 
 
 class scpl_clip(C.Structure):
@@ -125,11 +125,12 @@ class Params:
     alpha_num: int = 1
     alpha_den: int = 5
     max_buffer: int = 0
+    target_height: int = 0
 
     def c(self) -> scpl_params:
         return scpl_params(self.n_frames, self.height, self.width, self.channels, self.target_width,
                            self.seams_per_iter, self.energy_mode, self.use_buffer, self.alpha_num,
-                           self.alpha_den, self.max_buffer)
+                           self.alpha_den, self.max_buffer, self.target_height)
 
 
 def _ptr(t) -> int | None:
@@ -184,10 +185,12 @@ class Context:
         Returns dict(out, masks, buffer_id, n_buffers)."""
         import torch
         p = params_for(frames, target_width, seams_per_iter, **kw)
-        shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if frames.dim() == 4 else ())
+        Ht = p.target_height or p.height
+        shp = (p.n_frames, Ht, p.target_width) + ((p.channels,) if frames.dim() == 4 else ())
         out = torch.empty(shp, dtype=torch.uint8, device=frames.device)
+        both = Ht < p.height and p.target_width < p.width
         masks = torch.empty((p.n_frames, p.height, p.width), dtype=torch.int16, device=frames.device) \
-            if want_masks else None
+            if want_masks and not both else None
         bid = torch.empty(p.n_frames, dtype=torch.int32, device=frames.device)
         nb = C.c_int32(0)
         cp = p.c()
@@ -205,9 +208,10 @@ class Context:
         arr = (scpl_clip * len(clips))()
         for i, c in enumerate(clips):
             fr = c["frames"]
-            kw = {k: c[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer") if k in c}
+            kw = {k: c[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer",
+                                    "target_height") if k in c}
             p = params_for(fr, c["target_width"], c["seams_per_iter"], **kw)
-            shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
+            shp = (p.n_frames, p.target_height or p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
             if c.get("out") is None:
                 c["out"] = torch.empty(shp, dtype=torch.uint8, device=fr.device)
             if c.get("masks") is None and c.get("want_masks", False):
@@ -366,9 +370,10 @@ class Server:
     def submit(self, clip: dict) -> int:
         import torch
         fr = clip["frames"]
-        kw = {k: clip[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer") if k in clip}
+        kw = {k: clip[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer",
+                                   "target_height") if k in clip}
         p = params_for(fr, clip["target_width"], clip["seams_per_iter"], **kw)
-        shp = (p.n_frames, p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
+        shp = (p.n_frames, p.target_height or p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
         if clip.get("out") is None:
             clip["out"] = torch.empty(shp, dtype=torch.uint8, device=fr.device)
         if clip.get("masks") is None and clip.get("want_masks", False):

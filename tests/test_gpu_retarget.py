@@ -219,3 +219,51 @@ def test_uncapped_one_seam_per_parent(ctx, orc):
     taken literally)."""
     clip = synth.make_clip(960, 12, 40, 96, C=1, n_obj=3, cut_at=6, lattice=8)
     compare(ctx, orc, clip, 60, 96)
+
+
+# --------------------------------------------------- height and 2-D retargeting
+
+def compare_2d(ctx, orc, frames, Wt, Ht, k, **kw):
+    want_masks = not (Wt < frames.shape[2] and Ht < frames.shape[1])
+    res = ctx.retarget(dev(frames), Wt, k, want_masks=want_masks, target_height=Ht, **kw)
+    okw = dict(mode=kw.get("energy_mode", 1), use_buffer=kw.get("use_buffer", 1), anum=kw.get("alpha_num", 1),
+               aden=kw.get("alpha_den", 5), max_buffer=kw.get("max_buffer", 0))
+    want = orc.retarget_2d(frames, Wt, Ht, k, **okw)
+    assert np.array_equal(res["out"].cpu().numpy(), want["out"])
+    assert np.array_equal(res["buffer_id"].cpu().numpy(), want["buffer_id"])
+    assert np.array_equal(ctx.last_log(), want["log"])
+    if want_masks:
+        assert np.array_equal(masks_u16(res["masks"]), want["masks"])
+
+
+@pytest.mark.parametrize("seed,N,H,W,C,Wt,Ht,k", [
+    (1, 8, 40, 30, 3, 30, 29, 4),      # height only
+    (2, 12, 64, 48, 1, 48, 40, 16),
+    (3, 7, 35, 60, 3, 45, 28, 3),      # both: width first, then height
+    (4, 5, 90, 33, 1, 20, 70, 1000),
+])
+def test_height_and_2d(ctx, orc, seed, N, H, W, C, Wt, Ht, k):
+    clip = synth.make_clip(700 + seed, N, H, W, C=C, n_obj=3, cut_at=N // 2, lattice=8)
+    compare_2d(ctx, orc, clip, Wt, Ht, k)
+
+
+def test_batch_mixed_directions(ctx, orc):
+    specs = [(710, 9, 30, 50, 3, 40, 30), (711, 6, 44, 26, 1, 26, 33), (712, 10, 28, 40, 1, 31, 20)]
+    clips, host = [], []
+    for seed, N, H, W, C, Wt, Ht in specs:
+        f = synth.make_clip(seed, N, H, W, C=C, n_obj=2, cut_at=N // 2, lattice=8)
+        host.append((f, Wt, Ht))
+        clips.append(dict(frames=dev(f), target_width=Wt, target_height=Ht, seams_per_iter=6))
+    ctx.retarget_batch(clips)
+    torch.cuda.synchronize()
+    for c, (f, Wt, Ht) in zip(clips, host):
+        want = orc.retarget_2d(f, Wt, Ht, 6)
+        assert np.array_equal(c["out"].cpu().numpy(), want["out"])
+        assert np.array_equal(c["buffer_id"].cpu().numpy(), want["buffer_id"])
+
+
+def test_2d_masks_are_refused(ctx):
+    from paper_1903_03180_amd import scpl
+    f = dev(synth.make_clip(720, 4, 30, 30, C=1, n_obj=2, lattice=8))
+    with pytest.raises(scpl.ScplError):
+        ctx.retarget_batch([dict(frames=f, target_width=20, target_height=20, seams_per_iter=4, want_masks=True)])

@@ -54,6 +54,7 @@ def wsize(lib, p):
     dict(height=32768), dict(height=30000, width=30000), dict(channels=2), dict(target_width=0),
     dict(target_width=1921), dict(seams_per_iter=0), dict(energy_mode=2), dict(use_buffer=2),
     dict(alpha_num=-1), dict(alpha_den=0), dict(alpha_num=1025), dict(alpha_den=1025), dict(max_buffer=-1),
+    dict(target_height=-1), dict(target_height=1081),
 ])
 def test_invalid_params_rejected(lib, kw):
     st, _ = wsize(lib, base(**kw))
@@ -69,6 +70,9 @@ def test_workspace_size_scales(lib):
     assert a == b >= 120 * 1080 * 1920
     st, c = wsize(lib, base(height=2160, width=3840, target_width=2880, channels=1, n_frames=60))
     assert c > b
+    # a height pass adds its transposed frames
+    st, d = wsize(lib, base(target_height=720))
+    assert st == lib.SCPL_OK and d > a
 
 
 def test_null_context_and_pointers_rejected(lib):

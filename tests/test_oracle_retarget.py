@@ -179,3 +179,25 @@ def test_table1_target_width_rounding():
     assert len(rows) == 10
     for w, t, n, d in rows:
         assert target_width(int(w), int(n), int(d)) == int(t)
+
+
+def test_height_retarget_is_width_retarget_of_the_transpose(orc):
+    """Horizontal seams (Sec. 2): carving the height of a clip equals
+    carving the width of its transpose; every output column keeps its
+    pixels' order and loses exactly H - Ht of them."""
+    from paper_1903_03180_amd import synth
+    clip = synth.make_clip(41, 6, 30, 24, C=3, n_obj=2, lattice=8)
+    r = orc.retarget_2d(clip, 24, 21, 4)
+    assert r["out"].shape == (6, 21, 24, 3)
+    m = r["masks"]
+    assert np.all((m > 0).sum(axis=1) == 30 - 21)
+    for t in range(6):
+        for j in range(24):
+            keep = m[t][:, j] == 0
+            assert np.array_equal(r["out"][t][:, j], clip[t][keep, j])
+    # 2-D: width first, then height of the result
+    r2 = orc.retarget_2d(clip, 18, 21, 4)
+    w = orc.retarget(clip, 18, 4)
+    h = orc.retarget(np.swapaxes(w["out"], 1, 2), 21, 4)
+    assert np.array_equal(r2["out"], np.swapaxes(h["out"], 1, 2))
+    assert r2["masks"] is None and np.array_equal(r2["buffer_id"], w["buffer_id"])
