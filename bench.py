@@ -45,11 +45,9 @@ def _gen(args):
 
 def make_workload(name):
     """[(clip, target width, seams per iteration)], description."""
-    from multiprocessing import Pool
     if name == "1080p-batch16":
         seeds = list(range(2000, 2016))
-        with Pool(8) as pool:
-            clips = pool.map(_gen, [("1080p", s) for s in seeds])
+        clips = [_gen(("1080p", s)) for s in seeds]
         return [(c, 1440, 16) for c in clips], (
             "16 clips x 120 frames 1920x1080 RGB (1080p generator, seeds 2000-2015) -> 1440 wide, k=16 "
             "seams/iteration, alpha=1/5, motion energy")
@@ -59,8 +57,7 @@ def make_workload(name):
     if name == "mix64":
         from paper_1903_03180_amd import synth
         specs = synth.batch_mix_specs(64)
-        with Pool(8) as pool:
-            clips = pool.map(_gen_spec, specs)
+        clips = [_gen_spec(sp) for sp in specs]
         return [(c, s.Wt, 16) for c, s in zip(clips, specs)], (
             "64 clips of uneven size (luma, widths 480-2560, heights 360-1440, aspect 1:1-21:9, 30-240 frames, "
             "seeds 4000-4063) -> 3/4 of the width, k=16 seams/iteration, alpha=1/5, motion energy")
@@ -81,12 +78,10 @@ def serving_pool(n_mix, n_4k):
     """Requests drawn from the uneven batch mix (luma, widths 480-2560,
     heights 360-1440, 30-240 frames, target 3/4 of the width) plus 4K jobs
     (60 frames 3840x2160 luma)."""
-    import multiprocessing as mp
     from paper_1903_03180_amd import synth
     specs = synth.batch_mix_specs(n_mix)
     jobs = list(specs) + [("4k", 5000 + j) for j in range(n_4k)]
-    with mp.get_context("spawn").Pool(8) as pool:  # this process already uses the GPU: fresh workers
-        clips = pool.map(_gen_spec, jobs)
+    clips = [_gen_spec(j) for j in jobs]
     wt = [s.Wt for s in specs] + [2880] * n_4k
     k = [16] * n_mix + [32] * n_4k
     return clips, wt, k
@@ -170,10 +165,8 @@ def run_table1(np, torch, scpl, ctx):
     motion energy) against Raw (classic seam carving of every frame: one
     seam per iteration, no buffer, gradient energy) on synthetic RGB clips
     of Table 1's shapes, lengths and target widths, both on this GPU."""
-    import multiprocessing as mp
     import time as _t
-    with mp.get_context("spawn").Pool(8) as pool:
-        clips = pool.map(_gen_table1, list(enumerate(TABLE1)))
+    clips = [_gen_table1(r) for r in enumerate(TABLE1)]
     rows = []
     for (name, W, H, N, Wt, p_s, r_s), c in zip(TABLE1, clips):
         fr = torch.from_numpy(c).cuda()
@@ -239,6 +232,25 @@ def dp_bytes(per_job, jobs):
     buffer at width W_r, the 2-byte key of every carved pixel is read once
     and its 1-byte indicator code written once."""
     return sum(3 * jb["H"] * int(r[1]) for rows, jb in zip(per_job, jobs) for r in rows)
+
+
+def measured_dp_traffic(workload, q, hb, pf):
+    """HBM bytes per DP dispatch from the committed FETCH_SIZE / WRITE_SIZE
+    runs (scaled by the 1 GiB copy), if they were taken on this workload
+    with this DP kernel and the kernel source has not changed since; else
+    None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"dp_traffic_{workload.replace('-', '_')}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1903_03180_amd", "csrc", "scpl_kernels.hip")
+    with open(src, "rb") as f:
+        same = hashlib.sha256(f.read()).hexdigest() == rec["kernels_source_sha256"]
+    if not same or rec["kernel"] != f"dp_band_kernel<{q}, {hb}, {pf}>":
+        return None
+    return rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]
 
 
 def main() -> int:
@@ -335,6 +347,7 @@ def main() -> int:
     per_job = job_rows(log_rows, jobs)
     dp_bytes_launch = dp_bytes(per_job, jobs) * args.steps / max(dp_n, 1)
     achieved = dp_bytes_launch / (dp_launch_ms * 1e-3) / 1e9
+    traffic = measured_dp_traffic(args.workload, dpq, dphb, dppf)
 
     # plain path: clips one after another, buffers one after another
     plain_fps = None
@@ -423,7 +436,7 @@ def main() -> int:
         "kernel_ms_per_step": {kn: round(v[0] / args.steps, 4) for kn, v in prof.items() if v[1]},
         "dominant_kernel": dom,
         "roofline": {"kernel": "dp", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(dp_bytes_launch), "launch_ms": round(dp_launch_ms, 4)},
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
