@@ -152,7 +152,7 @@ size_t job_bytes(const JobShape &s)
     size_t b = 0;
     b += 2 * align_up(H * Wp * 2);       // M0, M1
     b += 2 * align_up((H + 1) * (size_t)s.Kp() * 2);  // K0, K1
-    b += align_up(H * Wp);               // dir
+    b += align_up(H * Wp + kDirScratch);  // dir + scratch row of discarded codes
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
     b += 2 * align_up(Wp * 4);           // ce_last, lab_last
@@ -183,7 +183,7 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.M1 = bp.take<int16_t>(H * Wp);
     J.K0 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
     J.K1 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
-    J.dir = bp.take<uint8_t>(H * Wp);
+    J.dir = bp.take<uint8_t>(H * Wp + kDirScratch);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
     J.ce_last = bp.take<int32_t>(Wp);

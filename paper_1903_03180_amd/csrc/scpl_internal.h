@@ -59,7 +59,8 @@ struct Job {
     uint16_t *K0, *K1;      // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
                             // 0xffff left of column 0 and at and beyond W_r; (H + 1) rows, the
                             // extra row all 0xffff
-    uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp
+    uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp,
+                            // then kDirScratch bytes the DP writes discarded codes to
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
     int32_t *ce_last;       // DP last row, Wp
@@ -113,6 +114,7 @@ bool dp_geom_fits(const DpGeom &g, int Wmax);
 extern const DpGeom kDpVariants[];
 extern const int kNumDpVariants;
 constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
+constexpr int kDirScratch = 64 * 16;  // after the indicator rows: discarded codes of one row (64 lanes x Q <= 16)
 void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStream_t s);
 void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s);
 void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s);

@@ -732,7 +732,11 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs)
     const uint16_t *K = (r & 1) ? J.K1 : J.K0;
     const uint16_t *kp = live ? K + J.KL + jl : K + (size_t)H * Kp;
     const size_t kstride = live ? (size_t)Kp : 0;
-    uint8_t *__restrict__ dir = J.dir;
+    // every lane stores its codes each row: lanes whose codes are not kept
+    // (halo, past the width) write to the job's scratch row instead, so
+    // the row loop has no branch around the store
+    uint8_t *__restrict__ cbase = stores ? J.dir + jl : J.dir + (size_t)H * Wp + lane * Q;
+    const size_t cstride = stores ? (size_t)Wp : 0;
 
     uint32_t key[Q];
     {
@@ -744,8 +748,10 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs)
             key[c] = k0.at(c);
             code[c] = 1;
         }
-        if (stores) store_codes<Q>(dir + jl, code);
+        store_codes<Q>(cbase, code);
     }
+    // neighbour registers: lane 0's left and lane 63's right stay all ones
+    uint32_t lnb = kKeyInf, rnb = kKeyInf;
     KRow<Q> cur[PF], nxt[PF];
 #pragma unroll
     for (int s = 0; s < PF; ++s) load_krow<Q>(cur[s], kp + (size_t)min(1 + s, H - 1) * kstride);
@@ -777,13 +783,11 @@ __global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs)
                     buf ^= 1;
                     band_left = HB;
                 }
-                const uint32_t lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[Q - 1], 0x138, 0xf,
-                                                                           0xf, false);
-                const uint32_t rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)kKeyInf, (int)key[0], 0x130, 0xf,
-                                                                           0xf, false);
+                lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
+                rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)rnb, (int)key[0], 0x130, 0xf, 0xf, false);
                 uint32_t best[Q];
                 dp_step<Q>(key, lnb, rnb, cur[s], best);
-                if (stores) store_codes<Q>(dir + (size_t)i * Wp + jl, best);
+                store_codes<Q>(cbase + (size_t)i * cstride, best);
                 --band_left;
             }
         }
