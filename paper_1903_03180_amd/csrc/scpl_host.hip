@@ -367,7 +367,7 @@ struct SegClip {
 // candidate frames; after one synchronisation the host accepts each clip's
 // candidates in order and restarts that clip from its first rejected frame.
 scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long long *d_sums,
-                          unsigned long long *h_sums, hipStream_t s)
+                          unsigned long long *h_sums, SegArgs *d_args, SegArgs *h_args, hipStream_t s)
 {
     const int nc = (int)cl.size();
     for (SegClip &c : cl) {
@@ -388,6 +388,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
     }
     for (;;) {
         bool any = false;
+        int na = 0, ntc_max = 0, h_max = 0;
         for (int ci = 0; ci < nc; ++ci) {
             SegClip &c = cl[ci];
             c.launched = false;
@@ -426,16 +427,21 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
             a.tb = c.t;
             a.te = c.te;
             a.init = c.valid ? 0 : 1;
-            if (!any) SCPL_TRY(hipMemsetAsync(d_sums, 0, (size_t)nc * kSegWindow * 8, s));
-            {
-                ProfScope ps(ctx, SCPL_KERNEL_SEGMENT, s);
-                launch_seg_window(a, s);
-            }
-            SCPL_CHECK_LAUNCH();
+            h_args[na++] = a;
+            ntc_max = std::max(ntc_max, c.ntc);
+            h_max = std::max(h_max, p->height);
             c.launched = true;
             any = true;
         }
         if (!any) break;
+        // one launch scans the windows of every open clip
+        SCPL_TRY(hipMemsetAsync(d_sums, 0, (size_t)nc * kSegWindow * 8, s));
+        SCPL_TRY(hipMemcpyAsync(d_args, h_args, sizeof(SegArgs) * (size_t)na, hipMemcpyHostToDevice, s));
+        {
+            ProfScope ps(ctx, SCPL_KERNEL_SEGMENT, s);
+            launch_seg_windows(d_args, na, ntc_max, h_max, s);
+        }
+        SCPL_CHECK_LAUNCH();
         SCPL_TRY(hipMemcpyAsync(h_sums, d_sums, (size_t)nc * kSegWindow * 8, hipMemcpyDeviceToHost, s));
         SCPL_TRY(hipStreamSynchronize(s));
         for (int ci = 0; ci < nc; ++ci) {
@@ -858,18 +864,22 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         a_bytes += seg_bytes((int64_t)p.height * p.width);
         Ntot += p.n_frames;
     }
+    a_bytes += align_up(sizeof(SegArgs) * (size_t)nc);
     SCPL_TRY(ensure_ws(ctx, a_bytes));
     const size_t pin_b = align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) +
-                         align_up(16 * (size_t)Ntot) + align_up(sizeof(Job) * (size_t)Ntot);
+                         align_up(16 * (size_t)Ntot) + align_up(sizeof(Job) * (size_t)Ntot) +
+                         align_up(sizeof(SegArgs) * (size_t)nc);
     SCPL_TRY(ensure_pinned(ctx, pin_b));
     Bump host{static_cast<char *>(ctx->pinned)};
     unsigned long long *h_sums = host.take<unsigned long long>((size_t)nc * kSegWindow);
+    SegArgs *h_args = host.take<SegArgs>((size_t)nc);
     int32_t *h_bid_all = host.take<int32_t>((size_t)Ntot);
     int32_t *h_states = host.take<int32_t>(4 * (size_t)Ntot);
     Job *h_jobs = host.take<Job>((size_t)Ntot);
 
     Bump dev{static_cast<char *>(ctx->ws)};
     unsigned long long *d_sums = dev.take<unsigned long long>((size_t)nc * kSegWindow);
+    SegArgs *d_args = dev.take<SegArgs>((size_t)nc);
     std::vector<SegClip> seg(nc);
     int64_t off = 0;
     for (int c = 0; c < nc; ++c) {
@@ -888,7 +898,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         launch_tile_luma(clips[c].d_frames, p.channels, p.n_frames, p.height, p.width, tiled, s);
     }
     SCPL_CHECK_LAUNCH();
-    scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, s);
+    scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
     if (st != SCPL_OK) return st;
     for (int c = 0; c < nc; ++c)
         if (clips[c].d_buffer_id)
@@ -1424,11 +1434,16 @@ scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t HW = (int64_t)p->height * p->width;
     const int64_t FS = tiled_frame_bytes(p->height, p->width);
-    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up((size_t)p->n_frames * FS) + seg_bytes(HW)));
-    SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8)));
+    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up(sizeof(SegArgs)) + align_up((size_t)p->n_frames * FS) +
+                                seg_bytes(HW)));
+    SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8) + align_up(sizeof(SegArgs))));
     Bump dev{static_cast<char *>(ctx->ws)};
     unsigned long long *d_sums = dev.take<unsigned long long>(kSegWindow);
+    SegArgs *d_args = dev.take<SegArgs>(1);
     uint8_t *tiled = dev.take<uint8_t>((size_t)p->n_frames * FS);
+    Bump host{static_cast<char *>(ctx->pinned)};
+    unsigned long long *h_sums = host.take<unsigned long long>(kSegWindow);
+    SegArgs *h_args = host.take<SegArgs>(1);
     std::vector<SegClip> seg(1);
     seg[0].p = p;
     seg[0].tiled = tiled;
@@ -1439,7 +1454,7 @@ scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
     seg[0].trace = h_s_trace;
     launch_tile_luma(d_luma, 1, p->n_frames, p->height, p->width, tiled, s);
     SCPL_CHECK_LAUNCH();
-    st = segment_clips(ctx, seg, d_sums, static_cast<unsigned long long *>(ctx->pinned), s);
+    st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
     if (h_n_buffers) *h_n_buffers = seg[0].nbuf;
     return st;
 }
@@ -1458,10 +1473,12 @@ scpl_status scpl_asde(scpl_ctx *ctx, int32_t n, int32_t H, int32_t W, int32_t mo
     const int64_t FS = tiled_frame_bytes(H, W);
     const int pre = (d_prev && mode == SCPL_ENERGY_MOTION) ? 1 : 0;  // tiled frame 0 is the predecessor
     const int nt = n + pre;
-    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up((size_t)nt * FS) + seg_bytes(HW)));
-    SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8)));
+    SCPL_TRY(ensure_ws(ctx, align_up(kSegWindow * 8) + align_up(sizeof(SegArgs)) + align_up((size_t)nt * FS) +
+                                seg_bytes(HW)));
+    SCPL_TRY(ensure_pinned(ctx, align_up(kSegWindow * 8) + align_up(sizeof(SegArgs))));
     Bump dev{static_cast<char *>(ctx->ws)};
     unsigned long long *d_sums = dev.take<unsigned long long>(kSegWindow);
+    SegArgs *d_args = dev.take<SegArgs>(1);
     uint8_t *tiled = dev.take<uint8_t>((size_t)nt * FS);
     char *state = dev.take<char>(seg_bytes(HW));
     if (pre) launch_tile_luma(d_prev, 1, 1, H, W, tiled, s);
@@ -1470,7 +1487,9 @@ scpl_status scpl_asde(scpl_ctx *ctx, int32_t n, int32_t H, int32_t W, int32_t mo
     // the moments start from the first frame and take the others in windows
     // of candidates; the sum after the last one is S of the whole buffer
     uint64_t S = 0;  // a single frame has no deviation
-    unsigned long long *h_sums = static_cast<unsigned long long *>(ctx->pinned);
+    Bump host{static_cast<char *>(ctx->pinned)};
+    unsigned long long *h_sums = host.take<unsigned long long>(kSegWindow);
+    SegArgs *h_args = host.take<SegArgs>(1);
     for (int tb = pre + 1; tb < nt; tb += kSegWindow) {
         SegArgs a{};
         Bump bp{state};
@@ -1488,7 +1507,10 @@ scpl_status scpl_asde(scpl_ctx *ctx, int32_t n, int32_t H, int32_t W, int32_t mo
         a.te = std::min(nt, tb + kSegWindow);
         a.init = tb == pre + 1 ? 1 : 0;
         SCPL_TRY(hipMemsetAsync(d_sums, 0, kSegWindow * 8, s));
-        launch_seg_window(a, s);
+        SCPL_TRY(hipStreamSynchronize(s));  // the pinned argument slot is reused
+        *h_args = a;
+        SCPL_TRY(hipMemcpyAsync(d_args, h_args, sizeof(SegArgs), hipMemcpyHostToDevice, s));
+        launch_seg_windows(d_args, 1, tiles_across(W), H, s);
         SCPL_CHECK_LAUNCH();
         if (a.te == nt) {
             SCPL_TRY(hipMemcpyAsync(h_sums, d_sums, kSegWindow * 8, hipMemcpyDeviceToHost, s));

@@ -93,7 +93,8 @@ void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
 void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *dst, hipStream_t s);
 // N tiled luma frames -> row-major H x W
 void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s);
-void launch_seg_window(const SegArgs &a, hipStream_t s);
+// window scans of n clips (d_args: n SegArgs in device memory), one grid layer each
+void launch_seg_windows(const SegArgs *d_args, int n, int ntc_max, int Hmax, hipStream_t s);
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 // DP geometry of a launch, chosen from its widest job: Q columns per

@@ -301,9 +301,11 @@ __device__ __forceinline__ void energy8(const int (&a)[10], const int (&b)[10], 
 
 constexpr int kSegRows = 2;
 
-__global__ __launch_bounds__(256) void seg_window_kernel(SegArgs a)
+__global__ __launch_bounds__(256) void seg_window_kernel(const SegArgs *args)
 {
     __shared__ unsigned long long part[kSegWindow];
+    const SegArgs &a = args[blockIdx.z];  // one clip's window per grid layer
+    if ((int)blockIdx.x * 64 >= a.ntc || (int)blockIdx.y * 4 * kSegRows >= a.H) return;
     const int tid = threadIdx.x;
     if (tid < kSegWindow) part[tid] = 0;
     __syncthreads();
@@ -1528,10 +1530,10 @@ void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s)
         hipLaunchKernelGGL(luma_vec_kernel, dim3(blocks_for(npx, 256 * 16)), dim3(256), 0, s, rgb, y, npx);
 }
 
-void launch_seg_window(const SegArgs &a, hipStream_t s)
+void launch_seg_windows(const SegArgs *d_args, int n, int ntc_max, int Hmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(tiles_across(a.W), 64), blocks_for(a.H, 4 * kSegRows)),
-                       dim3(256), 0, s, a);
+    hipLaunchKernelGGL(seg_window_kernel, dim3(blocks_for(ntc_max, 64), blocks_for(Hmax, 4 * kSegRows), n),
+                       dim3(256), 0, s, d_args);
 }
 
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
