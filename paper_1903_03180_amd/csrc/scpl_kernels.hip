@@ -1166,7 +1166,11 @@ constexpr int kRefreshRows = 16;
 constexpr int kRefreshList = 512;
 constexpr int kRefreshSeams = 64;  // seams whose positions are staged in LDS
 
-__global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
+// NT threads per block: 256 when the launch has blocks enough to fill the
+// device; 1024 when it has few (a pixel's frames then split over more
+// threads, which shortens the block).
+template <int NT>
+__global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
 {
     __shared__ int R[kRefreshRows + 2][kRefreshSeams];  // rows i0-1 .. i0+16 (clamped): old column - s
     __shared__ int flist[kRefreshList];                 // (row in band << 16) | new column
@@ -1191,7 +1195,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
     const bool rl = kk <= kRefreshSeams;
     if (tid == 0) nf = 0;
     if (rl)
-        for (int idx = tid; idx < (nrows + 2) * kk; idx += 256) {
+        for (int idx = tid; idx < (nrows + 2) * kk; idx += NT) {
             const int ss = idx / (nrows + 2), rr = idx - ss * (nrows + 2);  // consecutive threads: same seam
             const int row = min(max(i0 - 1 + rr, 0), H - 1);
             R[rr][ss] = J.seams[(size_t)row * J.kcap + ss] - ss;
@@ -1225,7 +1229,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
     };
     // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
     const int ncand = kk * nrows * 9;
-    for (int u = tid; u < ncand; u += 256) {
+    for (int u = tid; u < ncand; u += NT) {
         const int s = u / (nrows * 9);
         const int rem = u - s * (nrows * 9);
         const int rb = rem / 9, slot = rem - rb * 9;
@@ -1261,7 +1265,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
     }
     __syncthreads();
     const int n = min(nf, kRefreshList);
-    for (int p = tid; p < n; p += 256) {
+    for (int p = tid; p < n; p += NT) {
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
         const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
         fst[p] = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp, Mn + (size_t)ip * Wp, im, i, ip, c,
@@ -1271,8 +1275,8 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
     __syncthreads();
     if (n > 0) {
         // pixel p gets threads p, p + n, ...; each sums every tpp-th frame
-        const int tpp = max(256 / n, 1);
-        for (int u = tid; u < n * tpp; u += 256) {
+        const int tpp = max(NT / n, 1);
+        for (int u = tid; u < n * tpp; u += NT) {
             const int p = u % n, sub = u / n;
             uint32_t acc = 0;
             int t = sub;
@@ -1286,7 +1290,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(const Job *jobs)
         }
     }
     __syncthreads();
-    for (int p = tid; p < n; p += 256) {
+    for (int p = tid; p < n; p += NT) {
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
         Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
     }
@@ -1690,7 +1694,9 @@ void launch_update(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
 
 void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for(Hmax, kRefreshRows), njobs), dim3(256), 0, s, d_jobs);
+    const dim3 g(blocks_for(Hmax, kRefreshRows), njobs);
+    if ((int64_t)g.x * njobs < 2 * 256) hipLaunchKernelGGL(refresh_kernel<1024>, g, dim3(1024), 0, s, d_jobs);
+    else hipLaunchKernelGGL(refresh_kernel<256>, g, dim3(256), 0, s, d_jobs);
 }
 
 void launch_advance(const Job *d_jobs, int njobs, hipStream_t s)
