@@ -267,3 +267,40 @@ def test_2d_masks_are_refused(ctx):
     f = dev(synth.make_clip(720, 4, 30, 30, C=1, n_obj=2, lattice=8))
     with pytest.raises(scpl.ScplError):
         ctx.retarget_batch([dict(frames=f, target_width=20, target_height=20, seams_per_iter=4, want_masks=True)])
+
+
+def test_1080p_batch_as_benchmarked(ctx, orc):
+    """The benchmark's launch configuration at full size: several 1080p
+    clips in one batched call, two stream groups, autotuned DP geometry.
+    Every clip equals its plain-path result bit for bit; the first clip is
+    also checked against the oracle (segmentation, first iteration of every
+    buffer) and through the invariants."""
+    seeds = [2000, 2001, 2002]
+    frames = [synth.clip_1080p(s) for s in seeds]
+    ctx.batch_streams(2)
+    ctx.autotune_dp(1080, 1920, n_jobs=3 * len(seeds))
+    try:
+        clips = [dict(frames=dev(f), target_width=1440, seams_per_iter=16, want_masks=True) for f in frames]
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+        for c in clips:
+            solo = ctx.retarget(c["frames"], 1440, 16)
+            assert torch.equal(c["out"], solo["out"]) and torch.equal(c["masks"], solo["masks"])
+            assert torch.equal(c["buffer_id"], solo["buffer_id"])
+        res = dict(out=clips[0]["out"], masks=clips[0]["masks"], buffer_id=clips[0]["buffer_id"])
+        check_full_size(orc, frames[0], res, 1440, 16, 1, 1, 5)
+    finally:
+        ctx.dp_geometry(0)
+
+
+def test_uneven_mix_batch_equals_plain(ctx):
+    """Clips of the uneven mix (luma, widths up to 2560, 30-240 frames) in
+    one batch give exactly their plain-path results."""
+    specs = [s for s in synth.batch_mix_specs(64)][:6]
+    clips = [dict(frames=dev(synth.clip_from_spec(s)), target_width=s.Wt, seams_per_iter=16) for s in specs]
+    ctx.retarget_batch(clips)
+    torch.cuda.synchronize()
+    for c, s in zip(clips, specs):
+        solo = ctx.retarget(c["frames"], s.Wt, 16, want_masks=False)
+        assert torch.equal(c["out"], solo["out"]), s
+        assert torch.equal(c["buffer_id"], solo["buffer_id"]), s
