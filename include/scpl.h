@@ -231,8 +231,9 @@ scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms,
  * scpl_dp_geometry forces (Q, HB, PF, EX) for every later launch it fits
  * (Q = 0: automatic; PF = 0: the default depth of (Q, HB)).  Valid (Q, HB,
  * PF): (2,8,8) (2,8,16) (4,8,8) (4,8,16) (4,16,8) (4,16,16) (8,16,4)
- * (8,16,8) (8,32,4) (16,32,2) (16,64,2), and (32,0,2) for the
- * row-synchronous kernel; EX is 0 or 1.
+ * (8,16,8) (8,16,16) (8,32,4) (8,32,8) (16,32,2) (16,32,4) (16,32,8)
+ * (16,64,2) (16,64,4), and (32,0,2) for the row-synchronous kernel; EX is
+ * 0 or 1.
  * scpl_autotune_dp times every geometry that fits width W with n_jobs
  * concurrent H x W synthetic energies per launch (as in a batched launch;
  * null stream, synchronises) and keeps the fastest for launches whose widest

@@ -714,8 +714,12 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs)
 // owners publish their keys of the band's last row in LDS (ping-pong), the
 // block meets at one barrier, and the halo lanes take the neighbours' keys.
 // Only owned columns store indicator codes.
+// Variants with a deep key prefetch (Q PF >= 64) are limited to 512
+// threads, which doubles the registers a lane may use.
+__host__ __device__ constexpr int dp_max_threads(int Q, int PF) { return Q * PF >= 64 ? 512 : 1024; }
+
 template <int Q, int HB, int PF>
-__global__ __launch_bounds__(1024) void dp_band_kernel(const Job *jobs)
+__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Job *jobs)
 {
     constexpr int C = 64 * Q - 2 * HB;
     static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
@@ -1567,15 +1571,16 @@ int DpGeom::threads(int Wmax) const
 
 // Banded variants (Q columns per lane, HB halo columns = rows per band, PF
 // rows of key prefetch); for each (Q, HB) the first listed PF is the default.
-const DpGeom kDpVariants[] = {{2, 8, 1, 8, 0},  {2, 8, 1, 16, 0},  {4, 8, 1, 8, 0},   {4, 8, 1, 16, 0},
-                              {4, 16, 1, 8, 0}, {4, 16, 1, 16, 0}, {8, 16, 1, 4, 0},  {8, 16, 1, 8, 0},
-                              {8, 32, 1, 4, 0}, {16, 32, 1, 2, 0}, {16, 64, 1, 2, 0}};
+const DpGeom kDpVariants[] = {{2, 8, 1, 8, 0},   {2, 8, 1, 16, 0},  {4, 8, 1, 8, 0},   {4, 8, 1, 16, 0},
+                              {4, 16, 1, 8, 0},  {4, 16, 1, 16, 0}, {8, 16, 1, 4, 0},  {8, 16, 1, 8, 0},
+                              {8, 16, 1, 16, 0}, {8, 32, 1, 4, 0},  {8, 32, 1, 8, 0},  {16, 32, 1, 2, 0},
+                              {16, 32, 1, 4, 0}, {16, 32, 1, 8, 0}, {16, 64, 1, 2, 0}, {16, 64, 1, 4, 0}};
 const int kNumDpVariants = (int)(sizeof(kDpVariants) / sizeof(kDpVariants[0]));
 
 bool dp_geom_fits(const DpGeom &g, int Wmax)
 {
     if (!g.banded) return true;
-    return g.C() > 0 && g.threads(Wmax) <= 1024 && (size_t)2 * (g.cover(Wmax) + 64) * 4 <= 65536;
+    return g.C() > 0 && g.threads(Wmax) <= dp_max_threads(g.Q, g.PF) && (size_t)2 * (g.cover(Wmax) + 64) * 4 <= 65536;
 }
 
 DpGeom dp_geom(int Wmax)
@@ -1615,9 +1620,14 @@ void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStrea
     SCPL_DP_CASE(4, 16, 16)
     SCPL_DP_CASE(8, 16, 4)
     SCPL_DP_CASE(8, 16, 8)
+    SCPL_DP_CASE(8, 16, 16)
     SCPL_DP_CASE(8, 32, 4)
+    SCPL_DP_CASE(8, 32, 8)
     SCPL_DP_CASE(16, 32, 2)
+    SCPL_DP_CASE(16, 32, 4)
+    SCPL_DP_CASE(16, 32, 8)
     SCPL_DP_CASE(16, 64, 2)
+    SCPL_DP_CASE(16, 64, 4)
 #undef SCPL_DP_CASE
     hipLaunchKernelGGL(dp_kernel<32>, grid, block, 0, s, d_jobs);  // unreachable for valid geometries
 }
@@ -1664,7 +1674,10 @@ void set_kernel_attributes(size_t lds_cap)
         reinterpret_cast<const void *>(&dp_band_kernel<4, 8, 16>), reinterpret_cast<const void *>(&dp_band_kernel<4, 16, 8>),
         reinterpret_cast<const void *>(&dp_band_kernel<4, 16, 16>), reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 4>),
         reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 8>), reinterpret_cast<const void *>(&dp_band_kernel<8, 32, 4>),
-        reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 2>), reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 2>)};
+        reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 2>), reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 2>),
+        reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 16>), reinterpret_cast<const void *>(&dp_band_kernel<8, 32, 8>),
+        reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 4>), reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 8>),
+        reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 4>)};
     for (const void *f : dps) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);

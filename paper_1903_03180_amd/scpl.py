@@ -42,7 +42,8 @@ EXPORTS = [
 ]
 
 DP_GEOMETRIES = [(2, 8, 8), (2, 8, 16), (4, 8, 8), (4, 8, 16), (4, 16, 8), (4, 16, 16), (8, 16, 4), (8, 16, 8),
-                 (8, 32, 4), (16, 32, 2), (16, 64, 2), (32, 0, 2)]
+                 (8, 16, 16), (8, 32, 4), (8, 32, 8), (16, 32, 2), (16, 32, 4), (16, 32, 8), (16, 64, 2), (16, 64, 4),
+                 (32, 0, 2)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
