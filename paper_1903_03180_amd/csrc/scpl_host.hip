@@ -529,6 +529,11 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
 
 // Iterations per replay of a group's graph.
 constexpr int kGraphIters = 8;
+// At most this many iterations of a group are enqueued per look at its
+// states.  Enqueueing more can fill the stream's hardware queue, and then
+// the host thread blocks inside the launch until the GPU drains it, while
+// the other groups' read-backs wait unanswered.
+constexpr int kMaxAhead = 32;
 
 // A group of jobs that advances in lock-step on one stream: every stage of
 // an iteration is one launch over the group's jobs.  Groups on different
@@ -601,7 +606,7 @@ scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
         SCPL_TRY(ce);
         SCPL_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
     }
-    SCPL_TRY(group_iterate(ctx, G, G.rfirst));
+    SCPL_TRY(group_iterate(ctx, G, std::min(G.rfirst, kMaxAhead)));
     return group_readback(G);
 }
 
@@ -631,7 +636,7 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
         return SCPL_OK;
     }
     if (G.r > G.ls.Wmax + kGraphIters + 1) return SCPL_ERR_INTERNAL;  // each iteration removes >= 1 column
-    SCPL_TRY(group_iterate(ctx, G, more));
+    SCPL_TRY(group_iterate(ctx, G, std::min(more, kMaxAhead)));
     return group_readback(G);
 }
 

@@ -713,10 +713,28 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs)
 // owned columns are still exact.  At the end of each band of HB rows the
 // owners publish their keys of the band's last row in LDS (ping-pong), the
 // block meets at one barrier, and the halo lanes take the neighbours' keys.
-// Only owned columns store indicator codes.
-// Variants with a deep key prefetch (Q PF >= 64) are limited to 512
-// threads, which doubles the registers a lane may use.
+// Only owned columns keep indicator codes.
+//
+// Key rows are read PF rows at a time into two register sets used in turn
+// (no copies between them), so a group of rows is requested a whole group
+// ahead of its use and waiting for it never waits for the codes stored
+// since.  Row addresses are wave-uniform (scalar) plus a fixed 32-bit byte
+// offset per lane.  Variants with a deep key prefetch (Q PF >= 64) are
+// limited to 512 threads, which doubles the registers a lane may use.
 __host__ __device__ constexpr int dp_max_threads(int Q, int PF) { return Q * PF >= 64 ? 512 : 1024; }
+
+template <int Q>
+__device__ __forceinline__ void load_krow_at(KRow<Q> &dst, const char *row, uint32_t off)
+{
+    load_krow<Q>(dst, reinterpret_cast<const uint16_t *>(row + off));
+}
+
+// Whether row s of a group of PF rows (groups start at rows 1 + n PF) can
+// open a band of HB rows (bands start at rows 1 + m HB).
+__host__ __device__ constexpr bool dp_band_row(int s, int HB, int PF)
+{
+    return PF % HB == 0 ? s % HB == 0 : (HB % PF == 0 ? s == 0 : true);
+}
 
 template <int Q, int HB, int PF>
 __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Job *jobs)
@@ -728,77 +746,100 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int H = J.H, Kp = J.Kp, Wp = J.Wp;
     const int rb = Kp - J.KL;  // keys per row buffer
-    const int jl = wid * C - HB + lane * Q;  // first column of this lane
-    const bool live = wid < J.dpnw;
+    const int jl = wid * C - HB + lane * Q;  // first column of this lane (>= -KL)
+    const bool live = wid < J.dpnw;          // wave-uniform
     const bool owner = live && lane * Q >= HB && lane * Q < HB + C;
     const bool stores = owner && jl < Wp;
+    // waves past the job's columns read the all-ones row, at stride 0
     const uint16_t *K = (r & 1) ? J.K1 : J.K0;
-    const uint16_t *kp = live ? K + J.KL + jl : K + (size_t)H * Kp;
-    const size_t kstride = live ? (size_t)Kp : 0;
+    const char *kbase = reinterpret_cast<const char *>(live ? K : K + (size_t)H * Kp);
+    const size_t kpitch = live ? (size_t)Kp * 2 : 0;
+    const uint32_t koff = live ? (uint32_t)(J.KL + jl) * 2u : 0u;
     // every lane stores its codes each row: lanes whose codes are not kept
     // (halo, past the width) write to the job's scratch row instead, so
     // the row loop has no branch around the store
-    uint8_t *__restrict__ cbase = stores ? J.dir + jl : J.dir + (size_t)H * Wp + lane * Q;
-    const size_t cstride = stores ? (size_t)Wp : 0;
+    uint8_t *__restrict__ dir = J.dir;
+    uint32_t coff = stores ? (uint32_t)jl : (uint32_t)(H * Wp + lane * Q);
+    const uint32_t cstep = stores ? (uint32_t)Wp : 0u;
 
     uint32_t key[Q];
     {
         KRow<Q> k0;
-        load_krow<Q>(k0, kp);
+        load_krow_at<Q>(k0, kbase, koff);
         uint32_t code[Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             key[c] = k0.at(c);
             code[c] = 1;
         }
-        store_codes<Q>(cbase, code);
+        store_codes<Q>(dir + coff, code);
+        coff += cstep;
     }
     // neighbour registers: lane 0's left and lane 63's right stay all ones
     uint32_t lnb = kKeyInf, rnb = kKeyInf;
-    KRow<Q> cur[PF], nxt[PF];
-#pragma unroll
-    for (int s = 0; s < PF; ++s) load_krow<Q>(cur[s], kp + (size_t)min(1 + s, H - 1) * kstride);
-
     int band_left = HB;  // rows left in the current band
     int buf = 0;
-    for (int i0 = 1; i0 < H; i0 += PF) {
+
+    auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) load_krow<Q>(nxt[s], kp + (size_t)min(i0 + PF + s, H - 1) * kstride);
+        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (size_t)min(i0 + s, H - 1) * kpitch, koff);
+    };
+    auto step = [&](const KRow<Q> &kr) {
+        lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
+        rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)rnb, (int)key[0], 0x130, 0xf, 0xf, false);
+        uint32_t best[Q];
+        dp_step<Q>(key, lnb, rnb, kr, best);
+        store_codes<Q>(dir + coff, best);
+        coff += cstep;
+        --band_left;
+    };
+    auto exchange = [&]() {
+        // publish the band's last row, meet, refresh the halo
+        uint32_t *rowp = rowbuf + (size_t)buf * rb;
+        if (owner) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) {
-            const int i = i0 + s;
-            if (i < H) {
-                if (band_left == 0) {
-                    // publish the band's last row, meet, refresh the halo
-                    uint32_t *rowp = rowbuf + (size_t)buf * rb;
-                    if (owner) {
+            for (int c = 0; c < Q; ++c) rowp[jl + c] = key[c];
+        }
+        __syncthreads();
+        if (live && !owner) {
 #pragma unroll
-                        for (int c = 0; c < Q; ++c) rowp[jl + c] = key[c];
-                    }
-                    __syncthreads();
-                    if (live && !owner) {
-#pragma unroll
-                        for (int c = 0; c < Q; ++c) {
-                            const int j = jl + c;
-                            key[c] = (j >= 0 && j < Wr) ? rowp[j] : kKeyInf;
-                        }
-                    }
-                    buf ^= 1;
-                    band_left = HB;
-                }
-                lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
-                rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)rnb, (int)key[0], 0x130, 0xf, 0xf, false);
-                uint32_t best[Q];
-                dp_step<Q>(key, lnb, rnb, cur[s], best);
-                store_codes<Q>(cbase + (size_t)i * cstride, best);
-                --band_left;
+            for (int c = 0; c < Q; ++c) {
+                const int j = jl + c;
+                key[c] = (j >= 0 && j < Wr) ? rowp[j] : kKeyInf;
             }
         }
+        buf ^= 1;
+        band_left = HB;
+    };
+    // rows i0 .. i0 + PF - 1 from kr; `guard` for the last, partial groups
+    auto group = [&](const KRow<Q>(&kr)[PF], int i0, bool guard) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) cur[s] = nxt[s];
+        for (int s = 0; s < PF; ++s) {
+            if (guard && i0 + s >= H) break;
+            if (dp_band_row(s, HB, PF)) {
+                if (band_left == 0) exchange();
+            }
+            step(kr[s]);
+        }
+    };
+
+    KRow<Q> ka[PF], kb[PF];
+    fetch(ka, 1);
+    int i0 = 1;
+    for (; i0 + 2 * PF <= H; i0 += 2 * PF) {
+        fetch(kb, i0 + PF);
+        group(ka, i0, false);
+        fetch(ka, i0 + 2 * PF);
+        group(kb, i0 + PF, false);
+    }
+    if (i0 < H) {
+        fetch(kb, i0 + PF);
+        group(ka, i0, true);
+        if (i0 + PF < H) group(kb, i0 + PF, true);
     }
     if (owner) {
 #pragma unroll
