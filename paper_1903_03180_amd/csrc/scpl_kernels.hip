@@ -61,18 +61,30 @@ __device__ __forceinline__ int sobel9(int a0, int a1, int a2, int b0, int b2, in
     return abs(gx) + abs(gy);
 }
 
-// floor(sqrt(q)): the hardware reciprocal square root in double precision
-// (coarse), one Newton step (relative error then far below 2^-40, so the
-// estimate is within 1 of the root for every q < 2^64), then integer steps
-// until exact -- the steps also guarantee exactness whatever the estimate.
+// floor(sqrt(q)).  Below 2^40 (the common case): q as a float (two
+// conversions and one fma, relative error below 2^-23), the hardware single
+// precision square root (within 1 ulp), so the estimate of a root below 2^20
+// is off by less than 0.35 and its integer part by at most 1, which one
+// integer comparison either way repairs.  Otherwise: the hardware
+// reciprocal square root in double precision, one Newton step (relative
+// error then far below 2^-40, so the estimate is within 1 of the root for
+// every q < 2^64), then integer steps until exact.
 __device__ __forceinline__ uint32_t isqrt_u64(uint64_t q)
 {
+    if (q < (1ull << 40)) {
+        const float qf = fmaf((float)(uint32_t)(q >> 32), 4294967296.0f, (float)(uint32_t)q);
+        uint32_t r = (uint32_t)__builtin_amdgcn_sqrtf(qf);
+        const uint64_t r2 = (uint64_t)r * r;
+        if (r2 > q) --r;
+        else if (r2 + 2 * (uint64_t)r + 1 <= q) ++r;
+        return r;
+    }
     const double qd = (double)(uint32_t)(q >> 32) * 4294967296.0 + (double)(uint32_t)q;
-    double y = __builtin_amdgcn_rsq(q ? qd : 1.0);
+    double y = __builtin_amdgcn_rsq(qd);
     y = y * (1.5 - 0.5 * qd * y * y);
-    uint64_t r = q ? (uint64_t)(uint32_t)min(qd * y, 4294967295.0) : 0u;
+    uint64_t r = (uint64_t)(uint32_t)min(qd * y, 4294967295.0);
     while (r * r > q) --r;
-    while ((r + 1) * (r + 1) <= q) ++r;
+    while (r < 0xffffffffull && (r + 1) * (r + 1) <= q) ++r;
     return (uint32_t)r;
 }
 
@@ -468,14 +480,76 @@ __device__ __forceinline__ Stencil stencil_from_rows(const int16_t *ma, const in
     return s;
 }
 
-// Energy of buffer frame t (0-based within the buffer) at a stencil.
-__device__ __forceinline__ int energy_one(const Job &J, const Stencil &s, int t)
+// Frame source of a buffer's energies, copied into registers once so that
+// loops over frames reload nothing from the job table.
+struct FrameSrc {
+    const GLOBAL uint8_t *l0;  // frame t0 of the buffer
+    int64_t FS;
+    int mode, has_prev, T;
+};
+
+__device__ __forceinline__ FrameSrc frame_src(const Job &J)
 {
-    const GLOBAL uint8_t *f = gp(J.luma) + (size_t)(J.t0 + t) * J.FS;
-    const int g = sobel9(f[s.oa0], f[s.oa1], f[s.oa2], f[s.ob0], f[s.ob2], f[s.oc0], f[s.oc1], f[s.oc2]);
-    if (J.mode != 1) return g;
-    const int d = (t > 0 || J.has_prev) ? abs((int)f[s.ob1] - (int)f[(ptrdiff_t)s.ob1 - (ptrdiff_t)J.FS]) : 0;
-    return 2 * g + 18 * d;
+    return FrameSrc{gp(J.luma) + (size_t)J.t0 * J.FS, J.FS, J.mode, J.has_prev, J.T};
+}
+
+// Raw buffer resource over n bytes at p (untyped access, the word-3 value
+// of the gfx9 family).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const GLOBAL uint8_t *p, int64_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)n, 0x00020000);
+}
+
+// Sum over buffer frames t = t1, t1 + step, ... < T (0-based within the
+// buffer) of the energy at a stencil.  The difference term compares frame t
+// with its predecessor, which for t = 0 is the frame before the buffer (when
+// there is one).  t1 and step must be the same in every active lane: frame
+// addresses are then scalar and each pixel read is a 32-bit offset.  The
+// loads of four frames are issued before any is used.
+__device__ __forceinline__ uint32_t stencil_sum(const FrameSrc &fs, const Stencil &st, int t1, int step)
+{
+    uint32_t acc = 0;
+    const bool motion = fs.mode == 1;
+    // no branches between the loads: without a predecessor the centre
+    // pixel is compared with itself
+    // each frame is read through a buffer resource of its own (scalar base,
+    // FS bytes): a pixel read is one 32-bit offset, and an offset past the
+    // frame reads 0 instead of faulting
+    auto one = [&](int t, int (&v)[10]) {
+        t = __builtin_amdgcn_readfirstlane(t);
+        const GLOBAL uint8_t *f = fs.l0 + (size_t)t * fs.FS;
+        const GLOBAL uint8_t *pf = motion && (t > 0 || fs.has_prev) ? f - fs.FS : f;
+        const __amdgpu_buffer_rsrc_t rf = frame_rsrc(f, fs.FS), rp = frame_rsrc(pf, fs.FS);
+        v[0] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa0, 0, 0);
+        v[1] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa1, 0, 0);
+        v[2] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa2, 0, 0);
+        v[3] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob0, 0, 0);
+        v[4] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob2, 0, 0);
+        v[5] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc0, 0, 0);
+        v[6] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc1, 0, 0);
+        v[7] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc2, 0, 0);
+        v[8] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob1, 0, 0);
+        v[9] = __builtin_amdgcn_raw_buffer_load_b8(rp, st.ob1, 0, 0);
+    };
+    auto energy = [&](const int (&v)[10]) {
+        const int g = sobel9(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+        return motion ? (uint32_t)(2 * g + 18 * abs(v[8] - v[9])) : (uint32_t)g;
+    };
+    int t = t1;
+    for (; t + 3 * step < fs.T; t += 4 * step) {
+        int v0[10], v1[10], v2[10], v3[10];
+        one(t, v0);
+        one(t + step, v1);
+        one(t + 2 * step, v2);
+        one(t + 3 * step, v3);
+        acc += energy(v0) + energy(v1) + energy(v2) + energy(v3);
+    }
+    for (; t < fs.T; t += step) {
+        int v0[10];
+        one(t, v0);
+        acc += energy(v0);
+    }
+    return acc;
 }
 
 // Iteration 0 of every job: the DP key row 4 floor(sum of the T energy
@@ -1118,38 +1192,55 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 // frames (refresh_kernel).  This is exact: the result equals a full
 // recomputation.
 
-// One wavefront per row, four rows per block, no block barriers: each lane
-// builds 8 consecutive new columns (the count of seams left of them found
-// once, then stepped), gathers their old entries straight from global memory
-// (neighbouring lanes read neighbouring columns) and writes them with two
-// 16-byte stores.
+// One wavefront per row, four rows per block, no block barriers.  The
+// row's seam thresholds R_s - s are staged in LDS (one slot per lane).  A
+// lane builds 8 consecutive new columns of two 512-column chunks at a time:
+// the count of thresholds at or below its first column is found once, then
+// stepped; all 32 entries are requested (row-relative offsets through
+// buffer resources) before the first is used, and each chunk is written
+// with two 16-byte stores.
 constexpr int kUpdRows = 4;
+constexpr int kUpdSeams = 64;  // rows with more seams read their thresholds from global memory
 
 __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
 {
+    __shared__ int thr[kUpdRows][kUpdSeams + 1];
     const Job &J = jobs[blockIdx.y];
-    const int r = job_iter(J);
-    const int Wr = job_width(J, r);
+    // job state read from memory: the same in every lane
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
     if (Wr <= J.Wt) return;
-    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kUpdRows + (int)(threadIdx.x >> 6));
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kUpdRows + w);
     if (i >= J.H) return;
     const int lane = threadIdx.x & 63;
-    const int kk = J.log[4 * r + 2];
+    const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
     const int Wn = Wr - kk;
     const int Wp = J.Wp;
-    const int16_t *__restrict__ Mo = ((r & 1) ? J.M1 : J.M0) + (size_t)i * Wp;
+    const int16_t *Mo = ((r & 1) ? J.M1 : J.M0) + (size_t)i * Wp;
     int16_t *__restrict__ Mw = ((r & 1) ? J.M0 : J.M1) + (size_t)i * Wp;
-    const uint16_t *__restrict__ Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
+    const uint16_t *Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
     uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
     const bool keys = Wn > J.Wt;  // a further iteration reads the keys
     const int16_t *__restrict__ R = J.seams + (size_t)i * J.kcap;  // removed columns of row i, increasing
     // seam s removed old column R[s]; new column j reads old column j + #{s : R[s] - s <= j}
-    auto rs = [&](int s) -> int { return s < kk ? (int)R[s] - s : 0x7fffffff; };
-    for (int j0 = 0; j0 < Wn; j0 += 512) {
-        const int jb = j0 + 8 * lane;
+    const bool staged = kk <= kUpdSeams;
+    if (staged) {
+        thr[w][lane] = lane < kk ? (int)R[lane] - lane : 0x7fffffff;
+        if (lane == 0) thr[w][kUpdSeams] = 0x7fffffff;
+        __builtin_amdgcn_wave_barrier();
+    }
+    auto rs = [&](int s) -> int {
+        if (staged) return thr[w][min(s, kUpdSeams)];
+        return s < kk ? (int)R[s] - s : 0x7fffffff;
+    };
+    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mo, (short)0, 2 * Wr, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rK = __builtin_amdgcn_make_buffer_rsrc((void *)Ko, (short)0, 2 * Wr, 0x00020000);
+    // old columns of new columns jb .. jb + 7 (columns past Wn read a valid entry, never stored)
+    auto sources = [&](int jb, int (&src)[8]) {
         int a = 0;
         if (kk <= 32) {
-            for (int s = 0; s < kk; ++s) a += rs(s) <= jb ? 1 : 0;  // uniform loads
+            for (int s = 0; s < kk; ++s) a += rs(s) <= jb ? 1 : 0;  // same slot in every lane
         } else {
             int hi = kk;
             while (a < hi) {
@@ -1158,17 +1249,22 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
                 else hi = m;
             }
         }
-        if (jb >= Wn) continue;
         int nxt = rs(a);
-        uint32_t mv[8], kv[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int j = jb + q;
             while (nxt <= j) nxt = rs(++a);
-            const int src = min(j + a, Wr - 1);  // columns past Wn read a valid entry, never stored
-            mv[q] = (uint16_t)Mo[src];
-            kv[q] = keys ? Ko[src] : 0u;
+            src[q] = min(j + a, Wr - 1);
         }
+    };
+    auto fetch = [&](const int (&src)[8], uint32_t (&mv)[8], uint32_t (&kv)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            mv[q] = __builtin_amdgcn_raw_buffer_load_b16(rM, 2 * src[q], 0, 0);
+            kv[q] = keys ? __builtin_amdgcn_raw_buffer_load_b16(rK, 2 * src[q], 0, 0) : 0u;
+        }
+    };
+    auto put = [&](int jb, const uint32_t (&mv)[8], const uint32_t (&kv)[8]) {
         if (jb + 8 <= Wn) {
             *gp(reinterpret_cast<u32x4 *>(Mw + jb)) =
                 u32x4{mv[0] | (mv[1] << 16), mv[2] | (mv[3] << 16), mv[4] | (mv[5] << 16), mv[6] | (mv[7] << 16)};
@@ -1181,6 +1277,17 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
                 if (keys) Kn[jb + q] = (uint16_t)kv[q];
             }
         }
+    };
+    for (int j0 = 0; j0 < Wn; j0 += 1024) {
+        const int ja = j0 + 8 * lane, jc = ja + 512;
+        int sa[8], sc[8];
+        uint32_t ma[8], ka[8], mc[8], kc[8];
+        sources(ja, sa);
+        sources(jc, sc);
+        fetch(sa, ma, ka);
+        fetch(sc, mc, kc);
+        if (ja < Wn) put(ja, ma, ka);
+        if (jc < Wn) put(jc, mc, kc);
     }
     if (!keys) return;
     // the keys of the vacated columns become 0xffff; columns beyond the
@@ -1261,17 +1368,8 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
         }
         return c + a;
     };
-    auto full_sum = [&](const Stencil &st) {
-        uint32_t acc = 0;
-        int t = 0;
-        for (; t + 4 <= T; t += 4) {
-            const int e0 = energy_one(J, st, t), e1 = energy_one(J, st, t + 1);
-            const int e2 = energy_one(J, st, t + 2), e3 = energy_one(J, st, t + 3);
-            acc += (uint32_t)(e0 + e1 + e2 + e3);
-        }
-        for (; t < T; ++t) acc += (uint32_t)energy_one(J, st, t);
-        return acc;
-    };
+    const FrameSrc fsrc = frame_src(J);
+    auto full_sum = [&](const Stencil &st) { return stencil_sum(fsrc, st, 0, 1); };
     // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
     const int ncand = kk * nrows * 9;
     for (int u = tid; u < ncand; u += NT) {
@@ -1319,19 +1417,17 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
     }
     __syncthreads();
     if (n > 0) {
-        // pixel p gets threads p, p + n, ...; each sums every tpp-th frame
-        const int tpp = max(NT / n, 1);
-        for (int u = tid; u < n * tpp; u += NT) {
-            const int p = u % n, sub = u / n;
-            uint32_t acc = 0;
-            int t = sub;
-            for (; t + 3 * tpp < T; t += 4 * tpp) {
-                const int e0 = energy_one(J, fst[p], t), e1 = energy_one(J, fst[p], t + tpp);
-                const int e2 = energy_one(J, fst[p], t + 2 * tpp), e3 = energy_one(J, fst[p], t + 3 * tpp);
-                acc += (uint32_t)(e0 + e1 + e2 + e3);
+        // a wavefront takes 64 listed pixels and every tpp-th frame, so its
+        // lanes read the same frames
+        const int ng = (n + 63) >> 6, nw = NT >> 6;
+        const int tpp = max(nw / ng, 1);
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+        for (int task = w; task < ng * tpp; task += nw) {
+            const int p = (task % ng) * 64 + (tid & 63), sub = task / ng;
+            if (p < n) {
+                const Stencil st = fst[p];
+                atomicAdd(&fsum[p], stencil_sum(fsrc, st, sub, tpp));
             }
-            for (; t < T; t += tpp) acc += (uint32_t)energy_one(J, fst[p], t);
-            atomicAdd(&fsum[p], acc);
         }
     }
     __syncthreads();
