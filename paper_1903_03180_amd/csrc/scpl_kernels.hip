@@ -24,6 +24,9 @@ namespace {
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack2(u16x2 v) { return (uint32_t)v.x | ((uint32_t)v.y << 16); }
 
 __device__ __forceinline__ int job_width(const Job &J, int r) { return r < J.logcap ? J.log[4 * r] : J.Wt; }
 
@@ -505,7 +508,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const GLOBAL uint8_
 // with its predecessor, which for t = 0 is the frame before the buffer (when
 // there is one).  t1 and step must be the same in every active lane: frame
 // addresses are then scalar and each pixel read is a 32-bit offset.  The
-// loads of four frames are issued before any is used.
+// loads of eight (then four) frames are issued before any is used.
 __device__ __forceinline__ uint32_t stencil_sum(const FrameSrc &fs, const Stencil &st, int t1, int step)
 {
     uint32_t acc = 0;
@@ -536,13 +539,19 @@ __device__ __forceinline__ uint32_t stencil_sum(const FrameSrc &fs, const Stenci
         return motion ? (uint32_t)(2 * g + 18 * abs(v[8] - v[9])) : (uint32_t)g;
     };
     int t = t1;
+    for (; t + 7 * step < fs.T; t += 8 * step) {
+        int v[8][10];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) one(t + u * step, v[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += energy(v[u]);
+    }
     for (; t + 3 * step < fs.T; t += 4 * step) {
-        int v0[10], v1[10], v2[10], v3[10];
-        one(t, v0);
-        one(t + step, v1);
-        one(t + 2 * step, v2);
-        one(t + 3 * step, v3);
-        acc += energy(v0) + energy(v1) + energy(v2) + energy(v3);
+        int v[4][10];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(t + u * step, v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += energy(v[u]);
     }
     for (; t < fs.T; t += step) {
         int v0[10];
@@ -1194,11 +1203,11 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 
 // One wavefront per row, four rows per block, no block barriers.  The
 // row's seam thresholds R_s - s are staged in LDS (one slot per lane).  A
-// lane builds 8 consecutive new columns of two 512-column chunks at a time:
-// the count of thresholds at or below its first column is found once, then
-// stepped; all 32 entries are requested (row-relative offsets through
-// buffer resources) before the first is used, and each chunk is written
-// with two 16-byte stores.
+// lane builds 8 consecutive new columns in each of four 512-column chunks
+// at a time: the count of thresholds at or below its first column is found
+// once, then stepped; all 64 entries are requested (row-relative offsets
+// through buffer resources) before the first is used, and each chunk is
+// written with two 16-byte stores.
 constexpr int kUpdRows = 4;
 constexpr int kUpdSeams = 64;  // rows with more seams read their thresholds from global memory
 
@@ -1236,8 +1245,9 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
     };
     const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mo, (short)0, 2 * Wr, 0x00020000);
     const __amdgpu_buffer_rsrc_t rK = __builtin_amdgcn_make_buffer_rsrc((void *)Ko, (short)0, 2 * Wr, 0x00020000);
-    // old columns of new columns jb .. jb + 7 (columns past Wn read a valid entry, never stored)
-    auto sources = [&](int jb, int (&src)[8]) {
+    // entries of the old columns of new columns jb .. jb + 7, two 16-bit
+    // entries per register (columns past Wn read a valid entry, never stored)
+    auto gather8 = [&](int jb, u16x2 (&mv)[4], u16x2 (&kv)[4]) {
         int a = 0;
         if (kk <= 32) {
             for (int s = 0; s < kk; ++s) a += rs(s) <= jb ? 1 : 0;  // same slot in every lane
@@ -1254,40 +1264,33 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
         for (int q = 0; q < 8; ++q) {
             const int j = jb + q;
             while (nxt <= j) nxt = rs(++a);
-            src[q] = min(j + a, Wr - 1);
+            const int off = 2 * min(j + a, Wr - 1);
+            mv[q >> 1][q & 1] = __builtin_amdgcn_raw_buffer_load_b16(rM, off, 0, 0);
+            kv[q >> 1][q & 1] = keys ? __builtin_amdgcn_raw_buffer_load_b16(rK, off, 0, 0) : (uint16_t)0;
         }
     };
-    auto fetch = [&](const int (&src)[8], uint32_t (&mv)[8], uint32_t (&kv)[8]) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            mv[q] = __builtin_amdgcn_raw_buffer_load_b16(rM, 2 * src[q], 0, 0);
-            kv[q] = keys ? __builtin_amdgcn_raw_buffer_load_b16(rK, 2 * src[q], 0, 0) : 0u;
-        }
-    };
-    auto put = [&](int jb, const uint32_t (&mv)[8], const uint32_t (&kv)[8]) {
+    auto put = [&](int jb, const u16x2 (&mv)[4], const u16x2 (&kv)[4]) {
         if (jb + 8 <= Wn) {
-            *gp(reinterpret_cast<u32x4 *>(Mw + jb)) =
-                u32x4{mv[0] | (mv[1] << 16), mv[2] | (mv[3] << 16), mv[4] | (mv[5] << 16), mv[6] | (mv[7] << 16)};
-            if (keys)
-                *gp(reinterpret_cast<u32x4 *>(Kn + jb)) = u32x4{kv[0] | (kv[1] << 16), kv[2] | (kv[3] << 16),
-                                                                kv[4] | (kv[5] << 16), kv[6] | (kv[7] << 16)};
+            *gp(reinterpret_cast<u32x4 *>(Mw + jb)) = u32x4{pack2(mv[0]), pack2(mv[1]), pack2(mv[2]), pack2(mv[3])};
+            if (keys) *gp(reinterpret_cast<u32x4 *>(Kn + jb)) = u32x4{pack2(kv[0]), pack2(kv[1]), pack2(kv[2]), pack2(kv[3])};
         } else {
             for (int q = 0; q < 8 && jb + q < Wn; ++q) {
-                Mw[jb + q] = (int16_t)mv[q];
-                if (keys) Kn[jb + q] = (uint16_t)kv[q];
+                Mw[jb + q] = (int16_t)mv[q >> 1][q & 1];
+                if (keys) Kn[jb + q] = kv[q >> 1][q & 1];
             }
         }
     };
-    for (int j0 = 0; j0 < Wn; j0 += 1024) {
-        const int ja = j0 + 8 * lane, jc = ja + 512;
-        int sa[8], sc[8];
-        uint32_t ma[8], ka[8], mc[8], kc[8];
-        sources(ja, sa);
-        sources(jc, sc);
-        fetch(sa, ma, ka);
-        fetch(sc, mc, kc);
-        if (ja < Wn) put(ja, ma, ka);
-        if (jc < Wn) put(jc, mc, kc);
+    // up to 2048 columns per pass: every entry of the pass is requested
+    // before the first store, so a row of that width costs one round trip
+    for (int j0 = 0; j0 < Wn; j0 += 4 * 512) {
+        u16x2 mv[4][4], kv[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gather8(j0 + 512 * c + 8 * lane, mv[c], kv[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int jb = j0 + 512 * c + 8 * lane;
+            if (jb < Wn) put(jb, mv[c], kv[c]);
+        }
     }
     if (!keys) return;
     // the keys of the vacated columns become 0xffff; columns beyond the
