@@ -260,7 +260,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k", "mix64"])
     ap.add_argument("--plain-steps", type=int, default=1)
-    ap.add_argument("--streams", type=int, default=2, help="job groups (streams) of the batched path")
+    ap.add_argument("--streams", type=int, default=3, help="job groups (streams) of the batched path")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests per arrival rate (0: no serving run)")
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")

@@ -138,7 +138,7 @@ typedef struct {
 
 scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, void *stream);
 
-/* Number of job groups of scpl_retarget_batch (default 2, at most
+/* Number of job groups of scpl_retarget_batch (default 3, at most
  * SCPL_MAX_STREAMS).  The jobs are dealt to the groups in order of
  * decreasing buffer length; each group advances in lock-step on a stream of
  * its own (default priority) that starts after the work already on the
@@ -237,8 +237,10 @@ scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms,
  * scpl_autotune_dp times every geometry that fits width W with n_jobs
  * concurrent H x W synthetic energies per launch (as in a batched launch;
  * null stream, synchronises) and keeps the fastest for launches whose widest
- * job has width W; h_Q, h_HB, h_PF, h_EX, h_us (nullable) receive the choice
- * and its time per launch in microseconds. */
+ * job has width W; when the batched path runs more than one job group
+ * (scpl_batch_streams) only EX = 1 geometries are timed.  h_Q, h_HB, h_PF,
+ * h_EX, h_us (nullable) receive the choice and its time per launch in
+ * microseconds. */
 scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, int32_t EX);
 scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
                              int32_t *h_PF, int32_t *h_EX, double *h_us);

@@ -41,7 +41,7 @@ struct scpl_ctx {
     void *pinned = nullptr;    // host staging (job tables, sums, states)
     size_t pinned_size = 0;
     std::vector<int32_t> last_log;
-    int nstreams = 2;                    // job groups of the batched path, one stream each
+    int nstreams = 3;                    // job groups of the batched path, one stream each
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -119,13 +119,14 @@ struct Bump {
     }
 };
 
-// Rows per band: 64, or more for wide frames so that the band origins of
-// a whole frame (bands x width bytes) still fit in the selection kernel's
-// LDS next to its keys (16 bytes per column); int8 offsets cap it at 120.
+// Rows per band: 32 (short band walks), or more for tall and wide frames so
+// that the band origins of a whole frame (bands x width bytes) still fit in
+// the selection kernel's LDS next to its keys (16 bytes per column); int8
+// offsets cap it at 120.
 int32_t band_rows(int32_t H, int32_t W, size_t lds_cap)
 {
     const size_t keys = (size_t)16 * W;
-    for (int32_t B : {64, 96, 120}) {
+    for (int32_t B : {32, 64, 96, 120}) {
         const size_t nb = (size_t)(H + B - 1) / B;
         if (keys + nb * (size_t)W <= lds_cap) return B;
     }
@@ -1353,16 +1354,20 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
     SCPL_TRY(hipSetDevice(ctx->device));
     hipStream_t s = nullptr;
     std::vector<DpGeom> cand;
+    // with several job groups the DP runs beside the other groups' kernels,
+    // which a timing in isolation cannot see: it then keeps its compute
+    // units to itself (EX = 1)
+    const int ex0 = ctx->nstreams > 1 ? 1 : 0;
     for (int v = 0; v < kNumDpVariants; ++v)
         if (dp_geom_fits(kDpVariants[v], W))
-            for (int ex = 0; ex < 2; ++ex) {
+            for (int ex = ex0; ex < 2; ++ex) {
                 DpGeom g = kDpVariants[v];
                 g.EX = ex;
                 cand.push_back(g);
             }
     if (cand.empty()) {
         DpGeom g = dp_geom(W);
-        cand.push_back(g);
+        if (ex0 == 0) cand.push_back(g);
         g.EX = 1;
         cand.push_back(g);
     }

@@ -104,7 +104,7 @@ def test_batch_equals_oracle_and_plain(ctx, orc, nstreams):
         ctx.retarget_batch(clips)
         torch.cuda.synchronize()
     finally:
-        ctx.batch_streams(2)
+        ctx.batch_streams(3)
     for c, fr in zip(clips, host):
         kw = dict(mode=c.get("energy_mode", 1), use_buffer=c.get("use_buffer", 1), anum=c.get("alpha_num", 1),
                   aden=c.get("alpha_den", 5))
@@ -271,13 +271,13 @@ def test_2d_masks_are_refused(ctx):
 
 def test_1080p_batch_as_benchmarked(ctx, orc):
     """The benchmark's launch configuration at full size: several 1080p
-    clips in one batched call, two stream groups, autotuned DP geometry.
+    clips in one batched call, three stream groups, autotuned DP geometry.
     Every clip equals its plain-path result bit for bit; the first clip is
     also checked against the oracle (segmentation, first iteration of every
     buffer) and through the invariants."""
     seeds = [2000, 2001, 2002]
     frames = [synth.clip_1080p(s) for s in seeds]
-    ctx.batch_streams(2)
+    ctx.batch_streams(3)
     ctx.autotune_dp(1080, 1920, n_jobs=3 * len(seeds))
     try:
         clips = [dict(frames=dev(f), target_width=1440, seams_per_iter=16, want_masks=True) for f in frames]
