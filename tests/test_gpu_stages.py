@@ -185,6 +185,32 @@ def test_asde(ctx, orc, n, H, W, mode, prev, alpha):
     assert gS == S and grej == rej
 
 
+@pytest.mark.parametrize("n,prev", [(700, False), (900, True)])
+def test_asde_large_moments(ctx, orc, n, prev):
+    """A random frame shown twice, then black, over and over: the per-pixel
+    n^2-scaled variances n S2 - S1^2 spread across 2^40, so both the
+    single-precision and the double-precision paths of the kernel's integer
+    square root are taken, against the oracle's exact sums."""
+    H, W = 12, 20
+    rng = np.random.default_rng(n)
+    X = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    Y = np.stack([X if t % 3 else np.zeros_like(X) for t in range(n + 1)])
+    frames, before = Y[1:], Y[0]
+    s1 = np.zeros((H, W), dtype=np.uint64)
+    s2 = np.zeros((H, W), dtype=np.uint64)
+    for t in range(n):
+        p = (frames[t - 1] if t else before) if (t or prev) else None
+        e = orc.energy(frames[t], p, 1).astype(np.uint64)
+        s1 += e
+        s2 += e * e
+    q = n * s2.astype(object) - s1.astype(object) ** 2
+    assert min(q.flat) < 2 ** 40 < max(q.flat)
+    S = orc.asde_sum(s1, s2, n)
+    rej = orc.reject(S, n, H * W, orc.energy_max(1), 1, 5)
+    gS, grej = ctx.asde(dev(frames), dev(before) if prev else None, energy_mode=1, alpha_num=1, alpha_den=5)
+    assert gS == S and grej == rej
+
+
 @pytest.mark.parametrize("shape,kk,C", [((1, 5), 2, 1), ((40, 70), 7, 3), ((130, 300), 60, 1), ((9, 2000), 1500, 3),
                                         ((64, 64), 0, 1)])
 def test_compact(ctx, orc, shape, kk, C):
