@@ -239,18 +239,28 @@ def measured_dp_traffic(workload, q, hb, pf):
     runs (scaled by the 1 GiB copy), if they were taken on this workload
     with this DP kernel and the kernel source has not changed since; else
     None."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"dp_traffic_{workload.replace('-', '_')}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_1903_03180_amd", "csrc", "scpl_kernels.hip")
-    with open(src, "rb") as f:
-        same = hashlib.sha256(f.read()).hexdigest() == rec["kernels_source_sha256"]
+    same = dp_source_digest() == rec.get("dp_source_sha256")
     if not same or rec["kernel"] != f"dp_band_kernel<{q}, {hb}, {pf}>":
         return None
     return rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]
+
+
+def dp_source_digest() -> str:
+    """SHA-256 of the DP section of the kernel source (key rows, row step,
+    code stores, the DP kernels): a traffic record stays valid while that
+    text is unchanged."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1903_03180_amd", "csrc", "scpl_kernels.hip")
+    with open(src) as f:
+        text = f.read()
+    a = text.index("// ------------------------------------------------------------------- DP")
+    b = text.index("// ----------------------------------------------------------- band origins")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()
 
 
 def main() -> int:

@@ -2,19 +2,22 @@
 //
 // Method: "Fast Video Retargeting Based on Seam Carving with Parental
 // Labeling" (arXiv 1903.03180).  Stage map:
-//   luma_kernel        colour -> 8-bit luma (the paper does not say which
-//                      channel feeds the energy; BT.601 luma is used)
+//   luma / tile_luma   colour -> 8-bit luma (the paper does not say which
+//                      channel feeds the energy; BT.601 luma is used), tiled
 //   seg_window_kernel  energy (Sec. 3.3) + ASDE moments (eqs. 7-8) for a
 //                      window of candidate frames of one buffer (Sec. 3.2)
 //   energy_kernel      uniform energy of a buffer (Sec. 3.2): mean of the
-//                      frames' motion-aware energies, read through the
-//                      buffer's column map so frames are never recopied
-//   dp_kernel          cumulative energy, eq. (4), with the row-0 parent
-//                      label carried along the argmin path (Sec. 3.1)
-//   borg_kernel        band origins for the two-level backtrack
-//   select_kernel      per-parent least child (eq. 6), top-k, band jumps
+//                      frames' motion-aware energies, as 16-bit DP keys
+//   dp_band_kernel     cumulative energy, eq. (4), one workgroup per buffer,
+//                      leftmost tie-break, 2-bit indicator codes
+//   borg_kernel        band origins of the two-level backtrack
+//   select_kernel      row-0 parent labels through the band origins, per-
+//                      parent least child (eq. 6), top-k, band jumps
 //   fill_kernel        seams inside each band; buffer mask
-//   compact_kernel     removes k_iter seams from the column map in one pass
+//   update_kernel      removes the iteration's seams from the column map
+//                      and the DP keys in one pass
+//   refresh_kernel     recomputes the keys of the pixels whose carved 3x3
+//                      neighbourhood changed (exact)
 //   gather_kernel      carved output frames and masks
 #include "scpl_internal.h"
 
