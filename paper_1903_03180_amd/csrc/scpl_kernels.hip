@@ -1205,18 +1205,24 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 // recomputation.
 
 // One wavefront per row, four rows per block, no block barriers.  The
-// row's seam thresholds R_s - s are staged in LDS (one slot per lane).  A
-// lane builds 8 consecutive new columns in each of four 512-column chunks
-// at a time: the count of thresholds at or below its first column is found
-// once, then stepped; all 64 entries are requested (row-relative offsets
-// through buffer resources) before the first is used, and each chunk is
-// written with two 16-byte stores.
+// row's seam thresholds R_s - s are staged in LDS (one slot per lane).  Per
+// pass of up to 2048 new columns, the old entries they can come from (the
+// same columns plus kk) are copied into the wavefront's LDS with 16-byte
+// loads; a lane then builds 8 consecutive new columns in each of four
+// 512-column chunks -- the count of thresholds at or below its first column
+// found once, then stepped -- from LDS, and writes each chunk with 16-byte
+// stores.  Rows with more than kUpdSeams seams gather their entries straight
+// from global memory instead.
 constexpr int kUpdRows = 4;
-constexpr int kUpdSeams = 64;  // rows with more seams read their thresholds from global memory
+constexpr int kUpdSeams = 64;                          // seams per row staged in LDS
+constexpr int kUpdSpan = 2048;                         // new columns per pass
+constexpr int kUpdStage = kUpdSpan + kUpdSeams + 8;    // old entries staged per pass
 
 __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
 {
     __shared__ int thr[kUpdRows][kUpdSeams + 1];
+    __shared__ __align__(16) uint16_t stM[kUpdRows][kUpdStage];
+    __shared__ __align__(16) uint16_t stK[kUpdRows][kUpdStage];
     const Job &J = jobs[blockIdx.y];
     // job state read from memory: the same in every lane
     const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
@@ -1246,11 +1252,12 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
         if (staged) return thr[w][min(s, kUpdSeams)];
         return s < kk ? (int)R[s] - s : 0x7fffffff;
     };
-    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mo, (short)0, 2 * Wr, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rK = __builtin_amdgcn_make_buffer_rsrc((void *)Ko, (short)0, 2 * Wr, 0x00020000);
-    // entries of the old columns of new columns jb .. jb + 7, two 16-bit
-    // entries per register (columns past Wn read a valid entry, never stored)
-    auto gather8 = [&](int jb, u16x2 (&mv)[4], u16x2 (&kv)[4]) {
+    // row buffers (Wp and Kp - KL entries, multiples of 64) as buffer resources
+    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mo, (short)0, 2 * Wp, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rK =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Ko, (short)0, 2 * (J.Kp - J.KL), 0x00020000);
+    // count of thresholds at or below column jb
+    auto count = [&](int jb) {
         int a = 0;
         if (kk <= 32) {
             for (int s = 0; s < kk; ++s) a += rs(s) <= jb ? 1 : 0;  // same slot in every lane
@@ -1262,15 +1269,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
                 else hi = m;
             }
         }
-        int nxt = rs(a);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int j = jb + q;
-            while (nxt <= j) nxt = rs(++a);
-            const int off = 2 * min(j + a, Wr - 1);
-            mv[q >> 1][q & 1] = __builtin_amdgcn_raw_buffer_load_b16(rM, off, 0, 0);
-            kv[q >> 1][q & 1] = keys ? __builtin_amdgcn_raw_buffer_load_b16(rK, off, 0, 0) : (uint16_t)0;
-        }
+        return a;
     };
     auto put = [&](int jb, const u16x2 (&mv)[4], const u16x2 (&kv)[4]) {
         if (jb + 8 <= Wn) {
@@ -1283,16 +1282,64 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
             }
         }
     };
-    // up to 2048 columns per pass: every entry of the pass is requested
-    // before the first store, so a row of that width costs one round trip
-    for (int j0 = 0; j0 < Wn; j0 += 4 * 512) {
-        u16x2 mv[4][4], kv[4][4];
+    if (staged) {
+        uint16_t *sM = stM[w], *sK = stK[w];
+        for (int j0 = 0; j0 < Wn; j0 += kUpdSpan) {
+            // old columns [j0, hi) hold every source of new columns [j0, j0 + kUpdSpan)
+            const int hi = min(j0 + kUpdSpan + kk, Wr);
+            const int nv = (hi - j0 + 7) >> 3;  // 16-byte groups, within the row buffers
+            // all groups requested before the first is written (a group past
+            // the row buffer reads 0 and is not kept)
+            constexpr int kG = (kUpdStage / 8 + 63) / 64;
+            u32x4 tm[kG], tk[kG];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) gather8(j0 + 512 * c + 8 * lane, mv[c], kv[c]);
+            for (int u = 0; u < kG; ++u) {
+                const int off = 2 * (j0 + 8 * (lane + 64 * u));
+                tm[u] = __builtin_amdgcn_raw_buffer_load_b128(rM, off, 0, 0);
+                tk[u] = keys ? __builtin_amdgcn_raw_buffer_load_b128(rK, off, 0, 0) : u32x4{0u, 0u, 0u, 0u};
+            }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int jb = j0 + 512 * c + 8 * lane;
-            if (jb < Wn) put(jb, mv[c], kv[c]);
+            for (int u = 0; u < kG; ++u) {
+                const int v = lane + 64 * u;
+                if (v < nv) {
+                    *reinterpret_cast<u32x4 *>(sM + 8 * v) = tm[u];
+                    *reinterpret_cast<u32x4 *>(sK + 8 * v) = tk[u];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < kUpdSpan / 512; ++c) {
+                const int jb = j0 + 512 * c + 8 * lane;
+                if (jb >= Wn) break;
+                int a = count(jb);
+                int nxt = rs(a);
+                u16x2 mv[4], kv[4];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = jb + q;
+                    while (nxt <= j) nxt = rs(++a);
+                    const int x = min(j + a, Wr - 1) - j0;  // columns past Wn read a staged entry, never stored
+                    mv[q >> 1][q & 1] = sM[x];
+                    kv[q >> 1][q & 1] = keys ? sK[x] : (uint16_t)0;
+                }
+                put(jb, mv, kv);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else {
+        for (int jb = 8 * lane; jb < Wn; jb += 512) {
+            int a = count(jb);
+            int nxt = rs(a);
+            u16x2 mv[4], kv[4];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = jb + q;
+                while (nxt <= j) nxt = rs(++a);
+                const int off = 2 * min(j + a, Wr - 1);
+                mv[q >> 1][q & 1] = __builtin_amdgcn_raw_buffer_load_b16(rM, off, 0, 0);
+                kv[q >> 1][q & 1] = keys ? __builtin_amdgcn_raw_buffer_load_b16(rK, off, 0, 0) : (uint16_t)0;
+            }
+            put(jb, mv, kv);
         }
     }
     if (!keys) return;
