@@ -948,28 +948,53 @@ constexpr int kBorgCols = 256;
 
 __device__ __forceinline__ int code_step(uint8_t c) { return (int)(c & 3u) - 1; }
 
+// A pointer that is the same in every lane, moved into scalar registers
+// (buffer resources built from it then need no per-lane loop).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
 // Copies rows [r0, r0 + nrows) x columns [c0, c1) of a byte matrix with a
 // pitch that is a multiple of 4 into LDS (pitch lp bytes, column c0 & ~3 at
-// LDS column 0), using aligned 32-bit loads.  Returns the LDS column of c0.
+// LDS column 0), using aligned 32-bit loads.  Each thread requests its next
+// eight words before it writes any of them (words past the staged rows
+// read 0 through the buffer resource and are not written).  src, pitch,
+// r0, nrows, c0 and c1 are the same in every thread.  Returns the LDS
+// column of c0.
 __device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *src, int pitch, int r0, int nrows,
                                            int c0, int c1, int tid, int nthreads)
 {
     const int a0 = c0 & ~3;
     const int nw = (c1 - a0 + 3) >> 2;  // words per row
     if (nw <= 0 || nrows <= 0) return c0 - a0;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)uniform_ptr(src), (short)0, __builtin_amdgcn_readfirstlane((r0 + nrows) * pitch), 0x00020000);
     // (row, word) of this thread, advanced by nthreads words per step
     int rr = tid / nw, w = tid - rr * nw;
     const int drr = nthreads / nw, dw = nthreads - drr * nw;
-    const GLOBAL uint8_t *g = gp(src) + (size_t)r0 * pitch + a0;
+    constexpr int kBatch = 8;
     while (rr < nrows) {
-        const uint32_t v = *reinterpret_cast<const GLOBAL uint32_t *>(g + (size_t)rr * pitch + 4 * w);
-        *reinterpret_cast<uint32_t *>(lds + rr * lp + 4 * w) = v;
-        rr += drr;
-        w += dw;
-        if (w >= nw) {
-            w -= nw;
-            ++rr;
+        uint32_t v[kBatch];
+        int at[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            at[u] = rr < nrows ? rr * lp + 4 * w : -1;
+            v[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (r0 + rr) * pitch + a0 + 4 * w, 0, 0);
+            rr += drr;
+            w += dw;
+            if (w >= nw) {
+                w -= nw;
+                ++rr;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (at[u] >= 0) *reinterpret_cast<uint32_t *>(lds + at[u]) = v[u];
     }
     return c0 - a0;
 }
