@@ -350,6 +350,7 @@ size_t height_pass_bytes(const scpl_params &p)
 struct SegClip {
     const scpl_params *p;
     const uint8_t *tiled;  // N tiled luma frames
+    const uint8_t *seq;    // pixel-major luma, seq_pitch(N) entries per pixel
     int64_t FS;
     int ntc;
     void *state;           // seg_bytes(H W)
@@ -842,12 +843,14 @@ uint64_t scpl::clip_footprint(const scpl_params &p)
     JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, dp_geom(p.width)};
     const uint64_t N = (uint64_t)p.n_frames;
     uint64_t b = align_up((size_t)N * tiled_frame_bytes(p.height, p.width));
+    b += align_up((size_t)p.height * p.width * seq_pitch((int)N));
     b += seg_bytes((int64_t)p.height * p.width) + align_up(kSegWindow * 8);
     b += N * (job_bytes(js) + sizeof(Job) + 16) + 2 * kAlign;
     if (height_pass(p)) {
         const scpl_params q = transposed_params(p);
         JobShape jq{q.height, q.width, q.target_width, q.seams_per_iter, dp_geom(q.width)};
         uint64_t b2 = align_up((size_t)N * tiled_frame_bytes(q.height, q.width));
+        b2 += align_up((size_t)q.height * q.width * seq_pitch((int)N));
         b2 += seg_bytes((int64_t)q.height * q.width) + align_up(kSegWindow * 8);
         b2 += N * (job_bytes(jq) + sizeof(Job) + 16) + 2 * kAlign;
         b = std::max(b, b2) + height_temp_bytes(p);
@@ -867,6 +870,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     for (int c = 0; c < nc; ++c) {
         const scpl_params &p = clips[c].p;
         a_bytes += align_up((size_t)p.n_frames * tiled_frame_bytes(p.height, p.width));
+        a_bytes += align_up((size_t)p.height * p.width * seq_pitch(p.n_frames));
         a_bytes += seg_bytes((int64_t)p.height * p.width);
         Ntot += p.n_frames;
     }
@@ -895,13 +899,16 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         sc.FS = tiled_frame_bytes(p.height, p.width);
         sc.ntc = tiles_across(p.width);
         uint8_t *tiled = dev.take<uint8_t>((size_t)p.n_frames * sc.FS);
+        uint8_t *seq = dev.take<uint8_t>((size_t)p.height * p.width * seq_pitch(p.n_frames));
         sc.tiled = tiled;
+        sc.seq = seq;
         sc.state = dev.take<char>(seg_bytes((int64_t)p.height * p.width));
         sc.bid = h_bid_all + off;
         sc.trace = nullptr;
         off += p.n_frames;
         ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
         launch_tile_luma(clips[c].d_frames, p.channels, p.n_frames, p.height, p.width, tiled, s);
+        launch_seq(tiled, p.n_frames, p.height, p.width, seq, seq_pitch(p.n_frames), s);
     }
     SCPL_CHECK_LAUNCH();
     scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
@@ -963,6 +970,8 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         const JobShape js = shape_of(pend[q]);
         Job J = clip_job(&cl.p, cl.d_frames, seg[pend[q].clip].tiled, cl.d_out, cl.d_masks, pend[q].t0, pend[q].T,
                          pend[q].bindex);
+        J.seq = seg[pend[q].clip].seq;
+        J.seqp = seq_pitch(cl.p.n_frames);
         if (!batched) jb.off = 0;  // plain: every buffer reuses the same area
         carve_job(J, js, jb, d_states + 4 * slot[q]);
         h_jobs[slot[q]] = J;

@@ -39,6 +39,7 @@ constexpr int kDpThreads = 1024;
 struct Job {
     const uint8_t *frames;  // clip, N x H x W x C
     const uint8_t *luma;    // clip luma, N tiled frames of FS bytes
+    const uint8_t *seq;     // clip luma pixel-major (seq_kernel), seqp entries per pixel
     uint8_t *out;           // clip output, N x H x Wt x C
     uint16_t *masks;        // clip masks, N x H x W, or null
     int32_t H, W, C, Wt, k, mode;
@@ -46,6 +47,7 @@ struct Job {
     int32_t has_prev;       // frame t0 - 1 is the (carved) predecessor of t0
     int32_t ntc;            // luma tiles per tile row
     int64_t FS;             // bytes per tiled luma frame
+    int32_t seqp;           // entries per pixel of seq: N + 1 rounded up to 16
     int32_t Wp;             // padded row pitch of the job's 2-D workspace
     int32_t Kp, KL;         // key rows: pitch, and all-ones columns left of column 0
     int32_t dpnw;           // wavefronts the banded DP needs for this job
@@ -91,6 +93,10 @@ struct SegArgs {
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
 // N frames H x W x C (C = 1 or 3, row-major) -> tiled luma
 void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *dst, hipStream_t s);
+// N tiled luma frames -> pixel-major luma: seq[(row W + column) seqp + s] =
+// frame max(s - 1, 0) (s <= N; later entries repeat frame N - 1)
+inline int seq_pitch(int N) { return (N + 1 + 15) / 16 * 16; }
+void launch_seq(const uint8_t *tiled, int N, int H, int W, uint8_t *seq, int seqp, hipStream_t s);
 // N tiled luma frames -> row-major H x W
 void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s);
 // window scans of n clips (d_args: n SegArgs in device memory), one grid layer each

@@ -307,6 +307,47 @@ __device__ __forceinline__ void energy8(const int (&a)[10], const int (&b)[10], 
     for (int x = 0; x < 8; ++x) e[x] = (uint32_t)(2 * g[x] + (pf ? 18 * abs(b[x + 1] - byte_of(p, x)) : 0));
 }
 
+// ------------------------------------------------------ pixel-major luma
+//
+// The refresh reads the same few pixels in every frame of a buffer; a
+// pixel-major copy of the clip's luma makes those reads 16 frames wide.
+// seq[p seqp + s] (p = row W + column): entry 0 is a copy of frame 0, entry
+// s > 0 frame s - 1, entries past N copies of frame N - 1 (seqp is a
+// multiple of 16 above N).  A block of 128 threads takes one tile of 16 rows
+// x 8 columns: per 16 entries it loads the 16 frames' tiles with 16-byte
+// loads into LDS, then each thread writes its pixel's 16 entries with one
+// 16-byte store.
+
+__global__ __launch_bounds__(128) void seq_kernel(const uint8_t *__restrict__ tiled, int N, int H, int W, int64_t FS,
+                                                  int ntc, uint8_t *__restrict__ seq, int seqp)
+{
+    __shared__ __align__(16) uint8_t buf[16 * 128];  // 16 entries x one tile
+    const int tile = blockIdx.x;                    // tile row x ntc + tile column
+    const int tr = tile / ntc, tc = tile - tr * ntc;
+    const int tid = threadIdx.x;
+    // the pixel of byte tid of the tile: row tid / 8, column tid % 8 of the tile
+    const int r = tr * kTileH + (tid >> 3), j = tc * kTileW + (tid & 7);
+    const bool live = r < H && j < W;
+    GLOBAL uint8_t *dst = gp(seq) + ((size_t)r * W + j) * seqp;
+    for (int c = 0; c < seqp / 16; ++c) {
+        // thread tid loads bytes [16 (tid % 8), +16) of the tile of entry 16 c + tid / 8
+        const int f = min(max(16 * c + (tid >> 3) - 1, 0), N - 1);
+        const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(gp(tiled) + (size_t)f * FS + (size_t)tile * 128 +
+                                                                16 * (tid & 7));
+        __syncthreads();  // the previous chunk's reads of buf are done
+        *reinterpret_cast<u32x4 *>(buf + 16 * tid) = v;
+        __syncthreads();
+        if (live) {
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                w[k] = (uint32_t)buf[(4 * k) * 128 + tid] | ((uint32_t)buf[(4 * k + 1) * 128 + tid] << 8) |
+                       ((uint32_t)buf[(4 * k + 2) * 128 + tid] << 16) | ((uint32_t)buf[(4 * k + 3) * 128 + tid] << 24);
+            *reinterpret_cast<GLOBAL u32x4 *>(dst + 16 * c) = u32x4{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
 // ------------------------------------------------------- ASDE window scan
 //
 // A thread holds 8 columns x 2 rows of the original frame (one tile row in
@@ -464,102 +505,62 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
 // clip's first frame.
 
 struct Stencil {
-    int oa0, oa1, oa2, ob0, ob1, ob2, oc0, oc1, oc2;  // offsets in a frame
+    int pa0, pa1, pa2, pb0, pb1, pb2, pc0, pc1, pc2;  // pixels (original row W + original column)
 };
 
 // Stencil of carved pixel (i, j) from the column-map rows of i-1, i, i+1
 // (ma, mb, mc: carved column -> original column).
 __device__ __forceinline__ Stencil stencil_from_rows(const int16_t *ma, const int16_t *mb, const int16_t *mc, int im,
-                                                     int i, int ip, int j, int Wcur, int W, int ntc)
+                                                     int i, int ip, int j, int Wcur, int W)
 {
     const int jm = max(j - 1, 0), jp = min(j + 1, Wcur - 1);
     Stencil s;
-    s.oa0 = tofs(im, mcol(ma, jm, W), ntc);
-    s.oa1 = tofs(im, mcol(ma, j, W), ntc);
-    s.oa2 = tofs(im, mcol(ma, jp, W), ntc);
-    s.ob0 = tofs(i, mcol(mb, jm, W), ntc);
-    s.ob1 = tofs(i, mcol(mb, j, W), ntc);
-    s.ob2 = tofs(i, mcol(mb, jp, W), ntc);
-    s.oc0 = tofs(ip, mcol(mc, jm, W), ntc);
-    s.oc1 = tofs(ip, mcol(mc, j, W), ntc);
-    s.oc2 = tofs(ip, mcol(mc, jp, W), ntc);
+    s.pa0 = im * W + mcol(ma, jm, W);
+    s.pa1 = im * W + mcol(ma, j, W);
+    s.pa2 = im * W + mcol(ma, jp, W);
+    s.pb0 = i * W + mcol(mb, jm, W);
+    s.pb1 = i * W + mcol(mb, j, W);
+    s.pb2 = i * W + mcol(mb, jp, W);
+    s.pc0 = ip * W + mcol(mc, jm, W);
+    s.pc1 = ip * W + mcol(mc, j, W);
+    s.pc2 = ip * W + mcol(mc, jp, W);
     return s;
 }
 
-// Frame source of a buffer's energies, copied into registers once so that
-// loops over frames reload nothing from the job table.
-struct FrameSrc {
-    const GLOBAL uint8_t *l0;  // frame t0 of the buffer
-    int64_t FS;
-    int mode, has_prev, T;
-};
-
-__device__ __forceinline__ FrameSrc frame_src(const Job &J)
+// Sum over the buffer's frames of the energy at a stencil (Sec. 3.3), from
+// the clip's pixel-major luma: the sequence of pixel p is at seq + p seqp,
+// entry 0 a copy of frame 0 and entry s > 0 frame s - 1.  Buffer frame t
+// (clip frame t0 + t) is entry t0 + 1 + t and its predecessor entry t0 + t,
+// which for the clip's first frame is frame 0 itself (no difference term).
+// Entries come 16 at a time: ten 16-byte loads (the nine stencil pixels and
+// the centre's previous 16) serve 16 frames.  Chunks c1, c1 + step, ... of
+// the entries [t0 + 1, t0 + T] are summed; c1 and step are the same in
+// every lane.
+__device__ __forceinline__ uint32_t seq_sum(const Job &J, const Stencil &st, int c1, int step)
 {
-    return FrameSrc{gp(J.luma) + (size_t)J.t0 * J.FS, J.FS, J.mode, J.has_prev, J.T};
-}
-
-// Raw buffer resource over n bytes at p (untyped access, the word-3 value
-// of the gfx9 family).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const GLOBAL uint8_t *p, int64_t n)
-{
-    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)n, 0x00020000);
-}
-
-// Sum over buffer frames t = t1, t1 + step, ... < T (0-based within the
-// buffer) of the energy at a stencil.  The difference term compares frame t
-// with its predecessor, which for t = 0 is the frame before the buffer (when
-// there is one).  t1 and step must be the same in every active lane: frame
-// addresses are then scalar and each pixel read is a 32-bit offset.  The
-// loads of eight (then four) frames are issued before any is used.
-__device__ __forceinline__ uint32_t stencil_sum(const FrameSrc &fs, const Stencil &st, int t1, int step)
-{
+    const GLOBAL uint8_t *q = gp(J.seq);
+    const size_t sp = (size_t)J.seqp;
+    const bool motion = J.mode == 1;
+    const int s_lo = J.t0 + 1, s_hi = J.t0 + J.T;  // entries of the buffer's frames
+    const int cfirst = s_lo >> 4, clast = s_hi >> 4;
+    const int pix[10] = {st.pa0, st.pa1, st.pa2, st.pb0, st.pb2, st.pc0, st.pc1, st.pc2, st.pb1, st.pb1};
     uint32_t acc = 0;
-    const bool motion = fs.mode == 1;
-    // no branches between the loads: without a predecessor the centre
-    // pixel is compared with itself
-    // each frame is read through a buffer resource of its own (scalar base,
-    // FS bytes): a pixel read is one 32-bit offset, and an offset past the
-    // frame reads 0 instead of faulting
-    auto one = [&](int t, int (&v)[10]) {
-        t = __builtin_amdgcn_readfirstlane(t);
-        const GLOBAL uint8_t *f = fs.l0 + (size_t)t * fs.FS;
-        const GLOBAL uint8_t *pf = motion && (t > 0 || fs.has_prev) ? f - fs.FS : f;
-        const __amdgpu_buffer_rsrc_t rf = frame_rsrc(f, fs.FS), rp = frame_rsrc(pf, fs.FS);
-        v[0] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa0, 0, 0);
-        v[1] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa1, 0, 0);
-        v[2] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oa2, 0, 0);
-        v[3] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob0, 0, 0);
-        v[4] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob2, 0, 0);
-        v[5] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc0, 0, 0);
-        v[6] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc1, 0, 0);
-        v[7] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.oc2, 0, 0);
-        v[8] = __builtin_amdgcn_raw_buffer_load_b8(rf, st.ob1, 0, 0);
-        v[9] = __builtin_amdgcn_raw_buffer_load_b8(rp, st.ob1, 0, 0);
-    };
-    auto energy = [&](const int (&v)[10]) {
-        const int g = sobel9(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
-        return motion ? (uint32_t)(2 * g + 18 * abs(v[8] - v[9])) : (uint32_t)g;
-    };
-    int t = t1;
-    for (; t + 7 * step < fs.T; t += 8 * step) {
-        int v[8][10];
+    for (int c = cfirst + c1; c <= clast; c += step) {
+        u32x4 v[10];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) one(t + u * step, v[u]);
+        for (int k = 0; k < 9; ++k) v[k] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)pix[k] * sp + 16 * c);
+        // the centre's 16 entries before this chunk (the predecessor of the first)
+        v[9] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)pix[9] * sp + 16 * max(c - 1, 0));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += energy(v[u]);
-    }
-    for (; t + 3 * step < fs.T; t += 4 * step) {
-        int v[4][10];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) one(t + u * step, v[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += energy(v[u]);
-    }
-    for (; t < fs.T; t += step) {
-        int v0[10];
-        one(t, v0);
-        acc += energy(v0);
+        for (int u = 0; u < 16; ++u) {
+            const int e = 16 * c + u;
+            auto byte = [&](const u32x4 &w, int x) { return (int)((w[x >> 2] >> (8 * (x & 3))) & 255u); };
+            const int g = sobel9(byte(v[0], u), byte(v[1], u), byte(v[2], u), byte(v[3], u), byte(v[4], u),
+                                 byte(v[5], u), byte(v[6], u), byte(v[7], u));
+            const int prev = u > 0 ? byte(v[8], u - 1) : byte(v[9], 15);
+            const uint32_t en = motion ? (uint32_t)(2 * g + 18 * abs(byte(v[8], u) - prev)) : (uint32_t)g;
+            acc += (e >= s_lo && e <= s_hi) ? en : 0u;
+        }
     }
     return acc;
 }
@@ -1414,7 +1415,7 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
     if (Wn <= J.Wt) return;
-    const int H = J.H, Wp = J.Wp, W = J.W, T = J.T, ntc = J.ntc;
+    const int H = J.H, Wp = J.Wp, W = J.W, T = J.T;
     const int Kp = J.Kp;
     const int i0 = blockIdx.x * kRefreshRows;
     if (i0 >= H) return;
@@ -1446,8 +1447,7 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
         }
         return c + a;
     };
-    const FrameSrc fsrc = frame_src(J);
-    auto full_sum = [&](const Stencil &st) { return stencil_sum(fsrc, st, 0, 1); };
+    auto full_sum = [&](const Stencil &st) { return seq_sum(J, st, 0, 1); };
     // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
     const int ncand = kk * nrows * 9;
     for (int u = tid; u < ncand; u += NT) {
@@ -1479,7 +1479,7 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
             } else {  // list full: this thread does the pixel alone
                 const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
                 const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
-                                                     Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W, ntc);
+                                                     Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W);
                 Kn[(size_t)i * Kp + c] = (uint16_t)((full_sum(st) / (uint32_t)T) << 2);
             }
         }
@@ -1490,13 +1490,13 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
         const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
         const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
         fst[p] = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp, Mn + (size_t)ip * Wp, im, i, ip, c,
-                                   Wn, W, ntc);
+                                   Wn, W);
         fsum[p] = 0;
     }
     __syncthreads();
     if (n > 0) {
-        // a wavefront takes 64 listed pixels and every tpp-th frame, so its
-        // lanes read the same frames
+        // a wavefront takes 64 listed pixels and every tpp-th chunk of 16
+        // frames
         const int ng = (n + 63) >> 6, nw = NT >> 6;
         const int tpp = max(nw / ng, 1);
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1504,7 +1504,7 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
             const int p = (task % ng) * 64 + (tid & 63), sub = task / ng;
             if (p < n) {
                 const Stencil st = fst[p];
-                atomicAdd(&fsum[p], stencil_sum(fsrc, st, sub, tpp));
+                atomicAdd(&fsum[p], seq_sum(J, st, sub, tpp));
             }
         }
     }
@@ -1737,6 +1737,14 @@ void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *d
     const int vec = (W % kTileW == 0) && ((((uintptr_t)src) & 7) == 0);
     const dim3 g((unsigned)((int64_t)N * ((H + 15) / 16)), blocks_for(W, 128));
     hipLaunchKernelGGL(tile_luma_kernel, g, dim3(256), 0, s, src, C, N, H, W, dst, vec);
+}
+
+void launch_seq(const uint8_t *tiled, int N, int H, int W, uint8_t *seq, int seqp, hipStream_t s)
+{
+    const int ntc = tiles_across(W);
+    const int tiles = ((H + kTileH - 1) / kTileH) * ntc;
+    hipLaunchKernelGGL(seq_kernel, dim3(tiles), dim3(128), 0, s, tiled, N, H, W, tiled_frame_bytes(H, W), ntc, seq,
+                       seqp);
 }
 
 void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s)
