@@ -39,7 +39,7 @@ constexpr int kDpThreads = 1024;
 struct Job {
     const uint8_t *frames;  // clip, N x H x W x C
     const uint8_t *luma;    // clip luma, N tiled frames of FS bytes
-    const uint8_t *seq;     // clip luma pixel-major (seq_kernel), seqp entries per pixel
+    const uint8_t *seq;     // clip luma pixel-major in 16-entry pieces (seq_kernel), seqp entries per pixel
     uint8_t *out;           // clip output, N x H x Wt x C
     uint16_t *masks;        // clip masks, N x H x W, or null
     int32_t H, W, C, Wt, k, mode;
@@ -93,8 +93,9 @@ struct SegArgs {
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
 // N frames H x W x C (C = 1 or 3, row-major) -> tiled luma
 void launch_tile_luma(const uint8_t *src, int C, int N, int H, int W, uint8_t *dst, hipStream_t s);
-// N tiled luma frames -> pixel-major luma: seq[(row W + column) seqp + s] =
-// frame max(s - 1, 0) (s <= N; later entries repeat frame N - 1)
+// N tiled luma frames -> pixel-major luma: entry s = 16 c + u of pixel p =
+// row W + column at seq[(c H W + p) 16 + u] is frame max(s - 1, 0) (s <= N;
+// later entries, up to seqp per pixel, repeat frame N - 1)
 inline int seq_pitch(int N) { return (N + 1 + 15) / 16 * 16; }
 void launch_seq(const uint8_t *tiled, int N, int H, int W, uint8_t *seq, int seqp, hipStream_t s);
 // N tiled luma frames -> row-major H x W

@@ -311,12 +311,14 @@ __device__ __forceinline__ void energy8(const int (&a)[10], const int (&b)[10], 
 //
 // The refresh reads the same few pixels in every frame of a buffer; a
 // pixel-major copy of the clip's luma makes those reads 16 frames wide.
-// seq[p seqp + s] (p = row W + column): entry 0 is a copy of frame 0, entry
-// s > 0 frame s - 1, entries past N copies of frame N - 1 (seqp is a
-// multiple of 16 above N).  A block of 128 threads takes one tile of 16 rows
-// x 8 columns: per 16 entries it loads the 16 frames' tiles with 16-byte
-// loads into LDS, then each thread writes its pixel's 16 entries with one
-// 16-byte store.
+// Entries s = 16 c + u of pixel p (p = row W + column) are at
+// seq[(c H W + p) 16 + u]: 16 entries of a pixel are one 16-byte piece and
+// the pieces of neighbouring pixels are neighbours.  Entry 0 is a copy of
+// frame 0, entry s > 0 frame s - 1, entries past N copies of frame N - 1
+// (seqp, the entries per pixel, is a multiple of 16 above N).  A block of
+// 128 threads takes one tile of 16 rows x 8 columns: per 16 entries it loads
+// the 16 frames' tiles with 16-byte loads into LDS, then each thread writes
+// its pixel's piece with one 16-byte store.
 
 __global__ __launch_bounds__(128) void seq_kernel(const uint8_t *__restrict__ tiled, int N, int H, int W, int64_t FS,
                                                   int ntc, uint8_t *__restrict__ seq, int seqp)
@@ -328,7 +330,8 @@ __global__ __launch_bounds__(128) void seq_kernel(const uint8_t *__restrict__ ti
     // the pixel of byte tid of the tile: row tid / 8, column tid % 8 of the tile
     const int r = tr * kTileH + (tid >> 3), j = tc * kTileW + (tid & 7);
     const bool live = r < H && j < W;
-    GLOBAL uint8_t *dst = gp(seq) + ((size_t)r * W + j) * seqp;
+    const size_t HW = (size_t)H * W;
+    GLOBAL uint8_t *dst = gp(seq) + ((size_t)r * W + j) * 16;
     for (int c = 0; c < seqp / 16; ++c) {
         // thread tid loads bytes [16 (tid % 8), +16) of the tile of entry 16 c + tid / 8
         const int f = min(max(16 * c + (tid >> 3) - 1, 0), N - 1);
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(128) void seq_kernel(const uint8_t *__restrict__ ti
             for (int k = 0; k < 4; ++k)
                 w[k] = (uint32_t)buf[(4 * k) * 128 + tid] | ((uint32_t)buf[(4 * k + 1) * 128 + tid] << 8) |
                        ((uint32_t)buf[(4 * k + 2) * 128 + tid] << 16) | ((uint32_t)buf[(4 * k + 3) * 128 + tid] << 24);
-            *reinterpret_cast<GLOBAL u32x4 *>(dst + 16 * c) = u32x4{w[0], w[1], w[2], w[3]};
+            *reinterpret_cast<GLOBAL u32x4 *>(dst + (size_t)c * HW * 16) = u32x4{w[0], w[1], w[2], w[3]};
         }
     }
 }
@@ -528,8 +531,8 @@ __device__ __forceinline__ Stencil stencil_from_rows(const int16_t *ma, const in
 }
 
 // Sum over the buffer's frames of the energy at a stencil (Sec. 3.3), from
-// the clip's pixel-major luma: the sequence of pixel p is at seq + p seqp,
-// entry 0 a copy of frame 0 and entry s > 0 frame s - 1.  Buffer frame t
+// the clip's pixel-major luma (seq_kernel): entry 0 of a pixel is a copy of
+// frame 0 and entry s > 0 frame s - 1.  Buffer frame t
 // (clip frame t0 + t) is entry t0 + 1 + t and its predecessor entry t0 + t,
 // which for the clip's first frame is frame 0 itself (no difference term).
 // Entries come 16 at a time: ten 16-byte loads (the nine stencil pixels and
@@ -539,7 +542,7 @@ __device__ __forceinline__ Stencil stencil_from_rows(const int16_t *ma, const in
 __device__ __forceinline__ uint32_t seq_sum(const Job &J, const Stencil &st, int c1, int step)
 {
     const GLOBAL uint8_t *q = gp(J.seq);
-    const size_t sp = (size_t)J.seqp;
+    const size_t piece = (size_t)J.H * J.W * 16;  // bytes per chunk of 16 entries
     const bool motion = J.mode == 1;
     const int s_lo = J.t0 + 1, s_hi = J.t0 + J.T;  // entries of the buffer's frames
     const int cfirst = s_lo >> 4, clast = s_hi >> 4;
@@ -548,9 +551,10 @@ __device__ __forceinline__ uint32_t seq_sum(const Job &J, const Stencil &st, int
     for (int c = cfirst + c1; c <= clast; c += step) {
         u32x4 v[10];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)pix[k] * sp + 16 * c);
+        for (int k = 0; k < 9; ++k)
+            v[k] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)c * piece + 16 * (size_t)pix[k]);
         // the centre's 16 entries before this chunk (the predecessor of the first)
-        v[9] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)pix[9] * sp + 16 * max(c - 1, 0));
+        v[9] = *reinterpret_cast<const GLOBAL u32x4 *>(q + (size_t)max(c - 1, 0) * piece + 16 * (size_t)pix[9]);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = 16 * c + u;
