@@ -45,6 +45,7 @@ struct scpl_ctx {
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
+    hipEvent_t side_in = nullptr, side_out = nullptr;  // pixel-major lumas beside the segmentation
 };
 
 namespace {
@@ -230,6 +231,13 @@ scpl_status ensure_pinned(scpl_ctx *ctx, size_t bytes)
 
 // Streams and events for n job groups (streams only when n > 1: a single
 // group runs on the caller's stream).
+scpl_status ensure_side(scpl_ctx *ctx)
+{
+    if (!ctx->side_in) SCPL_TRY(hipEventCreateWithFlags(&ctx->side_in, hipEventDisableTiming));
+    if (!ctx->side_out) SCPL_TRY(hipEventCreateWithFlags(&ctx->side_out, hipEventDisableTiming));
+    return SCPL_OK;
+}
+
 scpl_status ensure_groups(scpl_ctx *ctx, int n)
 {
     if (!ctx->fork) SCPL_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
@@ -359,7 +367,7 @@ struct SegClip {
     int32_t nbuf = 0;
     // controller
     int t0 = 0, n = 1, nb = 0, t = 1, te = 0;
-    int win = kSegWindow / 2;  // candidates per scan: halved after a rejection, doubled after none
+    int win = kSegWindow;  // candidates per scan: halved after a rejection, doubled after none
     bool valid = false, done = false, launched = false;
 };
 
@@ -798,6 +806,8 @@ void scpl_destroy(scpl_ctx *ctx)
     for (hipStream_t st : ctx->gstreams) (void)hipStreamDestroy(st);
     for (hipEvent_t e : ctx->gevents) (void)hipEventDestroy(e);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->side_in) (void)hipEventDestroy(ctx->side_in);
+    if (ctx->side_out) (void)hipEventDestroy(ctx->side_out);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->jws) (void)hipFree(ctx->jws);
     if (ctx->tws) (void)hipFree(ctx->tws);
@@ -908,16 +918,35 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         off += p.n_frames;
         ProfScope ps(ctx, SCPL_KERNEL_LUMA, s);
         launch_tile_luma(clips[c].d_frames, p.channels, p.n_frames, p.height, p.width, tiled, s);
-        launch_seq(tiled, p.n_frames, p.height, p.width, seq, seq_pitch(p.n_frames), s);
     }
     SCPL_CHECK_LAUNCH();
+    // the pixel-major lumas (read from the first iteration's refresh on) are
+    // built while the segmentation runs, on the last job group's stream (no
+    // stream of their own: more streams than hardware queues would share one)
+    SCPL_TRY(ensure_side(ctx));
+    SCPL_TRY(ensure_groups(ctx, ctx->nstreams));
+    const hipStream_t side = (batched && ctx->nstreams > 1) ? ctx->gstreams[ctx->nstreams - 1] : s;
+    SCPL_TRY(hipEventRecord(ctx->side_in, s));
+    SCPL_TRY(hipStreamWaitEvent(side, ctx->side_in, 0));
+    for (int c = 0; c < nc; ++c) {
+        const scpl_params &p = clips[c].p;
+        ProfScope ps(ctx, SCPL_KERNEL_LUMA, side);
+        launch_seq(seg[c].tiled, p.n_frames, p.height, p.width, const_cast<uint8_t *>(seg[c].seq),
+                   seq_pitch(p.n_frames), side);
+    }
+    SCPL_CHECK_LAUNCH();
+    SCPL_TRY(hipEventRecord(ctx->side_out, side));
     scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
-    if (st != SCPL_OK) return st;
+    if (st != SCPL_OK) {
+        (void)hipStreamSynchronize(side);  // no workspace is released under it
+        return st;
+    }
     for (int c = 0; c < nc; ++c)
         if (clips[c].d_buffer_id)
             SCPL_TRY(hipMemcpyAsync(clips[c].d_buffer_id, seg[c].bid, (size_t)clips[c].p.n_frames * 4,
                                     hipMemcpyHostToDevice, s));
     if (h_nbuf_first) *h_nbuf_first = seg[0].nbuf;
+    SCPL_TRY(hipStreamWaitEvent(s, ctx->side_out, 0));
 
     // jobs: one per buffer of every clip
     struct Pending {
