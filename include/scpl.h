@@ -151,10 +151,12 @@ scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
  * Retarget requests are queued in arrival order.  Each of `lanes` worker
  * threads owns a context and a stream; whenever a lane is free it takes the
  * queued requests that fit the device-memory budget (in order, at most
- * max_batch) and retargets them as one batch (as scpl_retarget_batch).
+ * max_batch) and retargets them as one batch (as scpl_retarget_batch, with
+ * one job group on the lane's stream).
  * A request is admitted by an upper bound of the device memory its batch
- * share can claim (its tiled luma and buffer controller plus one carving
- * job per frame); the admitted requests' bounds never exceed hbm_budget.
+ * share can claim (its tiled and pixel-major luma and buffer controller
+ * plus one carving job per frame); the admitted requests' bounds never
+ * exceed hbm_budget.
  * Requests that arrive while batches run are admitted as lanes and memory
  * free up, and their work overlaps on the device with the batches in
  * flight.  Results are bit-identical to scpl_retarget on each clip alone.

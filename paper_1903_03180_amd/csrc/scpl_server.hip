@@ -130,6 +130,11 @@ scpl_status scpl_server_create(int32_t device, const scpl_server_config *cfg, sc
         scpl_ctx *c = nullptr;
         st = scpl_create(device, &c);
         if (st != SCPL_OK) break;
+        // a lane runs its batch as one job group on its own stream: lanes
+        // already overlap, and more streams than the device's hardware
+        // queues would make streams share queues
+        st = scpl_batch_streams(c, 1);
+        if (st != SCPL_OK) break;
         S->ctxs.push_back(c);
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
