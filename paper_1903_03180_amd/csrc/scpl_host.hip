@@ -152,8 +152,8 @@ size_t job_bytes(const JobShape &s)
 {
     const size_t H = s.H, Wp = s.Wp(), W = s.W, nb = s.nb(), kc = s.kcap(), lc = s.logcap();
     size_t b = 0;
-    b += 2 * align_up(H * Wp * 2);       // M0, M1
-    b += 2 * align_up((H + 1) * (size_t)s.Kp() * 2);  // K0, K1
+    b += align_up(H * Wp * 2);           // M
+    b += align_up((H + 1) * (size_t)s.Kp() * 2);  // K
     b += align_up(H * Wp + kDirScratch);  // dir + scratch row of discarded codes
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
@@ -181,10 +181,8 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.nb = (int32_t)nb;
     J.kcap = (int32_t)kc;
     J.logcap = (int32_t)lc;
-    J.M0 = bp.take<int16_t>(H * Wp);
-    J.M1 = bp.take<int16_t>(H * Wp);
-    J.K0 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
-    J.K1 = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
+    J.M = bp.take<int16_t>(H * Wp);
+    J.K = bp.take<uint16_t>((H + 1) * (size_t)J.Kp);
     J.dir = bp.take<uint8_t>(H * Wp + kDirScratch);
     J.borg = bp.take<int8_t>(nb * Wp);
     J.bmask = bp.take<uint16_t>(H * W);
@@ -1263,7 +1261,7 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
     ls.add(JobShape{H, W, 1, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, ls.Hmax, ls.Wmax, s);
     launch_energy(d_job, 1, H, W, s);
-    launch_keys_to_u(J.K0 + J.KL, d_e, H, W, J.Kp, s);
+    launch_keys_to_u(J.K + J.KL, d_e, H, W, J.Kp, s);
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipStreamSynchronize(s));  // the pinned job slot is reused by the next call
     return SCPL_OK;
@@ -1286,7 +1284,7 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, H, W, s);
-    launch_u_to_keys(d_u, J.K0 + J.KL, H, W, J.Kp, s);
+    launch_u_to_keys(d_u, J.K + J.KL, H, W, J.Kp, s);
     launch_dp(d_job, 1, ls.g, W, s);
     launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);
@@ -1437,7 +1435,7 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
         }
         SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
         launch_init_jobs(d_job, n_jobs, H, W, s);
-        for (int q = 0; q < n_jobs; ++q) launch_tune_fill(h[q].K0, H, W, h[q].Kp, h[q].KL, s);
+        for (int q = 0; q < n_jobs; ++q) launch_tune_fill(h[q].K, H, W, h[q].Kp, h[q].KL, s);
         launch_dp(d_job, n_jobs, g, W, s);  // warm-up
         const int reps = 5;
         SCPL_TRY(hipEventRecord(e0, s));

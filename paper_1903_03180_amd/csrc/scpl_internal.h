@@ -57,10 +57,10 @@ struct Job {
     int32_t logcap;         // records in log
     int32_t buffer_index;   // index of the buffer within its clip
     // workspace (device)
-    int16_t *M0, *M1;       // column maps (carved column -> original column), H x Wp
-    uint16_t *K0, *K1;      // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
+    int16_t *M;             // column map (carved column -> original column), H x Wp, compacted in place
+    uint16_t *K;            // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
                             // 0xffff left of column 0 and at and beyond W_r; (H + 1) rows, the
-                            // extra row all 0xffff
+                            // extra row all 0xffff; compacted in place
     uint8_t *dir;           // indicator codes 0/1/2 = predecessor column - column + 1, H x Wp,
                             // then kDirScratch bytes the DP writes discarded codes to
     int8_t *borg;           // band origins, nb x Wp

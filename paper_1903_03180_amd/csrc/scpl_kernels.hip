@@ -471,19 +471,17 @@ __global__ __launch_bounds__(256) void init_jobs_kernel(const Job *jobs)
     if (i > J.H) return;
     if (i == J.H) {  // the all-ones row read by DP lanes past the job's width
         for (int j = threadIdx.x; j < J.Kp; j += 256) {
-            J.K0[(size_t)i * J.Kp + j] = kRowInf;
-            J.K1[(size_t)i * J.Kp + j] = kRowInf;
+            J.K[(size_t)i * J.Kp + j] = kRowInf;
         }
         return;
     }
     for (int j = threadIdx.x; j < J.W; j += 256) {
-        J.M0[(size_t)i * J.Wp + j] = (int16_t)j;
+        J.M[(size_t)i * J.Wp + j] = (int16_t)j;
         J.bmask[(size_t)i * J.W + j] = 0;
     }
     for (int x = threadIdx.x; x < J.Kp; x += 256) {
         if (x >= J.KL && x < J.KL + J.W) continue;
-        J.K0[(size_t)i * J.Kp + x] = kRowInf;
-        J.K1[(size_t)i * J.Kp + x] = kRowInf;
+        J.K[(size_t)i * J.Kp + x] = kRowInf;
     }
     if (i == 0 && threadIdx.x == 0) {
         J.log[0] = J.W;
@@ -616,7 +614,7 @@ __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
         uint32_t k8[8];
 #pragma unroll
         for (int x = 0; x < 8; ++x) k8[x] = (acc[q][x] / T) << 2;
-        uint16_t *dst = J.K0 + (size_t)i * J.Kp + J.KL + 8 * tc;  // 16-byte aligned
+        uint16_t *dst = J.K + (size_t)i * J.Kp + J.KL + 8 * tc;  // 16-byte aligned
         if (nv == 8) {
             *gp(reinterpret_cast<u32x4 *>(dst)) =
                 u32x4{k8[0] | (k8[1] << 16), k8[2] | (k8[3] << 16), k8[4] | (k8[5] << 16), k8[6] | (k8[7] << 16)};
@@ -735,7 +733,7 @@ __global__ __launch_bounds__(1024) void dp_kernel(const Job *jobs)
     const int j0 = tid * Q;
     const int H = J.H, Kp = J.Kp, Wp = J.Wp;
     const bool owns = J.KL + j0 + Q <= Kp;
-    const uint16_t *K = (r & 1) ? J.K1 : J.K0;
+    const uint16_t *K = J.K;
     // lanes past the job's key rows read the all-ones row at stride 0
     const uint16_t *kp = owns ? K + J.KL + j0 : K + (size_t)H * Kp;
     const size_t kstride = owns ? (size_t)Kp : 0;
@@ -846,7 +844,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     const bool owner = live && lane * Q >= HB && lane * Q < HB + C;
     const bool stores = owner && jl < Wp;
     // waves past the job's columns read the all-ones row, at stride 0
-    const uint16_t *K = (r & 1) ? J.K1 : J.K0;
+    const uint16_t *K = J.K;
     const char *kbase = reinterpret_cast<const char *>(live ? K : K + (size_t)H * Kp);
     const size_t kpitch = live ? (size_t)Kp * 2 : 0;
     const uint32_t koff = live ? (uint32_t)(J.KL + jl) * 2u : 0u;
@@ -1190,7 +1188,7 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
     if (b >= J.nb) return;
     const int H = J.H, nb = J.nb, lane = threadIdx.x;
     const int fp = 2 * J.B + 8;  // LDS pitch: the window of a seam is at most 2 B - 1 wide, staged from a word
-    const int16_t *__restrict__ M = (r & 1) ? J.M1 : J.M0;
+    const int16_t *__restrict__ M = J.M;
     const int lo = b * J.B, hi = min(lo + J.B, H) - 1;
     const int span = hi - lo;  // < B <= kBandMax
     for (int s = blockIdx.x; s < kk; s += gridDim.x) {
@@ -1265,10 +1263,10 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
     const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
     const int Wn = Wr - kk;
     const int Wp = J.Wp;
-    const int16_t *Mo = ((r & 1) ? J.M1 : J.M0) + (size_t)i * Wp;
-    int16_t *__restrict__ Mw = ((r & 1) ? J.M0 : J.M1) + (size_t)i * Wp;
-    const uint16_t *Ko = ((r & 1) ? J.K1 : J.K0) + (size_t)i * J.Kp + J.KL;
-    uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + (size_t)i * J.Kp + J.KL;
+    // in place: new column j never reads an old column left of j, and every
+    // entry is read before the wavefront writes over it
+    int16_t *Mr = J.M + (size_t)i * Wp;
+    uint16_t *Kr = J.K + (size_t)i * J.Kp + J.KL;
     const bool keys = Wn > J.Wt;  // a further iteration reads the keys
     const int16_t *__restrict__ R = J.seams + (size_t)i * J.kcap;  // removed columns of row i, increasing
     // seam s removed old column R[s]; new column j reads old column j + #{s : R[s] - s <= j}
@@ -1283,9 +1281,12 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
         return s < kk ? (int)R[s] - s : 0x7fffffff;
     };
     // row buffers (Wp and Kp - KL entries, multiples of 64) as buffer resources
-    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mo, (short)0, 2 * Wp, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mr, (short)0, 2 * Wp, 0x00020000);
     const __amdgpu_buffer_rsrc_t rK =
-        __builtin_amdgcn_make_buffer_rsrc((void *)Ko, (short)0, 2 * (J.Kp - J.KL), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)Kr, (short)0, 2 * (J.Kp - J.KL), 0x00020000);
+    // columns left of the first threshold keep their entries: passes start at
+    // the 8-aligned column below it
+    const int jstart = min(rs(0), Wn) & ~7;
     // count of thresholds at or below column jb
     auto count = [&](int jb) {
         int a = 0;
@@ -1303,18 +1304,18 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
     };
     auto put = [&](int jb, const u16x2 (&mv)[4], const u16x2 (&kv)[4]) {
         if (jb + 8 <= Wn) {
-            *gp(reinterpret_cast<u32x4 *>(Mw + jb)) = u32x4{pack2(mv[0]), pack2(mv[1]), pack2(mv[2]), pack2(mv[3])};
-            if (keys) *gp(reinterpret_cast<u32x4 *>(Kn + jb)) = u32x4{pack2(kv[0]), pack2(kv[1]), pack2(kv[2]), pack2(kv[3])};
+            *gp(reinterpret_cast<u32x4 *>(Mr + jb)) = u32x4{pack2(mv[0]), pack2(mv[1]), pack2(mv[2]), pack2(mv[3])};
+            if (keys) *gp(reinterpret_cast<u32x4 *>(Kr + jb)) = u32x4{pack2(kv[0]), pack2(kv[1]), pack2(kv[2]), pack2(kv[3])};
         } else {
             for (int q = 0; q < 8 && jb + q < Wn; ++q) {
-                Mw[jb + q] = (int16_t)mv[q >> 1][q & 1];
-                if (keys) Kn[jb + q] = kv[q >> 1][q & 1];
+                Mr[jb + q] = (int16_t)mv[q >> 1][q & 1];
+                if (keys) Kr[jb + q] = kv[q >> 1][q & 1];
             }
         }
     };
     if (staged) {
         uint16_t *sM = stM[w], *sK = stK[w];
-        for (int j0 = 0; j0 < Wn; j0 += kUpdSpan) {
+        for (int j0 = jstart; j0 < Wn; j0 += kUpdSpan) {
             // old columns [j0, hi) hold every source of new columns [j0, j0 + kUpdSpan)
             const int hi = min(j0 + kUpdSpan + kk, Wr);
             const int nv = (hi - j0 + 7) >> 3;  // 16-byte groups, within the row buffers
@@ -1357,7 +1358,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
             __builtin_amdgcn_wave_barrier();
         }
     } else {
-        for (int jb = 8 * lane; jb < Wn; jb += 512) {
+        for (int jb = jstart + 8 * lane; jb < Wn; jb += 512) {
             int a = count(jb);
             int nxt = rs(a);
             u16x2 mv[4], kv[4];
@@ -1376,7 +1377,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
     // the keys of the vacated columns become 0xffff; columns beyond the
     // previous width of this buffer already are
     const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
-    for (int j = Wn + lane; j < wprev; j += 64) Kn[j] = kRowInf;
+    for (int j = Wn + lane; j < wprev; j += 64) Kr[j] = kRowInf;
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -1424,8 +1425,8 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
     const int i0 = blockIdx.x * kRefreshRows;
     if (i0 >= H) return;
     const int nrows = min(kRefreshRows, H - i0);
-    const int16_t *__restrict__ Mn = (r & 1) ? J.M0 : J.M1;
-    uint16_t *__restrict__ Kn = ((r & 1) ? J.K0 : J.K1) + J.KL;
+    const int16_t *__restrict__ Mn = J.M;
+    uint16_t *__restrict__ Kn = J.K + J.KL;
     const int tid = threadIdx.x;
     const bool rl = kk <= kRefreshSeams;
     if (tid == 0) nf = 0;
@@ -1551,8 +1552,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
     const Job &J = jobs[blockIdx.y];
     const int i = blockIdx.x;
     if (i >= J.H) return;
-    const int rd = J.state[0];
-    const int16_t *__restrict__ M = ((rd & 1) ? J.M1 : J.M0) + (size_t)i * J.Wp;
+    const int16_t *__restrict__ M = J.M + (size_t)i * J.Wp;
     const int C = J.C, W = J.W, Wt = J.Wt, H = J.H;
     const int inb = W * C, outb = Wt * C;
     const int tid = threadIdx.x;
