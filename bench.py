@@ -234,8 +234,14 @@ def dp_bytes(per_job, jobs):
     return sum(3 * jb["H"] * int(r[1]) for rows, jb in zip(per_job, jobs) for r in rows)
 
 
-def measured_dp_traffic(workload, q, hb, pf):
-    """HBM bytes per DP dispatch from the committed FETCH_SIZE / WRITE_SIZE
+def dp_kernel_name(g):
+    """rocprofv3 name of the DP kernel of geometry g (ctx.dp_chosen)."""
+    kind = "dp_chunk_kernel" if g["chunk_rows"] else "dp_band_kernel"
+    return f"{kind}<{g['cols_per_lane']}, {g['halo_rows']}, {g['prefetch_rows']}>"
+
+
+def measured_dp_traffic(workload, g):
+    """HBM bytes per DP (all its dispatches) from the committed FETCH_SIZE / WRITE_SIZE
     runs (scaled by the 1 GiB copy), if they were taken on this workload
     with this DP kernel and the kernel source has not changed since; else
     None."""
@@ -245,9 +251,10 @@ def measured_dp_traffic(workload, q, hb, pf):
     with open(path) as f:
         rec = json.load(f)
     same = dp_source_digest() == rec.get("dp_source_sha256")
-    if not same or rec["kernel"] != f"dp_band_kernel<{q}, {hb}, {pf}>":
+    if not same or rec["kernel"] != dp_kernel_name(g) or rec.get("chunk_rows", 0) != g["chunk_rows"]:
         return None
-    return rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]
+    # a DP of a chunked geometry is one dispatch per chunk of rows
+    return (rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) * rec.get("dispatches_per_dp", 1)
 
 
 def dp_source_digest() -> str:
@@ -306,9 +313,9 @@ def main() -> int:
                                           device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
-    dpq, dphb, dppf, dpex, dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))
-    log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpq} columns per lane, halo {dphb}, "
-        f"prefetch {dppf}, exclusive {dpex}: {dpus:.1f} us per launch")
+    dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
+    dpg = ctx.dp_chosen(Wmax)
+    log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -357,7 +364,7 @@ def main() -> int:
     per_job = job_rows(log_rows, jobs)
     dp_bytes_launch = dp_bytes(per_job, jobs) * args.steps / max(dp_n, 1)
     achieved = dp_bytes_launch / (dp_launch_ms * 1e-3) / 1e9
-    traffic = measured_dp_traffic(args.workload, dpq, dphb, dppf)
+    traffic = measured_dp_traffic(args.workload, dpg)
 
     # plain path: clips one after another, buffers one after another
     plain_fps = None
@@ -438,8 +445,7 @@ def main() -> int:
         "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
                    "clips": n_clips, "frames": n_frames, **shape, "buffers": nbuf,
                    "buffer_iterations": int(len(log_rows)),
-                   "dp_geometry": {"cols_per_lane": dpq, "halo_rows": dphb, "prefetch_rows": dppf,
-                                                        "exclusive_cu": dpex}, "streams": args.streams},
+                   "dp_geometry": dpg, "streams": args.streams},
         "value_graph_no_events": round(fps_graph, 2),
         "plain_fps": None if plain_fps is None else round(plain_fps, 2),
         "batched_over_plain": None if plain_fps is None else round(fps / plain_fps, 3),

@@ -236,7 +236,8 @@ scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms,
  * (8,16,8) (8,16,16) (8,32,4) (8,32,8) (16,32,2) (16,32,4) (16,32,8)
  * (16,64,2) (16,64,4), and (32,0,2) for the row-synchronous kernel; EX is
  * 0 or 1.
- * scpl_autotune_dp times every geometry that fits width W with n_jobs
+ * scpl_autotune_dp times every geometry that fits width W (the ones above
+ * and a few column-split ones) with n_jobs
  * concurrent H x W synthetic energies per launch (as in a batched launch;
  * null stream, synchronises) and keeps the fastest for launches whose widest
  * job has width W; when the batched path runs more than one job group
@@ -244,6 +245,17 @@ scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms,
  * h_EX, h_us (nullable) receive the choice and its time per launch in
  * microseconds. */
 scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, int32_t EX);
+/* Column-split DP: every buffer's DP runs as one launch per R rows, with a
+ * workgroup per P owned columns (each covering R more columns on either
+ * side, which stay exact for the R rows).  scpl_dp_chunking(ctx, R, P)
+ * applies to the geometry last forced by scpl_dp_geometry (R = 0: one
+ * launch of one workgroup per buffer again); valid for (Q, HB, PF) in
+ * (4,16,8) (2,8,16) (4,8,8) with R and P multiples of Q, R >= HB, and a
+ * cover of P + 2R columns that the workgroup's wavefronts can hold.
+ * scpl_dp_chosen writes the geometry used for launches whose widest job has
+ * width W: h_geom[6] = (Q, HB, PF, EX, R, P). */
+scpl_status scpl_dp_chunking(scpl_ctx *ctx, int32_t R, int32_t P);
+scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom);
 scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
                              int32_t *h_PF, int32_t *h_EX, double *h_us);
 

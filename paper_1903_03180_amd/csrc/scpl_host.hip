@@ -158,6 +158,7 @@ size_t job_bytes(const JobShape &s)
     b += align_up(nb * Wp);              // borg
     b += align_up(H * W * 2);            // bmask
     b += 2 * align_up(Wp * 4);           // ce_last, lab_last
+    b += align_up(2 * Wp * 4);           // bk
     b += align_up(2 * Wp * 8);           // keys
     b += align_up(kc * 4);               // children
     b += align_up(kc * nb * 4);          // bcol
@@ -188,6 +189,7 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.bmask = bp.take<uint16_t>(H * W);
     J.ce_last = bp.take<int32_t>(Wp);
     J.lab_last = bp.take<int32_t>(Wp);
+    J.bk = bp.take<uint32_t>(2 * Wp);
     J.keys = bp.take<uint64_t>(2 * Wp);
     J.children = bp.take<int32_t>(kc);
     J.bcol = bp.take<int32_t>(kc * nb);
@@ -510,7 +512,7 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
 {
     {
         ProfScope ps(ctx, SCPL_KERNEL_DP, s);
-        launch_dp(d_jobs, nj, ls.g, ls.Wmax, s);
+        launch_dp(d_jobs, nj, ls.g, ls.Wmax, ls.Hmax, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
@@ -1285,7 +1287,7 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W)});
     launch_init_jobs(d_job, 1, H, W, s);
     launch_u_to_keys(d_u, J.K + J.KL, H, W, J.Kp, s);
-    launch_dp(d_job, 1, ls.g, W, s);
+    launch_dp(d_job, 1, ls.g, W, H, s);
     launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);
     launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);
@@ -1381,6 +1383,32 @@ scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, i
     return SCPL_ERR_INVALID_ARG;
 }
 
+scpl_status scpl_dp_chunking(scpl_ctx *ctx, int32_t R, int32_t P)
+{
+    if (!ctx || R < 0 || P < 0) return SCPL_ERR_INVALID_ARG;
+    if (R == 0) {
+        ctx->forced.R = 0;
+        ctx->forced.P = 0;
+        return SCPL_OK;
+    }
+    DpGeom g = ctx->forced;
+    g.R = R;
+    g.P = P;
+    if (g.Q <= 0 || !g.banded || P > SCPL_MAX_WIDTH || R > SCPL_MAX_HEIGHT || !dp_geom_fits(g, 1))
+        return SCPL_ERR_INVALID_ARG;
+    ctx->forced = g;
+    return SCPL_OK;
+}
+
+scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom)
+{
+    if (!ctx || !h_geom || W < 1 || W > SCPL_MAX_WIDTH) return SCPL_ERR_INVALID_ARG;
+    const DpGeom g = select_geom(ctx, W);
+    const int32_t v[6] = {g.Q, g.banded ? g.HB : 0, g.PF, g.EX, g.R, g.P};
+    for (int q = 0; q < 6; ++q) h_geom[q] = v[q];
+    return SCPL_OK;
+}
+
 scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
                              int32_t *h_PF, int32_t *h_EX, double *h_us)
 {
@@ -1394,13 +1422,15 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
     // which a timing in isolation cannot see: it then keeps its compute
     // units to itself (EX = 1)
     const int ex0 = ctx->nstreams > 1 ? 1 : 0;
-    for (int v = 0; v < kNumDpVariants; ++v)
-        if (dp_geom_fits(kDpVariants[v], W))
+    for (int v = 0; v < kNumDpVariants + kNumDpChunked; ++v) {
+        const DpGeom &gv = v < kNumDpVariants ? kDpVariants[v] : kDpChunked[v - kNumDpVariants];
+        if (dp_geom_fits(gv, W))
             for (int ex = ex0; ex < 2; ++ex) {
-                DpGeom g = kDpVariants[v];
+                DpGeom g = gv;
                 g.EX = ex;
                 cand.push_back(g);
             }
+    }
     if (cand.empty()) {
         DpGeom g = dp_geom(W);
         if (ex0 == 0) cand.push_back(g);
@@ -1436,10 +1466,10 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
         SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job) * (size_t)n_jobs, hipMemcpyHostToDevice, s));
         launch_init_jobs(d_job, n_jobs, H, W, s);
         for (int q = 0; q < n_jobs; ++q) launch_tune_fill(h[q].K, H, W, h[q].Kp, h[q].KL, s);
-        launch_dp(d_job, n_jobs, g, W, s);  // warm-up
+        launch_dp(d_job, n_jobs, g, W, H, s);  // warm-up
         const int reps = 5;
         SCPL_TRY(hipEventRecord(e0, s));
-        for (int q = 0; q < reps; ++q) launch_dp(d_job, n_jobs, g, W, s);
+        for (int q = 0; q < reps; ++q) launch_dp(d_job, n_jobs, g, W, H, s);
         SCPL_TRY(hipEventRecord(e1, s));
         SCPL_TRY(hipEventSynchronize(e1));
         SCPL_CHECK_LAUNCH();

@@ -66,6 +66,7 @@ struct Job {
     int8_t *borg;           // band origins, nb x Wp
     uint16_t *bmask;        // buffer mask in original columns, H x W
     int32_t *ce_last;       // DP last row, Wp
+    uint32_t *bk;           // 2 x Wp: keys of a row chunk's last row (chunked DP)
     int32_t *lab_last;      // labels of the last row, Wp (stage entry points only)
     uint64_t *keys;         // 2 x Wp scratch for the selection
     int32_t *children;      // kcap
@@ -111,8 +112,11 @@ void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t
 // LDS of its compute unit, so no other workgroup shares that unit.
 struct DpGeom {
     int Q, HB, banded, PF, EX;
+    int R = 0, P = 0;  // chunked (R > 0): R rows per launch, P owned columns per workgroup
     int C() const { return 64 * Q - 2 * HB; }
     int waves(int W) const { return (W + C() - 1) / C(); }
+    int chunk_waves() const { return (P + 2 * R + C() - 1) / C(); }
+    int groups(int W) const { return R > 0 ? (W + P - 1) / P : 1; }
     // columns at or right of column 0 the DP may read for a job of width W
     int cover(int W) const;
     int threads(int Wmax) const;
@@ -121,9 +125,11 @@ DpGeom dp_geom(int Wmax);  // default for the widest job of a launch
 bool dp_geom_fits(const DpGeom &g, int Wmax);
 extern const DpGeom kDpVariants[];
 extern const int kNumDpVariants;
+extern const DpGeom kDpChunked[];
+extern const int kNumDpChunked;
 constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every HB)
 constexpr int kDirScratch = 64 * 16;  // after the indicator rows: discarded codes of one row (64 lanes x Q <= 16)
-void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStream_t s);
+void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax, hipStream_t s);
 void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s);
 void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s);
 void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s);

@@ -939,6 +939,149 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     }
 }
 
+// Column-split DP over a chunk of R rows: several workgroups per buffer, one
+// launch per chunk.  Workgroup g owns the columns [A, B) = [g P, (g + 1) P)
+// (clipped to W_r) and covers [X0, X0 + nwv C) with X0 = max(A - R, 0): as
+// in dp_band_kernel each wavefront owns C columns of the cover, computes HB
+// more on each side and meets the others every HB rows through LDS.
+// Columns outside the cover count as all ones, so the cover loses one exact
+// column per row at each inner edge; after R rows the owned columns are
+// still exact.  A chunk starts from the previous chunk's last row of 32-bit
+// keys (two rows per buffer, used by consecutive chunks in turn; columns
+// outside the frame start at all ones, which like the 0xffff padding never
+// wins) and leaves its own last row there; the first chunk starts from key
+// row 0, the last writes the last row's CE.  With fewer columns per lane
+// than one workgroup per buffer can afford, a row costs fewer instructions
+// per wavefront, and the launch boundaries replace any wait between
+// workgroups.
+template <int Q, int HB, int PF>
+__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int r0, int R, int P)
+{
+    constexpr int C = 64 * Q - 2 * HB;
+    static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
+    extern __shared__ uint32_t rowbuf[];  // 2 x nwv C keys: the cover
+    const Job &J = jobs[blockIdx.y];
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
+    if (Wr <= J.Wt) return;
+    const int H = J.H, Kp = J.Kp, Wp = J.Wp;
+    if (r0 >= H) return;
+    const int A = (int)blockIdx.x * P;
+    if (A >= Wr) return;
+    const int B = min(A + P, Wr);
+    const int Bs = B == Wr ? Wp : B;  // the last workgroup also stores the padding codes
+    const int nwv = blockDim.x >> 6;
+    const int cw = nwv * C;
+    const int X0 = max(A - R, 0);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int jl = X0 + wid * C - HB + lane * Q;  // first column of this lane (>= -HB)
+    const bool wown = lane * Q >= HB && lane * Q < HB + C;  // the wavefront's own columns
+    const bool stores = wown && jl >= A && jl < Bs;
+    const int ci = r0 / R;  // chunk index
+    const int i_end = min(r0 + R, H);
+    const char *kbase = reinterpret_cast<const char *>(J.K);
+    const size_t kpitch = (size_t)Kp * 2;
+    const uint32_t koff = (uint32_t)(J.KL + jl) * 2u;
+    uint8_t *__restrict__ dir = J.dir;
+    uint32_t coff = stores ? (uint32_t)jl : (uint32_t)(H * Wp + lane * Q);
+    const uint32_t cstep = stores ? (uint32_t)Wp : 0u;
+
+    uint32_t key[Q];
+    int i1;  // first row computed from the previous one
+    if (r0 == 0) {
+        KRow<Q> k0;
+        load_krow_at<Q>(k0, kbase, koff);
+        uint32_t code[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            key[c] = k0.at(c);
+            code[c] = 1;
+        }
+        store_codes<Q>(dir + coff, code);
+        i1 = 1;
+    } else {
+        const uint32_t *bk = J.bk + (size_t)((ci - 1) & 1) * Wp;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const int j = jl + c;
+            key[c] = (j >= 0 && j < Wr) ? bk[j] : kKeyInf;
+        }
+        i1 = r0;
+    }
+    coff += cstep * (uint32_t)i1;
+    uint32_t lnb = kKeyInf, rnb = kKeyInf;
+    int band_left = HB;
+    int buf = 0;
+
+    auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (size_t)min(i0 + s, H - 1) * kpitch, koff);
+    };
+    auto step = [&](const KRow<Q> &kr) {
+        lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
+        rnb = (uint32_t)__builtin_amdgcn_update_dpp((int)rnb, (int)key[0], 0x130, 0xf, 0xf, false);
+        uint32_t best[Q];
+        dp_step<Q>(key, lnb, rnb, kr, best);
+        store_codes<Q>(dir + coff, best);
+        coff += cstep;
+        --band_left;
+    };
+    auto exchange = [&]() {
+        uint32_t *rowp = rowbuf + (size_t)buf * cw;
+        if (wown) {
+#pragma unroll
+            for (int c = 0; c < Q; ++c) rowp[jl + c - X0] = key[c];
+        }
+        __syncthreads();
+        if (!wown) {
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const int j = jl + c;
+                key[c] = (j >= X0 && j < X0 + cw && j < Wr) ? rowp[j - X0] : kKeyInf;
+            }
+        }
+        buf ^= 1;
+        band_left = HB;
+    };
+    auto group = [&](const KRow<Q>(&kr)[PF], int i0, bool guard) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            if (guard && i0 + s >= i_end) break;
+            if (band_left == 0) exchange();
+            step(kr[s]);
+        }
+    };
+
+    KRow<Q> ka[PF], kb[PF];
+    fetch(ka, i1);
+    int i0 = i1;
+    for (; i0 + 2 * PF <= i_end; i0 += 2 * PF) {
+        fetch(kb, i0 + PF);
+        group(ka, i0, false);
+        fetch(ka, i0 + 2 * PF);
+        group(kb, i0 + PF, false);
+    }
+    if (i0 < i_end) {
+        fetch(kb, i0 + PF);
+        group(ka, i0, true);
+        if (i0 + PF < i_end) group(kb, i0 + PF, true);
+    }
+    // the chunk's last row: the next chunk's start, or the last row's CE
+    const bool last = i_end == H;
+    uint32_t *bko = J.bk + (size_t)(ci & 1) * Wp;
+    if (wown) {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const int j = jl + c;
+            if (j >= A && j < B) {
+                if (last) J.ce_last[j] = (int)(key[c] >> 2);
+                else bko[j] = key[c];
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- band origins
 //
 // For band b (rows [lo, hi]) and every column j at row hi: follow the
@@ -1784,6 +1927,7 @@ void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t
 
 int DpGeom::cover(int W) const
 {
+    if (banded && R > 0) return W + chunk_waves() * C() + HB;
     if (banded) return waves(W) * C() + HB;
     const int t = (W + Q - 1) / Q;
     return ((t + 63) / 64) * 64 * Q;
@@ -1791,6 +1935,7 @@ int DpGeom::cover(int W) const
 
 int DpGeom::threads(int Wmax) const
 {
+    if (banded && R > 0) return 64 * chunk_waves();
     if (banded) return 64 * waves(Wmax);
     const int t = (Wmax + Q - 1) / Q;
     return ((t + 63) / 64) * 64;
@@ -1804,9 +1949,21 @@ const DpGeom kDpVariants[] = {{2, 8, 1, 8, 0},   {2, 8, 1, 16, 0},  {4, 8, 1, 8,
                               {16, 32, 1, 4, 0}, {16, 32, 1, 8, 0}, {16, 64, 1, 2, 0}, {16, 64, 1, 4, 0}};
 const int kNumDpVariants = (int)(sizeof(kDpVariants) / sizeof(kDpVariants[0]));
 
+// Chunked variants (column-split DP, one launch per R rows).
+const DpGeom kDpChunked[] = {
+    {4, 16, 1, 8, 0, 256, 384}, {4, 16, 1, 8, 0, 384, 256},  {4, 16, 1, 8, 0, 320, 384}, {4, 16, 1, 8, 0, 192, 512},
+    {4, 16, 1, 8, 0, 128, 640}, {4, 16, 1, 8, 0, 512, 768},  {2, 8, 1, 16, 0, 128, 640}, {2, 8, 1, 16, 0, 64, 768},
+    {4, 8, 1, 8, 0, 128, 704}};
+const int kNumDpChunked = (int)(sizeof(kDpChunked) / sizeof(kDpChunked[0]));
+
 bool dp_geom_fits(const DpGeom &g, int Wmax)
 {
     if (!g.banded) return true;
+    if (g.R > 0)  // the instantiated dp_chunk_kernel variants
+        return ((g.Q == 4 && g.HB == 16 && g.PF == 8) || (g.Q == 2 && g.HB == 8 && g.PF == 16) ||
+                (g.Q == 4 && g.HB == 8 && g.PF == 8)) &&
+               g.C() > 0 && g.P > 0 && g.P % g.Q == 0 && g.R % g.Q == 0 && g.R >= g.HB &&
+               g.threads(Wmax) <= dp_max_threads(g.Q, g.PF) && (size_t)2 * g.chunk_waves() * g.C() * 4 <= 65536;
     return g.C() > 0 && g.threads(Wmax) <= dp_max_threads(g.Q, g.PF) && (size_t)2 * (g.cover(Wmax) + 64) * 4 <= 65536;
 }
 
@@ -1824,8 +1981,24 @@ DpGeom dp_geom(int Wmax)
 
 size_t g_dp_lds_cap = 65536;  // LDS of one compute unit as a workgroup may request it
 
-void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, hipStream_t s)
+void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax, hipStream_t s)
 {
+    if (g.banded && g.R > 0) {
+        const dim3 grid(g.groups(Wmax), njobs), block(g.threads(Wmax));
+        size_t lds = (size_t)2 * g.chunk_waves() * g.C() * sizeof(uint32_t);
+        if (g.EX && lds < g_dp_lds_cap) lds = g_dp_lds_cap;
+#define SCPL_DPC_CASE(q, hb, pf)                                                                          \
+    if (g.Q == q && g.HB == hb && g.PF == pf) {                                                           \
+        for (int r0 = 0; r0 < Hmax; r0 += g.R)                                                            \
+            hipLaunchKernelGGL((dp_chunk_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, r0, g.R, g.P);  \
+        return;                                                                                           \
+    }
+        SCPL_DPC_CASE(4, 16, 8)
+        SCPL_DPC_CASE(2, 8, 16)
+        SCPL_DPC_CASE(4, 8, 8)
+#undef SCPL_DPC_CASE
+        return;
+    }
     const dim3 grid(njobs), block(g.threads(Wmax));
     // two ping-pong rows of keys: the widest job's key row less its left pad
     size_t lds = g.banded ? (size_t)2 * (g.cover(Wmax) + 64) * sizeof(uint32_t) : 0;
@@ -1904,7 +2077,8 @@ void set_kernel_attributes(size_t lds_cap)
         reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 2>), reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 2>),
         reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 16>), reinterpret_cast<const void *>(&dp_band_kernel<8, 32, 8>),
         reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 4>), reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 8>),
-        reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 4>)};
+        reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 4>), reinterpret_cast<const void *>(&dp_chunk_kernel<4, 16, 8>),
+        reinterpret_cast<const void *>(&dp_chunk_kernel<2, 8, 16>), reinterpret_cast<const void *>(&dp_chunk_kernel<4, 8, 8>)};
     for (const void *f : dps) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);

@@ -36,7 +36,8 @@ EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_dp_geometry",
-    "scpl_autotune_dp", "scpl_batch_streams", "scpl_server_create", "scpl_server_submit", "scpl_server_poll",
+    "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_server_create",
+    "scpl_server_submit", "scpl_server_poll",
     "scpl_server_wait", "scpl_server_ticket_times", "scpl_server_release", "scpl_server_destroy",
     "scpl_server_footprint", "scpl_asde", "scpl_compact",
 ]
@@ -44,6 +45,10 @@ EXPORTS = [
 DP_GEOMETRIES = [(2, 8, 8), (2, 8, 16), (4, 8, 8), (4, 8, 16), (4, 16, 8), (4, 16, 16), (8, 16, 4), (8, 16, 8),
                  (8, 16, 16), (8, 32, 4), (8, 32, 8), (16, 32, 2), (16, 32, 4), (16, 32, 8), (16, 64, 2), (16, 64, 4),
                  (32, 0, 2)]
+# column-split DP (Q, HB, PF, R, P): one launch per R rows, a workgroup per P columns
+DP_CHUNKED = [(4, 16, 8, 256, 384), (4, 16, 8, 384, 256), (4, 16, 8, 320, 384), (4, 16, 8, 192, 512),
+              (4, 16, 8, 128, 640), (4, 16, 8, 512, 768), (2, 8, 16, 128, 640), (2, 8, 16, 64, 768),
+              (4, 8, 8, 128, 704)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
@@ -81,6 +86,8 @@ _sig = {
     "scpl_profile_enable": ([_P, _I32], C.c_int),
     "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
     "scpl_dp_geometry": ([_P, _I32, _I32, _I32, _I32], C.c_int),
+    "scpl_dp_chunking": ([_P, _I32, _I32], C.c_int),
+    "scpl_dp_chosen": ([_P, _I32, C.POINTER(_I32)], C.c_int),
     "scpl_batch_streams": ([_P, _I32], C.c_int),
     "scpl_server_create": ([_I32, C.POINTER(scpl_server_config), C.POINTER(C.c_void_p)], C.c_int),
     "scpl_server_submit": ([_P, C.POINTER(scpl_clip), C.POINTER(_I64)], C.c_int),
@@ -257,6 +264,19 @@ class Context:
         rows, PF = 0: default depth; EX = 1: one DP workgroup per compute
         unit and nothing beside it); Q = 0: automatic."""
         _check(scpl_dp_geometry(self.h, Q, HB, PF, EX), "scpl_dp_geometry")
+
+    def dp_chunking(self, R: int = 0, P: int = 0) -> None:
+        """Run the forced geometry's DP column-split: one launch per R rows,
+        a workgroup per P owned columns (R = 0: one launch, one workgroup
+        per buffer)."""
+        _check(scpl_dp_chunking(self.h, R, P), "scpl_dp_chunking")
+
+    def dp_chosen(self, W: int) -> dict:
+        """The DP geometry used for launches whose widest job has width W."""
+        g = (C.c_int32 * 6)()
+        _check(scpl_dp_chosen(self.h, W, g), "scpl_dp_chosen")
+        return dict(zip(("cols_per_lane", "halo_rows", "prefetch_rows", "exclusive_cu", "chunk_rows",
+                         "chunk_cols"), [int(x) for x in g]))
 
     def autotune_dp(self, H: int, W: int, n_jobs: int = 1):
         """Time every DP geometry on launches of n_jobs H x W jobs; keep the

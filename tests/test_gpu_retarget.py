@@ -204,6 +204,20 @@ def test_forced_geometry_retarget(ctx, orc, geom):
         ctx.dp_geometry(0)
 
 
+@pytest.mark.parametrize("geom", [(4, 16, 8, 1, 32, 64), (2, 8, 16, 0, 16, 96), (4, 16, 8, 1, 128, 640)])
+def test_chunked_geometry_retarget(ctx, orc, geom):
+    """Whole retargets with a column-split DP (many row chunks and
+    workgroups for the small R, P), against the oracle."""
+    clip = synth.make_clip(611, 8, 70, 300, C=3, n_obj=3, cut_at=4, lattice=8)
+    q, hb, pf, ex, R, P = geom
+    ctx.dp_geometry(q, hb, pf, ex)
+    ctx.dp_chunking(R, P)
+    try:
+        compare(ctx, orc, clip, 220, 6)
+    finally:
+        ctx.dp_geometry(0)
+
+
 @pytest.mark.parametrize("shape,Wt", [((3, 144, 176), 140), ((2, 144, 176), 105), ((2, 48, 64), 38)])
 def test_raw_baseline_matches_oracle(ctx, orc, shape, Wt):
     """The paper's comparison "Raw": classic seam carving of every frame on

@@ -119,6 +119,7 @@ def test_segment_max_buffer_and_off(ctx, orc):
     assert bid.tolist() == list(range(40))
 
 
+from paper_1903_03180_amd.scpl import DP_CHUNKED  # noqa: E402
 from paper_1903_03180_amd.scpl import DP_GEOMETRIES as GEOMETRIES  # noqa: E402
 
 
@@ -144,6 +145,36 @@ def test_dp_every_geometry(ctx, orc, geom):
         for shape in [(3, 1), (40, 333), (130, 1000), (77, 1920), (20, 3100), (9, 6000)]:
             rng = np.random.default_rng(shape[1] + geom[0])
             u = rng.integers(0, 40, size=shape).astype(np.int32)
+            ce, lab, d = ctx.dp(dev(u))
+            oce, olab, od = orc.dp(u)
+            assert np.array_equal(host(ce), oce[-1]), shape
+            assert np.array_equal(host(lab), olab[-1]), shape
+            assert np.array_equal(host(d), od), shape
+    finally:
+        ctx.dp_geometry(0)
+
+
+CHUNKED = DP_CHUNKED + [(4, 16, 8, 16, 64), (2, 8, 16, 8, 16), (4, 8, 8, 32, 96)]
+
+
+@pytest.mark.parametrize("geom", [g + (ex,) for g in CHUNKED for ex in (0, 1)])
+def test_dp_chunked(ctx, orc, geom):
+    """Column-split DP (one launch per R rows, a workgroup per P columns):
+    the oracle's result for heights below, at and above multiples of R and
+    widths below, at and above multiples of P, with the extreme key 16382
+    at the borders."""
+    q, hb, pf, R, P, ex = geom
+    ctx.dp_geometry(q, hb, pf, ex)
+    ctx.dp_chunking(R, P)
+    try:
+        g = ctx.dp_chosen(4096)
+        assert (g["chunk_rows"], g["chunk_cols"]) == (R, P)
+        for shape in [(1, 7), (2, 1), (R, P), (R + 1, P - q), (2 * R - 1, 2 * P + 5), (3 * R, 3 * P),
+                      (130, 1000), (77, 1920), (20, 3100)]:
+            rng = np.random.default_rng(shape[0] * 7 + shape[1] + q)
+            u = rng.integers(0, 40, size=shape).astype(np.int32)
+            u[:, 0] = 16382
+            u[::2, -1] = 16382
             ce, lab, d = ctx.dp(dev(u))
             oce, olab, od = orc.dp(u)
             assert np.array_equal(host(ce), oce[-1]), shape
