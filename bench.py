@@ -14,7 +14,10 @@ resident in HBM.  Workloads:
 clip advances together, one launch per stage per iteration, iterations
 replayed from a HIP graph); the plain path (one buffer after another, clip
 after clip) is timed beside it.  The oracle (plain C, one core) is timed on
-a bounded sample of the first clip.
+a bounded sample of the first clip.  Seam memorisation (only every m-th
+buffer of a clip carved, the others reusing its removal) is timed on the same
+workload for the periods of --memo-periods, with the fraction of output bytes
+it changes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
@@ -282,6 +285,8 @@ def main() -> int:
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--memo-periods", default="2,4",
+                    help="seam-memorisation periods to time on the same workload (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device tensor copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -351,6 +356,36 @@ def main() -> int:
     g1 = time.perf_counter()
     fps_graph = n_frames * args.steps / (g1 - g0)
     log(f"batched (graph, no event timing): {(g1 - g0) * 1e3 / args.steps:.2f} ms/step, {fps_graph:.1f} frames/s")
+
+    # seam memorisation (only buffers b with b mod m == 0 carved): graph-timed
+    # steps of the same workload, and how much of the output it changes
+    memo = []
+    periods = [int(x) for x in args.memo_periods.split(",") if x.strip()]
+    if periods:
+        full = [c["out"].clone() for c in clips]
+        for m in periods:
+            for c in clips:
+                c["memo_period"] = m
+            step_batched()
+            torch.cuda.synchronize()
+            m0 = time.perf_counter()
+            for i in range(args.steps):
+                step_batched()
+            torch.cuda.synchronize()
+            m1 = time.perf_counter()
+            diff = sum(int((c["out"] != f).sum().item()) for c, f in zip(clips, full))
+            total = sum(f.numel() for f in full)
+            nb_carved = sum(len([b for b in range(int(c["buffer_id"].max().item()) + 1) if b % m == 0])
+                            for c in clips)
+            memo.append({"period": m, "fps_graph": round(n_frames * args.steps / (m1 - m0), 2),
+                         "ms_per_step": round((m1 - m0) * 1e3 / args.steps, 3), "buffers_carved": nb_carved,
+                         "output_bytes_changed_frac": round(diff / total, 5)})
+            log(f"memorisation m={m}: {(m1 - m0) * 1e3 / args.steps:.2f} ms/step, "
+                f"{n_frames * args.steps / (m1 - m0):.1f} frames/s, {nb_carved} buffers carved, "
+                f"{diff / total:.4f} of output bytes changed")
+        for c in clips:
+            c["memo_period"] = 0
+        del full
 
     # dominant kernel and its roofline
     ktime = {kn: v[0] for kn, v in prof.items()}
@@ -462,6 +497,7 @@ def main() -> int:
                           "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "serving": serving,
         "raw_vs_proposed": table1,
+        "seam_memorisation": memo,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -90,7 +90,19 @@ typedef struct {
     int32_t alpha_den;
     int32_t max_buffer;     /* 0: unbounded (paper); > 0: force a new buffer at this length */
     int32_t target_height;  /* 0 or H: height kept; 1 <= Ht < H: horizontal seams, see below */
+    int32_t memo_period;    /* 0 or 1: every buffer carved; m >= 2: seam memorisation, see below */
 } scpl_params;
+
+/* Seam memorisation (Sec. 5 names it as future work without defining it;
+ * this is the library's reading).  With memo_period = m >= 2, buffer b of a
+ * clip (0-based, in time order) is carved only when b mod m == 0.  Every
+ * other buffer reuses the seams of buffer b - (b mod m): from each of its
+ * frames exactly the pixels that buffer removed are removed, so its output
+ * rows are its input rows without those pixels and its masks equal that
+ * buffer's masks (iteration numbers included).  The buffer segmentation is
+ * unchanged, memorised buffers add no record to scpl_last_log, and results
+ * differ from m <= 1 wherever a memorised buffer's own seams would differ.
+ * With a height pass the rule applies to each pass's buffers. */
 
 typedef struct scpl_ctx scpl_ctx;
 

@@ -56,7 +56,7 @@ def lib():
         L.oracle_segment.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, i32, i32, C.c_int, P, P]
         L.oracle_segment.restype = C.c_int
         L.oracle_retarget.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                      C.c_int, i32, i32, C.c_int, P, P, P, P, i64]
+                                      C.c_int, i32, i32, C.c_int, C.c_int, P, P, P, P, i64]
         L.oracle_retarget.restype = i64
         _lib = L
     return _lib
@@ -151,11 +151,14 @@ def segment(Y: np.ndarray, mode: int = MOTION, use_buffer: int = 1, anum: int = 
 
 
 def retarget(frames: np.ndarray, Wt: int, k: int, mode: int = MOTION, use_buffer: int = 1, anum: int = 1,
-             aden: int = 5, max_buffer: int = 0, want_masks: bool = True, log_cap: int = 1 << 16):
+             aden: int = 5, max_buffer: int = 0, want_masks: bool = True, log_cap: int = 1 << 16,
+             memo_period: int = 0):
     """frames: N x H x W (luma) or N x H x W x 3 (RGB) uint8.
 
+    memo_period m >= 2: only buffers b with b mod m == 0 are carved; the
+    others remove the pixels buffer b - (b mod m) removed (seam memorisation).
     Returns dict(out, masks, buffer_id, log) where log rows are
-    (buffer, W_r, P_eff, k_iter) for every iteration of every buffer."""
+    (buffer, W_r, P_eff, k_iter) for every iteration of every carved buffer."""
     frames = np.ascontiguousarray(frames, dtype=np.uint8)
     if frames.ndim == 3:
         N, H, W = frames.shape
@@ -168,7 +171,7 @@ def retarget(frames: np.ndarray, Wt: int, k: int, mode: int = MOTION, use_buffer
     bid = np.empty(N, dtype=np.int32)
     log = np.empty((log_cap, 4), dtype=np.int32)
     n = lib().oracle_retarget(_p(frames), N, H, W, Cc, Wt, k, mode, use_buffer, anum, aden, max_buffer,
-                              _p(out), _p(masks) if masks is not None else None, _p(bid), _p(log), log_cap)
+                              memo_period, _p(out), _p(masks) if masks is not None else None, _p(bid), _p(log), log_cap)
     if n < 0:
         raise ValueError(f"oracle_retarget failed with {n}")
     return dict(out=out, masks=masks, buffer_id=bid, log=log[:min(n, log_cap)].copy())

@@ -39,6 +39,11 @@
  *    candidate is rejected (buffer fixed, candidate starts the next buffer)
  *    when ASDE > phi(n), compared exactly in 128-bit integers.
  *  - uniform energy (Sec. 3.2): floor of the mean of the buffer's energy maps.
+ *  - seam memorisation (named as future work in Sec. 5, not defined there):
+ *    with a period m >= 2, buffer b is carved only when b mod m == 0; every
+ *    other buffer removes from each of its frames the very pixels that buffer
+ *    b - (b mod m) removed (same mask), keeping the rest of each row in
+ *    order.
  */
 #include "scpl_oracle.h"
 
@@ -332,14 +337,18 @@ static void remove_seams_i32(int32_t *img, int H, int W, const int32_t *seams, i
  * buffer, until the target width is reached.  frames: N x H x W x C u8.
  * out: N x H x Wt x C.  masks (nullable): N x H x W u16, 0 = kept, r+1 =
  * removed in iteration r of the frame's buffer.  buffer_id (nullable): N.
- * log (nullable): per iteration of every buffer, in order, four int32:
+ * memo_period: 0 or 1 carves every buffer; m >= 2 carves buffer b only when
+ * b mod m == 0 and gives every other buffer the removal of buffer
+ * b - (b mod m) (seam memorisation, see the readings above).
+ * log (nullable): per iteration of every carved buffer, in order, four int32:
  * (buffer, W_r, P_eff, k_iter); log_cap is its capacity in records and the
  * return value is the number of records (or a negative error). */
 int64_t oracle_retarget(const uint8_t *frames, int N, int H, int W, int C, int Wt, int k, int mode,
-                        int use_buffer, int32_t anum, int32_t aden, int max_buffer, uint8_t *out,
-                        uint16_t *masks, int32_t *buffer_id, int32_t *log, int64_t log_cap)
+                        int use_buffer, int32_t anum, int32_t aden, int max_buffer, int memo_period,
+                        uint8_t *out, uint16_t *masks, int32_t *buffer_id, int32_t *log, int64_t log_cap)
 {
-    if (N < 1 || H < 1 || W < 1 || (C != 1 && C != 3) || Wt < 1 || Wt > W || k < 1) return -1;
+    if (N < 1 || H < 1 || W < 1 || (C != 1 && C != 3) || Wt < 1 || Wt > W || k < 1 || memo_period < 0)
+        return -1;
     int64_t npx = (int64_t)H * W;
     uint8_t *Y = (uint8_t *)malloc((size_t)(N * npx));
     if (C == 3)
@@ -353,9 +362,30 @@ int64_t oracle_retarget(const uint8_t *frames, int N, int H, int W, int C, int W
 
     int64_t nlog = 0;
     int t0 = 0;
+    /* mask of the last carved buffer, for memorised buffers */
+    uint16_t *memo_mask = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)npx);
     for (int b = 0; b < nbuf; ++b) {
         int T = 0;
         while (t0 + T < N && bid[t0 + T] == b) ++T;
+        if (memo_period >= 2 && b % memo_period != 0) {
+            for (int f = t0; f < t0 + T; ++f) {
+                for (int i = 0; i < H; ++i) {
+                    const uint8_t *src = frames + ((int64_t)f * H + i) * W * C;
+                    uint8_t *dst = out + ((int64_t)f * H + i) * Wt * C;
+                    int o = 0;
+                    for (int j = 0; j < W; ++j) {
+                        if (memo_mask[(int64_t)i * W + j] != 0) continue;
+                        if (o >= Wt) return -3;
+                        for (int c = 0; c < C; ++c) dst[o * C + c] = src[j * C + c];
+                        ++o;
+                    }
+                    if (o != Wt) return -3;
+                }
+                if (masks) memcpy(masks + (int64_t)f * npx, memo_mask, sizeof(uint16_t) * (size_t)npx);
+            }
+            t0 += T;
+            continue;
+        }
         int ghost = (mode == ORACLE_ENERGY_MOTION && t0 > 0);
         int nwork = T + ghost; /* working luma frames: [ghost], t0 .. t0+T-1 */
         uint8_t *wy = (uint8_t *)malloc((size_t)(nwork * npx));
@@ -425,11 +455,13 @@ int64_t oracle_retarget(const uint8_t *frames, int N, int H, int W, int C, int W
             memcpy(out + (int64_t)(t0 + f) * H * Wt * C, wc + (int64_t)f * H * Wt * C, (size_t)((int64_t)H * Wt * C));
             if (masks) memcpy(masks + (int64_t)(t0 + f) * npx, bmask, sizeof(uint16_t) * (size_t)npx);
         }
+        memcpy(memo_mask, bmask, sizeof(uint16_t) * (size_t)npx);
         free(wy); free(wc); free(colmap); free(u); free(acc); free(e); free(ce); free(lab); free(dir);
         free(children); free(seams); free(mark); free(bmask);
         t0 += T;
     }
     free(Y);
     free(bid);
+    free(memo_mask);
     return nlog;
 }

@@ -26,8 +26,8 @@ int oracle_reject(int64_t S, int n, int64_t npx, int32_t emax, int32_t anum, int
 int oracle_segment(const uint8_t *Y, int N, int H, int W, int mode, int use_buffer, int32_t anum,
                    int32_t aden, int max_buffer, int32_t *buffer_id, int64_t *s_trace);
 int64_t oracle_retarget(const uint8_t *frames, int N, int H, int W, int C, int Wt, int k, int mode,
-                        int use_buffer, int32_t anum, int32_t aden, int max_buffer, uint8_t *out,
-                        uint16_t *masks, int32_t *buffer_id, int32_t *log, int64_t log_cap);
+                        int use_buffer, int32_t anum, int32_t aden, int max_buffer, int memo_period,
+                        uint8_t *out, uint16_t *masks, int32_t *buffer_id, int32_t *log, int64_t log_cap);
 
 #ifdef __cplusplus
 }

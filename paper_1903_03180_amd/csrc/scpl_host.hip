@@ -89,6 +89,7 @@ scpl_status validate(const scpl_params *p)
     if (p->alpha_den < 1 || p->alpha_den > SCPL_MAX_ALPHA_TERM) return SCPL_ERR_INVALID_ARG;
     if (p->max_buffer < 0) return SCPL_ERR_INVALID_ARG;
     if (p->target_height < 0 || p->target_height > p->height) return SCPL_ERR_INVALID_ARG;
+    if (p->memo_period < 0 || p->memo_period > SCPL_MAX_FRAMES) return SCPL_ERR_INVALID_ARG;
     return SCPL_OK;
 }
 
@@ -953,11 +954,27 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         int clip, t0, T, bindex;
     };
     std::vector<Pending> pend;
+    // seam memorisation: buffers that are not carved but reuse the seams of
+    // the last carved buffer of their clip (the pending job `src`)
+    struct Memo {
+        int src, t0, T, bindex;
+    };
+    std::vector<Memo> memo;
     for (int c = 0; c < nc; ++c) {
         const auto bufs = buffers_of(seg[c].bid, clips[c].p.n_frames);
-        for (size_t b = 0; b < bufs.size(); ++b) pend.push_back({c, bufs[b].first, bufs[b].second, (int)b});
+        const size_t m = (size_t)clips[c].p.memo_period;
+        int src = -1;
+        for (size_t b = 0; b < bufs.size(); ++b) {
+            if (m >= 2 && b % m != 0) {
+                memo.push_back({src, bufs[b].first, bufs[b].second, (int)b});
+                continue;
+            }
+            src = (int)pend.size();
+            pend.push_back({c, bufs[b].first, bufs[b].second, (int)b});
+        }
     }
     const int nj = (int)pend.size();
+    const int nm = (int)memo.size();
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
     // a batched DP launch serves every job: its geometry follows the widest
@@ -974,10 +991,10 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         const size_t jb = job_bytes(shape_of(q));
         job_area = batched ? job_area + jb : std::max(job_area, jb);
     }
-    SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)nj) + align_up(16 * (size_t)nj)));
+    SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)(nj + nm)) + align_up(16 * (size_t)nj)));
     Bump jdev{static_cast<char *>(ctx->jws)};
     char *job_ws = jdev.take<char>(job_area);
-    Job *d_jobs = jdev.take<Job>((size_t)nj);
+    Job *d_jobs = jdev.take<Job>((size_t)(nj + nm));  // carving jobs, then memorised buffers
     int32_t *d_states = jdev.take<int32_t>(4 * (size_t)nj);
     // batched: the jobs are dealt to the groups in order of decreasing
     // length, so that every group gets a share of the heavy buffers; a
@@ -1006,7 +1023,30 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         h_jobs[slot[q]] = J;
         jobs.push_back(J);
     }
-    SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)nj, hipMemcpyHostToDevice, s));
+    // a memorised buffer is gathered like its source job (same column map
+    // and mask, which hold that job's result once it is done) over its own
+    // frames
+    for (int q = 0; q < nm; ++q) {
+        Job J = h_jobs[slot[memo[q].src]];
+        J.t0 = memo[q].t0;
+        J.T = memo[q].T;
+        J.has_prev = 0;
+        J.buffer_index = memo[q].bindex;
+        h_jobs[nj + q] = J;
+    }
+    SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)(nj + nm), hipMemcpyHostToDevice, s));
+    // gathers the memorised buffers [lo, hi) on stream s, after their sources
+    auto gather_memo = [&](int lo, int hi) -> scpl_status {
+        if (lo >= hi) return SCPL_OK;
+        LaunchShape ls;
+        for (int q = lo; q < hi; ++q) ls.add(shape_of(pend[memo[q].src]), clips[pend[memo[q].src].clip].p.channels);
+        {
+            ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
+            launch_gather(d_jobs + nj + lo, hi - lo, ls.Hmax, ls.gather_lds, s);
+        }
+        SCPL_CHECK_LAUNCH();
+        return SCPL_OK;
+    };
     SCPL_TRY(ensure_groups(ctx, ng));
     ctx->last_log.clear();
     auto make_group = [&](int first, int n, hipStream_t st, hipEvent_t ev) {
@@ -1031,12 +1071,22 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
             gs.push_back(make_group(gfirst[g], gsize[g], ng > 1 ? ctx->gstreams[g] : s, ctx->gevents[g]));
         st = run_groups(ctx, gs, use_graph, s);
         if (st != SCPL_OK) return st;
+        st = gather_memo(0, nm);
+        if (st != SCPL_OK) return st;
         return collect_logs(ctx, jobs, s);
     }
+    // plain: the next buffer reuses the job area, so a source's memorised
+    // buffers are gathered right after it (they follow it in `memo`)
+    int mq = 0;
     for (int q = 0; q < nj; ++q) {
         std::vector<Group> gs(1, make_group(slot[q], 1, s, ctx->gevents[0]));
         st = run_groups(ctx, gs, false, s);
         if (st != SCPL_OK) return st;
+        int mend = mq;
+        while (mend < nm && memo[mend].src == q) ++mend;
+        st = gather_memo(mq, mend);
+        if (st != SCPL_OK) return st;
+        mq = mend;
         std::vector<Job> single(1, jobs[q]);
         st = collect_logs(ctx, single, s);
         if (st != SCPL_OK) return st;

@@ -56,7 +56,7 @@ KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update"
 class scpl_params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "n_frames", "height", "width", "channels", "target_width", "seams_per_iter", "energy_mode",
-        "use_buffer", "alpha_num", "alpha_den", "max_buffer", "target_height")]
+        "use_buffer", "alpha_num", "alpha_den", "max_buffer", "target_height", "memo_period")]
 
 
 class scpl_clip(C.Structure):
@@ -134,11 +134,12 @@ class Params:
     alpha_den: int = 5
     max_buffer: int = 0
     target_height: int = 0
+    memo_period: int = 0
 
     def c(self) -> scpl_params:
         return scpl_params(self.n_frames, self.height, self.width, self.channels, self.target_width,
                            self.seams_per_iter, self.energy_mode, self.use_buffer, self.alpha_num,
-                           self.alpha_den, self.max_buffer, self.target_height)
+                           self.alpha_den, self.max_buffer, self.target_height, self.memo_period)
 
 
 def _ptr(t) -> int | None:
@@ -217,7 +218,7 @@ class Context:
         for i, c in enumerate(clips):
             fr = c["frames"]
             kw = {k: c[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer",
-                                    "target_height") if k in c}
+                                    "target_height", "memo_period") if k in c}
             p = params_for(fr, c["target_width"], c["seams_per_iter"], **kw)
             shp = (p.n_frames, p.target_height or p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
             if c.get("out") is None:
@@ -392,7 +393,7 @@ class Server:
         import torch
         fr = clip["frames"]
         kw = {k: clip[k] for k in ("energy_mode", "use_buffer", "alpha_num", "alpha_den", "max_buffer",
-                                   "target_height") if k in clip}
+                                   "target_height", "memo_period") if k in clip}
         p = params_for(fr, clip["target_width"], clip["seams_per_iter"], **kw)
         shp = (p.n_frames, p.target_height or p.height, p.target_width) + ((p.channels,) if fr.dim() == 4 else ())
         if clip.get("out") is None:

@@ -54,7 +54,7 @@ def wsize(lib, p):
     dict(height=32768), dict(height=30000, width=30000), dict(channels=2), dict(target_width=0),
     dict(target_width=1921), dict(seams_per_iter=0), dict(energy_mode=2), dict(use_buffer=2),
     dict(alpha_num=-1), dict(alpha_den=0), dict(alpha_num=1025), dict(alpha_den=1025), dict(max_buffer=-1),
-    dict(target_height=-1), dict(target_height=1081),
+    dict(target_height=-1), dict(target_height=1081), dict(memo_period=-1), dict(memo_period=16385),
 ])
 def test_invalid_params_rejected(lib, kw):
     st, _ = wsize(lib, base(**kw))
