@@ -825,6 +825,38 @@ __host__ __device__ constexpr bool dp_band_row(int s, int HB, int PF)
     return PF % HB == 0 ? s % HB == 0 : (HB % PF == 0 ? s == 0 : true);
 }
 
+// Rows [i1, i_end) in groups of PF rows, from two register sets of key rows
+// used in turn.  The first group runs before the loop, so that every entry
+// into the loop has the same memory operations in flight (one group of key
+// loads, then one group of code stores).  With the first group inside the
+// loop, its entry from above has no stores in flight, and the compiler's
+// wait for each key row, which must hold on both entries, then also waits
+// on the back edge for a code store of the previous group (gfx9's vmcnt
+// counts stores too).
+template <int PF, class KR, class Fetch, class Group>
+__device__ __forceinline__ void dp_rows(KR (&ka)[PF], KR (&kb)[PF], int i1, int i_end, Fetch &&fetch, Group &&group)
+{
+    fetch(ka, i1);
+    fetch(kb, i1 + PF);
+    if (i1 + PF > i_end) {
+        group(ka, i1, true);
+        return;
+    }
+    group(ka, i1, false);
+    int i0 = i1 + PF;
+    for (; i0 + 2 * PF <= i_end; i0 += 2 * PF) {
+        fetch(ka, i0 + PF);
+        group(kb, i0, false);
+        fetch(kb, i0 + 2 * PF);
+        group(ka, i0 + PF, false);
+    }
+    if (i0 < i_end) {
+        fetch(ka, i0 + PF);
+        group(kb, i0, true);
+        if (i0 + PF < i_end) group(ka, i0 + PF, true);
+    }
+}
+
 template <int Q, int HB, int PF>
 __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Job *jobs)
 {
@@ -846,7 +878,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     // waves past the job's columns read the all-ones row, at stride 0
     const uint16_t *K = J.K;
     const char *kbase = reinterpret_cast<const char *>(live ? K : K + (size_t)H * Kp);
-    const size_t kpitch = live ? (size_t)Kp * 2 : 0;
+    const uint32_t kpitch = live ? (uint32_t)Kp * 2u : 0u;  // key rows span < 4 GiB
     const uint32_t koff = live ? (uint32_t)(J.KL + jl) * 2u : 0u;
     // every lane stores its codes each row: lanes whose codes are not kept
     // (halo, past the width) write to the job's scratch row instead, so
@@ -875,7 +907,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
 
     auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (size_t)min(i0 + s, H - 1) * kpitch, koff);
+        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (uint32_t)min(i0 + s, H - 1) * kpitch, koff);
     };
     auto step = [&](const KRow<Q> &kr) {
         lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
@@ -917,19 +949,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     };
 
     KRow<Q> ka[PF], kb[PF];
-    fetch(ka, 1);
-    int i0 = 1;
-    for (; i0 + 2 * PF <= H; i0 += 2 * PF) {
-        fetch(kb, i0 + PF);
-        group(ka, i0, false);
-        fetch(ka, i0 + 2 * PF);
-        group(kb, i0 + PF, false);
-    }
-    if (i0 < H) {
-        fetch(kb, i0 + PF);
-        group(ka, i0, true);
-        if (i0 + PF < H) group(kb, i0 + PF, true);
-    }
+    dp_rows<PF>(ka, kb, 1, H, fetch, group);
     if (owner) {
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
@@ -981,7 +1001,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     const int ci = r0 / R;  // chunk index
     const int i_end = min(r0 + R, H);
     const char *kbase = reinterpret_cast<const char *>(J.K);
-    const size_t kpitch = (size_t)Kp * 2;
+    const uint32_t kpitch = (uint32_t)Kp * 2u;
     const uint32_t koff = (uint32_t)(J.KL + jl) * 2u;
     uint8_t *__restrict__ dir = J.dir;
     uint32_t coff = stores ? (uint32_t)jl : (uint32_t)(H * Wp + lane * Q);
@@ -1016,7 +1036,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
 
     auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (size_t)min(i0 + s, H - 1) * kpitch, koff);
+        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (uint32_t)min(i0 + s, H - 1) * kpitch, koff);
     };
     auto step = [&](const KRow<Q> &kr) {
         lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
@@ -1054,19 +1074,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     };
 
     KRow<Q> ka[PF], kb[PF];
-    fetch(ka, i1);
-    int i0 = i1;
-    for (; i0 + 2 * PF <= i_end; i0 += 2 * PF) {
-        fetch(kb, i0 + PF);
-        group(ka, i0, false);
-        fetch(ka, i0 + 2 * PF);
-        group(kb, i0 + PF, false);
-    }
-    if (i0 < i_end) {
-        fetch(kb, i0 + PF);
-        group(ka, i0, true);
-        if (i0 + PF < i_end) group(kb, i0 + PF, true);
-    }
+    dp_rows<PF>(ka, kb, i1, i_end, fetch, group);
     // the chunk's last row: the next chunk's start, or the last row's CE
     const bool last = i_end == H;
     uint32_t *bko = J.bk + (size_t)(ci & 1) * Wp;
