@@ -643,6 +643,17 @@ __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
 
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
+// A pointer that is the same in every lane, moved into scalar registers
+// (buffer resources built from it then need no per-lane loop).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
 // Q consecutive 16-bit keys of one row, as loaded (two per word).
 template <int Q>
 struct KRow {
@@ -669,6 +680,31 @@ __device__ __forceinline__ void load_krow(KRow<Q> &dst, const uint16_t *p)
 #pragma unroll
         for (int q = 0; q < Q / 8; ++q) {
             const u32x4 v = gp(reinterpret_cast<const u32x4 *>(p))[q];
+            dst.w[4 * q] = v.x;
+            dst.w[4 * q + 1] = v.y;
+            dst.w[4 * q + 2] = v.z;
+            dst.w[4 * q + 3] = v.w;
+        }
+    }
+}
+
+// The same through a buffer resource: byte offset voff (per lane) plus soff
+// (wave-uniform, a scalar operand of the load, so a row step needs no
+// 64-bit address arithmetic).
+template <int Q>
+__device__ __forceinline__ void load_krow_buf(KRow<Q> &dst, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    static_assert(Q == 2 || Q == 4 || Q % 8 == 0, "whole 32-, 64- or 128-bit loads");
+    if constexpr (Q == 2) {
+        dst.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    } else if constexpr (Q == 4) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+        dst.w[0] = v.x;
+        dst.w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q / 8; ++q) {
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(voff + 16u * q), (int)soff, 0);
             dst.w[4 * q] = v.x;
             dst.w[4 * q + 1] = v.y;
             dst.w[4 * q + 2] = v.z;
@@ -880,6 +916,9 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     const char *kbase = reinterpret_cast<const char *>(live ? K : K + (size_t)H * Kp);
     const uint32_t kpitch = live ? (uint32_t)Kp * 2u : 0u;  // key rows span < 4 GiB
     const uint32_t koff = live ? (uint32_t)(J.KL + jl) * 2u : 0u;
+    const uint32_t rlast = (uint32_t)(H - 1) * kpitch;
+    const __amdgpu_buffer_rsrc_t krs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(kbase), (short)0, 0x7fffffff, 0x00020000);
     // every lane stores its codes each row: lanes whose codes are not kept
     // (halo, past the width) write to the job's scratch row instead, so
     // the row loop has no branch around the store
@@ -906,8 +945,9 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
     int buf = 0;
 
     auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
+        uint32_t ro = (uint32_t)i0 * kpitch;
 #pragma unroll
-        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (uint32_t)min(i0 + s, H - 1) * kpitch, koff);
+        for (int s = 0; s < PF; ++s, ro += kpitch) load_krow_buf<Q>(kr[s], krs, koff, min(ro, rlast));
     };
     auto step = [&](const KRow<Q> &kr) {
         lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
@@ -1003,6 +1043,9 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     const char *kbase = reinterpret_cast<const char *>(J.K);
     const uint32_t kpitch = (uint32_t)Kp * 2u;
     const uint32_t koff = (uint32_t)(J.KL + jl) * 2u;
+    const uint32_t rlast = (uint32_t)(H - 1) * kpitch;
+    const __amdgpu_buffer_rsrc_t krs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(kbase), (short)0, 0x7fffffff, 0x00020000);
     uint8_t *__restrict__ dir = J.dir;
     uint32_t coff = stores ? (uint32_t)jl : (uint32_t)(H * Wp + lane * Q);
     const uint32_t cstep = stores ? (uint32_t)Wp : 0u;
@@ -1035,8 +1078,9 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     int buf = 0;
 
     auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
+        uint32_t ro = (uint32_t)i0 * kpitch;
 #pragma unroll
-        for (int s = 0; s < PF; ++s) load_krow_at<Q>(kr[s], kbase + (uint32_t)min(i0 + s, H - 1) * kpitch, koff);
+        for (int s = 0; s < PF; ++s, ro += kpitch) load_krow_buf<Q>(kr[s], krs, koff, min(ro, rlast));
     };
     auto step = [&](const KRow<Q> &kr) {
         lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
@@ -1101,17 +1145,6 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
 constexpr int kBorgCols = 256;
 
 __device__ __forceinline__ int code_step(uint8_t c) { return (int)(c & 3u) - 1; }
-
-// A pointer that is the same in every lane, moved into scalar registers
-// (buffer resources built from it then need no per-lane loop).
-template <typename T>
-__device__ __forceinline__ T *uniform_ptr(T *p)
-{
-    const uint64_t v = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
-}
 
 // Copies rows [r0, r0 + nrows) x columns [c0, c1) of a byte matrix with a
 // pitch that is a multiple of 4 into LDS (pitch lp bytes, column c0 & ~3 at
@@ -1959,9 +1992,10 @@ const int kNumDpVariants = (int)(sizeof(kDpVariants) / sizeof(kDpVariants[0]));
 
 // Chunked variants (column-split DP, one launch per R rows).
 const DpGeom kDpChunked[] = {
-    {4, 16, 1, 8, 0, 256, 384}, {4, 16, 1, 8, 0, 384, 256},  {4, 16, 1, 8, 0, 320, 384}, {4, 16, 1, 8, 0, 192, 512},
-    {4, 16, 1, 8, 0, 128, 640}, {4, 16, 1, 8, 0, 512, 768},  {2, 8, 1, 16, 0, 128, 640}, {2, 8, 1, 16, 0, 64, 768},
-    {4, 8, 1, 8, 0, 128, 704}};
+    {4, 16, 1, 8, 0, 256, 384},  {4, 16, 1, 8, 0, 384, 256},  {4, 16, 1, 8, 0, 320, 384}, {4, 16, 1, 8, 0, 192, 512},
+    {4, 16, 1, 8, 0, 128, 640},  {4, 16, 1, 8, 0, 512, 768},  {4, 16, 1, 8, 0, 128, 768}, {4, 16, 1, 8, 0, 128, 1024},
+    {4, 16, 1, 8, 0, 192, 896},  {4, 16, 1, 8, 0, 256, 768},  {4, 16, 1, 8, 0, 256, 1024}, {4, 16, 1, 8, 0, 320, 640},
+    {2, 8, 1, 16, 0, 128, 640},  {2, 8, 1, 16, 0, 64, 768},   {4, 8, 1, 8, 0, 128, 704}};
 const int kNumDpChunked = (int)(sizeof(kDpChunked) / sizeof(kDpChunked[0]));
 
 bool dp_geom_fits(const DpGeom &g, int Wmax)
