@@ -254,7 +254,8 @@ def measured_dp_traffic(workload, g):
     with open(path) as f:
         rec = json.load(f)
     same = dp_source_digest() == rec.get("dp_source_sha256")
-    if not same or rec["kernel"] != dp_kernel_name(g) or rec.get("chunk_rows", 0) != g["chunk_rows"]:
+    if not same or rec["kernel"] != dp_kernel_name(g) or rec.get("chunk_rows", 0) != g["chunk_rows"] \
+            or rec.get("chunk_cols", 0) != g["chunk_cols"]:
         return None
     # a DP of a chunked geometry is one dispatch per chunk of rows
     return (rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) * rec.get("dispatches_per_dp", 1)
@@ -285,6 +286,9 @@ def main() -> int:
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--dp-geometry", default="", metavar="Q,HB,PF,EX,R,P",
+                    help="use this DP geometry instead of autotuning (e.g. under a profiler, whose per-dispatch "
+                         "overhead distorts the autotuner's timings)")
     ap.add_argument("--memo-periods", default="2,4",
                     help="seam-memorisation periods to time on the same workload (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -318,9 +322,16 @@ def main() -> int:
                                           device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
-    dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
-    dpg = ctx.dp_chosen(Wmax)
-    log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
+    if args.dp_geometry:
+        q, hb, pf, ex, r, p = (int(x) for x in args.dp_geometry.split(","))
+        ctx.dp_geometry(q, hb, pf, ex)
+        ctx.dp_chunking(r, p)
+        dpg = ctx.dp_chosen(Wmax)
+        log(f"DP geometry forced: {dpg}")
+    else:
+        dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
+        dpg = ctx.dp_chosen(Wmax)
+        log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
 
     def step_batched():
         ctx.retarget_batch(clips)
