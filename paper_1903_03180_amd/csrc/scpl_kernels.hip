@@ -1044,8 +1044,10 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     const uint32_t kpitch = (uint32_t)Kp * 2u;
     const uint32_t koff = (uint32_t)(J.KL + jl) * 2u;
     const uint32_t rlast = (uint32_t)(H - 1) * kpitch;
+    // the resource spans the key rows and the all-ones row after them
+    const uint32_t nrec = (uint32_t)(H + 1) * kpitch;
     const __amdgpu_buffer_rsrc_t krs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(kbase), (short)0, 0x7fffffff, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(kbase), (short)0, (int)nrec, 0x00020000);
     uint8_t *__restrict__ dir = J.dir;
     uint32_t coff = stores ? (uint32_t)jl : (uint32_t)(H * Wp + lane * Q);
     const uint32_t cstep = stores ? (uint32_t)Wp : 0u;
@@ -1077,10 +1079,19 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     int band_left = HB;
     int buf = 0;
 
+    // Only the columns within T - t of the owned ones at step t of T can still
+    // reach them, so a lane's key row is needed up to row i_end - 1 plus its
+    // distance to [A, B) (negative outside).  Beyond that the lane reads past
+    // the end of the buffer resource (offset nrec, out of range whether or not
+    // the row offset is counted), which returns zeros and moves no data.
+    const int lastrow = i_end - 1 + min(jl + Q - 1 - A, B - 1 - jl);
     auto fetch = [&](KRow<Q>(&kr)[PF], int i0) {
+        // decided once per group, by its first row: a lane still needed there
+        // reads the whole group
+        const uint32_t vo = i0 <= lastrow ? koff : nrec;
         uint32_t ro = (uint32_t)i0 * kpitch;
 #pragma unroll
-        for (int s = 0; s < PF; ++s, ro += kpitch) load_krow_buf<Q>(kr[s], krs, koff, min(ro, rlast));
+        for (int s = 0; s < PF; ++s, ro += kpitch) load_krow_buf<Q>(kr[s], krs, vo, min(ro, rlast));
     };
     auto step = [&](const KRow<Q> &kr) {
         lnb = (uint32_t)__builtin_amdgcn_update_dpp((int)lnb, (int)key[Q - 1], 0x138, 0xf, 0xf, false);
