@@ -194,6 +194,33 @@ def test_4k_clip_full_size(ctx, orc, alpha):
     check_full_size(orc, frames, res, 2880, 32, 1, alpha[0], alpha[1], n_first=1)
 
 
+@pytest.mark.parametrize("which", ["1080p", "4k"])
+def test_full_size_with_benchmarked_chunked_dp(ctx, orc, which):
+    """The full-size single clips with the column-split DP the autotuner
+    picks for them in the benchmark ((4,16,8), 256 rows x 384 columns per
+    workgroup): bit-identical to a single-workgroup DP (8,16,8), and
+    segmentation plus the first iteration of the first buffer exact against
+    the oracle."""
+    if which == "1080p":
+        frames, Wt, k = synth.clip_1080p(2), 1440, 16
+    else:
+        frames, Wt, k = synth.clip_4k(3), 2880, 32
+    d = dev(frames)
+    try:
+        ctx.dp_geometry(8, 16, 8, 1)
+        ref = ctx.retarget(d, Wt, k)
+        ctx.dp_geometry(4, 16, 8, 1)
+        ctx.dp_chunking(256, 384)
+        res = ctx.retarget(d, Wt, k)
+        torch.cuda.synchronize()
+    finally:
+        ctx.dp_geometry(0)
+    assert torch.equal(res["out"], ref["out"])
+    assert torch.equal(res["masks"], ref["masks"])
+    assert torch.equal(res["buffer_id"], ref["buffer_id"])
+    check_full_size(orc, frames, res, Wt, k, 1, 1, 5, n_first=1)
+
+
 @pytest.mark.parametrize("geom", [(4, 8, 16, 1), (4, 16, 8, 0), (8, 16, 8, 1), (8, 32, 4, 0), (32, 0, 2, 1)])
 def test_forced_geometry_retarget(ctx, orc, geom):
     clip = synth.make_clip(610, 8, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
