@@ -2023,13 +2023,18 @@ bool dp_geom_fits(const DpGeom &g, int Wmax)
 
 DpGeom dp_geom(int Wmax)
 {
-    // defaults: the fewest wavefronts that cover the width with balanced
-    // SIMDs; the autotuner may replace them
+    // defaults (the autotuner may replace them): up to 448 columns, one
+    // workgroup of four wavefronts; wider, the column-split DP (4,16,8) with
+    // 256 rows by 384 columns per workgroup, which is faster than every
+    // single-workgroup variant at any number of concurrent 1080- or 2160-row
+    // buffers; beyond 8960 columns the row-synchronous kernel
     if (Wmax <= 448) return DpGeom{2, 8, 1, 8, 0};
-    if (Wmax <= 1920) return DpGeom{4, 8, 1, 8, 0};
-    if (Wmax <= 3840) return DpGeom{8, 16, 1, 4, 0};
-    if (Wmax <= 7680) return DpGeom{16, 32, 1, 2, 0};
-    if (Wmax <= 8960) return DpGeom{16, 64, 1, 2, 0};
+    if (Wmax <= 8960) {
+        DpGeom g{4, 16, 1, 8, 1};
+        g.R = 256;
+        g.P = 384;
+        return g;
+    }
     return DpGeom{32, 0, 0, 2, 0};
 }
 
