@@ -2007,7 +2007,9 @@ const DpGeom kDpChunked[] = {
     {4, 16, 1, 8, 0, 128, 640},  {4, 16, 1, 8, 0, 512, 768},  {4, 16, 1, 8, 0, 128, 768}, {4, 16, 1, 8, 0, 128, 1024},
     {4, 16, 1, 8, 0, 192, 896},  {4, 16, 1, 8, 0, 256, 768},  {4, 16, 1, 8, 0, 256, 1024}, {4, 16, 1, 8, 0, 320, 640},
     {4, 16, 1, 8, 0, 384, 128},  {4, 16, 1, 8, 0, 352, 192},  {4, 16, 1, 8, 0, 288, 320},
-    {2, 8, 1, 16, 0, 128, 640},  {2, 8, 1, 16, 0, 64, 768},   {4, 8, 1, 8, 0, 128, 704}};
+    {2, 8, 1, 16, 0, 128, 640},  {2, 8, 1, 16, 0, 64, 768},   {4, 8, 1, 8, 0, 128, 704},
+    {2, 8, 1, 16, 0, 192, 64},   {2, 8, 1, 16, 0, 160, 128},  {2, 8, 1, 16, 0, 128, 192},
+    {2, 8, 1, 16, 0, 208, 32},   {2, 8, 1, 16, 0, 216, 16}};
 const int kNumDpChunked = (int)(sizeof(kDpChunked) / sizeof(kDpChunked[0]));
 
 bool dp_geom_fits(const DpGeom &g, int Wmax)

@@ -50,7 +50,9 @@ DP_CHUNKED = [(4, 16, 8, 256, 384), (4, 16, 8, 384, 256), (4, 16, 8, 320, 384), 
               (4, 16, 8, 128, 640), (4, 16, 8, 512, 768), (4, 16, 8, 128, 768), (4, 16, 8, 128, 1024),
               (4, 16, 8, 192, 896), (4, 16, 8, 256, 768), (4, 16, 8, 256, 1024), (4, 16, 8, 320, 640),
               (4, 16, 8, 384, 128), (4, 16, 8, 352, 192), (4, 16, 8, 288, 320),
-              (2, 8, 16, 128, 640), (2, 8, 16, 64, 768), (4, 8, 8, 128, 704)]
+              (2, 8, 16, 128, 640), (2, 8, 16, 64, 768), (4, 8, 8, 128, 704),
+              (2, 8, 16, 192, 64), (2, 8, 16, 160, 128), (2, 8, 16, 128, 192), (2, 8, 16, 208, 32),
+              (2, 8, 16, 216, 16)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
 
