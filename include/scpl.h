@@ -233,6 +233,12 @@ enum {
 };
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);
 scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms, int64_t *h_launches);
+/* Which kernel kinds the timing brackets: bit k set = SCPL_KERNEL_k is
+ * bracketed (default: all).  The others then run without events, which
+ * keeps the instrumentation of a timed run to the kinds it needs.  Takes
+ * effect at the next launch; bits at or above SCPL_KERNEL_COUNT are an
+ * error. */
+scpl_status scpl_profile_kinds(scpl_ctx *ctx, uint32_t mask);
 
 /* ---- DP geometry and its autotuner (performance only: every geometry
  * gives bit-identical results) ----

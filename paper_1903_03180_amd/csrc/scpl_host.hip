@@ -26,6 +26,7 @@ struct scpl_ctx {
     DpGeom forced{0, 0, 0, 0, 0};                       // DP geometry forced by the caller (Q = 0: none)
     std::vector<std::pair<int, DpGeom>> tuned;    // autotuned geometry per widest-job width
     bool profiling = false;
+    uint32_t prof_mask = ~0u;  // kernel kinds bracketed when profiling
     std::vector<ProfPair> prof_pending;  // recorded, not yet read
     std::vector<ProfPair> prof_free;     // reusable event pairs
     double prof_ms[SCPL_KERNEL_COUNT] = {};
@@ -277,7 +278,7 @@ struct ProfScope {
     bool on = false;
     ProfScope(scpl_ctx *c, int k, hipStream_t st) : ctx(c), s(st), kind(k)
     {
-        if (!ctx->profiling) return;
+        if (!ctx->profiling || !((ctx->prof_mask >> kind) & 1u)) return;
         if (!ctx->prof_free.empty()) {
             pp = ctx->prof_free.back();
             ctx->prof_free.pop_back();
@@ -1220,6 +1221,13 @@ scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on)
         ctx->prof_n[k] = 0;
     }
     ctx->profiling = on != 0;
+    return SCPL_OK;
+}
+
+scpl_status scpl_profile_kinds(scpl_ctx *ctx, uint32_t mask)
+{
+    if (!ctx || (mask >> SCPL_KERNEL_COUNT) != 0) return SCPL_ERR_INVALID_ARG;
+    ctx->prof_mask = mask;
     return SCPL_OK;
 }
 

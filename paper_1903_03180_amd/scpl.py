@@ -35,7 +35,7 @@ SCPL_ENERGY_MOTION = 1
 EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
-    "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_dp_geometry",
+    "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_profile_kinds", "scpl_dp_geometry",
     "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_server_create",
     "scpl_server_submit", "scpl_server_poll",
     "scpl_server_wait", "scpl_server_ticket_times", "scpl_server_release", "scpl_server_destroy",
@@ -89,6 +89,7 @@ _sig = {
     "scpl_segment": ([_P, C.POINTER(scpl_params), _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_profile_enable": ([_P, _I32], C.c_int),
     "scpl_profile_read": ([_P, _I32, C.POINTER(C.c_double), C.POINTER(_I64)], C.c_int),
+    "scpl_profile_kinds": ([_P, C.c_uint32], C.c_int),
     "scpl_dp_geometry": ([_P, _I32, _I32, _I32, _I32], C.c_int),
     "scpl_dp_chunking": ([_P, _I32, _I32], C.c_int),
     "scpl_dp_chosen": ([_P, _I32, C.POINTER(_I32)], C.c_int),
@@ -250,8 +251,11 @@ class Context:
         _check(scpl_batch_streams(self.h, n), "scpl_batch_streams")
 
     # ---------------------------------------------------------- timing
-    def profile(self, on: bool = True) -> None:
-        """Start (and reset) or stop per-kernel event timing."""
+    def profile(self, on: bool = True, kinds=None) -> None:
+        """Start (and reset) or stop per-kernel event timing; kinds: the
+        kernel names of KERNELS to bracket (None: all)."""
+        mask = (1 << len(KERNELS)) - 1 if kinds is None else sum(1 << KERNELS.index(k) for k in kinds)
+        _check(scpl_profile_kinds(self.h, mask), "scpl_profile_kinds")
         _check(scpl_profile_enable(self.h, 1 if on else 0), "scpl_profile_enable")
 
     def profile_read(self) -> dict:
