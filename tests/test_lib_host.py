@@ -83,6 +83,8 @@ def test_null_context_and_pointers_rejected(lib):
     assert lib.scpl_create(0, None) == lib.SCPL_ERR_INVALID_ARG
     n = C.c_int64(0)
     assert lib.scpl_last_log(None, None, 0, C.byref(n)) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_profile_kinds(None, 1) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_dp_chunking(None, 256, 384) == lib.SCPL_ERR_INVALID_ARG
 
 
 def test_target_width_rule_for_batch_mix():
