@@ -345,3 +345,22 @@ def test_uneven_mix_batch_equals_plain(ctx):
         solo = ctx.retarget(c["frames"], s.Wt, 16, want_masks=False)
         assert torch.equal(c["out"], solo["out"]), s
         assert torch.equal(c["buffer_id"], solo["buffer_id"]), s
+
+
+def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
+    from paper_1903_03180_amd import scpl
+    clip = dev(synth.make_clip(620, 8, 30, 80, C=3, n_obj=2, lattice=8))
+    try:
+        ctx.profile(True, kinds=["dp"])
+        ctx.retarget_batch([dict(frames=clip, target_width=60, seams_per_iter=4)])
+        prof = ctx.profile_read()
+        assert prof["dp"][1] > 0 and prof["dp"][0] > 0
+        assert all(n == 0 for k, (ms, n) in prof.items() if k != "dp")
+        ctx.profile(True)
+        ctx.retarget_batch([dict(frames=clip, target_width=60, seams_per_iter=4)])
+        prof = ctx.profile_read()
+        assert all(prof[k][1] > 0 for k in ("luma", "segment", "dp", "select", "update", "gather"))
+    finally:
+        ctx.profile(False)
+    with pytest.raises(scpl.ScplError):
+        scpl._check(scpl.scpl_profile_kinds(ctx.h, 1 << len(scpl.KERNELS)), "scpl_profile_kinds")
