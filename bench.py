@@ -329,6 +329,8 @@ def main() -> int:
         dpg = ctx.dp_chosen(Wmax)
         log(f"DP geometry forced: {dpg}")
     else:
+        if args.plain_steps > 0 and len(clips) > 1:  # the plain path runs one buffer at a time
+            ctx.autotune_dp(Hmax, Wmax, n_jobs=1)
         dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
         dpg = ctx.dp_chosen(Wmax)
         log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")

@@ -259,7 +259,10 @@ scpl_status scpl_profile_kinds(scpl_ctx *ctx, uint32_t mask);
  * concurrent H x W synthetic energies per launch (as in a batched launch;
  * null stream, synchronises) and keeps the fastest for launches whose widest
  * job has width W; when the batched path runs more than one job group
- * (scpl_batch_streams) only EX = 1 geometries are timed.  h_Q, h_HB, h_PF,
+ * (scpl_batch_streams) only EX = 1 geometries are timed.  Choices made for
+ * several n_jobs at one width are all kept: a launch takes the one timed with
+ * the nearest number of concurrent jobs (by ratio), counting every job of a
+ * batched call, and one job for the plain path and the stage calls.  h_Q, h_HB, h_PF,
  * h_EX, h_us (nullable) receive the choice and its time per launch in
  * microseconds. */
 scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, int32_t EX);
@@ -271,7 +274,8 @@ scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, i
  * (4,16,8) (2,8,16) (4,8,8) with R and P multiples of Q, R >= HB, and a
  * cover of P + 2R columns that the workgroup's wavefronts can hold.
  * scpl_dp_chosen writes the geometry used for launches whose widest job has
- * width W: h_geom[6] = (Q, HB, PF, EX, R, P).
+ * width W and that run the most concurrent jobs any choice at W was timed
+ * with: h_geom[6] = (Q, HB, PF, EX, R, P).
  * Without a forced or tuned geometry: (2,8,8) for W <= 448; the column-split
  * (4,16,8) with EX = 1, R = 256 and P = 384 up to W = 8960; the
  * row-synchronous kernel beyond. */

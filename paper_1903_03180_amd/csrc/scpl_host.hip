@@ -4,6 +4,7 @@
 // every clip per launch, the iteration loop replayed from a HIP graph), and
 // the stage entry points.  Declarations: include/scpl.h.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -24,7 +25,11 @@ struct ProfPair {
 
 struct scpl_ctx {
     DpGeom forced{0, 0, 0, 0, 0};                       // DP geometry forced by the caller (Q = 0: none)
-    std::vector<std::pair<int, DpGeom>> tuned;    // autotuned geometry per widest-job width
+    struct Tuned {
+        int W, n;  // widest-job width, concurrent jobs the timing launched
+        DpGeom g;
+    };
+    std::vector<Tuned> tuned;  // autotuned geometries
     bool profiling = false;
     uint32_t prof_mask = ~0u;  // kernel kinds bracketed when profiling
     std::vector<ProfPair> prof_pending;  // recorded, not yet read
@@ -256,14 +261,25 @@ scpl_status ensure_groups(scpl_ctx *ctx, int n)
     return SCPL_OK;
 }
 
-// DP geometry of a launch whose widest job is Wmax: forced, autotuned, or
-// the default table.
-DpGeom select_geom(const scpl_ctx *ctx, int Wmax)
+// DP geometry of a launch whose widest job is Wmax, with njobs jobs running
+// concurrently (all job groups together): forced; else of the geometries
+// autotuned for this width, the one timed with the nearest job count (by
+// ratio); else the default table.
+DpGeom select_geom(const scpl_ctx *ctx, int Wmax, int njobs = 1 << 20)
 {
     if (ctx->forced.Q > 0 && dp_geom_fits(ctx->forced, Wmax)) return ctx->forced;
+    const scpl_ctx::Tuned *best = nullptr;
+    double bd = 0.0;
+    const double ln = std::log((double)std::min(std::max(njobs, 1), 1 << 20));
     for (const auto &t : ctx->tuned)
-        if (t.first == Wmax) return t.second;
-    return dp_geom(Wmax);
+        if (t.W == Wmax) {
+            const double d = std::fabs(std::log((double)t.n) - ln);
+            if (!best || d < bd) {
+                best = &t;
+                bd = d;
+            }
+        }
+    return best ? best->g : dp_geom(Wmax);
 }
 
 // ----------------------------------------------------------- kernel timing
@@ -979,10 +995,10 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
     // a batched DP launch serves every job: its geometry follows the widest
-    const DpGeom gall = select_geom(ctx, Wall);
+    const DpGeom gall = select_geom(ctx, Wall, nj);
     auto shape_of = [&](const Pending &q) {
         const scpl_params &p = clips[q.clip].p;
-        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, batched ? gall : select_geom(ctx, p.width)};
+        JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, batched ? gall : select_geom(ctx, p.width, 1)};
         return js;
     };
     // area B: job workspaces (all jobs when batched; one shared per clip shape
@@ -1266,7 +1282,7 @@ scpl_status scpl_luma(scpl_ctx *ctx, const uint8_t *d_rgb, int64_t npx, uint8_t 
 static scpl_status stage_job(scpl_ctx *ctx, int32_t H, int32_t W, int32_t Wt, int32_t k, size_t extra, Job &J,
                              Job *&d_job, int32_t *&d_state, char *&d_extra, hipStream_t s)
 {
-    JobShape js{H, W, Wt, k, select_geom(ctx, W)};
+    JobShape js{H, W, Wt, k, select_geom(ctx, W, 1)};
     const size_t total = job_bytes(js) + align_up(sizeof(Job)) + align_up(16) + align_up(extra);
     SCPL_TRY(ensure_ws(ctx, total));
     SCPL_TRY(ensure_pinned(ctx, align_up(sizeof(Job)) + 64));
@@ -1318,7 +1334,7 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
     *h = J;
     SCPL_TRY(hipMemcpyAsync(d_job, h, sizeof(Job), hipMemcpyHostToDevice, s));
     LaunchShape ls;
-    ls.add(JobShape{H, W, 1, 1, select_geom(ctx, W)});
+    ls.add(JobShape{H, W, 1, 1, select_geom(ctx, W, 1)});
     launch_init_jobs(d_job, 1, ls.Hmax, ls.Wmax, s);
     launch_energy(d_job, 1, H, W, s);
     launch_keys_to_u(J.K + J.KL, d_e, H, W, J.Kp, s);
@@ -1342,7 +1358,7 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     scpl_status st = stage_job(ctx, H, W, 0, 1, 0, J, d_job, d_state, unused, s);
     if (st != SCPL_OK) return st;
     LaunchShape ls;
-    ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W)});
+    ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W, 1)});
     launch_init_jobs(d_job, 1, H, W, s);
     launch_u_to_keys(d_u, J.K + J.KL, H, W, J.Kp, s);
     launch_dp(d_job, 1, ls.g, W, H, s);
@@ -1411,7 +1427,7 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     std::memcpy(h, rec, 16);
     SCPL_TRY(hipMemcpyAsync(J.log, h, 16, hipMemcpyHostToDevice, s));
     LaunchShape ls;
-    ls.add(JobShape{H, W, 0, kk, select_geom(ctx, W)});
+    ls.add(JobShape{H, W, 0, kk, select_geom(ctx, W, 1)});
     launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
     launch_jump_only(d_job, 1, s);
     launch_fill(d_job, 1, kk, ls.nbmax, ls.Bmax, s);
@@ -1542,14 +1558,14 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SCPL_OK) return st;
+    bool found = false;
     for (auto &t : ctx->tuned)
-        if (t.first == W) {
-            t.second = best;
-            best = DpGeom{-1, 0, 0, 0, 0};
-            break;
+        if (t.W == W && t.n == n_jobs) {
+            t.g = best;
+            found = true;
         }
-    if (best.Q != -1) ctx->tuned.emplace_back(W, best);
-    const DpGeom chosen = select_geom(ctx, W);
+    if (!found) ctx->tuned.push_back({W, n_jobs, best});
+    const DpGeom chosen = select_geom(ctx, W, n_jobs);
     if (h_Q) *h_Q = chosen.Q;
     if (h_HB) *h_HB = chosen.HB;
     if (h_PF) *h_PF = chosen.PF;
