@@ -538,7 +538,10 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_SELECT, s);
-        launch_select(d_jobs, nj, 0, ctx->lds_cap, s);
+        // LDS for the widest job's keys and band origins, not the whole CU, so
+        // that the workgroups need not wait for an empty compute unit
+        const size_t need = (size_t)16 * ls.Wmax + (size_t)ls.nbmax * (size_t)((ls.Wmax + 7) & ~3);
+        launch_select(d_jobs, nj, 0, std::min(need, ctx->lds_cap), s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_FILL, s);
