@@ -553,9 +553,9 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_REFRESH, s);
+        // also ends the iteration: moves every job still carving on
         launch_refresh(d_jobs, nj, ls.kmax, ls.Hmax, s);
     }
-    launch_advance(d_jobs, nj, s);
 }
 
 // Iterations per replay of a group's graph.

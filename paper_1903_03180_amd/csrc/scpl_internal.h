@@ -138,8 +138,6 @@ void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s);
 void launch_update(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, hipStream_t s);
-// end of an iteration: each job still carving moves to its next iteration
-void launch_advance(const Job *d_jobs, int njobs, hipStream_t s);
 // LDS of the gather for a job (0: the job gathers directly from global memory)
 size_t gather_lds_bytes(int W, int Wt, int C);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);

@@ -17,7 +17,7 @@
 //   update_kernel      removes the iteration's seams from the column map
 //                      and the DP keys in one pass
 //   refresh_kernel     recomputes the keys of the pixels whose carved 3x3
-//                      neighbourhood changed (exact)
+//                      neighbourhood changed (exact); ends the iteration
 //   gather_kernel      carved output frames and masks
 #include "scpl_internal.h"
 
@@ -34,9 +34,10 @@ __device__ __forceinline__ uint32_t pack2(u16x2 v) { return (uint32_t)v.x | ((ui
 __device__ __forceinline__ int job_width(const Job &J, int r) { return r < J.logcap ? J.log[4 * r] : J.Wt; }
 
 // The job's current iteration: every kernel of an iteration reads it from
-// the job's state, and advance_kernel moves it on after the iteration's last
-// kernel, so that each job advances at its own pace and a fixed sequence of
-// launches (a graph) can be replayed for any number of iterations.
+// the job's state, and the iteration's last kernel (the refresh) moves it on
+// when its last workgroup for the job is done, so that each job advances at
+// its own pace and a fixed sequence of launches (a graph) can be replayed for
+// any number of iterations.
 __device__ __forceinline__ int job_iter(const Job &J) { return J.state[3]; }
 
 // Global-address-space views of pointers held in job descriptors.  Loads
@@ -1600,6 +1601,23 @@ constexpr int kRefreshSeams = 64;  // seams whose positions are staged in LDS
 // NT threads per block: 256 when the launch has blocks enough to fill the
 // device; 1024 when it has few (a pixel's frames then split over more
 // threads, which shortens the block).
+// The end of a job's iteration: the last workgroup of the launch to finish
+// for a job (counted in the iteration's free log word, which the selection
+// of the iteration before, or the job set-up, zeroed) moves the job's
+// iteration counter on.  Every workgroup has read the counter by then, since
+// each reads it first and counts itself last.  The count is a relaxed atomic
+// with no fence: the next kernel sees the keys written here through the
+// kernel boundary, and an agent-scope fence per workgroup would write back
+// the XCD's whole L2 each time.
+__device__ __forceinline__ void end_iteration(const Job &J, int r)
+{
+    __syncthreads();
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(&J.log[4 * r + 3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            (int)gridDim.x - 1)
+        J.state[3] = r + 1;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
 {
@@ -1611,119 +1629,111 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
     const Job &J = jobs[blockIdx.y];
     const int r = job_iter(J);
     const int Wr = job_width(J, r);
-    if (Wr <= J.Wt) return;
+    if (Wr <= J.Wt) return;  // finished before this iteration: no iteration to end
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
-    if (Wn <= J.Wt) return;
     const int H = J.H, Wp = J.Wp, W = J.W, T = J.T;
     const int Kp = J.Kp;
     const int i0 = blockIdx.x * kRefreshRows;
-    if (i0 >= H) return;
-    const int nrows = min(kRefreshRows, H - i0);
-    const int16_t *__restrict__ Mn = J.M;
-    uint16_t *__restrict__ Kn = J.K + J.KL;
-    const int tid = threadIdx.x;
-    const bool rl = kk <= kRefreshSeams;
-    if (tid == 0) nf = 0;
-    if (rl)
-        for (int idx = tid; idx < (nrows + 2) * kk; idx += NT) {
-            const int ss = idx / (nrows + 2), rr = idx - ss * (nrows + 2);  // consecutive threads: same seam
-            const int row = min(max(i0 - 1 + rr, 0), H - 1);
-            R[rr][ss] = J.seams[(size_t)row * J.kcap + ss] - ss;
-        }
-    __syncthreads();
-    // seam positions (old column - rank) of row `row` (absolute, clamped)
-    auto rsd = [&](int row, int ss) -> int {
-        row = min(max(row, 0), H - 1);
-        return rl ? R[row - (i0 - 1)][ss] : (int)J.seams[(size_t)row * J.kcap + ss] - ss;
-    };
-    // old column of new column c in row `row`
-    auto oldcol = [&](int row, int c) -> int {
-        int a = 0, b = kk;
-        while (a < b) {
-            const int m = (a + b) >> 1;
-            if (rsd(row, m) <= c) a = m + 1;
-            else b = m;
-        }
-        return c + a;
-    };
-    auto full_sum = [&](const Stencil &st) { return seq_sum(J, st, 0, 1); };
-    // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
-    const int ncand = kk * nrows * 9;
-    for (int u = tid; u < ncand; u += NT) {
-        const int s = u / (nrows * 9);
-        const int rem = u - s * (nrows * 9);
-        const int rb = rem / 9, slot = rem - rb * 9;
-        const int i = i0 + rb;
-        const int a0 = rsd(i - 1, s), a1 = rsd(i, s), a2 = rsd(i + 1, s);
-        const int lo = max(min(min(a0, a1), a2) - 3, 0);
-        const int hi = min(max(max(a0, a1), a2) + 3, Wn - 1);
-        const int c = lo + slot;
-        if (c > hi) continue;
-        if (s > 0 && c <= max(max(rsd(i - 1, s - 1), rsd(i, s - 1)), rsd(i + 1, s - 1)) + 3) continue;
-        const int src = oldcol(i, c);
-        bool same = true;
-#pragma unroll
-        for (int dq = -1; dq <= 1; ++dq)
-#pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-                if (dq == 0 && dj == 0) continue;
-                const int cn = min(max(c + dj, 0), Wn - 1);
-                const int co = min(max(src + dj, 0), Wr - 1);
-                same = same && oldcol(i + dq, cn) == co;
+    // the job's last iteration needs no refresh, nor do rows past its height,
+    // but every workgroup of the job counts itself done below
+    if (Wn > J.Wt && i0 < H) {
+        const int nrows = min(kRefreshRows, H - i0);
+        const int16_t *__restrict__ Mn = J.M;
+        uint16_t *__restrict__ Kn = J.K + J.KL;
+        const int tid = threadIdx.x;
+        const bool rl = kk <= kRefreshSeams;
+        if (tid == 0) nf = 0;
+        if (rl)
+            for (int idx = tid; idx < (nrows + 2) * kk; idx += NT) {
+                const int ss = idx / (nrows + 2), rr = idx - ss * (nrows + 2);  // consecutive threads: same seam
+                const int row = min(max(i0 - 1 + rr, 0), H - 1);
+                R[rr][ss] = J.seams[(size_t)row * J.kcap + ss] - ss;
             }
-        if (!same) {
-            const int idx = atomicAdd(&nf, 1);
-            if (idx < kRefreshList) {
-                flist[idx] = (rb << 16) | c;
-            } else {  // list full: this thread does the pixel alone
-                const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
-                const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
-                                                     Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W);
-                Kn[(size_t)i * Kp + c] = (uint16_t)((full_sum(st) / (uint32_t)T) << 2);
+        __syncthreads();
+        // seam positions (old column - rank) of row `row` (absolute, clamped)
+        auto rsd = [&](int row, int ss) -> int {
+            row = min(max(row, 0), H - 1);
+            return rl ? R[row - (i0 - 1)][ss] : (int)J.seams[(size_t)row * J.kcap + ss] - ss;
+        };
+        // old column of new column c in row `row`
+        auto oldcol = [&](int row, int c) -> int {
+            int a = 0, b = kk;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (rsd(row, m) <= c) a = m + 1;
+                else b = m;
             }
-        }
-    }
-    __syncthreads();
-    const int n = min(nf, kRefreshList);
-    for (int p = tid; p < n; p += NT) {
-        const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
-        const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
-        fst[p] = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp, Mn + (size_t)ip * Wp, im, i, ip, c,
-                                   Wn, W);
-        fsum[p] = 0;
-    }
-    __syncthreads();
-    if (n > 0) {
-        // a wavefront takes 64 listed pixels and every tpp-th chunk of 16
-        // frames
-        const int ng = (n + 63) >> 6, nw = NT >> 6;
-        const int tpp = max(nw / ng, 1);
-        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-        for (int task = w; task < ng * tpp; task += nw) {
-            const int p = (task % ng) * 64 + (tid & 63), sub = task / ng;
-            if (p < n) {
-                const Stencil st = fst[p];
-                atomicAdd(&fsum[p], seq_sum(J, st, sub, tpp));
+            return c + a;
+        };
+        auto full_sum = [&](const Stencil &st) { return seq_sum(J, st, 0, 1); };
+        // candidates: (seam, row in band, slot) triples; windows are at most 9 wide
+        const int ncand = kk * nrows * 9;
+        for (int u = tid; u < ncand; u += NT) {
+            const int s = u / (nrows * 9);
+            const int rem = u - s * (nrows * 9);
+            const int rb = rem / 9, slot = rem - rb * 9;
+            const int i = i0 + rb;
+            const int a0 = rsd(i - 1, s), a1 = rsd(i, s), a2 = rsd(i + 1, s);
+            const int lo = max(min(min(a0, a1), a2) - 3, 0);
+            const int hi = min(max(max(a0, a1), a2) + 3, Wn - 1);
+            const int c = lo + slot;
+            if (c > hi) continue;
+            if (s > 0 && c <= max(max(rsd(i - 1, s - 1), rsd(i, s - 1)), rsd(i + 1, s - 1)) + 3) continue;
+            const int src = oldcol(i, c);
+            bool same = true;
+    #pragma unroll
+            for (int dq = -1; dq <= 1; ++dq)
+    #pragma unroll
+                for (int dj = -1; dj <= 1; ++dj) {
+                    if (dq == 0 && dj == 0) continue;
+                    const int cn = min(max(c + dj, 0), Wn - 1);
+                    const int co = min(max(src + dj, 0), Wr - 1);
+                    same = same && oldcol(i + dq, cn) == co;
+                }
+            if (!same) {
+                const int idx = atomicAdd(&nf, 1);
+                if (idx < kRefreshList) {
+                    flist[idx] = (rb << 16) | c;
+                } else {  // list full: this thread does the pixel alone
+                    const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
+                    const Stencil st = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp,
+                                                         Mn + (size_t)ip * Wp, im, i, ip, c, Wn, W);
+                    Kn[(size_t)i * Kp + c] = (uint16_t)((full_sum(st) / (uint32_t)T) << 2);
+                }
             }
         }
+        __syncthreads();
+        const int n = min(nf, kRefreshList);
+        for (int p = tid; p < n; p += NT) {
+            const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
+            const int im = max(i - 1, 0), ip = min(i + 1, H - 1);
+            fst[p] = stencil_from_rows(Mn + (size_t)im * Wp, Mn + (size_t)i * Wp, Mn + (size_t)ip * Wp, im, i, ip, c,
+                                       Wn, W);
+            fsum[p] = 0;
+        }
+        __syncthreads();
+        if (n > 0) {
+            // a wavefront takes 64 listed pixels and every tpp-th chunk of 16
+            // frames
+            const int ng = (n + 63) >> 6, nw = NT >> 6;
+            const int tpp = max(nw / ng, 1);
+            const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+            for (int task = w; task < ng * tpp; task += nw) {
+                const int p = (task % ng) * 64 + (tid & 63), sub = task / ng;
+                if (p < n) {
+                    const Stencil st = fst[p];
+                    atomicAdd(&fsum[p], seq_sum(J, st, sub, tpp));
+                }
+            }
+        }
+        __syncthreads();
+        for (int p = tid; p < n; p += NT) {
+            const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
+            Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
+        }
     }
-    __syncthreads();
-    for (int p = tid; p < n; p += NT) {
-        const int i = i0 + (flist[p] >> 16), c = flist[p] & 0xffff;
-        Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
-    }
-}
-
-// End of an iteration: every job still carving moves on to its next
-// iteration.
-__global__ __launch_bounds__(256) void advance_kernel(const Job *jobs, int njobs)
-{
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= njobs) return;
-    const Job &J = jobs[q];
-    const int r = job_iter(J);
-    if (job_width(J, r) > J.Wt) J.state[3] = r + 1;
+    end_iteration(J, r);
 }
 
 // ----------------------------------------------------------------- gather
@@ -2172,11 +2182,6 @@ void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, hipStream_t s)
     const dim3 g(blocks_for(Hmax, kRefreshRows), njobs);
     if ((int64_t)g.x * njobs < 2 * 256) hipLaunchKernelGGL(refresh_kernel<1024>, g, dim3(1024), 0, s, d_jobs);
     else hipLaunchKernelGGL(refresh_kernel<256>, g, dim3(256), 0, s, d_jobs);
-}
-
-void launch_advance(const Job *d_jobs, int njobs, hipStream_t s)
-{
-    hipLaunchKernelGGL(advance_kernel, dim3(blocks_for(njobs, 256)), dim3(256), 0, s, d_jobs, njobs);
 }
 
 size_t gather_lds_bytes(int W, int Wt, int C)
