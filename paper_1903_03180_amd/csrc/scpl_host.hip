@@ -385,7 +385,7 @@ struct SegClip {
     int32_t nbuf = 0;
     // controller
     int t0 = 0, n = 1, nb = 0, t = 1, te = 0;
-    int win = kSegWindow;  // candidates per scan: halved after a rejection, doubled after none
+    int win = kSegWindow;  // candidates per scan: kSegRestart after a rejection, doubled after none
     bool valid = false, done = false, launched = false;
 };
 
@@ -489,7 +489,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
                     c.n = 1;
                     c.valid = false;
                     c.t = tt + 1;
-                    c.win = std::max(8, c.win / 2);
+                    c.win = kSegRestart;
                     rejected = true;
                     break;
                 }

@@ -31,6 +31,10 @@ __host__ __device__ inline int tofs(int r, int c, int ntc)
 }
 // Frames per launch of the speculative ASDE scan.
 constexpr int kSegWindow = 64;
+// candidates of the first scan of a new buffer: a rejection often comes
+// right after another (a scene cut leaves a one-frame buffer), and a long
+// scan that ends early wastes the candidates after the rejection
+constexpr int kSegRestart = 8;
 constexpr int kDpThreads = 1024;
 
 // One buffer of one clip: a carving job.  Every iteration of SCPL runs on
