@@ -17,7 +17,8 @@ after clip) is timed beside it.  The oracle (plain C, one core) is timed on
 a bounded sample of the first clip.  Seam memorisation (only every m-th
 buffer of a clip carved, the others reusing its removal) is timed on the same
 workload for the periods of --memo-periods, with the fraction of output bytes
-it changes.
+it changes, and horizontal seams (3/4 of the height, alone and with 3/4 of the
+width) on the first clip.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
@@ -196,6 +197,30 @@ def run_table1(np, torch, scpl, ctx):
             "inputs": "synthetic RGB clips of each row's size, length and target (seeds 6000-6011)"}
 
 
+def run_height(torch, ctx, clip_np, Wt, k, steps):
+    """Horizontal seams (Sec. 2, as vertical seams of the transposed frames):
+    the workload's first clip carved to 3/4 of its height alone, and to 3/4
+    of its width and height, as one batched call each."""
+    import time as _t
+    fr = torch.from_numpy(clip_np).cuda()
+    N, H, W = clip_np.shape[:3]
+    Ht = (3 * H) // 4
+    out = {"clip": f"{N} frames {W}x{H}", "target_height": Ht}
+    for name, wt in (("height_only", W), ("width_and_height", Wt)):
+        job = [dict(frames=fr, target_width=wt, target_height=Ht, seams_per_iter=k)]
+        ctx.retarget_batch(job)  # warm-up (workspace, graphs)
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        for _ in range(steps):
+            ctx.retarget_batch(job)
+        torch.cuda.synchronize()
+        fps = N * steps / (_t.perf_counter() - t0)
+        out[name] = {"target": f"{wt}x{Ht}", "frames_per_s": round(fps, 1)}
+        log(f"{name.replace('_', ' ')} ({W}x{H} -> {wt}x{Ht}): {fps:.1f} frames/s")
+    del fr
+    return out
+
+
 def _oracle_sample(args):
     clip, Wt, k, nf = args
     import oracle
@@ -284,6 +309,7 @@ def main() -> int:
     ap.add_argument("--streams", type=int, default=3, help="job groups (streams) of the batched path")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests per arrival rate (0: no serving run)")
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
+    ap.add_argument("--no-height", action="store_true", help="skip the height (horizontal seam) runs")
     ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dp-geometry", default="", metavar="Q,HB,PF,EX,R,P",
@@ -477,6 +503,7 @@ def main() -> int:
         log(f"oracle on {procs} cores: {done} frames in {c1 - c0:.1f} s")
 
     table1 = None if args.no_table1 else run_table1(np, torch, scpl, ctx)
+    height = None if args.no_height else run_height(torch, ctx, clips_np[0], work[0][1], work[0][2], 2)
 
     serving = None
     n_clips = len(clips)
@@ -521,6 +548,7 @@ def main() -> int:
         "serving": serving,
         "raw_vs_proposed": table1,
         "seam_memorisation": memo,
+        "horizontal_seams": height,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
