@@ -118,3 +118,22 @@ def test_invalid_period_is_refused(ctx):
     f = dev(synth.make_clip(1500, 4, 20, 30, C=1, n_obj=2, lattice=8))
     with pytest.raises(scpl.ScplError):
         ctx.retarget(f, 20, 4, memo_period=-1)
+
+
+def test_batched_2d(ctx, orc):
+    """Batched calls with both dimensions shrinking and memorisation in each
+    pass, next to a clip without it."""
+    specs = [(1600, 10, 36, 44, 3, 34, 28, dict(memo_period=2, max_buffer=2)),
+             (1601, 8, 30, 40, 1, 40, 22, dict(memo_period=3, max_buffer=1)),
+             (1602, 9, 28, 48, 1, 36, 28, dict(max_buffer=3))]
+    clips, host = [], []
+    for seed, N, H, W, C, Wt, Ht, kw in specs:
+        f = synth.make_clip(seed, N, H, W, C=C, n_obj=2, lattice=8)
+        host.append((f, Wt, Ht, kw))
+        clips.append(dict(frames=dev(f), target_width=Wt, target_height=Ht, seams_per_iter=4, **kw))
+    ctx.retarget_batch(clips)
+    torch.cuda.synchronize()
+    for c, (f, Wt, Ht, kw) in zip(clips, host):
+        want = orc.retarget_2d(f, Wt, Ht, 4, **oracle_kw(kw))
+        assert np.array_equal(c["out"].cpu().numpy(), want["out"])
+        assert np.array_equal(c["buffer_id"].cpu().numpy(), want["buffer_id"])
