@@ -198,7 +198,7 @@ def run_table1(np, torch, scpl, ctx):
 
 
 def run_height(torch, ctx, clip_np, Wt, k, steps):
-    """Horizontal seams (Sec. 2, as vertical seams of the transposed frames):
+    """Horizontal seams (Sec. 3.1, eq. 2, as vertical seams of the transposed frames):
     the workload's first clip carved to 3/4 of its height alone, and to 3/4
     of its width and height, as one batched call each."""
     import time as _t

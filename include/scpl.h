@@ -112,8 +112,11 @@ scpl_status scpl_create(int32_t hip_device, scpl_ctx **out);
 void scpl_destroy(scpl_ctx *ctx);
 const char *scpl_status_str(scpl_status s);
 
-/* Device bytes of workspace the library needs for one clip with params p
- * (the plain path, one buffer at a time).  Pure host arithmetic. */
+/* Device bytes of the workspace scpl_retarget needs for one clip with
+ * params p (the plain path, one buffer at a time): the tiled and
+ * pixel-major luma of the clip, the buffer controller's state, one carving
+ * job's workspace (bounded for every DP geometry) and, with a target height,
+ * the temporaries of the height pass.  Pure host arithmetic; validates p. */
 scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
 
 /* Whole retarget of one clip (Secs. 3.1-3.3).
@@ -122,7 +125,7 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
  * d_masks (nullable): N x H x W uint16; 0 = kept, r + 1 = removed in
  *   iteration r of the frame's buffer (all frames of a buffer share a mask).
  * d_buffer_id (nullable): N int32, buffer index of each frame.
- * Height (Sec. 2: horizontal seams are vertical seams of the transposed
+ * Height (Sec. 3.1, eq. 2: horizontal seams are vertical seams of the transposed
  * frames): with target_height Ht < H the clip is carved in width first (if
  * Wt < W), then its frames are transposed, carved from H to Ht columns the
  * same way (buffers, energies and seams of the transposed frames) and
@@ -130,11 +133,19 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
  * Wt == W; when both dimensions shrink, buffer ids describe the width pass
  * and d_masks must be null.
  * h_n_buffers (nullable): receives the number of buffers.
+ * d_workspace (nullable): device memory of workspace_bytes bytes (at least
+ *   scpl_workspace_size(p), 256-byte aligned) that the call uses instead of
+ *   the context's own workspace; owned by the caller, who keeps it alive
+ *   and untouched until the work on `stream` is complete.  The call then
+ *   allocates no device memory (its host staging may still grow).  Null:
+ *   the context's workspace, grown on demand.  A region that is too small
+ *   or misaligned returns SCPL_ERR_INVALID_ARG.
  * The segmentation step synchronises `stream` a few times; the carving is
  * asynchronous apart from one check of the iteration count per buffer.
  * Buffers are carved one after another (the plain path). */
 scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
-                          uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream);
+                          uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream);
 
 /* Many clips at once (the batched path): every buffer of every clip is a job,
  * and each stage of an SCPL iteration runs as one launch over all jobs, the
@@ -185,7 +196,8 @@ scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
  * scpl_server_wait: blocks until the request is done.
  * scpl_server_ticket_times: host steady-clock milliseconds from submission
  *   to the start of the request's batch and to its completion (done only).
- * scpl_server_release: forgets a done ticket.
+ * scpl_server_release: forgets a done ticket (SCPL_ERR_NOT_READY while the
+ *   request runs or another thread still waits on it).
  * scpl_server_destroy: requests already running finish; queued ones are
  *   dropped; then the lanes' contexts are destroyed. */
 #define SCPL_MAX_LANES 16
@@ -295,9 +307,12 @@ scpl_status scpl_energy(scpl_ctx *ctx, int32_t H, int32_t W, int32_t mode, const
                         const uint8_t *d_yprev, int32_t *d_e, void *stream);
 
 /* Cumulative energy, eq. (4), with parent labels (Sec. 3.1) and the
- * indicator array.  d_u: H x W int32 in [0, 16382] (values outside are
- * clamped into it: the DP keeps 4 U in 16 bits per column), H <= 16383 (so
- * that 4 x the cumulative energy fits 32 bits).  d_ce_last, d_label_last:
+ * indicator array.  d_u: H x W int32 in [0, 16382] (the DP keeps 4 U in 16
+ * bits per column; the largest uniform energy is 7650), H <= 16383 (so that
+ * 4 x the cumulative energy fits 32 bits).  A value of d_u outside
+ * [0, 16382] returns SCPL_ERR_INVALID_ARG: the values are checked on the
+ * device (one launch and a synchronisation) before the DP runs, and the
+ * outputs are then left untouched.  d_ce_last, d_label_last:
  * W int32 (last row).  d_dir: H x W int8 in {-1, 0, 1} (predecessor column
  * minus column; row 0 is 0). */
 scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int32_t *d_ce_last,

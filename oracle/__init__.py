@@ -183,7 +183,7 @@ def _t(a: np.ndarray) -> np.ndarray:
 
 
 def retarget_2d(frames: np.ndarray, Wt: int, Ht: int, k: int, **kw):
-    """Width, then height (Sec. 2: a horizontal seam is a vertical seam of
+    """Width, then height (Sec. 3.1, eq. 2: a horizontal seam is a vertical seam of
     the transposed frame): the frames are carved to width Wt as by
     retarget(), then transposed, carved to Ht columns, and transposed back.
     Masks and buffer ids describe the height pass when only the height

@@ -46,6 +46,8 @@ struct scpl_ctx {
     size_t tws_size = 0;
     void *pinned = nullptr;    // host staging (job tables, sums, states)
     size_t pinned_size = 0;
+    bool fixed_ws = false;     // ws / jws / tws point into a caller's region: never grown or freed
+    bool fixed_pinned = false; // the host staging is never grown
     std::vector<int32_t> last_log;
     int nstreams = 3;                    // job groups of the batched path, one stream each
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
@@ -143,13 +145,23 @@ int32_t band_rows(int32_t H, int32_t W, size_t lds_cap)
 
 size_t g_lds_cap = 65536;  // set from the device at context creation
 
+// Columns right of the width that the DP may read under any geometry: a
+// banded workgroup covers at most W + C + HB (C <= 1024), the row-synchronous
+// kernel at most W + 64 Q (Q = 32), a column-split one at most W + 16 waves x
+// C + HB (C <= 256).
+constexpr int32_t kCoverSlack = 16 * 256 + 64;
+
 struct JobShape {
     int32_t H, W, Wt, k;
     DpGeom g;  // DP geometry of the launch the job runs in
+    bool bound = false;  // sizes for every geometry and band height (workspace bounds)
     int32_t Wp() const { return (int32_t)align_up((size_t)W, 64); }
     const DpGeom &geom() const { return g; }
-    int32_t Kp() const { return kKeyLeft + (int32_t)align_up((size_t)geom().cover(W), 64); }
-    int32_t B() const { return band_rows(H, W, g_lds_cap); }
+    int32_t Kp() const
+    {
+        return kKeyLeft + (int32_t)align_up((size_t)(bound ? W + kCoverSlack : geom().cover(W)), 64);
+    }
+    int32_t B() const { return bound ? 32 : band_rows(H, W, g_lds_cap); }
     int32_t nb() const { return (H + B() - 1) / B(); }
     int32_t kcap() const { return std::min(k, W); }
     int32_t logcap() const { return W - Wt + 2; }
@@ -205,9 +217,10 @@ void carve_job(Job &J, const JobShape &s, Bump &bp, int32_t *state)
     J.state = state;
 }
 
-scpl_status grow(void *&buf, size_t &size, size_t bytes)
+scpl_status grow(void *&buf, size_t &size, size_t bytes, bool fixed)
 {
     if (bytes <= size) return SCPL_OK;
+    if (fixed) return SCPL_ERR_CAPACITY;  // a caller's region is never replaced
     if (buf) {
         SCPL_TRY(hipFree(buf));  // implicitly waits for work using it
         buf = nullptr;
@@ -219,12 +232,14 @@ scpl_status grow(void *&buf, size_t &size, size_t bytes)
     return SCPL_OK;
 }
 
-scpl_status ensure_ws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->ws, ctx->ws_size, bytes); }
-scpl_status ensure_jws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->jws, ctx->jws_size, bytes); }
+scpl_status ensure_ws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->ws, ctx->ws_size, bytes, ctx->fixed_ws); }
+scpl_status ensure_jws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->jws, ctx->jws_size, bytes, ctx->fixed_ws); }
+scpl_status ensure_tws(scpl_ctx *ctx, size_t bytes) { return grow(ctx->tws, ctx->tws_size, bytes, ctx->fixed_ws); }
 
 scpl_status ensure_pinned(scpl_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->pinned_size) return SCPL_OK;
+    if (ctx->fixed_pinned) return SCPL_ERR_CAPACITY;
     if (ctx->pinned) {
         SCPL_TRY(hipHostFree(ctx->pinned));
         ctx->pinned = nullptr;
@@ -360,18 +375,87 @@ size_t height_temp_bytes(const scpl_params &p)
     return b;
 }
 
-// Workspace of the height pass run itself (plain path, one buffer at a time).
-size_t height_pass_bytes(const scpl_params &p)
+// Device bytes of the plain path (one clip, one buffer at a time), by area:
+// A holds the tiled and pixel-major luma, the buffer controller's state and
+// the window sums; B one carving job's workspace (sized for every DP
+// geometry and band height) with the job table and states; T the height
+// pass's temporaries.  A pass of the width and a pass of the height reuse A
+// and B one after the other.
+struct PlainLayout {
+    size_t ws = 0, jws = 0, tws = 0;
+    size_t total() const { return ws + jws + tws; }
+};
+
+size_t area_a_bytes(const scpl_params &p)
 {
-    if (!height_pass(p)) return 0;
-    const scpl_params q = transposed_params(p);
-    JobShape js{q.height, q.width, q.target_width, q.seams_per_iter, dp_geom(q.width)};
-    size_t b = align_up((size_t)q.n_frames * tiled_frame_bytes(q.height, q.width));
-    b += seg_bytes((int64_t)q.height * q.width) + align_up(kSegWindow * 8);
-    b += job_bytes(js) + align_up(sizeof(Job) * (size_t)q.n_frames) + align_up(16 * (size_t)q.n_frames);
-    return b;
+    const size_t N = p.n_frames;
+    return align_up(kSegWindow * 8) + align_up(N * tiled_frame_bytes(p.height, p.width)) +
+           align_up((size_t)p.height * p.width * seq_pitch(p.n_frames)) + seg_bytes((int64_t)p.height * p.width) +
+           align_up(sizeof(SegArgs));
 }
 
+size_t area_b_bytes(const scpl_params &p)
+{
+    const size_t N = p.n_frames;  // at most one buffer per frame
+    JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, dp_geom(p.width), true};
+    return job_bytes(js) + align_up(sizeof(Job) * N) + align_up(16 * N);
+}
+
+PlainLayout plain_layout(const scpl_params &p)
+{
+    PlainLayout L;
+    if (!height_pass(p)) {
+        L.ws = area_a_bytes(p);
+        L.jws = area_b_bytes(p);
+        return L;
+    }
+    if (p.target_width < p.width) {
+        scpl_params w = p;
+        w.target_height = 0;
+        L.ws = area_a_bytes(w);
+        L.jws = area_b_bytes(w);
+    }
+    const scpl_params q = transposed_params(p);
+    L.ws = std::max(L.ws, area_a_bytes(q));
+    L.jws = std::max(L.jws, area_b_bytes(q));
+    L.tws = height_temp_bytes(p);
+    return L;
+}
+
+// Points the context's three device workspaces (and, with fixed_host, its
+// host staging as it stands) into one region laid out by L for the length of
+// a call; the context's own allocations are restored afterwards and never
+// freed or grown meanwhile.
+struct FixedArena {
+    scpl_ctx *ctx;
+    void *ws, *jws, *tws;
+    size_t ws_size, jws_size, tws_size;
+    FixedArena(scpl_ctx *c, void *base, const PlainLayout &L, bool fixed_host)
+        : ctx(c), ws(c->ws), jws(c->jws), tws(c->tws), ws_size(c->ws_size), jws_size(c->jws_size),
+          tws_size(c->tws_size)
+    {
+        char *b = static_cast<char *>(base);
+        c->ws = b;
+        c->ws_size = L.ws;
+        c->jws = b + L.ws;
+        c->jws_size = L.jws;
+        c->tws = b + L.ws + L.jws;
+        c->tws_size = L.tws;
+        c->fixed_ws = true;
+        c->fixed_pinned = fixed_host;
+    }
+    ~FixedArena()
+    {
+        ctx->ws = ws;
+        ctx->jws = jws;
+        ctx->tws = tws;
+        ctx->ws_size = ws_size;
+        ctx->jws_size = jws_size;
+        ctx->tws_size = tws_size;
+        ctx->fixed_ws = false;
+        ctx->fixed_pinned = false;
+    }
+};
 
 struct SegClip {
     const scpl_params *p;
@@ -841,14 +925,7 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes)
     scpl_status st = validate(p);
     if (st != SCPL_OK) return st;
     if (!device_bytes) return SCPL_ERR_INVALID_ARG;
-    const int64_t HW = (int64_t)p->height * p->width;
-    JobShape js{p->height, p->width, p->target_width, p->seams_per_iter, dp_geom(p->width)};
-    size_t b = align_up((size_t)p->n_frames * tiled_frame_bytes(p->height, p->width));
-    b += seg_bytes(HW) + align_up(kSegWindow * 8);
-    b += job_bytes(js) + align_up(sizeof(Job) * (size_t)p->n_frames) + align_up(16 * (size_t)p->n_frames);
-    b = std::max<size_t>(b, height_pass_bytes(*p));
-    b += height_temp_bytes(*p);
-    *device_bytes = b;
+    *device_bytes = plain_layout(*p).total();
     return SCPL_OK;
 }
 
@@ -1114,10 +1191,6 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     return SCPL_OK;
 }
 
-extern "C" {
-
-}  // extern "C"
-
 // Width pass for every clip, then the height pass (transposed) for the clips
 // with a target height.  Each pass is one run of the clips it concerns.
 scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
@@ -1132,7 +1205,7 @@ scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bo
             if (clips[c].p.target_width < clips[c].p.width && clips[c].d_masks) return SCPL_ERR_INVALID_ARG;
         }
     if (!any) return run_clips(ctx, clips, nc, batched, h_nbuf_first, s, use_graph);
-    SCPL_TRY(grow(ctx->tws, ctx->tws_size, tbytes));
+    SCPL_TRY(ensure_tws(ctx, tbytes));
     std::vector<scpl_clip> pass1, pass2;
     struct Back {
         const scpl_clip *clip;
@@ -1201,13 +1274,20 @@ scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bo
 extern "C" {
 
 scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
-                          uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream)
+                          uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream)
 {
     if (!ctx || !d_frames || !d_out) return SCPL_ERR_INVALID_ARG;
     scpl_status st = validate(p);
     if (st != SCPL_OK) return st;
+    if (d_workspace) {
+        if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign != 0) return SCPL_ERR_INVALID_ARG;
+        if (workspace_bytes < plain_layout(*p).total()) return SCPL_ERR_INVALID_ARG;
+    }
     SCPL_TRY(hipSetDevice(ctx->device));
     scpl_clip c{*p, d_frames, d_out, d_masks, d_buffer_id};
+    if (!d_workspace) return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
+    FixedArena arena(ctx, d_workspace, plain_layout(*p), false);
     return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
 }
 
@@ -1357,13 +1437,20 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     Job J{};
     Job *d_job;
     int32_t *d_state;
-    char *unused;
-    scpl_status st = stage_job(ctx, H, W, 0, 1, 0, J, d_job, d_state, unused, s);
+    char *d_flag;
+    scpl_status st = stage_job(ctx, H, W, 0, 1, 4, J, d_job, d_state, d_flag, s);
     if (st != SCPL_OK) return st;
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, 1, select_geom(ctx, W, 1)});
+    int32_t *bad = reinterpret_cast<int32_t *>(d_flag);
+    int32_t *h_bad = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned) + align_up(sizeof(Job)));
+    SCPL_TRY(hipMemsetAsync(bad, 0, 4, s));
     launch_init_jobs(d_job, 1, H, W, s);
-    launch_u_to_keys(d_u, J.K + J.KL, H, W, J.Kp, s);
+    launch_u_to_keys(d_u, J.K + J.KL, H, W, J.Kp, bad, s);
+    SCPL_CHECK_LAUNCH();
+    SCPL_TRY(hipMemcpyAsync(h_bad, bad, 4, hipMemcpyDeviceToHost, s));
+    SCPL_TRY(hipStreamSynchronize(s));
+    if (*h_bad) return SCPL_ERR_INVALID_ARG;  // eq. (4) keys hold 4 U in 16 bits
     launch_dp(d_job, 1, ls.g, W, H, s);
     launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
     launch_labels(d_job, 1, W, s);

@@ -145,7 +145,8 @@ void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, hipStream_
 // LDS of the gather for a job (0: the job gathers directly from global memory)
 size_t gather_lds_bytes(int W, int Wt, int C);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);
-void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s);
+// U (H x W int32) -> key rows; *bad |= 1 if some U is outside [0, 16382]
+void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s);
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);
 // N frames H x W of C-byte pixels -> N frames W x H (and of 16-bit entries)
 void launch_transpose(const uint8_t *src, int N, int H, int W, int C, uint8_t *dst, hipStream_t s);

@@ -1892,13 +1892,16 @@ __global__ __launch_bounds__(256) void compact_frame_kernel(const uint8_t *in, i
 
 // ------------------------------------------------- stage-API conversions
 
-// U -> key row entry; U outside [0, 16382] is clamped into it
-__global__ void u_to_keys_kernel(const int32_t *src, uint16_t *dst, int H, int W, int pitch)
+// U -> key row entry; *bad is set when some U lies outside [0, 16382] (the
+// caller then runs no DP on the keys)
+__global__ void u_to_keys_kernel(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= (int64_t)H * W) return;
     const int i = (int)(p / W), j = (int)(p - (int64_t)i * W);
-    dst[(size_t)i * pitch + j] = (uint16_t)(min(max(src[p], 0), 16382) << 2);
+    const int32_t u = src[p];
+    if ((uint32_t)u > 16382u) atomicOr(bad, 1);
+    dst[(size_t)i * pitch + j] = (uint16_t)((uint32_t)u << 2);
 }
 
 __global__ void keys_to_u_kernel(const uint16_t *src, int32_t *dst, int H, int W, int pitch)
@@ -2196,10 +2199,10 @@ void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream
     hipLaunchKernelGGL(gather_kernel, dim3(Hmax, njobs), dim3(256), lds, s, d_jobs);
 }
 
-void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, hipStream_t s)
+void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s)
 {
     hipLaunchKernelGGL(u_to_keys_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, src, dst, H, W,
-                       pitch);
+                       pitch, bad);
 }
 
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s)

@@ -31,6 +31,7 @@ double now_us()
 struct Ticket {
     scpl_clip clip;
     uint64_t bytes = 0;
+    int waiters = 0;  // threads inside scpl_server_wait on this ticket
     bool done = false;
     scpl_status result = SCPL_OK;
     double t_submit = 0, t_start = 0, t_done = 0;
@@ -191,8 +192,14 @@ scpl_status scpl_server_wait(scpl_server *S, int64_t ticket, scpl_status *h_resu
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->tickets.find(ticket);
     if (it == S->tickets.end()) return SCPL_ERR_INVALID_ARG;
-    S->cv_done.wait(lk, [&] { return it->second.done; });
-    if (h_result) *h_result = it->second.result;
+    // a submit may rehash the map while this thread waits: iterators then
+    // go stale, element addresses do not; the waiter count keeps
+    // scpl_server_release from erasing the ticket meanwhile
+    Ticket *tk = &it->second;
+    ++tk->waiters;
+    S->cv_done.wait(lk, [&] { return tk->done; });
+    --tk->waiters;
+    if (h_result) *h_result = tk->result;
     return SCPL_OK;
 }
 
@@ -214,7 +221,7 @@ scpl_status scpl_server_release(scpl_server *S, int64_t ticket)
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->tickets.find(ticket);
     if (it == S->tickets.end()) return SCPL_ERR_INVALID_ARG;
-    if (!it->second.done) return SCPL_ERR_NOT_READY;
+    if (!it->second.done || it->second.waiters > 0) return SCPL_ERR_NOT_READY;
     S->tickets.erase(it);
     return SCPL_OK;
 }

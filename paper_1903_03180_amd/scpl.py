@@ -78,7 +78,7 @@ _sig = {
     "scpl_destroy": ([_P], None),
     "scpl_status_str": ([C.c_int], C.c_char_p),
     "scpl_workspace_size": ([C.POINTER(scpl_params), C.POINTER(C.c_uint64)], C.c_int),
-    "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
+    "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P, C.c_uint64, _P], C.c_int),
     "scpl_retarget_batch": ([_P, C.POINTER(scpl_clip), _I32, _P], C.c_int),
     "scpl_last_log": ([_P, _P, _I64, C.POINTER(_I64)], C.c_int),
     "scpl_luma": ([_P, _P, _I64, _P, _P], C.c_int),
@@ -161,6 +161,14 @@ def _stream(stream):
     return stream.cuda_stream
 
 
+def workspace_size(params: Params) -> int:
+    """Device bytes scpl_retarget needs for a clip with these parameters."""
+    b = C.c_uint64(0)
+    cp = params.c()
+    _check(scpl_workspace_size(C.byref(cp), C.byref(b)), "scpl_workspace_size")
+    return int(b.value)
+
+
 def params_for(frames, target_width: int, seams_per_iter: int, **kw) -> Params:
     if frames.dim() == 3:
         N, H, W = frames.shape
@@ -194,8 +202,10 @@ class Context:
 
     # ---------------------------------------------------------- whole path
     def retarget(self, frames, target_width: int, seams_per_iter: int, want_masks: bool = True, stream=None,
-                 **kw):
+                 workspace=None, **kw):
         """frames: uint8 cuda tensor N x H x W (luma) or N x H x W x 3 (RGB).
+        workspace: optional uint8 cuda tensor of at least workspace_size()
+        bytes that the call uses instead of the context's own workspace.
         Returns dict(out, masks, buffer_id, n_buffers)."""
         import torch
         p = params_for(frames, target_width, seams_per_iter, **kw)
@@ -208,8 +218,9 @@ class Context:
         bid = torch.empty(p.n_frames, dtype=torch.int32, device=frames.device)
         nb = C.c_int32(0)
         cp = p.c()
+        wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
         _check(scpl_retarget(self.h, C.byref(cp), _ptr(frames), _ptr(out), _ptr(masks), _ptr(bid), C.byref(nb),
-                             _stream(stream)), "scpl_retarget")
+                             _ptr(workspace), wsb, _stream(stream)), "scpl_retarget")
         return dict(out=out, masks=masks, buffer_id=bid, n_buffers=int(nb.value))
 
     def retarget_batch(self, clips, stream=None):
@@ -411,6 +422,10 @@ class Server:
         if clip.get("buffer_id") is None:
             clip["buffer_id"] = torch.empty(p.n_frames, dtype=torch.int32, device=fr.device)
         c = scpl_clip(p.c(), _ptr(fr), _ptr(clip["out"]), _ptr(clip.get("masks")), _ptr(clip["buffer_id"]))
+        # the server's lanes write the outputs on streams of their own: the
+        # frames, and whatever earlier work on this stream used the memory
+        # the outputs were just given, must be complete first
+        torch.cuda.current_stream(fr.device).synchronize()
         t = C.c_int64(0)
         _check(scpl_server_submit(self.h, C.byref(c), C.byref(t)), "scpl_server_submit")
         self._live[t.value] = clip  # keeps the tensors alive

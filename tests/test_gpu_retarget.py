@@ -114,6 +114,68 @@ def test_batch_equals_oracle_and_plain(ctx, orc, nstreams):
         assert np.array_equal(c["buffer_id"].cpu().numpy(), want["buffer_id"])
 
 
+@pytest.mark.parametrize("seed,N,H,W,C,Wt,Ht,k", [
+    (1, 12, 30, 52, 3, 38, 0, 3),
+    (2, 9, 70, 300, 1, 220, 0, 6),
+    (3, 7, 35, 60, 3, 45, 28, 3),   # width and height: the height pass's temporaries too
+    (4, 8, 40, 30, 1, 30, 29, 4),   # height only
+])
+def test_caller_workspace_equals_own(ctx, orc, seed, N, H, W, C, Wt, Ht, k):
+    """scpl_retarget with a caller's workspace of exactly
+    scpl_workspace_size bytes gives the result of the context's own
+    workspace (and the oracle's); the region is left to the caller."""
+    from paper_1903_03180_amd import scpl
+    clip = synth.make_clip(630 + seed, N, H, W, C=C, n_obj=3, cut_at=N // 2, lattice=8)
+    d = dev(clip)
+    kw = dict(target_height=Ht) if Ht else {}
+    want_masks = not (Ht and Wt < W)
+    p = scpl.params_for(d, Wt, k, **kw)
+    nbytes = scpl.workspace_size(p)
+    ws = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    a = ctx.retarget(d, Wt, k, want_masks=want_masks, workspace=ws, **kw)
+    b = ctx.retarget(d, Wt, k, want_masks=want_masks, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(a["out"], b["out"]) and torch.equal(a["buffer_id"], b["buffer_id"])
+    if want_masks:
+        assert torch.equal(a["masks"], b["masks"])
+    want = orc.retarget_2d(clip, Wt, Ht, k) if Ht else orc.retarget(clip, Wt, k)
+    assert np.array_equal(a["out"].cpu().numpy(), want["out"])
+
+
+def test_caller_workspace_too_small_or_misaligned(ctx):
+    from paper_1903_03180_amd import scpl
+    d = dev(synth.make_clip(640, 5, 20, 40, C=1, n_obj=2, lattice=8))
+    nbytes = scpl.workspace_size(scpl.params_for(d, 30, 4))
+    ws = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(scpl.ScplError) as e:
+        ctx.retarget(d, 30, 4, workspace=ws[:nbytes - 1])
+    assert e.value.status == scpl.SCPL_ERR_INVALID_ARG
+    with pytest.raises(scpl.ScplError) as e:
+        ctx.retarget(d, 30, 4, workspace=ws[16:16 + nbytes])
+    assert e.value.status == scpl.SCPL_ERR_INVALID_ARG
+    ctx.retarget(d, 30, 4, workspace=ws[256:256 + nbytes])
+
+
+@pytest.mark.parametrize("seed,N,H,W,C,Wt,k,kw", [
+    (1, 48, 36, 100, 1, 70, 4, dict(alpha_num=1, alpha_den=2)),   # one 48-frame buffer: 3 pieces of 16 frames
+    (2, 70, 20, 64, 3, 44, 3, dict(alpha_num=1, alpha_den=2, max_buffer=40)),  # 40 + 30 frames, RGB
+    (3, 2, 6, 12000, 1, 11900, 40, {}),   # selection keys in global memory (W > 10176)
+    (4, 3, 300, 8000, 1, 7950, 32, {}),   # 96-row bands (selection LDS of 159 KiB)
+    (5, 3, 450, 3000, 1, 2950, 16, {}),   # 96-row bands under a 63 KiB selection LDS
+])
+def test_paths_full_sizes_reach(ctx, orc, seed, N, H, W, C, Wt, k, kw):
+    """Paths the full-size workloads take that the small clips do not:
+    buffers longer than 32 frames (the refresh's sum over several
+    16-frame pieces of the pixel-major luma), widths whose selection keys do
+    not fit LDS, and band heights above 32 rows.  Against the oracle."""
+    clip = synth.make_clip(650 + seed, N, H, W, C=C, n_obj=3, lattice=8)
+    res, want = compare(ctx, orc, clip, Wt, k, **kw)
+    if seed == 1:
+        assert np.bincount(want["buffer_id"]).tolist() == [48]
+    if seed == 2:
+        assert np.bincount(want["buffer_id"]).tolist() == [40, 30]
+
+
 def test_repeat_runs_identical(ctx):
     clip = dev(synth.make_clip(9, 16, 72, 128, C=3, n_obj=3, cut_at=8, lattice=8))
     a = ctx.retarget(clip, 90, 8)

@@ -69,7 +69,32 @@ def test_dp(ctx, orc, shape, hi):
     assert np.array_equal(host(d), od)
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (5, 6), (60, 1920), (9, 3000), (40, 4100)])
+@pytest.mark.parametrize("bad", [-1, 16383, 1 << 30])
+def test_dp_refuses_energy_outside_key_range(ctx, bad):
+    """U outside [0, 16382] does not fit the 16-bit key rows: the call
+    returns SCPL_ERR_INVALID_ARG and leaves the outputs untouched."""
+    from paper_1903_03180_amd import scpl
+    u = np.full((9, 40), 5, dtype=np.int32)
+    u[4, 17] = bad
+    ce = torch.full((40,), -7, dtype=torch.int32, device="cuda")
+    lab = torch.full((40,), -7, dtype=torch.int32, device="cuda")
+    d = torch.full((9, 40), 9, dtype=torch.int8, device="cuda")
+    du = dev(u)
+    st = scpl.scpl_dp(ctx.h, 9, 40, du.data_ptr(), ce.data_ptr(), lab.data_ptr(), d.data_ptr(),
+                      torch.cuda.current_stream().cuda_stream)
+    assert st == scpl.SCPL_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((ce == -7).all()) and bool((lab == -7).all()) and bool((d == 9).all())
+    # the context stays usable
+    u[4, 17] = 16382
+    ce2, _, _ = ctx.dp(dev(u))
+    assert ce2.shape == (40,)
+
+
+# widths above 10176 hold the selection keys (16 bytes per column) in global
+# memory instead of the 159 KiB of LDS
+@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (5, 6), (60, 1920), (9, 3000), (40, 4100), (3, 12000),
+                                   (2, 20000)])
 @pytest.mark.parametrize("k", [1, 3, 16, 10**6])
 def test_select(ctx, orc, shape, k):
     rng = np.random.default_rng(shape[1] + k % 1000)

@@ -75,10 +75,24 @@ def test_workspace_size_scales(lib):
     assert st == lib.SCPL_OK and d > a
 
 
+def test_workspace_size_covers_the_clip_areas(lib):
+    """The plain path holds the clip's luma twice (16 x 8 tiles for the
+    stencils, pixel-major 16-frame pieces for the refresh: N + 1 entries per
+    pixel rounded up to 16) and one job per buffer at a time."""
+    N, H, W = 120, 1080, 1920
+    st, a = wsize(lib, base())
+    tiled = N * ((H + 15) // 16) * ((W + 7) // 8) * 128
+    seq = H * W * ((N + 1 + 15) // 16 * 16)
+    job = H * W * (2 + 2 + 1 + 2)  # column map, key rows, indicator codes, mask
+    assert a >= tiled + seq + job
+    assert a < tiled + seq + 4 * job
+
+
 def test_null_context_and_pointers_rejected(lib):
     p = base()
     nb = C.c_int32(0)
-    assert lib.scpl_retarget(None, C.byref(p), 1, 1, None, None, C.byref(nb), None) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_retarget(None, C.byref(p), 1, 1, None, None, C.byref(nb), None, 0, None) == \
+        lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_retarget_batch(None, None, 0, None) == lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_create(0, None) == lib.SCPL_ERR_INVALID_ARG
     n = C.c_int64(0)

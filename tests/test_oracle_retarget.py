@@ -182,7 +182,7 @@ def test_table1_target_width_rounding():
 
 
 def test_height_retarget_is_width_retarget_of_the_transpose(orc):
-    """Horizontal seams (Sec. 2): carving the height of a clip equals
+    """Horizontal seams (Sec. 3.1, eq. 2): carving the height of a clip equals
     carving the width of its transpose; every output column keeps its
     pixels' order and loses exactly H - Ht of them."""
     from paper_1903_03180_amd import synth
