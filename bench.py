@@ -91,33 +91,49 @@ def serving_pool(n_mix, n_4k):
     return clips, wt, k
 
 
-def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=32, fracs=(0.5, 0.8, 0.95), lanes=4, seed=5):
+def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=400, warm=0.1, p4k=0.1, n_cap=64,
+                fracs=(0.5, 0.8, 0.95), lanes=4, seed=5):
     """Poisson arrivals of retarget requests at fractions of the measured
-    capacity; p50 / p99 of completion minus arrival, and frames/s."""
+    capacity.  A request is a clip of the uneven mix, or with probability
+    p4k a 4K clip; the first `warm` fraction of each rate's requests (by
+    arrival) is left out of the latency figures.  p50 / p99 of completion
+    minus arrival, and frames/s over the whole rate."""
     import time as _t
     clips_np, wts, ks = serving_pool(n_mix, n_4k)
     dev = [torch.from_numpy(c).cuda() for c in clips_np]
     torch.cuda.synchronize()
     srv = scpl.Server(0, lanes=lanes, max_batch=8)
+    rng = np.random.default_rng(seed)
+
+    def draw(n):
+        is4k = rng.random(n) < p4k
+        return np.where(is4k, n_mix + rng.integers(0, n_4k, size=n), rng.integers(0, n_mix, size=n))
 
     def req(q):
         return dict(frames=dev[q], target_width=wts[q], seams_per_iter=ks[q])
 
-    # capacity: the whole pool submitted at once
+    # capacity: a burst of n_cap requests of the same mix submitted at once
+    burst = draw(n_cap)
+    for q in range(len(dev)):  # every clip once first (lane workspaces)
+        t = srv.submit(req(q))
+        srv.wait(t)
+        srv.release(t)
     t0 = _t.perf_counter()
-    ts = [srv.submit(req(q)) for q in range(len(dev))]
+    ts = [srv.submit(req(int(q))) for q in burst]
     for t in ts:
         srv.wait(t)
         srv.release(t)
-    cap = len(dev) / (_t.perf_counter() - t0)
-    log(f"serving capacity on the pool ({len(dev)} requests): {cap:.2f} requests/s")
-    rng = np.random.default_rng(seed)
-    out = {"capacity_req_per_s": round(cap, 3), "pool": f"{n_mix} clips of the uneven mix + {n_4k} 4K clips",
-           "requests_per_rate": n_req, "lanes": lanes, "rates": []}
+    cap = n_cap / (_t.perf_counter() - t0)
+    log(f"serving capacity ({n_cap} requests at once): {cap:.2f} requests/s")
+    n_warm = int(round(warm * n_req))
+    out = {"capacity_req_per_s": round(cap, 3),
+           "pool": f"{n_mix} clips of the uneven mix, and with probability {p4k} one of {n_4k} 4K clips",
+           "requests_per_rate": n_req, "warmup_requests": n_warm, "latency_samples": n_req - n_warm,
+           "lanes": lanes, "rates": []}
     for f in fracs:
         lam = f * cap
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
-        picks = rng.integers(0, len(dev), size=n_req)
+        picks = draw(n_req)
         tickets = []
         start = _t.perf_counter()
         for a, q in zip(arrivals, picks):
@@ -126,19 +142,22 @@ def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=32, fracs=(0.5, 0.8, 0.
                 _t.sleep(a - now)
             lag = max(0.0, (_t.perf_counter() - start) - a)
             tickets.append((srv.submit(req(int(q))), lag, int(q)))
-        lat, frames = [], 0
-        for t, lag, q in tickets:
+        lat, frames, n4k = [], 0, 0
+        for i, (t, lag, q) in enumerate(tickets):
             srv.wait(t)
             _, total_ms = srv.times(t)
-            lat.append(total_ms + 1e3 * lag)
+            if i >= n_warm:
+                lat.append(total_ms + 1e3 * lag)
+                n4k += q >= n_mix
             frames += dev[q].shape[0]
             srv.release(t)
         span = _t.perf_counter() - start
         lat = np.array(lat)
         rec = {"load": f, "arrival_req_per_s": round(lam, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
-               "p99_ms": round(float(np.percentile(lat, 99)), 2), "frames_per_s": round(frames / span, 1)}
-        log(f"serving at {f:.2f} x capacity: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
-            f"{rec['frames_per_s']} frames/s")
+               "p99_ms": round(float(np.percentile(lat, 99)), 2), "frames_per_s": round(frames / span, 1),
+               "samples": int(len(lat)), "samples_4k": int(n4k)}
+        log(f"serving at {f:.2f} x capacity: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms over "
+            f"{len(lat)} requests ({n4k} 4K), {rec['frames_per_s']} frames/s")
         out["rates"].append(rec)
     srv.close()
     del dev
@@ -222,10 +241,50 @@ def run_height(torch, ctx, clip_np, Wt, k, steps):
 
 
 def _oracle_sample(args):
-    clip, Wt, k, nf = args
+    """Whole oracle retarget of the first nf frames of a workload clip (the
+    clip regenerated here, so that nothing large crosses processes);
+    returns (frames, seconds of the oracle call alone)."""
+    workload, index, nf = args
+    import numpy as np
+
     import oracle
-    oracle.retarget(clip[:nf], Wt, k, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
-    return nf
+    clip, Wt, k = _workload_clip(workload, index)
+    clip = np.ascontiguousarray(clip[:nf])
+    t0 = time.perf_counter()
+    oracle.retarget(clip, Wt, k, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
+    return clip.shape[0], time.perf_counter() - t0
+
+
+def _workload_clip(workload, index):
+    """Clip `index` of a workload with its target width and seams per
+    iteration (as make_workload draws them)."""
+    from paper_1903_03180_amd import synth
+    if workload == "1080p-batch16":
+        return synth.clip_1080p(2000 + index), 1440, 16
+    if workload == "1080p":
+        return synth.clip_1080p(2), 1440, 16
+    if workload == "mix64":
+        sp = synth.batch_mix_specs(64)[index]
+        return synth.clip_from_spec(sp), sp.Wt, 16
+    return synth.clip_4k(3), 2880, 32
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def job_rows(log_rows, jobs):
@@ -286,6 +345,30 @@ def measured_dp_traffic(workload, g):
     return (rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) * rec.get("dispatches_per_dp", 1)
 
 
+def measured_step_traffic(workload, g):
+    """The committed whole-step counter record of this workload, if it was
+    taken with this DP geometry and no kernel or host source has changed
+    since; else None."""
+    path = os.path.join(ROOT, "profiles", f"step_traffic_{workload.replace('-', '_')}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sources_sha256") != sources_digest() or rec.get("dp_geometry") != g:
+        return None
+    return rec
+
+
+def sources_digest() -> str:
+    """SHA-256 over the library's kernel and host sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("scpl_kernels.hip", "scpl_host.hip", "scpl_internal.h", "scpl_runtime.h"):
+        with open(os.path.join(ROOT, "paper_1903_03180_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def dp_source_digest() -> str:
     """SHA-256 of the DP section of the kernel source (key rows, row step,
     code stores, the DP kernels): a traffic record stays valid while that
@@ -307,10 +390,13 @@ def main() -> int:
     ap.add_argument("--workload", default="1080p-batch16", choices=["1080p-batch16", "1080p", "4k", "mix64"])
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--streams", type=int, default=3, help="job groups (streams) of the batched path")
-    ap.add_argument("--serve-requests", type=int, default=32, help="requests per arrival rate (0: no serving run)")
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate (0: no serving run)")
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
     ap.add_argument("--no-height", action="store_true", help="skip the height (horizontal seam) runs")
-    ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the oracle's bounded sample")
+    ap.add_argument("--cpu-frames", type=int, default=0,
+                    help="frames of the oracle's bounded sample (0: 61 for the 1080p workloads, i.e. the first "
+                         "buffer and the one-frame buffer of the scene cut; 8 for 4k; 30 for mix64)")
+    ap.add_argument("--cpu-procs", type=int, default=16, help="most processes of the all-cores oracle leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--dp-geometry", default="", metavar="Q,HB,PF,EX,R,P",
                     help="use this DP geometry instead of autotuning (e.g. under a profiler, whose per-dispatch "
@@ -325,7 +411,18 @@ def main() -> int:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
+    import multiprocessing as mp
+
     import numpy as np
+
+    # the oracle's one-core leg runs in a fresh process beside the GPU legs
+    # (spawned before this process touches the GPU)
+    cpu_frames = args.cpu_frames or {"4k": 8, "mix64": 30}.get(args.workload, 61)
+    cpu_pool = cpu_job = None
+    if not args.no_cpu:
+        cpu_pool = mp.get_context("spawn").Pool(1)
+        cpu_job = cpu_pool.apply_async(_oracle_sample, ((args.workload, 0, cpu_frames),))
+
     import torch
 
     from paper_1903_03180_amd import scpl
@@ -464,55 +561,75 @@ def main() -> int:
         log(f"plain: {(p1 - p0) * 1e3 / args.plain_steps:.2f} ms/step, {plain_fps:.1f} frames/s")
 
     if args.copy_calibration > 0:
-        a = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        # kernels of known traffic for scaling the hardware byte counters: a
+        # copy (n read, n written), a sum (n read), a fill (n written)
+        nb = args.copy_calibration << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        log(f"calibration copy: {args.copy_calibration} MiB read and written")
+        total = int(a.view(torch.int32).sum(dtype=torch.int64).item())
+        b.fill_(2)
+        torch.cuda.synchronize()
+        log(f"calibration: copy of {args.copy_calibration} MiB, sum of {args.copy_calibration} MiB "
+            f"(= {total}), fill of {args.copy_calibration} MiB")
         del a, b
 
     # paper-literal algorithmic bytes per step
     balg = balg_bytes(per_job, jobs)
-
-    cpu = None
-    cpu_all = None
-    if not args.no_cpu:
-        import oracle
-        Wt0, k0 = work[0][1], work[0][2]
-        nf = min(args.cpu_frames, clips_np[0].shape[0])
-        c0 = time.perf_counter()
-        oracle.retarget(clips_np[0][:nf], Wt0, k0, mode=1, use_buffer=1, anum=1, aden=5, want_masks=False)
-        c1 = time.perf_counter()
-        cpu = {"value": round(nf / (c1 - c0), 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {nf} frames of the first clip, whole retarget (segmentation and every "
-                         f"iteration of the sample's buffers), {c1 - c0:.1f} s on one core"}
-        log(f"oracle: {nf} frames in {c1 - c0:.1f} s")
-        # all host cores: the same sample of every clip, one process per clip
-        import multiprocessing as mp
-        procs = min(len(clips_np), os.cpu_count() or 1, 16)
-        samples = [(np.ascontiguousarray(w[0][:nf]), w[1], w[2], min(nf, w[0].shape[0])) for w in work[:procs]]
-        with mp.get_context("spawn").Pool(procs) as pool:  # fresh workers: this process uses the GPU
-            pool.map(_oracle_sample, [(samples[0][0][:1], Wt0, k0, 1)] * procs)  # start-up and oracle load
-            c0 = time.perf_counter()
-            done = sum(pool.map(_oracle_sample, samples))
-        c1 = time.perf_counter()
-        cpu_all = {"value": round(done / (c1 - c0), 4), "unit": "frames/s", "cores": procs, "kind": "oracle",
-                   "sample": f"first {nf} frames of each of {procs} clips, one process per clip, {c1 - c0:.1f} s"}
-        log(f"oracle on {procs} cores: {done} frames in {c1 - c0:.1f} s")
+    # HBM bytes a step actually moves, from the committed counter runs
+    step_hbm = None
+    step_rec = measured_step_traffic(args.workload, dpg)
+    if step_rec is not None:
+        gbs = step_rec["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
+        step_hbm = {"source": "rocprofv3 FETCH_SIZE + WRITE_SIZE over every dispatch of a step (calibrated), "
+                              "profiles/" + step_rec["summary"],
+                    "bytes_per_step": step_rec["bytes_per_step"], "GBps": round(gbs, 1),
+                    "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
     table1 = None if args.no_table1 else run_table1(np, torch, scpl, ctx)
     height = None if args.no_height else run_height(torch, ctx, clips_np[0], work[0][1], work[0][2], 2)
 
     serving = None
-    n_clips = len(clips)
+    n_clips = n_clips_all = len(clips)
     shape = {"height": Hmax, "width": Wmax, "target_width": work[0][1], "seams_per_iter": work[0][2]} \
         if len({(c.shape[1:], w, kk) for c, w, kk in work}) == 1 else {"uneven": True}
     if args.serve_requests > 0:
         del clips, clips_np, work
         torch.cuda.empty_cache()
         serving = run_serving(np, torch, scpl, n_req=args.serve_requests)
+
+    # the oracle: its one-core leg has run beside the GPU legs; then every
+    # usable core (up to --cpu-procs), one process per clip on the same
+    # sample of each clip
+    cpu = cpu_all = None
+    if cpu_job is not None:
+        nf, secs = cpu_job.get()
+        cpu_pool.close()
+        cpu_pool.join()
+        where = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": usable_cores()}
+        sample = (f"the first {nf} frames of the first clip of the workload, retargeted whole by the oracle "
+                  f"(segmentation and every iteration of each of the sample's buffers; for the 1080p clips the "
+                  f"workload's first buffer, 60 frames, and the one-frame buffer of the scene cut), "
+                  f"{secs:.1f} s on one core")
+        cpu = {"value": round(nf / secs, 4), "unit": "frames/s", "cores": 1, "kind": "oracle", "sample": sample,
+               **where}
+        log(f"oracle: {nf} frames in {secs:.1f} s on one core ({where['cpu_model']}, nproc {where['nproc']})")
+        procs = max(1, min(args.cpu_procs, usable_cores(), n_clips_all))
+        with mp.get_context("spawn").Pool(procs) as pool:
+            c0 = time.perf_counter()
+            res = pool.map(_oracle_sample, [(args.workload, i, cpu_frames) for i in range(procs)])
+            c1 = time.perf_counter()
+        done = sum(r[0] for r in res)
+        slowest = max(r[1] for r in res)
+        cpu_all = {"value": round(done / slowest, 4), "unit": "frames/s", "cores": procs, "kind": "oracle",
+                   "sample": f"the same sample of each of the first {procs} clips, one process per clip, all "
+                             f"started together: {done} frames; the slowest process's oracle call took "
+                             f"{slowest:.1f} s ({c1 - c0:.1f} s with start-up and clip generation)",
+                   **where}
+        log(f"oracle on {procs} cores: {done} frames, slowest oracle call {slowest:.1f} s")
 
     line = {
         "metric": METRIC,
@@ -541,10 +658,13 @@ def main() -> int:
                      "bytes_per_launch": int(dp_bytes_launch), "launch_ms": round(dp_launch_ms, 4)},
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
-        "effective_hbm": {"accounting": "paper-literal B_alg: input read, output written, colour luma written, "
-                                        "carved luma re-read by every frame of a buffer at every iteration >= 1",
-                          "bytes_per_step": int(balg), "GBps": round(balg / (ms_per_step * 1e-3) / 1e9, 1),
-                          "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "hbm_measured": step_hbm,
+        "paper_literal_bytes": {
+            "accounting": "algorithmic, not measured: input read, output written, colour luma written, and the "
+                          "carved luma re-read by every frame of a buffer at every iteration >= 1 (the full "
+                          "energy recompute the partial refresh never performs)",
+            "bytes_per_step": int(balg), "GBps": round(balg / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "serving": serving,
         "raw_vs_proposed": table1,
         "seam_memorisation": memo,

@@ -1,7 +1,8 @@
 """Host-side pieces of the benchmark: the one-GPU refusal, the split of the
 iteration log into buffers, the algorithmic byte counts behind `roofline`
-and `effective_hbm`, and the rule that pairs a committed counter record
-with the DP it was taken on.  Hand-computed values; no GPU."""
+and `paper_literal_bytes`, the rules that pair a committed counter record
+with the DP (or the step) it was taken on, and the oracle-sample helpers.
+Hand-computed values; no GPU."""
 import json
 import os
 import subprocess
@@ -71,3 +72,34 @@ def test_counter_record_matches_only_its_dp():
     other = dict(g, chunk_cols=g["chunk_cols"] + 4)
     assert bench.measured_dp_traffic("1080p-batch16", other) is None
     assert bench.measured_dp_traffic("4k", g) is None
+
+
+def test_step_record_needs_same_sources_and_geometry(tmp_path, monkeypatch):
+    g = dict(cols_per_lane=4, halo_rows=16, prefetch_rows=8, exclusive_cu=1, chunk_rows=256, chunk_cols=384)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = dict(bytes_per_step=123, dp_geometry=g, sources_sha256=bench.sources_digest(), summary="x.md")
+    (prof / "step_traffic_1080p_batch16.json").write_text(json.dumps(rec))
+    csrc = tmp_path / "paper_1903_03180_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for name in ("scpl_kernels.hip", "scpl_host.hip", "scpl_internal.h", "scpl_runtime.h"):
+        (csrc / name).write_bytes(open(os.path.join(ROOT, "paper_1903_03180_amd", "csrc", name), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_step_traffic("1080p-batch16", g)["bytes_per_step"] == 123
+    assert bench.measured_step_traffic("1080p-batch16", dict(g, chunk_rows=128)) is None
+    assert bench.measured_step_traffic("4k", g) is None
+    (csrc / "scpl_host.hip").write_text("changed")
+    assert bench.measured_step_traffic("1080p-batch16", g) is None
+
+
+def test_workload_clip_matches_make_workload():
+    from paper_1903_03180_amd import synth
+    spec = synth.batch_mix_specs(64)[3]
+    clip, wt, k = bench._workload_clip("mix64", 3)
+    assert clip.shape[:3] == (spec.N, spec.H, spec.W) and wt == spec.Wt and k == 16
+
+
+def test_oracle_sample_times_the_oracle():
+    n, secs = bench._oracle_sample(("mix64", 0, 2))
+    assert n == 2 and secs > 0
+    assert bench.usable_cores() >= 1 and isinstance(bench.cpu_model(), str)
