@@ -107,7 +107,9 @@ typedef struct {
 typedef struct scpl_ctx scpl_ctx;
 
 /* Create a context on HIP device `hip_device`.  The context owns a
- * workspace that grows on demand and is freed by scpl_destroy. */
+ * workspace that grows on demand and is freed by scpl_destroy.  Creation
+ * also allocates the host staging of a call with up to SCPL_MAX_FRAMES
+ * frames (a few MiB of pinned memory) and the events of the plain path. */
 scpl_status scpl_create(int32_t hip_device, scpl_ctx **out);
 void scpl_destroy(scpl_ctx *ctx);
 const char *scpl_status_str(scpl_status s);
@@ -146,6 +148,27 @@ scpl_status scpl_workspace_size(const scpl_params *p, uint64_t *device_bytes);
 scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
                           uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *d_workspace,
                           uint64_t workspace_bytes, void *stream);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): scpl_retarget of
+ * one clip on the plain path, with the same arguments apart from the
+ * workspace and the same results, that allocates nothing.  Its device
+ * workspace is a fixed array of SCPL_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends; its host staging
+ * and events are made by scpl_create.
+ *  - A clip whose workspace (scpl_workspace_size) exceeds
+ *    SCPL_NOALLOC_SCRATCH_BYTES returns SCPL_ERR_CAPACITY and launches
+ *    nothing.  Kernel timing (scpl_profile_enable) makes it return
+ *    SCPL_ERR_INVALID_ARG.
+ *  - Every call on one device, from any context, uses that device's one
+ *    array, which keeps the last call's contents (the call initialises what
+ *    it reads).  Calls whose work overlaps on one device race: issue them on
+ *    one stream, or wait for the previous call's work before the next.
+ *  - Synchronisation as scpl_retarget (the segmentation reads results back
+ *    to the host). */
+#define SCPL_NOALLOC_SCRATCH_BYTES (64u << 20)
+scpl_status scpl_retarget_noalloc(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
+                                  uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream);
 
 /* Many clips at once (the batched path): every buffer of every clip is a job,
  * and each stage of an SCPL iteration runs as one launch over all jobs, the

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -48,6 +49,7 @@ struct scpl_ctx {
     size_t pinned_size = 0;
     bool fixed_ws = false;     // ws / jws / tws point into a caller's region: never grown or freed
     bool fixed_pinned = false; // the host staging is never grown
+    void *scratch = nullptr;   // this device's no-allocation workspace (device address of `scratch`)
     std::vector<int32_t> last_log;
     int nstreams = 3;                    // job groups of the batched path, one stream each
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
@@ -345,6 +347,14 @@ scpl_status prof_drain(scpl_ctx *ctx)
 // Device state of one clip's buffer controller: moments S1, S2 per pixel
 // and the window sums.
 size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8); }
+
+// Host staging of one run of nc clips with Ntot frames in all: window sums,
+// segmentation arguments, buffer ids, job states and the job table.
+size_t pinned_bytes(int nc, int64_t Ntot)
+{
+    return align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) + align_up(16 * (size_t)Ntot) +
+           align_up(sizeof(Job) * (size_t)Ntot) + align_up(sizeof(SegArgs) * (size_t)nc);
+}
 
 // ------------------------------------------------------- height retargeting
 
@@ -859,6 +869,36 @@ int first_batch_iterations(const scpl_params *p)
 
 }  // namespace
 
+// ============================================== no-allocation workspace
+
+// The device workspace of scpl_retarget_noalloc: one array per device,
+// held from the library's load until the process ends.  Host code never
+// passes `scratch` itself to a kernel or a copy (in host code the name is a
+// stand-in, not a device address); scpl_create looks up each device's
+// address once, with that device current, and the calls use that.
+static __device__ __align__(256) unsigned char scratch[SCPL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+scpl_status scratch_address(int dev, void **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxScratchDevices) return SCPL_OK;  // no no-allocation workspace on this device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        SCPL_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return SCPL_OK;
+}
+}  // namespace
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -895,6 +935,18 @@ scpl_status scpl_create(int32_t hip_device, scpl_ctx **out)
     c->lds_cap = prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : prop.sharedMemPerBlock;
     g_lds_cap = c->lds_cap;
     set_kernel_attributes(c->lds_cap);
+    // everything the plain path needs besides its workspace is made here, so
+    // that scpl_retarget_noalloc allocates nothing: the events of one job
+    // group, host staging for the most frames a call may have, and this
+    // device's address of the no-allocation workspace
+    scpl_status st = ensure_side(c);
+    if (st == SCPL_OK) st = ensure_groups(c, 1);
+    if (st == SCPL_OK) st = ensure_pinned(c, pinned_bytes(1, SCPL_MAX_FRAMES));
+    if (st == SCPL_OK) st = scratch_address(hip_device, &c->scratch);
+    if (st != SCPL_OK) {
+        scpl_destroy(c);
+        return st;
+    }
     *out = c;
     return SCPL_OK;
 }
@@ -984,10 +1036,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     }
     a_bytes += align_up(sizeof(SegArgs) * (size_t)nc);
     SCPL_TRY(ensure_ws(ctx, a_bytes));
-    const size_t pin_b = align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) +
-                         align_up(16 * (size_t)Ntot) + align_up(sizeof(Job) * (size_t)Ntot) +
-                         align_up(sizeof(SegArgs) * (size_t)nc);
-    SCPL_TRY(ensure_pinned(ctx, pin_b));
+    SCPL_TRY(ensure_pinned(ctx, pinned_bytes(nc, Ntot)));
     Bump host{static_cast<char *>(ctx->pinned)};
     unsigned long long *h_sums = host.take<unsigned long long>((size_t)nc * kSegWindow);
     SegArgs *h_args = host.take<SegArgs>((size_t)nc);
@@ -1022,7 +1071,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     // built while the segmentation runs, on the last job group's stream (no
     // stream of their own: more streams than hardware queues would share one)
     SCPL_TRY(ensure_side(ctx));
-    SCPL_TRY(ensure_groups(ctx, ctx->nstreams));
+    SCPL_TRY(ensure_groups(ctx, batched ? ctx->nstreams : 1));
     const hipStream_t side = (batched && ctx->nstreams > 1) ? ctx->gstreams[ctx->nstreams - 1] : s;
     SCPL_TRY(hipEventRecord(ctx->side_in, s));
     SCPL_TRY(hipStreamWaitEvent(side, ctx->side_in, 0));
@@ -1288,6 +1337,22 @@ scpl_status scpl_retarget(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_
     scpl_clip c{*p, d_frames, d_out, d_masks, d_buffer_id};
     if (!d_workspace) return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
     FixedArena arena(ctx, d_workspace, plain_layout(*p), false);
+    return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
+}
+
+scpl_status scpl_retarget_noalloc(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_frames, uint8_t *d_out,
+                                  uint16_t *d_masks, int32_t *d_buffer_id, int32_t *h_n_buffers, void *stream)
+{
+    if (!ctx || !d_frames || !d_out) return SCPL_ERR_INVALID_ARG;
+    scpl_status st = validate(p);
+    if (st != SCPL_OK) return st;
+    if (ctx->profiling) return SCPL_ERR_INVALID_ARG;  // kernel timing creates events
+    const PlainLayout L = plain_layout(*p);
+    if (L.total() > SCPL_NOALLOC_SCRATCH_BYTES) return SCPL_ERR_CAPACITY;
+    if (!ctx->scratch || pinned_bytes(1, p->n_frames) > ctx->pinned_size) return SCPL_ERR_INTERNAL;
+    SCPL_TRY(hipSetDevice(ctx->device));
+    scpl_clip c{*p, d_frames, d_out, d_masks, d_buffer_id};
+    FixedArena arena(ctx, ctx->scratch, L, true);
     return run_clips_2d(ctx, &c, 1, false, h_n_buffers, static_cast<hipStream_t>(stream));
 }
 

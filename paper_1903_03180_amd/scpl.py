@@ -31,9 +31,11 @@ SCPL_ERR_NOT_READY = 5
 SCPL_ERR_INTERNAL = 6
 SCPL_ENERGY_GRADIENT = 0
 SCPL_ENERGY_MOTION = 1
+SCPL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
+    "scpl_retarget_noalloc",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_profile_kinds", "scpl_dp_geometry",
     "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_server_create",
@@ -79,6 +81,7 @@ _sig = {
     "scpl_status_str": ([C.c_int], C.c_char_p),
     "scpl_workspace_size": ([C.POINTER(scpl_params), C.POINTER(C.c_uint64)], C.c_int),
     "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P, C.c_uint64, _P], C.c_int),
+    "scpl_retarget_noalloc": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_retarget_batch": ([_P, C.POINTER(scpl_clip), _I32, _P], C.c_int),
     "scpl_last_log": ([_P, _P, _I64, C.POINTER(_I64)], C.c_int),
     "scpl_luma": ([_P, _P, _I64, _P, _P], C.c_int),
@@ -222,6 +225,30 @@ class Context:
         _check(scpl_retarget(self.h, C.byref(cp), _ptr(frames), _ptr(out), _ptr(masks), _ptr(bid), C.byref(nb),
                              _ptr(workspace), wsb, _stream(stream)), "scpl_retarget")
         return dict(out=out, masks=masks, buffer_id=bid, n_buffers=int(nb.value))
+
+    def retarget_noalloc(self, frames, target_width: int, seams_per_iter: int, out=None, masks=None,
+                         buffer_id=None, want_masks: bool = True, stream=None, **kw):
+        """scpl_retarget_noalloc: as retarget(), with the library's fixed
+        device workspace (SCPL_NOALLOC_SCRATCH_BYTES) and no allocation in
+        the call.  out / masks / buffer_id: the caller's output tensors
+        (those left None are allocated here, before the call).
+        Returns dict(out, masks, buffer_id, n_buffers)."""
+        import torch
+        p = params_for(frames, target_width, seams_per_iter, **kw)
+        Ht = p.target_height or p.height
+        shp = (p.n_frames, Ht, p.target_width) + ((p.channels,) if frames.dim() == 4 else ())
+        if out is None:
+            out = torch.empty(shp, dtype=torch.uint8, device=frames.device)
+        both = Ht < p.height and p.target_width < p.width
+        if masks is None and want_masks and not both:
+            masks = torch.empty((p.n_frames, p.height, p.width), dtype=torch.int16, device=frames.device)
+        if buffer_id is None:
+            buffer_id = torch.empty(p.n_frames, dtype=torch.int32, device=frames.device)
+        nb = C.c_int32(0)
+        cp = p.c()
+        _check(scpl_retarget_noalloc(self.h, C.byref(cp), _ptr(frames), _ptr(out), _ptr(masks), _ptr(buffer_id),
+                                     C.byref(nb), _stream(stream)), "scpl_retarget_noalloc")
+        return dict(out=out, masks=masks, buffer_id=buffer_id, n_buffers=int(nb.value))
 
     def retarget_batch(self, clips, stream=None):
         """clips: list of dicts with keys frames (cuda uint8 tensor),
