@@ -1,6 +1,8 @@
 """Request server (continuous batching): every request's result is
-bit-identical alone and inside a mix of uneven clips submitted while others
-are running, and admission follows the device-memory budget."""
+bit-identical alone, inside a mix of uneven clips submitted while others
+are running, and to the oracle; a request joins a lane's table while other
+requests carve and completes when its own buffers are done; a request that
+fails does so alone; admission follows the device-memory budget."""
 import time
 
 import numpy as np
@@ -72,11 +74,73 @@ def test_server_results_alone_and_in_the_mix(ctx, orc):
     finally:
         srv.close()
     # and the solo results are the oracle's
-    for f, s, a in list(zip(frames, MIX, solo))[:3]:
+    for f, s, a in zip(frames, MIX, solo):
         okw = dict(mode=s.get("energy_mode", 1), use_buffer=s.get("use_buffer", 1), anum=s.get("alpha_num", 1),
                    aden=s.get("alpha_den", 5), max_buffer=s.get("max_buffer", 0))
         want = orc.retarget(f, s["Wt"], s["k"], **okw)
         assert np.array_equal(a["out"].cpu().numpy(), want["out"])
+        assert np.array_equal(a["masks"].cpu().numpy().view(np.uint16), want["masks"])
+        assert np.array_equal(a["buffer_id"].cpu().numpy(), want["buffer_id"])
+
+
+def test_small_request_joins_and_leaves_before_a_large_one(ctx, orc):
+    """One lane: a long request (one seam per iteration, 500 iterations)
+    starts carving; a small one submitted while it runs joins the same
+    table between iterations and is done well before the long one.  Both
+    results are the plain path's, the small one also the oracle's."""
+    from paper_1903_03180_amd import scpl
+    big = synth.make_clip(910, 8, 1080, 1920, C=1, n_obj=4, lattice=32)
+    small = make(MIX[0])
+    dbig, dsmall = dev(big), dev(small)
+    solo_big = ctx.retarget(dbig, 1420, 1)
+    torch.cuda.synchronize()
+    srv = scpl.Server(0, lanes=1, max_batch=4)
+    try:
+        tb = srv.submit(dict(frames=dbig, target_width=1420, seams_per_iter=1, want_masks=True))
+        time.sleep(0.02)
+        ts = srv.submit(dict(frames=dsmall, target_width=MIX[0]["Wt"], seams_per_iter=MIX[0]["k"], want_masks=True))
+        rs = srv.wait(ts)
+        done_big, _ = srv.poll(tb)
+        _, tot_s = srv.times(ts)
+        rb = srv.wait(tb)
+        _, tot_b = srv.times(tb)
+    finally:
+        srv.close()
+    assert not done_big  # the small request finished while the long one carved on
+    assert tot_s + 20.0 < tot_b
+    want = orc.retarget(small, MIX[0]["Wt"], MIX[0]["k"])
+    assert np.array_equal(rs["out"].cpu().numpy(), want["out"])
+    assert np.array_equal(rs["masks"].cpu().numpy().view(np.uint16), want["masks"])
+    assert torch.equal(rb["out"], solo_big["out"]) and torch.equal(rb["masks"], solo_big["masks"])
+
+
+def test_failing_request_fails_alone(ctx):
+    """A request that fails at admission (masks asked for a clip carved in
+    both dimensions) reports its error; the requests around it in the same
+    lane are unaffected and bit-identical to their plain results."""
+    from paper_1903_03180_amd import scpl
+    frames = [make(s) for s in MIX[:3]]
+    solo = [ctx.retarget(dev(f), s["Wt"], s["k"], **kwargs(s)) for f, s in zip(frames, MIX)]
+    torch.cuda.synchronize()
+    bad = make(MIX[3])
+    srv = scpl.Server(0, lanes=1, max_batch=8)
+    try:
+        ts = []
+        for i, (f, s) in enumerate(zip(frames, MIX)):
+            ts.append(srv.submit(dict(frames=dev(f), target_width=s["Wt"], seams_per_iter=s["k"], want_masks=True,
+                                      **kwargs(s))))
+            if i == 1:
+                tbad = srv.submit(dict(frames=dev(bad), target_width=MIX[3]["Wt"], target_height=30,
+                                       seams_per_iter=4, want_masks=True))
+        with pytest.raises(scpl.ScplError) as e:
+            srv.wait(tbad)
+        assert e.value.status == scpl.SCPL_ERR_INVALID_ARG
+        for t, a in zip(ts, solo):
+            r = srv.wait(t)
+            assert torch.equal(r["out"], a["out"]) and torch.equal(r["masks"], a["masks"])
+            assert torch.equal(r["buffer_id"], a["buffer_id"])
+    finally:
+        srv.close()
 
 
 def test_server_admission_by_budget(ctx):
