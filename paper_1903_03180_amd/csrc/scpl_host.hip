@@ -1296,7 +1296,10 @@ extern "C" {
 
 const char *scpl_status_str(scpl_status s)
 {
-    switch (s) {
+    // a C caller may pass any int: read it as one, not as the enumeration
+    int v = 0;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
     case SCPL_OK: return "ok";
     case SCPL_ERR_INVALID_ARG: return "invalid argument";
     case SCPL_ERR_OUT_OF_MEMORY: return "out of device memory";
