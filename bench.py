@@ -216,6 +216,45 @@ def run_table1(np, torch, scpl, ctx):
             "inputs": "synthetic RGB clips of each row's size, length and target (seeds 6000-6011)"}
 
 
+def run_mix(np, torch, ctx, steps):
+    """The 64 clips of uneven size (luma, widths 480-2560, heights 360-1440,
+    aspect 1:1-21:9, 30-240 frames, target 3/4 of the width): the batched
+    path (DP autotuned for the mix, graph-replayed steps) and the plain
+    path, frames/s of each."""
+    import time as _t
+    work, desc = make_workload("mix64")
+    n_frames = sum(c.shape[0] for c, _, _ in work)
+    Hmax = max(c.shape[1] for c, _, _ in work)
+    Wmax = max(c.shape[2] for c, _, _ in work)
+    clips = [dict(frames=torch.from_numpy(c).cuda(), target_width=wt, seams_per_iter=kk) for c, wt, kk in work]
+    del work
+    torch.cuda.synchronize()
+    ctx.autotune_dp(Hmax, Wmax, n_jobs=1)
+    dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=256)[4]
+    g = ctx.dp_chosen(Wmax)
+    ctx.retarget_batch(clips)  # warm-up (workspace, graphs)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        ctx.retarget_batch(clips)
+    torch.cuda.synchronize()
+    t1 = _t.perf_counter()
+    fps = n_frames * steps / (t1 - t0)
+    p0 = _t.perf_counter()
+    for c in clips:
+        ctx.retarget(c["frames"], c["target_width"], c["seams_per_iter"], want_masks=False)
+    torch.cuda.synchronize()
+    p1 = _t.perf_counter()
+    plain = n_frames / (p1 - p0)
+    log(f"mix64: batched {fps:.1f} frames/s ({(t1 - t0) * 1e3 / steps:.1f} ms/step), plain {plain:.1f} frames/s, "
+        f"DP {g} ({dpus:.1f} us per DP)")
+    del clips
+    torch.cuda.empty_cache()
+    return {"workload": desc, "frames": n_frames, "steps": steps, "batched_fps": round(fps, 2),
+            "ms_per_step": round((t1 - t0) * 1e3 / steps, 3), "plain_fps": round(plain, 2),
+            "batched_over_plain": round(fps / plain, 3), "dp_geometry": g}
+
+
 def run_height(torch, ctx, clip_np, Wt, k, steps):
     """Horizontal seams (Sec. 3.1, eq. 2, as vertical seams of the transposed frames):
     the workload's first clip carved to 3/4 of its height alone, and to 3/4
@@ -392,6 +431,9 @@ def main() -> int:
     ap.add_argument("--streams", type=int, default=3, help="job groups (streams) of the batched path")
     ap.add_argument("--serve-requests", type=int, default=400, help="requests per arrival rate (0: no serving run)")
     ap.add_argument("--no-table1", action="store_true", help="skip the Proposed-vs-Raw runs on Table 1 shapes")
+    ap.add_argument("--mix-leg", type=int, default=1,
+                    help="also time the 64 clips of uneven size (batched and plain) after the main workload")
+    ap.add_argument("--steps-mix", type=int, default=2, help="timed batched steps of the uneven-mix leg")
     ap.add_argument("--no-height", action="store_true", help="skip the height (horizontal seam) runs")
     ap.add_argument("--cpu-frames", type=int, default=0,
                     help="frames of the oracle's bounded sample (0: 61 for the 1080p workloads, i.e. the first "
@@ -596,9 +638,13 @@ def main() -> int:
     n_clips = n_clips_all = len(clips)
     shape = {"height": Hmax, "width": Wmax, "target_width": work[0][1], "seams_per_iter": work[0][2]} \
         if len({(c.shape[1:], w, kk) for c, w, kk in work}) == 1 else {"uneven": True}
-    if args.serve_requests > 0:
+    mix = None
+    if args.serve_requests > 0 or (args.mix_leg and args.workload != "mix64"):
         del clips, clips_np, work
         torch.cuda.empty_cache()
+    if args.mix_leg and args.workload != "mix64":
+        mix = run_mix(np, torch, ctx, args.steps_mix)
+    if args.serve_requests > 0:
         serving = run_serving(np, torch, scpl, n_req=args.serve_requests)
 
     # the oracle: its one-core leg has run beside the GPU legs; then every
@@ -665,6 +711,7 @@ def main() -> int:
                           "energy recompute the partial refresh never performs)",
             "bytes_per_step": int(balg), "GBps": round(balg / (ms_per_step * 1e-3) / 1e9, 1),
             "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "mix64": mix,
         "serving": serving,
         "raw_vs_proposed": table1,
         "seam_memorisation": memo,
