@@ -604,7 +604,9 @@ def main() -> int:
 
     if args.copy_calibration > 0:
         # kernels of known traffic for scaling the hardware byte counters: a
-        # copy (n read, n written), a sum (n read), a fill (n written)
+        # copy (n read, n written); a sum of the int32 view into int64, which
+        # torch runs as a conversion (n read, 2n written) and a reduction (2n
+        # read); a fill (n written)
         nb = args.copy_calibration << 20
         a = torch.empty(nb, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -621,6 +623,15 @@ def main() -> int:
 
     # paper-literal algorithmic bytes per step
     balg = balg_bytes(per_job, jobs)
+    # VALU busy per kernel, from the committed counter run (same sources)
+    valu_busy = None
+    vpath = os.path.join(ROOT, "profiles", f"valu_busy_{args.workload.replace('-', '_')}.json")
+    if os.path.exists(vpath):
+        with open(vpath) as f:
+            vrec = json.load(f)
+        if vrec.get("sources_sha256") == sources_digest():
+            valu_busy = {"source": "rocprofv3 VALUBusy per dispatch (each dispatch alone), profiles/" +
+                                   vrec["summary"], "per_kernel": vrec["valu_busy"]}
     # HBM bytes a step actually moves, from the committed counter runs
     step_hbm = None
     step_rec = measured_step_traffic(args.workload, dpg)
@@ -705,6 +716,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "hbm_measured": step_hbm,
+        "valu_busy": valu_busy,
         "paper_literal_bytes": {
             "accounting": "algorithmic, not measured: input read, output written, colour luma written, and the "
                           "carved luma re-read by every frame of a buffer at every iteration >= 1 (the full "
