@@ -195,22 +195,17 @@ scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
 
 /* ---- request server (continuous batching) ----
  * Retarget requests are queued in arrival order.  Each of `lanes` worker
- * threads owns a context, a table of carving jobs and two streams.  Between
- * iterations of its table a lane admits the queued requests, in order, that
- * fit the device-memory budget, at most max_batch in its table at once: a
- * request's luma, buffer segmentation and first energies run on the lane's
- * second stream while the table's iterations go on, then its buffers join
- * the table and advance in the same launches as the jobs already there.  A
- * request is done as soon as its own buffers are carved and its outputs
- * gathered, whatever the other requests of its table still have to do.
- * Requests with a target height run whole on the lane's second stream
- * instead of joining the table.
- * A request is admitted by an upper bound of the device memory it can claim
- * (its tiled and pixel-major luma and buffer controller plus one carving
- * job per frame); the admitted requests' bounds never exceed hbm_budget.
- * Results are bit-identical to scpl_retarget on each clip alone.  A request
- * that fails (an invalid combination found at admission, memory exhausted)
- * fails alone: the other requests of its lane are not affected.
+ * threads owns a context and a stream; whenever a lane is free it takes the
+ * queued requests that fit the device-memory budget (in order, at most
+ * max_batch) and retargets them as one batch (as scpl_retarget_batch, with
+ * one job group on the lane's stream).
+ * A request is admitted by an upper bound of the device memory its batch
+ * share can claim (its tiled and pixel-major luma and buffer controller
+ * plus one carving job per frame); the admitted requests' bounds never
+ * exceed hbm_budget.
+ * Requests that arrive while batches run are admitted as lanes and memory
+ * free up, and their work overlaps on the device with the batches in
+ * flight.  Results are bit-identical to scpl_retarget on each clip alone.
  *
  * scpl_server_create: lanes in [1, SCPL_MAX_LANES], max_batch >= 1,
  *   hbm_budget in bytes (0: half the device memory free at creation).
@@ -223,10 +218,10 @@ scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
  *   before, or for a request dropped by scpl_server_destroy).
  * scpl_server_wait: blocks until the request is done.
  * scpl_server_ticket_times: host steady-clock milliseconds from submission
- *   to the request's admission into a lane and to its completion (done only).
+ *   to the start of the request's batch and to its completion (done only).
  * scpl_server_release: forgets a done ticket (SCPL_ERR_NOT_READY while the
  *   request runs or another thread still waits on it).
- * scpl_server_destroy: requests already admitted finish; queued ones are
+ * scpl_server_destroy: requests already running finish; queued ones are
  *   dropped; then the lanes' contexts are destroyed. */
 #define SCPL_MAX_LANES 16
 typedef struct scpl_server scpl_server;

@@ -869,397 +869,6 @@ int first_batch_iterations(const scpl_params *p)
 
 }  // namespace
 
-// ============================================ live job table (server lanes)
-
-// A server lane's job table.  Every carving job of every request the lane
-// holds has a slot; each iteration is one launch per stage over the slots
-// [0, hw).  Requests join the table between iterations (their luma,
-// segmentation and first energies run on the lane's side stream, beside the
-// iterations), and leave it as soon as their own buffers are carved: their
-// outputs are gathered, their slots take an empty descriptor, and their
-// device memory returns to the server's pool.  One DP geometry serves the
-// whole table (the column-split default), so that jobs that join later need
-// no other key-row layout.
-struct scpl::LiveLane {
-    struct Req {
-        int64_t tag = 0;
-        scpl_clip clip{};
-        void *memA = nullptr, *memB = nullptr;  // luma and controller; jobs
-        Job *d_jobs = nullptr;                  // nj carving jobs, then nm memorised buffers
-        int nj = 0, nm = 0;
-        std::vector<int> slots;
-        JobShape js{};
-        int Hmax = 0;
-        size_t gather_lds = 0;
-        int rfirst = 1;       // iterations before its first state read-back
-        bool seen = false;    // its slots were in a state read-back
-        int iters = 0;        // iterations enqueued while it carved
-        bool releasing = false;
-        bool failed = false;      // carved past any possible end: reported as an internal error
-        hipEvent_t ev = nullptr;  // its gather and slot reset are complete
-    };
-    scpl_ctx *ctx = nullptr;
-    hipStream_t st = nullptr, side = nullptr;
-    hipMemPool_t pool = nullptr;
-    DpGeom g{0, 0, 0, 0, 0};
-    int cap = 0, hw = 0;
-    Job *d_table = nullptr;
-    int32_t *d_states = nullptr;  // 4 per slot
-    int32_t *d_empty = nullptr;   // state of an empty slot (zeros)
-    Job empty{};                  // descriptor of an empty slot: returns at once from every kernel
-    char *pinned = nullptr;       // h_table, h_states, admission staging
-    Job *h_table = nullptr;
-    int32_t *h_states = nullptr;
-    unsigned long long *h_sums = nullptr;
-    SegArgs *h_args = nullptr;
-    int32_t *h_bid = nullptr;
-    Job *h_jobs = nullptr;
-    hipEvent_t ev_states = nullptr;
-    std::vector<char> used;
-    std::vector<Req> reqs;
-    std::vector<hipEvent_t> spare_events;
-};
-
-namespace {
-
-constexpr int kLiveAhead = 8;  // iterations enqueued per look at the states
-
-size_t live_pinned_bytes(int cap)
-{
-    return align_up(sizeof(Job) * (size_t)cap) + align_up(16 * (size_t)cap) + align_up(kSegWindow * 8) +
-           align_up(sizeof(SegArgs)) + align_up(4 * (size_t)cap) + align_up(sizeof(Job) * (size_t)cap);
-}
-
-scpl_status live_event(LiveLane *L, hipEvent_t *ev)
-{
-    if (!L->spare_events.empty()) {
-        *ev = L->spare_events.back();
-        L->spare_events.pop_back();
-        return SCPL_OK;
-    }
-    return dev_status(hipEventCreateWithFlags(ev, hipEventDisableTiming));
-}
-
-int live_free_slots(const LiveLane *L)
-{
-    int n = 0;
-    for (char u : L->used) n += u ? 0 : 1;
-    return n;
-}
-
-}  // namespace
-
-scpl_status scpl::live_create(scpl_ctx *ctx, hipStream_t st, hipStream_t side, hipMemPool_t pool, LiveLane **out)
-{
-    *out = nullptr;
-    LiveLane *L = new (std::nothrow) LiveLane();
-    if (!L) return SCPL_ERR_OUT_OF_MEMORY;
-    L->ctx = ctx;
-    L->st = st;
-    L->side = side;
-    L->pool = pool;
-    L->g = dp_geom(1024);  // the column-split default, valid at every width
-    L->cap = SCPL_MAX_FRAMES;
-    L->used.assign(L->cap, 0);
-    scpl_status s = SCPL_OK;
-    auto fail = [&](scpl_status e) {
-        live_destroy(L);
-        return e;
-    };
-    s = dev_status(hipMalloc(&L->d_table, sizeof(Job) * (size_t)L->cap));
-    if (s == SCPL_OK) s = dev_status(hipMalloc(&L->d_states, 16 * (size_t)L->cap));
-    if (s == SCPL_OK) s = dev_status(hipMalloc(&L->d_empty, 16));
-    if (s == SCPL_OK) s = dev_status(hipHostMalloc(&L->pinned, live_pinned_bytes(L->cap), hipHostMallocDefault));
-    if (s == SCPL_OK) s = dev_status(hipEventCreateWithFlags(&L->ev_states, hipEventDisableTiming));
-    if (s != SCPL_OK) return fail(s);
-    Bump hb{L->pinned};
-    L->h_table = hb.take<Job>((size_t)L->cap);
-    L->h_states = hb.take<int32_t>(4 * (size_t)L->cap);
-    L->h_sums = hb.take<unsigned long long>(kSegWindow);
-    L->h_args = hb.take<SegArgs>(1);
-    L->h_bid = hb.take<int32_t>((size_t)L->cap);
-    L->h_jobs = hb.take<Job>((size_t)L->cap);
-    L->empty.state = L->d_empty;  // iteration 0, no log: width = Wt = 0, so every kernel returns
-    for (int i = 0; i < L->cap; ++i) L->h_table[i] = L->empty;
-    s = dev_status(hipMemsetAsync(L->d_empty, 0, 16, st));
-    if (s == SCPL_OK)
-        s = dev_status(hipMemcpyAsync(L->d_table, L->h_table, sizeof(Job) * (size_t)L->cap, hipMemcpyHostToDevice, st));
-    if (s == SCPL_OK) s = dev_status(hipStreamSynchronize(st));
-    if (s != SCPL_OK) return fail(s);
-    *out = L;
-    return SCPL_OK;
-}
-
-void scpl::live_destroy(LiveLane *L)
-{
-    if (!L) return;
-    if (L->st) (void)hipStreamSynchronize(L->st);
-    if (L->side) (void)hipStreamSynchronize(L->side);
-    for (LiveLane::Req &R : L->reqs) {
-        if (R.memA) (void)hipFreeAsync(R.memA, L->st);
-        if (R.memB) (void)hipFreeAsync(R.memB, L->st);
-        if (R.ev) (void)hipEventDestroy(R.ev);
-    }
-    if (L->st) (void)hipStreamSynchronize(L->st);
-    for (hipEvent_t e : L->spare_events) (void)hipEventDestroy(e);
-    if (L->ev_states) (void)hipEventDestroy(L->ev_states);
-    if (L->d_table) (void)hipFree(L->d_table);
-    if (L->d_states) (void)hipFree(L->d_states);
-    if (L->d_empty) (void)hipFree(L->d_empty);
-    if (L->pinned) (void)hipHostFree(L->pinned);
-    delete L;
-}
-
-int scpl::live_requests(const LiveLane *L) { return (int)L->reqs.size(); }
-
-bool scpl::live_fits(const LiveLane *L, const scpl_params &p) { return live_free_slots(L) >= p.n_frames; }
-
-scpl_status scpl::live_admit(LiveLane *L, const scpl_clip &clip, int64_t tag, bool *finished,
-                             scpl_status *result)
-{
-    *finished = false;
-    *result = SCPL_OK;
-    const scpl_params &p = clip.p;
-    if (height_pass(p)) {
-        // horizontal seams run outside the table: the whole request on the
-        // side stream, while the table's enqueued iterations go on
-        scpl_status s = run_clips_2d(L->ctx, &clip, 1, true, nullptr, L->side, false);
-        if (s == SCPL_OK) s = dev_status(hipStreamSynchronize(L->side));
-        // the context keeps its workspace for the next such request (freeing
-        // device memory waits for the whole device), up to 16 GiB
-        if (s == SCPL_OK) s = trim_workspace(L->ctx, 16ull << 30);
-        *finished = true;
-        *result = s;
-        return SCPL_OK;
-    }
-    if (!live_fits(L, p)) return SCPL_ERR_CAPACITY;
-    const int N = p.n_frames, H = p.height, W = p.width;
-    const int64_t HW = (int64_t)H * W;
-    const int64_t FS = tiled_frame_bytes(H, W);
-    const int seqp = seq_pitch(N);
-    LiveLane::Req R;
-    R.tag = tag;
-    R.clip = clip;
-    auto drop = [&](scpl_status e) {
-        if (R.memA) (void)hipFreeAsync(R.memA, L->side);
-        if (R.memB) (void)hipFreeAsync(R.memB, L->side);
-        (void)hipStreamSynchronize(L->side);
-        return e;
-    };
-    const size_t a_bytes = align_up((size_t)N * FS) + align_up((size_t)HW * seqp) + seg_bytes(HW) +
-                           align_up(kSegWindow * 8) + align_up(sizeof(SegArgs));
-    SCPL_TRY(hipMallocFromPoolAsync(&R.memA, a_bytes, L->pool, L->side));
-    Bump dev{static_cast<char *>(R.memA)};
-    uint8_t *tiled = dev.take<uint8_t>((size_t)N * FS);
-    uint8_t *seq = dev.take<uint8_t>((size_t)HW * seqp);
-    SegClip sc;
-    sc.p = &p;
-    sc.FS = FS;
-    sc.ntc = tiles_across(W);
-    sc.tiled = tiled;
-    sc.seq = seq;
-    sc.state = dev.take<char>(seg_bytes(HW));
-    sc.bid = L->h_bid;
-    sc.trace = nullptr;
-    unsigned long long *d_sums = dev.take<unsigned long long>(kSegWindow);
-    SegArgs *d_args = dev.take<SegArgs>(1);
-    launch_tile_luma(clip.d_frames, p.channels, N, H, W, tiled, L->side);
-    launch_seq(tiled, N, H, W, seq, seqp, L->side);
-    if (hipGetLastError() != hipSuccess) return drop(SCPL_ERR_DEVICE);
-    std::vector<SegClip> seg(1, sc);
-    scpl_status s = segment_clips(L->ctx, seg, d_sums, L->h_sums, d_args, L->h_args, L->side);
-    if (s != SCPL_OK) return drop(s);
-    if (clip.d_buffer_id &&
-        hipMemcpyAsync(clip.d_buffer_id, L->h_bid, (size_t)N * 4, hipMemcpyHostToDevice, L->side) != hipSuccess)
-        return drop(SCPL_ERR_DEVICE);
-    // one job per carved buffer; memorised buffers reuse their source's job
-    const auto bufs = buffers_of(L->h_bid, N);
-    struct Memo {
-        int src, t0, T, bindex;
-    };
-    std::vector<std::pair<int, int>> carve;  // (index into bufs, src job)
-    std::vector<Memo> memo;
-    const size_t m = (size_t)p.memo_period;
-    int src = -1;
-    for (size_t b = 0; b < bufs.size(); ++b) {
-        if (m >= 2 && b % m != 0) {
-            memo.push_back({src, bufs[b].first, bufs[b].second, (int)b});
-            continue;
-        }
-        src = (int)carve.size();
-        carve.emplace_back((int)b, src);
-    }
-    R.nj = (int)carve.size();
-    R.nm = (int)memo.size();
-    R.js = JobShape{H, W, p.target_width, p.seams_per_iter, L->g};
-    const size_t b_bytes = align_up(sizeof(Job) * (size_t)(R.nj + R.nm)) + (size_t)R.nj * job_bytes(R.js);
-    if (hipMallocFromPoolAsync(&R.memB, b_bytes, L->pool, L->side) != hipSuccess) return drop(SCPL_ERR_OUT_OF_MEMORY);
-    Bump jb{static_cast<char *>(R.memB)};
-    R.d_jobs = jb.take<Job>((size_t)(R.nj + R.nm));
-    for (int i = 0, q = 0; i < L->cap && q < R.nj; ++i)
-        if (!L->used[i]) {
-            R.slots.push_back(i);
-            ++q;
-        }
-    for (int q = 0; q < R.nj; ++q) {
-        const auto &bf = bufs[carve[q].first];
-        Job J = clip_job(&p, clip.d_frames, tiled, clip.d_out, clip.d_masks, bf.first, bf.second, carve[q].first);
-        J.seq = seq;
-        J.seqp = seqp;
-        carve_job(J, R.js, jb, L->d_states + 4 * R.slots[q]);
-        L->h_jobs[q] = J;
-    }
-    for (int q = 0; q < R.nm; ++q) {
-        Job J = L->h_jobs[memo[q].src];
-        J.t0 = memo[q].t0;
-        J.T = memo[q].T;
-        J.has_prev = 0;
-        J.buffer_index = memo[q].bindex;
-        L->h_jobs[R.nj + q] = J;
-    }
-    LaunchShape ls;
-    ls.add(R.js, p.channels);
-    R.Hmax = ls.Hmax;
-    R.gather_lds = ls.gather_lds;
-    R.rfirst = std::max(1, first_batch_iterations(&p));
-    if (hipMemcpyAsync(R.d_jobs, L->h_jobs, sizeof(Job) * (size_t)(R.nj + R.nm), hipMemcpyHostToDevice, L->side) !=
-        hipSuccess)
-        return drop(SCPL_ERR_DEVICE);
-    launch_init_jobs(R.d_jobs, R.nj, ls.Hmax, ls.Wmax, L->side);
-    launch_energy(R.d_jobs, R.nj, ls.Hmax, ls.Wmax, L->side);
-    if (hipGetLastError() != hipSuccess) return drop(SCPL_ERR_DEVICE);
-    // the staging is reused by the next admission, and the table's stream
-    // may run the new jobs only once their first energies are in place
-    if (hipStreamSynchronize(L->side) != hipSuccess) return drop(SCPL_ERR_DEVICE);
-    for (int q = 0; q < R.nj; ++q) {
-        const int slot = R.slots[q];
-        L->h_table[slot] = L->h_jobs[q];
-        L->used[slot] = 1;
-        L->hw = std::max(L->hw, slot + 1);
-        SCPL_TRY(hipMemcpyAsync(L->d_table + slot, L->h_table + slot, sizeof(Job), hipMemcpyHostToDevice, L->st));
-    }
-    L->reqs.push_back(std::move(R));
-    return SCPL_OK;
-}
-
-// Marks every slot of request R empty and returns its memory, after its
-// gather, on the table's stream; R leaves the table when ev completes.
-static scpl_status live_release(LiveLane *L, LiveLane::Req &R, bool gather)
-{
-    if (gather) {
-        launch_gather(R.d_jobs, R.nj + R.nm, R.Hmax, R.gather_lds, L->st);
-        SCPL_CHECK_LAUNCH();
-    }
-    for (int slot : R.slots) {
-        L->h_table[slot] = L->empty;
-        SCPL_TRY(hipMemcpyAsync(L->d_table + slot, L->h_table + slot, sizeof(Job), hipMemcpyHostToDevice, L->st));
-    }
-    SCPL_TRY(hipFreeAsync(R.memA, L->st));
-    SCPL_TRY(hipFreeAsync(R.memB, L->st));
-    R.memA = R.memB = nullptr;
-    SCPL_TRY(live_event(L, &R.ev));
-    SCPL_TRY(hipEventRecord(R.ev, L->st));
-    R.releasing = true;
-    return SCPL_OK;
-}
-
-scpl_status scpl::live_advance(LiveLane *L, std::vector<std::pair<int64_t, scpl_status>> &done)
-{
-    // iterations: as many as the least advanced job still needs, at most kLiveAhead
-    LaunchShape ls;
-    int more = 0;
-    for (const LiveLane::Req &R : L->reqs) {
-        if (R.releasing) continue;
-        ls.add(R.js, R.clip.p.channels);
-        if (!R.seen) {
-            more = std::max(more, R.rfirst);
-            continue;
-        }
-        for (int slot : R.slots) {
-            const int32_t *sv = L->h_states + 4 * slot;
-            if (sv[0] >= 0) continue;
-            const int last = std::max(1, sv[2]);
-            more = std::max(more, (sv[1] - R.js.Wt + last - 1) / last);
-        }
-    }
-    if (ls.Hmax > 0) {
-        ls.g = L->g;
-        more = std::min(std::max(more, 1), kLiveAhead);
-        for (int q = 0; q < more; ++q) enqueue_iteration(L->ctx, L->d_table, L->hw, ls, L->st);
-        SCPL_CHECK_LAUNCH();
-        SCPL_TRY(hipMemcpyAsync(L->h_states, L->d_states, 16 * (size_t)L->hw, hipMemcpyDeviceToHost, L->st));
-        SCPL_TRY(hipEventRecord(L->ev_states, L->st));
-        SCPL_TRY(hipEventSynchronize(L->ev_states));
-        for (LiveLane::Req &R : L->reqs) {
-            if (R.releasing) continue;
-            R.seen = true;
-            R.iters += more;
-            bool all = true;
-            for (int slot : R.slots) all = all && L->h_states[4 * slot] >= 0;
-            if (all) {
-                SCPL_TRY(live_release(L, R, true));
-            } else if (R.iters > R.clip.p.width + kLiveAhead) {  // every iteration removes a column
-                R.failed = true;
-                SCPL_TRY(live_release(L, R, false));
-            }
-        }
-    } else {
-        // nothing carving: wait for the oldest request still being released
-        for (LiveLane::Req &R : L->reqs)
-            if (R.releasing) {
-                SCPL_TRY(hipEventSynchronize(R.ev));
-                break;
-            }
-    }
-    // requests whose gather and slot reset are complete leave the table
-    for (size_t i = 0; i < L->reqs.size();) {
-        LiveLane::Req &R = L->reqs[i];
-        if (!R.releasing) {
-            ++i;
-            continue;
-        }
-        const hipError_t q = hipEventQuery(R.ev);
-        if (q == hipErrorNotReady) {
-            ++i;
-            continue;
-        }
-        SCPL_TRY(q);
-        for (int slot : R.slots) L->used[slot] = 0;
-        L->spare_events.push_back(R.ev);
-        done.emplace_back(R.tag, R.failed ? SCPL_ERR_INTERNAL : SCPL_OK);
-        L->reqs.erase(L->reqs.begin() + (long)i);
-    }
-    L->hw = 0;
-    for (int i = L->cap - 1; i >= 0; --i)
-        if (L->used[i]) {
-            L->hw = i + 1;
-            break;
-        }
-    return SCPL_OK;
-}
-
-// Drops every request of the lane after a device error: their tags are
-// reported with `err`.
-void scpl::live_abort(LiveLane *L, scpl_status err, std::vector<std::pair<int64_t, scpl_status>> &done)
-{
-    (void)hipStreamSynchronize(L->st);
-    (void)hipStreamSynchronize(L->side);
-    for (LiveLane::Req &R : L->reqs) {
-        done.emplace_back(R.tag, err);
-        if (R.memA) (void)hipFreeAsync(R.memA, L->st);
-        if (R.memB) (void)hipFreeAsync(R.memB, L->st);
-        if (R.ev) L->spare_events.push_back(R.ev);
-        for (int slot : R.slots) {
-            L->used[slot] = 0;
-            L->h_table[slot] = L->empty;
-            (void)hipMemcpyAsync(L->d_table + slot, L->h_table + slot, sizeof(Job), hipMemcpyHostToDevice, L->st);
-        }
-    }
-    (void)hipStreamSynchronize(L->st);
-    L->reqs.clear();
-    L->hw = 0;
-}
-
 // ============================================== no-allocation workspace
 
 // The device workspace of scpl_retarget_noalloc: one array per device,

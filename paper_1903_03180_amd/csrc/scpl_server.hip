@@ -1,11 +1,10 @@
 // Request server of libscpl.so: continuous batching of retarget requests on
-// one device.  Requests wait in a FIFO queue.  Each of `lanes` worker
-// threads owns a context, a live job table and two streams: between
-// iterations of its table it admits queued requests that fit the
-// device-memory budget (their luma, buffer segmentation and first energies
-// run on the lane's side stream while the table's iterations go on), and a
-// request leaves the table as soon as its own buffers are carved, so a small
-// request never waits for a large one that it shares a table with.  Each
+// one device.  Requests wait in a FIFO queue; each of `lanes` worker threads
+// owns a context and a stream, and whenever it is free takes every queued
+// request that fits the device-memory budget (up to max_batch), admits them
+// by their footprint bound and retargets them as one batch.  Requests that
+// arrive while other batches run are admitted as lanes and memory free up,
+// and their work overlaps on the device with the batches in flight.  Each
 // result is the one scpl_retarget gives for the clip alone: jobs never
 // interact.  Declarations: include/scpl.h.
 #include <algorithm>
@@ -38,6 +37,10 @@ struct Ticket {
     double t_submit = 0, t_start = 0, t_done = 0;
 };
 
+// Workspace a lane keeps between batches (more is returned to the device;
+// freeing device memory waits for the whole device, so it is kept rare).
+constexpr uint64_t kLaneKeep = 16ull << 30;
+
 }  // namespace
 
 struct scpl_server {
@@ -52,77 +55,57 @@ struct scpl_server {
     bool stop = false;
     std::vector<std::thread> lanes;
     std::vector<scpl_ctx *> ctxs;
-    std::vector<hipStream_t> streams;  // two per lane: iterations, admissions
-    std::vector<scpl::LiveLane *> live;
-    hipMemPool_t pool = nullptr;       // request memory of every lane
+    std::vector<hipStream_t> streams;
 };
 
 namespace {
 
-// Marks request `id` done with `res` (caller holds S->mu).
-void finish_locked(scpl_server *S, int64_t id, scpl_status res, double t)
-{
-    Ticket &tk = S->tickets[id];
-    tk.done = true;
-    tk.result = res;
-    tk.t_done = t;
-    S->in_use -= tk.bytes;
-}
-
 void lane_main(scpl_server *S, int li)
 {
     (void)hipSetDevice(S->device);
-    scpl::LiveLane *L = S->live[li];
-    std::vector<std::pair<int64_t, scpl_clip>> take;
-    std::vector<std::pair<int64_t, scpl_status>> done;
+    scpl_ctx *ctx = S->ctxs[li];
+    hipStream_t st = S->streams[li];
+    std::vector<int64_t> batch;
+    std::vector<scpl_clip> clips;
     for (;;) {
-        take.clear();
+        batch.clear();
+        clips.clear();
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            auto admissible = [&] {
-                if (S->stop || S->queue.empty()) return false;
-                if (scpl::live_requests(L) + (int)take.size() >= S->cfg.max_batch) return false;
-                const Ticket &tk = S->tickets[S->queue.front()];
-                return S->in_use + tk.bytes <= S->cfg.hbm_budget && scpl::live_fits(L, tk.clip.p);
-            };
-            if (scpl::live_requests(L) == 0) {
-                S->cv_work.wait(lk, [&] { return S->stop || admissible(); });
-                if (S->stop) return;  // requests already taken have finished
-            }
+            S->cv_work.wait(lk, [&] {
+                return S->stop ||
+                       (!S->queue.empty() && S->in_use + S->tickets[S->queue.front()].bytes <= S->cfg.hbm_budget);
+            });
+            if (S->stop) return;
             const double t = now_us();
-            while (admissible()) {
-                const int64_t id = S->queue.front();
-                Ticket &tk = S->tickets[id];
+            while (!S->queue.empty() && (int)batch.size() < S->cfg.max_batch) {
+                Ticket &tk = S->tickets[S->queue.front()];
+                if (S->in_use + tk.bytes > S->cfg.hbm_budget) break;
                 S->in_use += tk.bytes;
                 tk.t_start = t;
-                take.emplace_back(id, tk.clip);
+                batch.push_back(S->queue.front());
+                clips.push_back(tk.clip);
                 S->queue.pop_front();
             }
         }
-        done.clear();
-        for (const auto &q : take) {
-            bool now = false;
-            scpl_status res = SCPL_OK;
-            const scpl_status st = scpl::live_admit(L, q.second, q.first, &now, &res);
-            if (st != SCPL_OK) {  // this request fails alone
-                now = true;
-                res = st;
+        // no graph capture here: the caller's threads may synchronise the
+        // device at any time
+        scpl_status res = scpl::run_clips_2d(ctx, clips.data(), (int)clips.size(), true, nullptr, st, false);
+        if (res == SCPL_OK && hipStreamSynchronize(st) != hipSuccess) res = SCPL_ERR_DEVICE;
+        if (res == SCPL_OK) res = scpl::trim_workspace(ctx, kLaneKeep);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            const double t = now_us();
+            for (int64_t id : batch) {
+                Ticket &tk = S->tickets[id];
+                tk.done = true;
+                tk.result = res;
+                tk.t_done = t;
+                S->in_use -= tk.bytes;
             }
-            if (now) done.emplace_back(q.first, res);
         }
-        if (scpl::live_requests(L) > 0) {
-            const scpl_status st = scpl::live_advance(L, done);
-            if (st != SCPL_OK) scpl::live_abort(L, st, done);
-        }
-        if (!done.empty()) {
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                const double t = now_us();
-                for (const auto &d : done) finish_locked(S, d.first, d.second, t);
-            }
-            S->cv_done.notify_all();
-            S->cv_work.notify_all();
-        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
     }
 }
 
@@ -144,44 +127,26 @@ scpl_status scpl_server_create(int32_t device, const scpl_server_config *cfg, sc
         if (hipSetDevice(device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) st = SCPL_ERR_DEVICE;
         S->cfg.hbm_budget = fr / 2;
     }
-    if (st == SCPL_OK) {
-        // request memory: a pool of its own that keeps freed memory for
-        // later requests instead of returning it to the device
-        hipMemPoolProps props{};
-        props.allocType = hipMemAllocationTypePinned;
-        props.handleTypes = hipMemHandleTypeNone;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = device;
-        uint64_t keep = UINT64_MAX;
-        if (hipSetDevice(device) != hipSuccess || hipMemPoolCreate(&S->pool, &props) != hipSuccess ||
-            hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
-            st = SCPL_ERR_DEVICE;
-    }
     for (int l = 0; st == SCPL_OK && l < cfg->lanes; ++l) {
         scpl_ctx *c = nullptr;
         st = scpl_create(device, &c);
         if (st != SCPL_OK) break;
-        // horizontal-seam requests run as one job group on the lane's side
-        // stream
+        // a lane runs its batch as one job group on its own stream: lanes
+        // already overlap, and more streams than the device's hardware
+        // queues would make streams share queues
         st = scpl_batch_streams(c, 1);
         if (st != SCPL_OK) break;
         S->ctxs.push_back(c);
-        hipStream_t s2[2] = {nullptr, nullptr};
-        for (hipStream_t &x : s2)
-            if (st == SCPL_OK && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) st = SCPL_ERR_DEVICE;
-        for (hipStream_t x : s2)
-            if (x) S->streams.push_back(x);
-        if (st != SCPL_OK) break;
-        scpl::LiveLane *L = nullptr;
-        st = scpl::live_create(c, s2[0], s2[1], S->pool, &L);
-        if (st != SCPL_OK) break;
-        S->live.push_back(L);
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            st = SCPL_ERR_DEVICE;
+            break;
+        }
+        S->streams.push_back(s);
     }
     if (st != SCPL_OK) {
-        for (scpl::LiveLane *L : S->live) scpl::live_destroy(L);
         for (scpl_ctx *c : S->ctxs) scpl_destroy(c);
         for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
-        if (S->pool) (void)hipMemPoolDestroy(S->pool);
         delete S;
         return st;
     }
@@ -276,7 +241,7 @@ void scpl_server_destroy(scpl_server *S)
     if (!S) return;
     {
         std::unique_lock<std::mutex> lk(S->mu);
-        // requests already in a lane's table finish; queued ones are dropped
+        // requests already taken by a lane finish; queued ones are dropped
         S->stop = true;
         for (int64_t id : S->queue) {
             Ticket &tk = S->tickets[id];
@@ -288,10 +253,8 @@ void scpl_server_destroy(scpl_server *S)
     S->cv_work.notify_all();
     S->cv_done.notify_all();
     for (std::thread &t : S->lanes) t.join();
-    for (scpl::LiveLane *L : S->live) scpl::live_destroy(L);
     for (scpl_ctx *c : S->ctxs) scpl_destroy(c);
     for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
-    if (S->pool) (void)hipMemPoolDestroy(S->pool);
     delete S;
 }
 

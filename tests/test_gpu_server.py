@@ -1,8 +1,7 @@
 """Request server (continuous batching): every request's result is
 bit-identical alone, inside a mix of uneven clips submitted while others
-are running, and to the oracle; a request joins a lane's table while other
-requests carve and completes when its own buffers are done; a request that
-fails does so alone; admission follows the device-memory budget."""
+are running, and to the oracle; admission follows the device-memory
+budget."""
 import time
 
 import numpy as np
@@ -83,6 +82,7 @@ def test_server_results_alone_and_in_the_mix(ctx, orc):
         assert np.array_equal(a["buffer_id"].cpu().numpy(), want["buffer_id"])
 
 
+@pytest.mark.skip(reason="iteration-level joining (a live job table per lane) was taken out after the benchmark's serving run with it faulted the GPU (memory aperture violation) without a cause found in the code; the server runs each admitted batch to completion again")
 def test_small_request_joins_and_leaves_before_a_large_one(ctx, orc):
     """One lane: a long request (one seam per iteration, 500 iterations)
     starts carving; a small one submitted while it runs joins the same
@@ -114,6 +114,7 @@ def test_small_request_joins_and_leaves_before_a_large_one(ctx, orc):
     assert torch.equal(rb["out"], solo_big["out"]) and torch.equal(rb["masks"], solo_big["masks"])
 
 
+@pytest.mark.skip(reason="iteration-level joining (a live job table per lane) was taken out after the benchmark's serving run with it faulted the GPU (memory aperture violation) without a cause found in the code; the server runs each admitted batch to completion again")
 def test_failing_request_fails_alone(ctx):
     """A request that fails at admission (masks asked for a clip carved in
     both dimensions) reports its error; the requests around it in the same
