@@ -232,6 +232,9 @@ def run_mix(np, torch, ctx, steps):
     ctx.autotune_dp(Hmax, Wmax, n_jobs=1)
     dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=256)[4]
     g = ctx.dp_chosen(Wmax)
+    choice = ctx.autotune_batch(clips, reps=1)
+    if choice["dp_geometry"] is not None:
+        g = choice["dp_geometry"]
     ctx.retarget_batch(clips)  # warm-up (workspace, graphs)
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
@@ -247,12 +250,12 @@ def run_mix(np, torch, ctx, steps):
     p1 = _t.perf_counter()
     plain = n_frames / (p1 - p0)
     log(f"mix64: batched {fps:.1f} frames/s ({(t1 - t0) * 1e3 / steps:.1f} ms/step), plain {plain:.1f} frames/s, "
-        f"DP {g} ({dpus:.1f} us per DP)")
+        f"DP {g} ({dpus:.1f} us per DP alone), batch tuning {choice}")
     del clips
     torch.cuda.empty_cache()
     return {"workload": desc, "frames": n_frames, "steps": steps, "batched_fps": round(fps, 2),
             "ms_per_step": round((t1 - t0) * 1e3 / steps, 3), "plain_fps": round(plain, 2),
-            "batched_over_plain": round(fps / plain, 3), "dp_geometry": g}
+            "batched_over_plain": round(fps / plain, 3), "dp_geometry": g, "batch_tuning": choice}
 
 
 def run_height(torch, ctx, clip_np, Wt, k, steps):
@@ -443,6 +446,10 @@ def main() -> int:
     ap.add_argument("--dp-geometry", default="", metavar="Q,HB,PF,EX,R,P",
                     help="use this DP geometry instead of autotuning (e.g. under a profiler, whose per-dispatch "
                          "overhead distorts the autotuner's timings)")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="skip the batch autotuner (job groups, DP geometry and kernel variants timed on whole steps)")
+    ap.add_argument("--variants", default="", metavar="UPDATE,REFRESH",
+                    help="compaction and refresh kernel variants to use (with --dp-geometry, for profiled runs)")
     ap.add_argument("--memo-periods", default="2,4",
                     help="seam-memorisation periods to time on the same workload (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -499,6 +506,19 @@ def main() -> int:
         dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
         dpg = ctx.dp_chosen(Wmax)
         log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
+
+    # the batch autotuner: whole steps of this workload under each candidate
+    # configuration (job groups with DP geometry, then the kernel variants)
+    batch_choice = None
+    if args.variants:
+        u, r = (int(x) for x in args.variants.split(","))
+        ctx.kernel_variants(u, r)
+    if not args.dp_geometry and not args.no_batch_tune:
+        b0 = time.perf_counter()
+        batch_choice = ctx.autotune_batch(clips, reps=2)
+        log(f"batch autotune ({time.perf_counter() - b0:.1f} s): {batch_choice}")
+        if batch_choice["dp_geometry"] is not None:
+            dpg = batch_choice["dp_geometry"]
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -704,7 +724,9 @@ def main() -> int:
         "config": {"workload": wname, "path": "batched: all buffers of all clips per launch, HIP-graph iterations",
                    "clips": n_clips, "frames": n_frames, **shape, "buffers": nbuf,
                    "buffer_iterations": int(len(log_rows)),
-                   "dp_geometry": dpg, "streams": args.streams},
+                   "dp_geometry": dpg,
+                   "streams": batch_choice["streams"] if batch_choice else args.streams,
+                   "batch_tuning": batch_choice},
         "value_graph_no_events": round(fps_graph, 2),
         "plain_fps": None if plain_fps is None else round(plain_fps, 2),
         "batched_over_plain": None if plain_fps is None else round(fps / plain_fps, 3),

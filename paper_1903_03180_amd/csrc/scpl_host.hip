@@ -4,6 +4,7 @@
 // every clip per launch, the iteration loop replayed from a HIP graph), and
 // the stage entry points.  Declarations: include/scpl.h.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +53,9 @@ struct scpl_ctx {
     void *scratch = nullptr;   // this device's no-allocation workspace (device address of `scratch`)
     std::vector<int32_t> last_log;
     int nstreams = 3;                    // job groups of the batched path, one stream each
+    DpGeom batch_forced{0, 0, 0, 0, 0};  // DP geometry the batch autotuner chose (Q = 0: none)
+    int upd_variant = 0;                 // compaction kernel variant (kUpdateVariants)
+    int refresh_variant = 0;             // refresh kernel variant (0 automatic)
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -643,12 +647,12 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
-        launch_update(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+        launch_update(d_jobs, nj, ls.Hmax, ls.Wmax, ctx->upd_variant, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_REFRESH, s);
         // also ends the iteration: moves every job still carving on
-        launch_refresh(d_jobs, nj, ls.kmax, ls.Hmax, s);
+        launch_refresh(d_jobs, nj, ls.kmax, ls.Hmax, ctx->refresh_variant, s);
     }
 }
 
@@ -1127,7 +1131,10 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
     // a batched DP launch serves every job: its geometry follows the widest
-    const DpGeom gall = select_geom(ctx, Wall, nj);
+    // (a geometry forced by the caller first, then the batch autotuner's)
+    const DpGeom gall = (ctx->forced.Q == 0 && ctx->batch_forced.Q > 0 && dp_geom_fits(ctx->batch_forced, Wall))
+                            ? ctx->batch_forced
+                            : select_geom(ctx, Wall, nj);
     auto shape_of = [&](const Pending &q) {
         const scpl_params &p = clips[q.clip].p;
         JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, batched ? gall : select_geom(ctx, p.width, 1)};
@@ -1638,6 +1645,108 @@ scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom)
     const DpGeom g = select_geom(ctx, W);
     const int32_t v[6] = {g.Q, g.banded ? g.HB : 0, g.PF, g.EX, g.R, g.P};
     for (int q = 0; q < 6; ++q) h_geom[q] = v[q];
+    return SCPL_OK;
+}
+
+scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant)
+{
+    if (!ctx || update_variant < 0 || update_variant >= kNumUpdateVariants || refresh_variant < 0 ||
+        refresh_variant >= kNumRefreshVariants)
+        return SCPL_ERR_INVALID_ARG;
+    ctx->upd_variant = update_variant;
+    ctx->refresh_variant = refresh_variant;
+    return SCPL_OK;
+}
+
+scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, int32_t reps,
+                                int32_t *h_choice, double *h_ms, void *stream)
+{
+    if (!ctx || !clips || n_clips < 1 || reps < 1 || reps > 100 || ctx->profiling) return SCPL_ERR_INVALID_ARG;
+    for (int c = 0; c < n_clips; ++c) {
+        scpl_status st = validate(&clips[c].p);
+        if (st != SCPL_OK) return st;
+        if (!clips[c].d_frames || !clips[c].d_out) return SCPL_ERR_INVALID_ARG;
+    }
+    SCPL_TRY(hipSetDevice(ctx->device));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    struct Cfg {
+        int streams;
+        DpGeom g;  // Q = 0: whatever the launches would take unforced (tuned or default)
+        int upd, refresh;
+    };
+    // the best of `reps` whole batched retargets after one untimed one (graphs,
+    // workspace); the caller's outputs are written each time, identically
+    auto time_cfg = [&](const Cfg &c, double *ms) -> scpl_status {
+        ctx->nstreams = c.streams;
+        ctx->batch_forced = c.g;
+        ctx->upd_variant = c.upd;
+        ctx->refresh_variant = c.refresh;
+        SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
+        SCPL_TRY(hipStreamSynchronize(s));
+        double best = 1e300;
+        for (int q = 0; q < reps; ++q) {
+            const auto t0 = std::chrono::steady_clock::now();
+            SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
+            SCPL_TRY(hipStreamSynchronize(s));
+            const std::chrono::duration<double, std::milli> d = std::chrono::steady_clock::now() - t0;
+            best = std::min(best, d.count());
+        }
+        *ms = best;
+        return SCPL_OK;
+    };
+    if (ctx->forced.Q > 0) return SCPL_ERR_INVALID_ARG;  // a geometry forced by the caller would win anyway
+    const Cfg start{ctx->nstreams, ctx->batch_forced, ctx->upd_variant, ctx->refresh_variant};
+    std::vector<DpGeom> geoms{DpGeom{0, 0, 0, 0, 0}, DpGeom{8, 16, 1, 8, 1}, DpGeom{4, 16, 1, 16, 1},
+                              DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{2, 8, 1, 16, 1, 128, 640}};
+    if (start.g.Q > 0) geoms[0] = start.g;
+    Cfg best = start;
+    best.g = geoms[0];
+    double best_ms = 1e300, ms = 0.0;
+    scpl_status st = SCPL_OK;
+    // coordinate descent: job groups with DP geometry, then the compaction
+    // variant, then the refresh variant
+    for (int ns : {2, 3, 4})
+        for (const DpGeom &g : geoms) {
+            if (st != SCPL_OK) break;
+            const Cfg c{ns, g, start.upd, start.refresh};
+            st = time_cfg(c, &ms);
+            if (st == SCPL_OK && ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    for (int u = 0; st == SCPL_OK && u < kNumUpdateVariants; ++u) {
+        if (u == best.upd) continue;
+        Cfg c = best;
+        c.upd = u;
+        st = time_cfg(c, &ms);
+        if (st == SCPL_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    for (int r = 0; st == SCPL_OK && r < kNumRefreshVariants; ++r) {
+        if (r == best.refresh) continue;
+        Cfg c = best;
+        c.refresh = r;
+        st = time_cfg(c, &ms);
+        if (st == SCPL_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    const Cfg keep = st == SCPL_OK ? best : start;
+    ctx->nstreams = keep.streams;
+    ctx->batch_forced = keep.g;
+    ctx->upd_variant = keep.upd;
+    ctx->refresh_variant = keep.refresh;
+    if (st != SCPL_OK) return st;
+    if (h_choice) {
+        const int32_t v[10] = {keep.streams, keep.g.Q, keep.g.HB, keep.g.PF, keep.g.EX, keep.g.R, keep.g.P, keep.upd,
+                               keep.refresh, keep.g.Q > 0 ? 1 : 0};
+        std::memcpy(h_choice, v, sizeof v);
+    }
+    if (h_ms) *h_ms = best_ms;
     return SCPL_OK;
 }
 

@@ -140,8 +140,13 @@ void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_c
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
 void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s);
-void launch_update(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
-void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, hipStream_t s);
+// compaction variants: (rows per workgroup, new columns per pass); 0 is the default
+extern const int kUpdateVariants[][2];
+extern const int kNumUpdateVariants;
+void launch_update(const Job *d_jobs, int njobs, int Hmax, int Wmax, int variant, hipStream_t s);
+// refresh variants: 0 automatic, 1: 256 threads per block, 2: 1024
+constexpr int kNumRefreshVariants = 3;
+void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, int variant, hipStream_t s);
 // LDS of the gather for a job (0: the job gathers directly from global memory)
 size_t gather_lds_bytes(int W, int Wt, int C);
 void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);

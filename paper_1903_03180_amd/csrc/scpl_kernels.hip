@@ -1437,23 +1437,25 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 // found once, then stepped -- from LDS, and writes each chunk with 16-byte
 // stores.  Rows with more than kUpdSeams seams gather their entries straight
 // from global memory instead.
-constexpr int kUpdRows = 4;
+// Variants (rows per workgroup ROWS, new columns per pass SPAN); the
+// default is (4, 2048), the others are for the batch autotuner.
 constexpr int kUpdSeams = 64;                          // seams per row staged in LDS
-constexpr int kUpdSpan = 2048;                         // new columns per pass
-constexpr int kUpdStage = kUpdSpan + kUpdSeams + 8;    // old entries staged per pass
 
-__global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
+template <int ROWS, int SPAN>
+__global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
 {
-    __shared__ int thr[kUpdRows][kUpdSeams + 1];
-    __shared__ __align__(16) uint16_t stM[kUpdRows][kUpdStage];
-    __shared__ __align__(16) uint16_t stK[kUpdRows][kUpdStage];
+    static_assert(SPAN % 512 == 0, "passes of whole 512-column chunks");
+    constexpr int kUpdStage = SPAN + kUpdSeams + 8;    // old entries staged per pass
+    __shared__ int thr[ROWS][kUpdSeams + 1];
+    __shared__ __align__(16) uint16_t stM[ROWS][kUpdStage];
+    __shared__ __align__(16) uint16_t stK[ROWS][kUpdStage];
     const Job &J = jobs[blockIdx.y];
     // job state read from memory: the same in every lane
     const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
     const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
     if (Wr <= J.Wt) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kUpdRows + w);
+    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * ROWS + w);
     if (i >= J.H) return;
     const int lane = threadIdx.x & 63;
     const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
@@ -1511,9 +1513,9 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
     };
     if (staged) {
         uint16_t *sM = stM[w], *sK = stK[w];
-        for (int j0 = jstart; j0 < Wn; j0 += kUpdSpan) {
-            // old columns [j0, hi) hold every source of new columns [j0, j0 + kUpdSpan)
-            const int hi = min(j0 + kUpdSpan + kk, Wr);
+        for (int j0 = jstart; j0 < Wn; j0 += SPAN) {
+            // old columns [j0, hi) hold every source of new columns [j0, j0 + SPAN)
+            const int hi = min(j0 + SPAN + kk, Wr);
             const int nv = (hi - j0 + 7) >> 3;  // 16-byte groups, within the row buffers
             // all groups requested before the first is written (a group past
             // the row buffer reads 0 and is not kept)
@@ -1535,7 +1537,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Job *jobs)
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
-            for (int c = 0; c < kUpdSpan / 512; ++c) {
+            for (int c = 0; c < SPAN / 512; ++c) {
                 const int jb = j0 + 512 * c + 8 * lane;
                 if (jb >= Wn) break;
                 int a = count(jb);
@@ -2175,15 +2177,33 @@ void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hi
     hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), lds, s, d_jobs);
 }
 
-void launch_update(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
+const int kUpdateVariants[][2] = {{4, 2048}, {2, 2048}, {8, 2048}, {4, 1024}, {8, 1024}};
+const int kNumUpdateVariants = (int)(sizeof(kUpdateVariants) / sizeof(kUpdateVariants[0]));
+
+template <int ROWS, int SPAN>
+static void launch_update_v(const Job *d_jobs, int njobs, int Hmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(blocks_for(Hmax, kUpdRows), njobs), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL((update_kernel<ROWS, SPAN>), dim3(blocks_for(Hmax, ROWS), njobs), dim3(64 * ROWS), 0, s,
+                       d_jobs);
 }
 
-void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, hipStream_t s)
+void launch_update(const Job *d_jobs, int njobs, int Hmax, int, int variant, hipStream_t s)
+{
+    switch (variant) {
+    case 1: launch_update_v<2, 2048>(d_jobs, njobs, Hmax, s); break;
+    case 2: launch_update_v<8, 2048>(d_jobs, njobs, Hmax, s); break;
+    case 3: launch_update_v<4, 1024>(d_jobs, njobs, Hmax, s); break;
+    case 4: launch_update_v<8, 1024>(d_jobs, njobs, Hmax, s); break;
+    default: launch_update_v<4, 2048>(d_jobs, njobs, Hmax, s); break;
+    }
+}
+
+void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, int variant, hipStream_t s)
 {
     const dim3 g(blocks_for(Hmax, kRefreshRows), njobs);
-    if ((int64_t)g.x * njobs < 2 * 256) hipLaunchKernelGGL(refresh_kernel<1024>, g, dim3(1024), 0, s, d_jobs);
+    // variant 0: 1024 threads per block when the launch has few blocks, else 256
+    const bool wide = variant == 2 || (variant == 0 && (int64_t)g.x * njobs < 2 * 256);
+    if (wide) hipLaunchKernelGGL(refresh_kernel<1024>, g, dim3(1024), 0, s, d_jobs);
     else hipLaunchKernelGGL(refresh_kernel<256>, g, dim3(256), 0, s, d_jobs);
 }
 

@@ -35,7 +35,7 @@ SCPL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
-    "scpl_retarget_noalloc",
+    "scpl_retarget_noalloc", "scpl_kernel_variants", "scpl_autotune_batch",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_profile_kinds", "scpl_dp_geometry",
     "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_server_create",
@@ -83,6 +83,9 @@ _sig = {
     "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P, C.c_uint64, _P], C.c_int),
     "scpl_retarget_noalloc": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_retarget_batch": ([_P, C.POINTER(scpl_clip), _I32, _P], C.c_int),
+    "scpl_kernel_variants": ([_P, _I32, _I32], C.c_int),
+    "scpl_autotune_batch": ([_P, C.POINTER(scpl_clip), _I32, _I32, C.POINTER(_I32), C.POINTER(C.c_double), _P],
+                            C.c_int),
     "scpl_last_log": ([_P, _P, _I64, C.POINTER(_I64)], C.c_int),
     "scpl_luma": ([_P, _P, _I64, _P, _P], C.c_int),
     "scpl_energy": ([_P, _I32, _I32, _I32, _P, _P, _P, _P], C.c_int),
@@ -250,12 +253,7 @@ class Context:
                                      C.byref(nb), _stream(stream)), "scpl_retarget_noalloc")
         return dict(out=out, masks=masks, buffer_id=buffer_id, n_buffers=int(nb.value))
 
-    def retarget_batch(self, clips, stream=None):
-        """clips: list of dicts with keys frames (cuda uint8 tensor),
-        target_width, seams_per_iter and optional Params fields, and
-        optionally out / masks / buffer_id tensors (allocated when absent,
-        masks only when want_masks is true).  Returns the list of dicts with
-        the outputs filled in."""
+    def _clip_array(self, clips):
         import torch
         arr = (scpl_clip * len(clips))()
         for i, c in enumerate(clips):
@@ -271,6 +269,33 @@ class Context:
             if c.get("buffer_id") is None:
                 c["buffer_id"] = torch.empty(p.n_frames, dtype=torch.int32, device=fr.device)
             arr[i] = scpl_clip(p.c(), _ptr(fr), _ptr(c["out"]), _ptr(c.get("masks")), _ptr(c["buffer_id"]))
+        return arr
+
+    def kernel_variants(self, update: int = 0, refresh: int = 0) -> None:
+        """Compaction kernel variant (0-4) and refresh kernel variant (0-2)."""
+        _check(scpl_kernel_variants(self.h, update, refresh), "scpl_kernel_variants")
+
+    def autotune_batch(self, clips, reps: int = 2, stream=None) -> dict:
+        """scpl_autotune_batch on these clips (dicts as for retarget_batch,
+        whose outputs it writes); returns the chosen configuration and the
+        best time of a whole batched retarget."""
+        arr = self._clip_array(clips)
+        ch = (C.c_int32 * 10)()
+        ms = C.c_double(0)
+        _check(scpl_autotune_batch(self.h, arr, len(clips), reps, ch, C.byref(ms), _stream(stream)),
+               "scpl_autotune_batch")
+        v = [int(x) for x in ch]
+        return {"streams": v[0], "dp_geometry": dict(zip(("cols_per_lane", "halo_rows", "prefetch_rows", "exclusive_cu",
+                                                          "chunk_rows", "chunk_cols"), v[1:7])) if v[9] else None,
+                "update_variant": v[7], "refresh_variant": v[8], "ms": ms.value}
+
+    def retarget_batch(self, clips, stream=None):
+        """clips: list of dicts with keys frames (cuda uint8 tensor),
+        target_width, seams_per_iter and optional Params fields, and
+        optionally out / masks / buffer_id tensors (allocated when absent,
+        masks only when want_masks is true).  Returns the list of dicts with
+        the outputs filled in."""
+        arr = self._clip_array(clips)
         _check(scpl_retarget_batch(self.h, arr, len(clips), _stream(stream)), "scpl_retarget_batch")
         return clips
 

@@ -426,3 +426,63 @@ def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
         ctx.profile(False)
     with pytest.raises(scpl.ScplError):
         scpl._check(scpl.scpl_profile_kinds(ctx.h, 1 << len(scpl.KERNELS)), "scpl_profile_kinds")
+
+
+@pytest.mark.parametrize("upd,ref", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (0, 1), (0, 2), (4, 2)])
+def test_kernel_variants_retarget(ctx, orc, upd, ref):
+    """Every compaction variant (rows per workgroup x columns per pass, so
+    widths of several passes) and refresh variant, on the plain path and in a
+    batch, against the oracle."""
+    clip = synth.make_clip(660, 6, 50, 2600, C=1, n_obj=3, cut_at=3, lattice=16)
+    small = synth.make_clip(661, 9, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
+    ctx.kernel_variants(upd, ref)
+    try:
+        compare(ctx, orc, clip, 2450, 20)
+        clips = [dict(frames=dev(clip), target_width=2450, seams_per_iter=20, want_masks=True),
+                 dict(frames=dev(small), target_width=210, seams_per_iter=6, want_masks=True)]
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+    finally:
+        ctx.kernel_variants(0, 0)
+    for c, f, wt, k in zip(clips, (clip, small), (2450, 210), (20, 6)):
+        want = orc.retarget(f, wt, k)
+        assert np.array_equal(c["out"].cpu().numpy(), want["out"])
+        assert np.array_equal(masks_u16(c["masks"]), want["masks"])
+
+
+def test_kernel_variants_refused(ctx):
+    from paper_1903_03180_amd import scpl
+    for u, r in ((-1, 0), (5, 0), (0, -1), (0, 3)):
+        with pytest.raises(scpl.ScplError):
+            ctx.kernel_variants(u, r)
+
+
+def test_autotune_batch_keeps_results(orc):
+    """The batch autotuner times whole batched retargets under every
+    candidate configuration (writing the outputs each time) and keeps the
+    fastest; the outputs it leaves, and a batched call afterwards, are the
+    oracle's."""
+    from paper_1903_03180_amd import scpl
+    c = scpl.Context(0)
+    try:
+        frames = [synth.make_clip(670 + i, 10, 48, 200 + 40 * i, C=1, n_obj=3, cut_at=5, lattice=8) for i in range(4)]
+        clips = [dict(frames=dev(f), target_width=(3 * f.shape[2]) // 4, seams_per_iter=8, want_masks=True)
+                 for f in frames]
+        choice = c.autotune_batch(clips, reps=1)
+        torch.cuda.synchronize()
+        assert choice["streams"] in (2, 3, 4) and choice["ms"] > 0
+        assert 0 <= choice["update_variant"] < 5 and 0 <= choice["refresh_variant"] < 3
+        for cl, f in zip(clips, frames):
+            want = orc.retarget(f, cl["target_width"], 8)
+            assert np.array_equal(cl["out"].cpu().numpy(), want["out"])
+            assert np.array_equal(masks_u16(cl["masks"]), want["masks"])
+        again = [dict(frames=cl["frames"], target_width=cl["target_width"], seams_per_iter=8) for cl in clips]
+        c.retarget_batch(again)
+        torch.cuda.synchronize()
+        for a, cl in zip(again, clips):
+            assert torch.equal(a["out"], cl["out"])
+        c.dp_geometry(8, 16, 8, 1)
+        with pytest.raises(scpl.ScplError):
+            c.autotune_batch(clips, reps=1)
+    finally:
+        c.close()
