@@ -448,8 +448,9 @@ def main() -> int:
                          "overhead distorts the autotuner's timings)")
     ap.add_argument("--no-batch-tune", action="store_true",
                     help="skip the batch autotuner (job groups, DP geometry and kernel variants timed on whole steps)")
-    ap.add_argument("--variants", default="", metavar="UPDATE,REFRESH",
-                    help="compaction and refresh kernel variants to use (with --dp-geometry, for profiled runs)")
+    ap.add_argument("--variants", default="", metavar="UPDATE,REFRESH,BORG",
+                    help="compaction, refresh and band-origin kernel variants to use (with --dp-geometry, for "
+                         "profiled runs)")
     ap.add_argument("--memo-periods", default="2,4",
                     help="seam-memorisation periods to time on the same workload (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -511,8 +512,7 @@ def main() -> int:
     # configuration (job groups with DP geometry, then the kernel variants)
     batch_choice = None
     if args.variants:
-        u, r = (int(x) for x in args.variants.split(","))
-        ctx.kernel_variants(u, r)
+        ctx.kernel_variants(*(int(x) for x in args.variants.split(",")))
     if not args.dp_geometry and not args.no_batch_tune:
         b0 = time.perf_counter()
         batch_choice = ctx.autotune_batch(clips, reps=2)

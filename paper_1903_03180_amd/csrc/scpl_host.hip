@@ -56,6 +56,7 @@ struct scpl_ctx {
     DpGeom batch_forced{0, 0, 0, 0, 0};  // DP geometry the batch autotuner chose (Q = 0: none)
     int upd_variant = 0;                 // compaction kernel variant (kUpdateVariants)
     int refresh_variant = 0;             // refresh kernel variant (0 automatic)
+    int borg_variant = 0;                // band-origin kernel variant
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -632,7 +633,7 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_BORG, s);
-        launch_borg(d_jobs, nj, ls.nbmax, ls.Bmax, ls.Wmax, s);
+        launch_borg(d_jobs, nj, ls.nbmax, ls.Bmax, ls.Wmax, ctx->borg_variant, s);
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_SELECT, s);
@@ -1527,7 +1528,7 @@ scpl_status scpl_dp(scpl_ctx *ctx, int32_t H, int32_t W, const int32_t *d_u, int
     SCPL_TRY(hipStreamSynchronize(s));
     if (*h_bad) return SCPL_ERR_INVALID_ARG;  // eq. (4) keys hold 4 U in 16 bits
     launch_dp(d_job, 1, ls.g, W, H, s);
-    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
+    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, 0, s);
     launch_labels(d_job, 1, W, s);
     launch_dir_out(J.dir, J.Wp, d_dir, H, W, s);
     SCPL_CHECK_LAUNCH();
@@ -1593,7 +1594,7 @@ scpl_status scpl_backtrack(scpl_ctx *ctx, int32_t H, int32_t W, const int8_t *d_
     SCPL_TRY(hipMemcpyAsync(J.log, h, 16, hipMemcpyHostToDevice, s));
     LaunchShape ls;
     ls.add(JobShape{H, W, 0, kk, select_geom(ctx, W, 1)});
-    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, s);
+    launch_borg(d_job, 1, ls.nbmax, ls.Bmax, W, 0, s);
     launch_jump_only(d_job, 1, s);
     launch_fill(d_job, 1, kk, ls.nbmax, ls.Bmax, s);
     launch_seams_out(J.seams, J.kcap, d_seams, kk, H, s);
@@ -1648,13 +1649,15 @@ scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom)
     return SCPL_OK;
 }
 
-scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant)
+scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant,
+                                 int32_t borg_variant)
 {
     if (!ctx || update_variant < 0 || update_variant >= kNumUpdateVariants || refresh_variant < 0 ||
-        refresh_variant >= kNumRefreshVariants)
+        refresh_variant >= kNumRefreshVariants || borg_variant < 0 || borg_variant >= kNumBorgVariants)
         return SCPL_ERR_INVALID_ARG;
     ctx->upd_variant = update_variant;
     ctx->refresh_variant = refresh_variant;
+    ctx->borg_variant = borg_variant;
     return SCPL_OK;
 }
 
@@ -1672,7 +1675,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     struct Cfg {
         int streams;
         DpGeom g;  // Q = 0: whatever the launches would take unforced (tuned or default)
-        int upd, refresh;
+        int upd, refresh, borg;
     };
     // the best of `reps` whole batched retargets after one untimed one (graphs,
     // workspace); the caller's outputs are written each time, identically
@@ -1681,6 +1684,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         ctx->batch_forced = c.g;
         ctx->upd_variant = c.upd;
         ctx->refresh_variant = c.refresh;
+        ctx->borg_variant = c.borg;
         SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
         SCPL_TRY(hipStreamSynchronize(s));
         double best = 1e300;
@@ -1695,55 +1699,60 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         return SCPL_OK;
     };
     if (ctx->forced.Q > 0) return SCPL_ERR_INVALID_ARG;  // a geometry forced by the caller would win anyway
-    const Cfg start{ctx->nstreams, ctx->batch_forced, ctx->upd_variant, ctx->refresh_variant};
+    const Cfg start{ctx->nstreams, ctx->batch_forced, ctx->upd_variant, ctx->refresh_variant, ctx->borg_variant};
     std::vector<DpGeom> geoms{DpGeom{0, 0, 0, 0, 0}, DpGeom{8, 16, 1, 8, 1}, DpGeom{4, 16, 1, 16, 1},
                               DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{2, 8, 1, 16, 1, 128, 640}};
     if (start.g.Q > 0) geoms[0] = start.g;
+    // the configuration the calls would use now is the incumbent; a
+    // candidate replaces it only when it is at least 1% faster, so that
+    // run-to-run noise does not decide the choice
     Cfg best = start;
     best.g = geoms[0];
     double best_ms = 1e300, ms = 0.0;
-    scpl_status st = SCPL_OK;
-    // coordinate descent: job groups with DP geometry, then the compaction
-    // variant, then the refresh variant
+    scpl_status st = time_cfg(best, &best_ms);
+    auto challenge = [&](const Cfg &c) {
+        if (st != SCPL_OK) return;
+        st = time_cfg(c, &ms);
+        if (st == SCPL_OK && ms < 0.99 * best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    };
+    // coordinate descent: job groups with DP geometry, then the compaction,
+    // refresh and band-origin variants
+    const Cfg inc = best;
     for (int ns : {2, 3, 4})
-        for (const DpGeom &g : geoms) {
-            if (st != SCPL_OK) break;
-            const Cfg c{ns, g, start.upd, start.refresh};
-            st = time_cfg(c, &ms);
-            if (st == SCPL_OK && ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
+        for (const DpGeom &g : geoms)
+            if (ns != inc.streams || std::memcmp(&g, &inc.g, sizeof g) != 0)
+                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg});
+    for (int u = 0; u < kNumUpdateVariants; ++u)
+        if (u != best.upd) {
+            Cfg c = best;
+            c.upd = u;
+            challenge(c);
         }
-    for (int u = 0; st == SCPL_OK && u < kNumUpdateVariants; ++u) {
-        if (u == best.upd) continue;
-        Cfg c = best;
-        c.upd = u;
-        st = time_cfg(c, &ms);
-        if (st == SCPL_OK && ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    for (int r = 0; r < kNumRefreshVariants; ++r)
+        if (r != best.refresh) {
+            Cfg c = best;
+            c.refresh = r;
+            challenge(c);
         }
-    }
-    for (int r = 0; st == SCPL_OK && r < kNumRefreshVariants; ++r) {
-        if (r == best.refresh) continue;
-        Cfg c = best;
-        c.refresh = r;
-        st = time_cfg(c, &ms);
-        if (st == SCPL_OK && ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    for (int b = 0; b < kNumBorgVariants; ++b)
+        if (b != best.borg) {
+            Cfg c = best;
+            c.borg = b;
+            challenge(c);
         }
-    }
     const Cfg keep = st == SCPL_OK ? best : start;
     ctx->nstreams = keep.streams;
     ctx->batch_forced = keep.g;
     ctx->upd_variant = keep.upd;
     ctx->refresh_variant = keep.refresh;
+    ctx->borg_variant = keep.borg;
     if (st != SCPL_OK) return st;
     if (h_choice) {
-        const int32_t v[10] = {keep.streams, keep.g.Q, keep.g.HB, keep.g.PF, keep.g.EX, keep.g.R, keep.g.P, keep.upd,
-                               keep.refresh, keep.g.Q > 0 ? 1 : 0};
+        const int32_t v[11] = {keep.streams, keep.g.Q,   keep.g.HB, keep.g.PF,          keep.g.EX, keep.g.R,
+                               keep.g.P,     keep.upd,   keep.refresh, keep.g.Q > 0 ? 1 : 0, keep.borg};
         std::memcpy(h_choice, v, sizeof v);
     }
     if (h_ms) *h_ms = best_ms;

@@ -135,7 +135,9 @@ constexpr int kKeyLeft = 64;  // all-ones key columns left of column 0 (>= every
 constexpr int kDirScratch = 64 * 16;  // after the indicator rows: discarded codes of one row (64 lanes x Q <= 16)
 void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax, hipStream_t s);
 void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s);
-void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s);
+// band-origin variants: 0 (256 columns per workgroup), 1 (128), 2 (512)
+constexpr int kNumBorgVariants = 3;
+void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, int variant, hipStream_t s);
 void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s);
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
 void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s);

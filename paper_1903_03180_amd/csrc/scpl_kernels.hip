@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
 // column - j, |.| <= B.  The band's indicator rows around the block's 128
 // columns are staged in LDS with 32-bit loads.
 
-constexpr int kBorgCols = 256;
+constexpr int kBorgCols = 256;  // columns per workgroup of the default variant
 
 __device__ __forceinline__ int code_step(uint8_t c) { return (int)(c & 3u) - 1; }
 
@@ -1198,24 +1198,25 @@ __device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *
     return c0 - a0;
 }
 
-__global__ __launch_bounds__(kBorgCols) void borg_kernel(const Job *jobs)
+template <int COLS>
+__global__ __launch_bounds__(COLS) void borg_kernel(const Job *jobs)
 {
-    extern __shared__ uint8_t tile[];  // B rows x (kBorgCols + 2B + 8) bytes
+    extern __shared__ uint8_t tile[];  // B rows x (COLS + 2B + 8) bytes
     const Job &J = jobs[blockIdx.z];
     const int r = job_iter(J);
     const int Wr = job_width(J, r);
     if (Wr <= J.Wt) return;
     const int b = blockIdx.y;
     if (b >= J.nb) return;
-    const int c0 = blockIdx.x * kBorgCols;
+    const int c0 = blockIdx.x * COLS;
     if (c0 >= Wr) return;
     const int B = J.B;
     const int lo = b * B, hi = min(lo + B, J.H) - 1;
     const int rlo = max(lo, 1);
     const int nrows = hi - rlo + 1;  // 0 when the job has a single row
-    const int wlo = max(c0 - nrows, 0), whi = min(c0 + kBorgCols + nrows, Wr);
-    const int lp = kBorgCols + 2 * B + 8;
-    const int sh = stage_bytes(tile, lp, J.dir, J.Wp, rlo, nrows, wlo, whi, threadIdx.x, kBorgCols) - wlo;
+    const int wlo = max(c0 - nrows, 0), whi = min(c0 + COLS + nrows, Wr);
+    const int lp = COLS + 2 * B + 8;
+    const int sh = stage_bytes(tile, lp, J.dir, J.Wp, rlo, nrows, wlo, whi, threadIdx.x, COLS) - wlo;
     __syncthreads();
     const int j = c0 + threadIdx.x;
     if (j < Wr) {
@@ -2127,11 +2128,18 @@ void launch_tune_fill(uint16_t *K, int H, int W, int Kp, int KL, hipStream_t s)
     hipLaunchKernelGGL(tune_fill_kernel, dim3(blocks_for((int64_t)H * W, 256)), dim3(256), 0, s, K, H, W, Kp, KL);
 }
 
-void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s)
+template <int COLS>
+static void launch_borg_v(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, hipStream_t s)
 {
-    const size_t lds = (size_t)Bmax * (kBorgCols + 2 * Bmax + 8);
-    hipLaunchKernelGGL(borg_kernel, dim3(blocks_for(Wmax, kBorgCols), nbmax, njobs), dim3(kBorgCols), lds, s,
-                       d_jobs);
+    const size_t lds = (size_t)Bmax * (COLS + 2 * Bmax + 8);
+    hipLaunchKernelGGL((borg_kernel<COLS>), dim3(blocks_for(Wmax, COLS), nbmax, njobs), dim3(COLS), lds, s, d_jobs);
+}
+
+void launch_borg(const Job *d_jobs, int njobs, int nbmax, int Bmax, int Wmax, int variant, hipStream_t s)
+{
+    if (variant == 1) launch_borg_v<128>(d_jobs, njobs, nbmax, Bmax, Wmax, s);
+    else if (variant == 2) launch_borg_v<512>(d_jobs, njobs, nbmax, Bmax, Wmax, s);
+    else launch_borg_v<kBorgCols>(d_jobs, njobs, nbmax, Bmax, Wmax, s);
 }
 
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s)
@@ -2177,7 +2185,7 @@ void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hi
     hipLaunchKernelGGL(fill_kernel, dim3(gx, nbmax, njobs), dim3(64), lds, s, d_jobs);
 }
 
-const int kUpdateVariants[][2] = {{4, 2048}, {2, 2048}, {8, 2048}, {4, 1024}, {8, 1024}};
+const int kUpdateVariants[][2] = {{4, 2048}, {2, 2048}, {8, 2048}, {4, 1024}, {8, 1024}, {1, 2048}, {2, 1024}};
 const int kNumUpdateVariants = (int)(sizeof(kUpdateVariants) / sizeof(kUpdateVariants[0]));
 
 template <int ROWS, int SPAN>
@@ -2194,6 +2202,8 @@ void launch_update(const Job *d_jobs, int njobs, int Hmax, int, int variant, hip
     case 2: launch_update_v<8, 2048>(d_jobs, njobs, Hmax, s); break;
     case 3: launch_update_v<4, 1024>(d_jobs, njobs, Hmax, s); break;
     case 4: launch_update_v<8, 1024>(d_jobs, njobs, Hmax, s); break;
+    case 5: launch_update_v<1, 2048>(d_jobs, njobs, Hmax, s); break;
+    case 6: launch_update_v<2, 1024>(d_jobs, njobs, Hmax, s); break;
     default: launch_update_v<4, 2048>(d_jobs, njobs, Hmax, s); break;
     }
 }

@@ -428,14 +428,15 @@ def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
         scpl._check(scpl.scpl_profile_kinds(ctx.h, 1 << len(scpl.KERNELS)), "scpl_profile_kinds")
 
 
-@pytest.mark.parametrize("upd,ref", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (0, 1), (0, 2), (4, 2)])
-def test_kernel_variants_retarget(ctx, orc, upd, ref):
+@pytest.mark.parametrize("upd,ref,borg", [(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0), (5, 0, 0), (6, 0, 0),
+                                          (0, 1, 0), (0, 2, 0), (0, 0, 1), (0, 0, 2), (4, 2, 2), (5, 1, 1)])
+def test_kernel_variants_retarget(ctx, orc, upd, ref, borg):
     """Every compaction variant (rows per workgroup x columns per pass, so
-    widths of several passes) and refresh variant, on the plain path and in a
-    batch, against the oracle."""
+    widths of several passes), refresh variant and band-origin variant, on
+    the plain path and in a batch, against the oracle."""
     clip = synth.make_clip(660, 6, 50, 2600, C=1, n_obj=3, cut_at=3, lattice=16)
     small = synth.make_clip(661, 9, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
-    ctx.kernel_variants(upd, ref)
+    ctx.kernel_variants(upd, ref, borg)
     try:
         compare(ctx, orc, clip, 2450, 20)
         clips = [dict(frames=dev(clip), target_width=2450, seams_per_iter=20, want_masks=True),
@@ -452,9 +453,9 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref):
 
 def test_kernel_variants_refused(ctx):
     from paper_1903_03180_amd import scpl
-    for u, r in ((-1, 0), (5, 0), (0, -1), (0, 3)):
+    for u, r, b in ((-1, 0, 0), (7, 0, 0), (0, -1, 0), (0, 3, 0), (0, 0, -1), (0, 0, 3)):
         with pytest.raises(scpl.ScplError):
-            ctx.kernel_variants(u, r)
+            ctx.kernel_variants(u, r, b)
 
 
 def test_autotune_batch_keeps_results(orc):
@@ -471,7 +472,8 @@ def test_autotune_batch_keeps_results(orc):
         choice = c.autotune_batch(clips, reps=1)
         torch.cuda.synchronize()
         assert choice["streams"] in (2, 3, 4) and choice["ms"] > 0
-        assert 0 <= choice["update_variant"] < 5 and 0 <= choice["refresh_variant"] < 3
+        assert 0 <= choice["update_variant"] < 7 and 0 <= choice["refresh_variant"] < 3
+        assert 0 <= choice["borg_variant"] < 3
         for cl, f in zip(clips, frames):
             want = orc.retarget(f, cl["target_width"], 8)
             assert np.array_equal(cl["out"].cpu().numpy(), want["out"])
