@@ -387,7 +387,7 @@ def measured_dp_traffic(workload, g):
     return (rec["read_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]) * rec.get("dispatches_per_dp", 1)
 
 
-def measured_step_traffic(workload, g):
+def measured_step_traffic(workload, g, variants=None):
     """The committed whole-step counter record of this workload, if it was
     taken with this DP geometry and no kernel or host source has changed
     since; else None."""
@@ -397,6 +397,8 @@ def measured_step_traffic(workload, g):
     with open(path) as f:
         rec = json.load(f)
     if rec.get("sources_sha256") != sources_digest() or rec.get("dp_geometry") != g:
+        return None
+    if variants is not None and rec.get("variants") != variants:
         return None
     return rec
 
@@ -654,7 +656,12 @@ def main() -> int:
                                    vrec["summary"], "per_kernel": vrec["valu_busy"]}
     # HBM bytes a step actually moves, from the committed counter runs
     step_hbm = None
-    step_rec = measured_step_traffic(args.workload, dpg)
+    variants = None
+    if batch_choice is not None:
+        variants = [batch_choice["update_variant"], batch_choice["refresh_variant"], batch_choice["borg_variant"]]
+    elif args.variants:
+        variants = [int(x) for x in args.variants.split(",")]
+    step_rec = measured_step_traffic(args.workload, dpg, variants or [0, 0, 0])
     if step_rec is not None:
         gbs = step_rec["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
         step_hbm = {"source": "rocprofv3 FETCH_SIZE + WRITE_SIZE over every dispatch of a step (calibrated), "
