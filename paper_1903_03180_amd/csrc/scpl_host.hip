@@ -57,6 +57,7 @@ struct scpl_ctx {
     int upd_variant = 0;                 // compaction kernel variant (kUpdateVariants)
     int refresh_variant = 0;             // refresh kernel variant (0 automatic)
     int borg_variant = 0;                // band-origin kernel variant
+    int gather_variant = 0;              // gather kernel variant (frames per pass)
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -609,11 +610,12 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
 
 struct LaunchShape {
     int Hmax = 0, Wmax = 0, nbmax = 0, kmax = 0, Bmax = 0;
-    size_t gather_lds = 0;
+    int gin = 0, gout = 0;  // largest source and output row in bytes (gather)
     DpGeom g{0, 0, 0, 0, 0};
     void add(const JobShape &s, int C = 1)
     {
-        gather_lds = std::max(gather_lds, gather_lds_bytes(s.W, s.Wt, C));
+        gin = std::max(gin, s.W * C);
+        gout = std::max(gout, s.Wt * C);
         Hmax = std::max(Hmax, s.H);
         Wmax = std::max(Wmax, s.W);
         nbmax = std::max(nbmax, s.nb());
@@ -758,7 +760,7 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
     if (all) {
         {
             ProfScope ps(ctx, SCPL_KERNEL_GATHER, G.st);
-            launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gather_lds, G.st);
+            launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gin, G.ls.gout, ctx->gather_variant, G.st);
         }
         SCPL_CHECK_LAUNCH();
         SCPL_TRY(hipEventRecord(G.ev, G.st));
@@ -1199,7 +1201,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         for (int q = lo; q < hi; ++q) ls.add(shape_of(pend[memo[q].src]), clips[pend[memo[q].src].clip].p.channels);
         {
             ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
-            launch_gather(d_jobs + nj + lo, hi - lo, ls.Hmax, ls.gather_lds, s);
+            launch_gather(d_jobs + nj + lo, hi - lo, ls.Hmax, ls.gin, ls.gout, ctx->gather_variant, s);
         }
         SCPL_CHECK_LAUNCH();
         return SCPL_OK;
@@ -1650,14 +1652,16 @@ scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom)
 }
 
 scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant,
-                                 int32_t borg_variant)
+                                 int32_t borg_variant, int32_t gather_variant)
 {
     if (!ctx || update_variant < 0 || update_variant >= kNumUpdateVariants || refresh_variant < 0 ||
-        refresh_variant >= kNumRefreshVariants || borg_variant < 0 || borg_variant >= kNumBorgVariants)
+        refresh_variant >= kNumRefreshVariants || borg_variant < 0 || borg_variant >= kNumBorgVariants ||
+        gather_variant < 0 || gather_variant >= kNumGatherVariants)
         return SCPL_ERR_INVALID_ARG;
     ctx->upd_variant = update_variant;
     ctx->refresh_variant = refresh_variant;
     ctx->borg_variant = borg_variant;
+    ctx->gather_variant = gather_variant;
     return SCPL_OK;
 }
 
@@ -1675,7 +1679,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     struct Cfg {
         int streams;
         DpGeom g;  // Q = 0: whatever the launches would take unforced (tuned or default)
-        int upd, refresh, borg;
+        int upd, refresh, borg, gather;
     };
     // the best of `reps` whole batched retargets after one untimed one (graphs,
     // workspace); the caller's outputs are written each time, identically
@@ -1685,6 +1689,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         ctx->upd_variant = c.upd;
         ctx->refresh_variant = c.refresh;
         ctx->borg_variant = c.borg;
+        ctx->gather_variant = c.gather;
         SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
         SCPL_TRY(hipStreamSynchronize(s));
         double best = 1e300;
@@ -1699,7 +1704,8 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         return SCPL_OK;
     };
     if (ctx->forced.Q > 0) return SCPL_ERR_INVALID_ARG;  // a geometry forced by the caller would win anyway
-    const Cfg start{ctx->nstreams, ctx->batch_forced, ctx->upd_variant, ctx->refresh_variant, ctx->borg_variant};
+    const Cfg start{ctx->nstreams,       ctx->batch_forced, ctx->upd_variant,
+                    ctx->refresh_variant, ctx->borg_variant,  ctx->gather_variant};
     std::vector<DpGeom> geoms{DpGeom{0, 0, 0, 0, 0}, DpGeom{8, 16, 1, 8, 1}, DpGeom{4, 16, 1, 16, 1},
                               DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{2, 8, 1, 16, 1, 128, 640}};
     if (start.g.Q > 0) geoms[0] = start.g;
@@ -1724,7 +1730,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     for (int ns : {2, 3, 4})
         for (const DpGeom &g : geoms)
             if (ns != inc.streams || std::memcmp(&g, &inc.g, sizeof g) != 0)
-                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg});
+                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg, inc.gather});
     for (int u = 0; u < kNumUpdateVariants; ++u)
         if (u != best.upd) {
             Cfg c = best;
@@ -1743,16 +1749,23 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
             c.borg = b;
             challenge(c);
         }
+    for (int g = 0; g < kNumGatherVariants; ++g)
+        if (g != best.gather) {
+            Cfg c = best;
+            c.gather = g;
+            challenge(c);
+        }
     const Cfg keep = st == SCPL_OK ? best : start;
     ctx->nstreams = keep.streams;
     ctx->batch_forced = keep.g;
     ctx->upd_variant = keep.upd;
     ctx->refresh_variant = keep.refresh;
     ctx->borg_variant = keep.borg;
+    ctx->gather_variant = keep.gather;
     if (st != SCPL_OK) return st;
     if (h_choice) {
-        const int32_t v[11] = {keep.streams, keep.g.Q,   keep.g.HB, keep.g.PF,          keep.g.EX, keep.g.R,
-                               keep.g.P,     keep.upd,   keep.refresh, keep.g.Q > 0 ? 1 : 0, keep.borg};
+        const int32_t v[12] = {keep.streams, keep.g.Q, keep.g.HB,    keep.g.PF,            keep.g.EX, keep.g.R,
+                               keep.g.P,     keep.upd, keep.refresh, keep.g.Q > 0 ? 1 : 0, keep.borg, keep.gather};
         std::memcpy(h_choice, v, sizeof v);
     }
     if (h_ms) *h_ms = best_ms;

@@ -149,9 +149,11 @@ void launch_update(const Job *d_jobs, int njobs, int Hmax, int Wmax, int variant
 // refresh variants: 0 automatic, 1: 256 threads per block, 2: 1024
 constexpr int kNumRefreshVariants = 3;
 void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, int variant, hipStream_t s);
-// LDS of the gather for a job (0: the job gathers directly from global memory)
-size_t gather_lds_bytes(int W, int Wt, int C);
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s);
+// gather variants: 1, 2, 4 or 8 frames of a row staged per pass (fewer when
+// the launch's widest rows would not fit); inb_max / outb_max: the launch's
+// largest source and output row in bytes
+extern const int kNumGatherVariants;
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int variant, hipStream_t s);
 // U (H x W int32) -> key rows; *bad |= 1 if some U is outside [0, 16382]
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s);
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);

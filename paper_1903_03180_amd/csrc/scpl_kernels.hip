@@ -1744,17 +1744,18 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
 // Carved output of every frame of the buffer: out(t, i, j) = frame(t, i,
 // M(i, j)) for j < Wt, all channels; masks of every frame = buffer mask.
 
-// Staged form, for rows of at most kGatherIn source and kGatherOut output
-// bytes: the byte offsets of the output row within the source row are
-// computed once per row, then for every frame of the buffer the source row
-// is loaded into LDS with coalesced loads and the output row is assembled
-// from it and written with 16-byte stores.  Wider rows gather directly.
-constexpr int kGatherIn = 32768;
-constexpr int kGatherOut = 16384;
+// Staged form, when FPB source rows and the offsets of the output row fit
+// the launch's LDS: the byte offsets of the output row within the source row
+// are computed once per row, then for every FPB frames of the buffer their
+// source rows are loaded into LDS with coalesced 16-byte loads (all requested
+// before any is used) and the output rows are assembled from them and written
+// with 16-byte stores.  Otherwise the row gathers directly.
+constexpr size_t kGatherLds = 65536;  // LDS a gather workgroup may take
 
 __device__ __forceinline__ uint32_t div3(uint32_t x) { return __umulhi(x, 0xAAAAAAABu) >> 1; }
 
-__global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
+template <int FPB>
+__global__ __launch_bounds__(256) void gather_kernel(const Job *jobs, int lds_bytes)
 {
     extern __shared__ __align__(16) uint8_t gsm[];
     const Job &J = jobs[blockIdx.y];
@@ -1763,6 +1764,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
     const int16_t *__restrict__ M = J.M + (size_t)i * J.Wp;
     const int C = J.C, W = J.W, Wt = J.Wt, H = J.H;
     const int inb = W * C, outb = Wt * C;
+    const int ip = (inb + 15) & ~15;  // LDS pitch of a staged source row
     const int tid = threadIdx.x;
     const uint16_t *msrc = J.bmask + (size_t)i * W;
     const bool vmask = J.masks && ((((uintptr_t)J.masks) | (uintptr_t)(2 * W)) & 15) == 0;
@@ -1775,7 +1777,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
             for (int j = tid; j < W; j += 256) mdst[j] = msrc[j];
         }
     };
-    if (inb > kGatherIn || outb > kGatherOut) {
+    if ((size_t)FPB * ip + 2 * (size_t)outb > (size_t)lds_bytes) {
         for (int t = J.t0; t < J.t0 + J.T; ++t) {
             const uint8_t *src = J.frames + ((size_t)t * H + i) * inb;
             uint8_t *dst = J.out + ((size_t)t * H + i) * outb;
@@ -1788,42 +1790,67 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs)
         return;
     }
     uint8_t *srow = gsm;
-    uint16_t *ofs = reinterpret_cast<uint16_t *>(gsm + ((inb + 15) & ~15));
+    uint16_t *ofs = reinterpret_cast<uint16_t *>(gsm + (size_t)FPB * ip);
     for (int b = tid; b < outb; b += 256) {
         const int j = C == 1 ? b : (int)div3((uint32_t)b);
         ofs[b] = (uint16_t)(mcol(M, j, W) * C + (b - j * C));
     }
     const bool vin = ((((uintptr_t)J.frames) | (uintptr_t)inb) & 15) == 0;
     const bool vout = ((((uintptr_t)J.out) | (uintptr_t)outb) & 15) == 0;
-    for (int t = J.t0; t < J.t0 + J.T; ++t) {
-        const uint8_t *src = J.frames + ((size_t)t * H + i) * inb;
-        uint8_t *dst = J.out + ((size_t)t * H + i) * outb;
-        __syncthreads();  // offsets written; the previous frame's reads of srow done
+    const int q16 = inb / 16;
+    for (int t0 = J.t0; t0 < J.t0 + J.T; t0 += FPB) {
+        const int nf = min(FPB, J.t0 + J.T - t0);
+        __syncthreads();  // offsets written; the previous frames' reads of the rows done
         if (vin) {
-            for (int q = tid; q < inb / 16; q += 256)
-                reinterpret_cast<u32x4 *>(srow)[q] = gp(reinterpret_cast<const u32x4 *>(src))[q];
-        } else {
-            for (int b = tid; b < inb; b += 256) srow[b] = gp(src)[b];
-        }
-        __syncthreads();
-        if (vout) {
-            for (int q = tid; q < outb / 16; q += 256) {
-                const u32x4 oa = reinterpret_cast<const u32x4 *>(ofs)[2 * q];
-                const u32x4 ob = reinterpret_cast<const u32x4 *>(ofs)[2 * q + 1];
-                const uint32_t o[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
-                uint32_t w[4];
+            constexpr int kReq = 4;  // 16-byte loads per thread and frame held before any is stored
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t p0 = o[2 * k], p1 = o[2 * k + 1];
-                    w[k] = (uint32_t)srow[p0 & 0xffff] | ((uint32_t)srow[p0 >> 16] << 8) |
-                           ((uint32_t)srow[p1 & 0xffff] << 16) | ((uint32_t)srow[p1 >> 16] << 24);
+            for (int f = 0; f < FPB; ++f) {
+                if (f >= nf) break;
+                const u32x4 *src = reinterpret_cast<const u32x4 *>(J.frames + ((size_t)(t0 + f) * H + i) * inb);
+                u32x4 *dst = reinterpret_cast<u32x4 *>(srow + (size_t)f * ip);
+                for (int q0 = tid; q0 < q16; q0 += 256 * kReq) {
+                    u32x4 v[kReq];
+#pragma unroll
+                    for (int u = 0; u < kReq; ++u) {
+                        const int q = q0 + 256 * u;
+                        if (q < q16) v[u] = gp(src)[q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kReq; ++u) {
+                        const int q = q0 + 256 * u;
+                        if (q < q16) dst[q] = v[u];
+                    }
                 }
-                gp(reinterpret_cast<u32x4 *>(dst))[q] = u32x4{w[0], w[1], w[2], w[3]};
             }
         } else {
-            for (int b = tid; b < outb; b += 256) dst[b] = srow[ofs[b]];
+            for (int f = 0; f < nf; ++f) {
+                const uint8_t *src = J.frames + ((size_t)(t0 + f) * H + i) * inb;
+                for (int b = tid; b < inb; b += 256) srow[(size_t)f * ip + b] = gp(src)[b];
+            }
         }
-        if (J.masks) copy_mask(t);
+        __syncthreads();
+        for (int f = 0; f < nf; ++f) {
+            const uint8_t *sr = srow + (size_t)f * ip;
+            uint8_t *dst = J.out + ((size_t)(t0 + f) * H + i) * outb;
+            if (vout) {
+                for (int q = tid; q < outb / 16; q += 256) {
+                    const u32x4 oa = reinterpret_cast<const u32x4 *>(ofs)[2 * q];
+                    const u32x4 ob = reinterpret_cast<const u32x4 *>(ofs)[2 * q + 1];
+                    const uint32_t o[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
+                    uint32_t w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t p0 = o[2 * k], p1 = o[2 * k + 1];
+                        w[k] = (uint32_t)sr[p0 & 0xffff] | ((uint32_t)sr[p0 >> 16] << 8) |
+                               ((uint32_t)sr[p1 & 0xffff] << 16) | ((uint32_t)sr[p1 >> 16] << 24);
+                    }
+                    gp(reinterpret_cast<u32x4 *>(dst))[q] = u32x4{w[0], w[1], w[2], w[3]};
+                }
+            } else {
+                for (int b = tid; b < outb; b += 256) dst[b] = sr[ofs[b]];
+            }
+            if (J.masks) copy_mask(t0 + f);
+        }
     }
 }
 
@@ -2217,16 +2244,31 @@ void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, int variant, hi
     else hipLaunchKernelGGL(refresh_kernel<256>, g, dim3(256), 0, s, d_jobs);
 }
 
-size_t gather_lds_bytes(int W, int Wt, int C)
+// frames staged per pass of the gather variants
+constexpr int kGatherFrames[] = {1, 2, 4, 8};
+const int kNumGatherVariants = (int)(sizeof(kGatherFrames) / sizeof(kGatherFrames[0]));
+
+template <int FPB>
+static void launch_gather_v(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, hipStream_t s)
 {
-    const size_t inb = (size_t)W * C, outb = (size_t)Wt * C;
-    if (inb > (size_t)kGatherIn || outb > (size_t)kGatherOut) return 0;
-    return ((inb + 15) & ~(size_t)15) + 2 * outb;
+    const size_t ip = ((size_t)inb_max + 15) & ~(size_t)15;
+    size_t lds = (size_t)FPB * ip + 2 * (size_t)outb_max;
+    if (lds > kGatherLds) lds = 0;  // every row of the launch gathers directly
+    hipLaunchKernelGGL((gather_kernel<FPB>), dim3(Hmax, njobs), dim3(256), lds, s, d_jobs, (int)lds);
 }
 
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, size_t lds, hipStream_t s)
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int variant, hipStream_t s)
 {
-    hipLaunchKernelGGL(gather_kernel, dim3(Hmax, njobs), dim3(256), lds, s, d_jobs);
+    // fewer frames per pass when the variant's rows do not fit the LDS
+    const size_t ip = ((size_t)inb_max + 15) & ~(size_t)15;
+    int v = std::min(std::max(variant, 0), kNumGatherVariants - 1);
+    while (v > 0 && (size_t)kGatherFrames[v] * ip + 2 * (size_t)outb_max > kGatherLds) --v;
+    switch (kGatherFrames[v]) {
+    case 2: launch_gather_v<2>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
+    case 4: launch_gather_v<4>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
+    case 8: launch_gather_v<8>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
+    default: launch_gather_v<1>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
+    }
 }
 
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s)

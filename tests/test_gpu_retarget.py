@@ -428,15 +428,18 @@ def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
         scpl._check(scpl.scpl_profile_kinds(ctx.h, 1 << len(scpl.KERNELS)), "scpl_profile_kinds")
 
 
-@pytest.mark.parametrize("upd,ref,borg", [(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0), (5, 0, 0), (6, 0, 0),
-                                          (0, 1, 0), (0, 2, 0), (0, 0, 1), (0, 0, 2), (4, 2, 2), (5, 1, 1)])
-def test_kernel_variants_retarget(ctx, orc, upd, ref, borg):
+@pytest.mark.parametrize("upd,ref,borg,gat", [(0, 0, 0, 0), (1, 0, 0, 0), (2, 0, 0, 0), (3, 0, 0, 0), (4, 0, 0, 0),
+                                              (5, 0, 0, 0), (6, 0, 0, 0), (0, 1, 0, 0), (0, 2, 0, 0), (0, 0, 1, 0),
+                                              (0, 0, 2, 0), (0, 0, 0, 1), (0, 0, 0, 2), (0, 0, 0, 3), (4, 2, 2, 3),
+                                              (5, 1, 1, 2)])
+def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat):
     """Every compaction variant (rows per workgroup x columns per pass, so
-    widths of several passes), refresh variant and band-origin variant, on
-    the plain path and in a batch, against the oracle."""
+    widths of several passes), refresh variant, band-origin variant and
+    gather variant (frames per pass; buffers whose length is not a multiple
+    of it), on the plain path and in a batch, against the oracle."""
     clip = synth.make_clip(660, 6, 50, 2600, C=1, n_obj=3, cut_at=3, lattice=16)
     small = synth.make_clip(661, 9, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
-    ctx.kernel_variants(upd, ref, borg)
+    ctx.kernel_variants(upd, ref, borg, gat)
     try:
         compare(ctx, orc, clip, 2450, 20)
         clips = [dict(frames=dev(clip), target_width=2450, seams_per_iter=20, want_masks=True),
@@ -444,7 +447,7 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref, borg):
         ctx.retarget_batch(clips)
         torch.cuda.synchronize()
     finally:
-        ctx.kernel_variants(0, 0)
+        ctx.kernel_variants(0, 0, 0, 0)
     for c, f, wt, k in zip(clips, (clip, small), (2450, 210), (20, 6)):
         want = orc.retarget(f, wt, k)
         assert np.array_equal(c["out"].cpu().numpy(), want["out"])
@@ -453,9 +456,10 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref, borg):
 
 def test_kernel_variants_refused(ctx):
     from paper_1903_03180_amd import scpl
-    for u, r, b in ((-1, 0, 0), (7, 0, 0), (0, -1, 0), (0, 3, 0), (0, 0, -1), (0, 0, 3)):
+    for u, r, b, g in ((-1, 0, 0, 0), (7, 0, 0, 0), (0, -1, 0, 0), (0, 3, 0, 0), (0, 0, -1, 0), (0, 0, 3, 0),
+                       (0, 0, 0, -1), (0, 0, 0, 4)):
         with pytest.raises(scpl.ScplError):
-            ctx.kernel_variants(u, r, b)
+            ctx.kernel_variants(u, r, b, g)
 
 
 def test_autotune_batch_keeps_results(orc):
@@ -473,7 +477,7 @@ def test_autotune_batch_keeps_results(orc):
         torch.cuda.synchronize()
         assert choice["streams"] in (2, 3, 4) and choice["ms"] > 0
         assert 0 <= choice["update_variant"] < 7 and 0 <= choice["refresh_variant"] < 3
-        assert 0 <= choice["borg_variant"] < 3
+        assert 0 <= choice["borg_variant"] < 3 and 0 <= choice["gather_variant"] < 4
         for cl, f in zip(clips, frames):
             want = orc.retarget(f, cl["target_width"], 8)
             assert np.array_equal(cl["out"].cpu().numpy(), want["out"])
