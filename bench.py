@@ -450,9 +450,9 @@ def main() -> int:
                          "overhead distorts the autotuner's timings)")
     ap.add_argument("--no-batch-tune", action="store_true",
                     help="skip the batch autotuner (job groups, DP geometry and kernel variants timed on whole steps)")
-    ap.add_argument("--variants", default="", metavar="UPDATE,REFRESH,BORG,GATHER",
-                    help="compaction, refresh, band-origin and gather kernel variants to use (with --dp-geometry, "
-                         "for profiled runs)")
+    ap.add_argument("--variants", default="", metavar="UPDATE,REFRESH,BORG,GATHER,FUSE",
+                    help="compaction, refresh, band-origin, gather and fused kernel variants to use (with "
+                         "--dp-geometry, for profiled runs)")
     ap.add_argument("--memo-periods", default="2,4",
                     help="seam-memorisation periods to time on the same workload (empty: none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -659,10 +659,10 @@ def main() -> int:
     variants = None
     if batch_choice is not None:
         variants = [batch_choice["update_variant"], batch_choice["refresh_variant"], batch_choice["borg_variant"],
-                    batch_choice["gather_variant"]]
+                    batch_choice["gather_variant"], batch_choice["fuse_variant"]]
     elif args.variants:
         variants = [int(x) for x in args.variants.split(",")]
-    step_rec = measured_step_traffic(args.workload, dpg, variants or [0, 0, 0, 0])
+    step_rec = measured_step_traffic(args.workload, dpg, variants or [0, 0, 0, 0, 0])
     if step_rec is not None:
         gbs = step_rec["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
         step_hbm = {"source": "rocprofv3 FETCH_SIZE + WRITE_SIZE over every dispatch of a step (calibrated), "

@@ -330,7 +330,11 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
  * borg_variant 0 (256), 1 (128) or 2 (512); and the output gather's
  * frames per pass (rows of that many frames staged in LDS together),
  * gather_variant 0 (1), 1 (2), 2 (4) or 3 (8), fewer when the rows do not
- * fit 64 KiB.
+ * fit 64 KiB; and whether the seam trace within bands and the compaction
+ * run as two launches (fuse_variant 0) or as one kernel per band of rows
+ * with 8 (1) or 16 (2) wavefronts per workgroup, which serves launches whose
+ * buffers all have 32-row bands and at most 64 seams per iteration (the
+ * others run the two launches).
  * scpl_autotune_batch times whole batched retargets of the given clips
  * (writing their outputs, identically, each time) and keeps the fastest
  * configuration for later batched calls of the context: first the number of
@@ -338,20 +342,20 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
  * take without it, the single-workgroup (8,16,8) and (4,16,16), the
  * column-split (4,16,8) with 256 rows x 384 columns and (2,8,16) with 128 x
  * 640, all with EX = 1), then the compaction variant, then the refresh
- * variant, then the band-origin and gather variants; each candidate is run once
+ * variant, then the band-origin, fused and gather variants; each candidate is run once
  * untimed and then `reps` times, and its best time counts.  The
  * configuration the calls would use before the call is timed first, and a
  * candidate replaces the best so far only when it is at least 1% faster
  * (so that run-to-run noise does not decide the choice).  Synchronises
- * `stream`.  h_choice (nullable, 12 int32): job groups, Q, HB, PF, EX, R, P
+ * `stream`.  h_choice (nullable, 13 int32): job groups, Q, HB, PF, EX, R, P
  * of the DP geometry (Q = 0: not forced), compaction variant, refresh
  * variant, 1 if a DP geometry is forced for batched calls, band-origin
- * variant, gather variant; *h_ms (nullable): the best time of a whole retarget in
+ * variant, gather variant, fused variant; *h_ms (nullable): the best time of a whole retarget in
  * milliseconds.  A geometry forced with scpl_dp_geometry takes
  * precedence over the batch choice, and the batch autotuner then returns
  * SCPL_ERR_INVALID_ARG, as it does with kernel timing enabled. */
 scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant,
-                                 int32_t borg_variant, int32_t gather_variant);
+                                 int32_t borg_variant, int32_t gather_variant, int32_t fuse_variant);
 scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n_clips, int32_t reps,
                                 int32_t *h_choice, double *h_ms, void *stream);
 

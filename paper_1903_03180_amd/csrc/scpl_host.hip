@@ -58,6 +58,7 @@ struct scpl_ctx {
     int refresh_variant = 0;             // refresh kernel variant (0 automatic)
     int borg_variant = 0;                // band-origin kernel variant
     int gather_variant = 0;              // gather kernel variant (frames per pass)
+    int fuse_variant = 0;                // fill + compaction: 0 two launches, 1/2 fused per band
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -644,13 +645,19 @@ void enqueue_iteration(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchSha
         const size_t need = (size_t)16 * ls.Wmax + (size_t)ls.nbmax * (size_t)((ls.Wmax + 7) & ~3);
         launch_select(d_jobs, nj, 0, std::min(need, ctx->lds_cap), s);
     }
-    {
-        ProfScope ps(ctx, SCPL_KERNEL_FILL, s);
-        launch_fill(d_jobs, nj, ls.kmax, ls.nbmax, ls.Bmax, s);
-    }
-    {
+    if (ctx->fuse_variant > 0 && band_update_fits(ls.kmax, ls.Bmax)) {
+        // fill and compaction fused per band (timed as the compaction)
         ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
-        launch_update(d_jobs, nj, ls.Hmax, ls.Wmax, ctx->upd_variant, s);
+        launch_band_update(d_jobs, nj, ls.nbmax, ctx->fuse_variant, s);
+    } else {
+        {
+            ProfScope ps(ctx, SCPL_KERNEL_FILL, s);
+            launch_fill(d_jobs, nj, ls.kmax, ls.nbmax, ls.Bmax, s);
+        }
+        {
+            ProfScope ps(ctx, SCPL_KERNEL_UPDATE, s);
+            launch_update(d_jobs, nj, ls.Hmax, ls.Wmax, ctx->upd_variant, s);
+        }
     }
     {
         ProfScope ps(ctx, SCPL_KERNEL_REFRESH, s);
@@ -1652,12 +1659,14 @@ scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom)
 }
 
 scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant,
-                                 int32_t borg_variant, int32_t gather_variant)
+                                 int32_t borg_variant, int32_t gather_variant, int32_t fuse_variant)
 {
     if (!ctx || update_variant < 0 || update_variant >= kNumUpdateVariants || refresh_variant < 0 ||
         refresh_variant >= kNumRefreshVariants || borg_variant < 0 || borg_variant >= kNumBorgVariants ||
-        gather_variant < 0 || gather_variant >= kNumGatherVariants)
+        gather_variant < 0 || gather_variant >= kNumGatherVariants || fuse_variant < 0 ||
+        fuse_variant >= kNumFuseVariants)
         return SCPL_ERR_INVALID_ARG;
+    ctx->fuse_variant = fuse_variant;
     ctx->upd_variant = update_variant;
     ctx->refresh_variant = refresh_variant;
     ctx->borg_variant = borg_variant;
@@ -1679,7 +1688,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     struct Cfg {
         int streams;
         DpGeom g;  // Q = 0: whatever the launches would take unforced (tuned or default)
-        int upd, refresh, borg, gather;
+        int upd, refresh, borg, gather, fuse;
     };
     // the best of `reps` whole batched retargets after one untimed one (graphs,
     // workspace); the caller's outputs are written each time, identically
@@ -1690,6 +1699,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         ctx->refresh_variant = c.refresh;
         ctx->borg_variant = c.borg;
         ctx->gather_variant = c.gather;
+        ctx->fuse_variant = c.fuse;
         SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
         SCPL_TRY(hipStreamSynchronize(s));
         double best = 1e300;
@@ -1704,8 +1714,8 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         return SCPL_OK;
     };
     if (ctx->forced.Q > 0) return SCPL_ERR_INVALID_ARG;  // a geometry forced by the caller would win anyway
-    const Cfg start{ctx->nstreams,       ctx->batch_forced, ctx->upd_variant,
-                    ctx->refresh_variant, ctx->borg_variant,  ctx->gather_variant};
+    const Cfg start{ctx->nstreams,     ctx->batch_forced,   ctx->upd_variant, ctx->refresh_variant,
+                    ctx->borg_variant, ctx->gather_variant, ctx->fuse_variant};
     std::vector<DpGeom> geoms{DpGeom{0, 0, 0, 0, 0}, DpGeom{8, 16, 1, 8, 1}, DpGeom{4, 16, 1, 16, 1},
                               DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{2, 8, 1, 16, 1, 128, 640}};
     if (start.g.Q > 0) geoms[0] = start.g;
@@ -1730,7 +1740,7 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     for (int ns : {2, 3, 4})
         for (const DpGeom &g : geoms)
             if (ns != inc.streams || std::memcmp(&g, &inc.g, sizeof g) != 0)
-                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg, inc.gather});
+                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg, inc.gather, inc.fuse});
     for (int u = 0; u < kNumUpdateVariants; ++u)
         if (u != best.upd) {
             Cfg c = best;
@@ -1749,6 +1759,12 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
             c.borg = b;
             challenge(c);
         }
+    for (int f = 0; f < kNumFuseVariants; ++f)
+        if (f != best.fuse) {
+            Cfg c = best;
+            c.fuse = f;
+            challenge(c);
+        }
     for (int g = 0; g < kNumGatherVariants; ++g)
         if (g != best.gather) {
             Cfg c = best;
@@ -1762,10 +1778,12 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     ctx->refresh_variant = keep.refresh;
     ctx->borg_variant = keep.borg;
     ctx->gather_variant = keep.gather;
+    ctx->fuse_variant = keep.fuse;
     if (st != SCPL_OK) return st;
     if (h_choice) {
-        const int32_t v[12] = {keep.streams, keep.g.Q, keep.g.HB,    keep.g.PF,            keep.g.EX, keep.g.R,
-                               keep.g.P,     keep.upd, keep.refresh, keep.g.Q > 0 ? 1 : 0, keep.borg, keep.gather};
+        const int32_t v[13] = {keep.streams, keep.g.Q,  keep.g.HB,   keep.g.PF,    keep.g.EX,
+                               keep.g.R,     keep.g.P,  keep.upd,    keep.refresh, keep.g.Q > 0 ? 1 : 0,
+                               keep.borg,    keep.gather, keep.fuse};
         std::memcpy(h_choice, v, sizeof v);
     }
     if (h_ms) *h_ms = best_ms;

@@ -142,6 +142,12 @@ void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_c
 void launch_labels(const Job *d_jobs, int njobs, int Wmax, hipStream_t s);
 void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s);
 void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s);
+// fill + compaction fused per band (variant 1: 8 wavefronts per workgroup,
+// 2: 16), for launches whose jobs all have 32-row bands and at most 64 seams
+// per iteration (band_update_fits)
+constexpr int kNumFuseVariants = 3;  // 0: fill and compaction as two launches
+bool band_update_fits(int kmax, int Bmax);
+void launch_band_update(const Job *d_jobs, int njobs, int nbmax, int variant, hipStream_t s);
 // compaction variants: (rows per workgroup, new columns per pass); 0 is the default
 extern const int kUpdateVariants[][2];
 extern const int kNumUpdateVariants;

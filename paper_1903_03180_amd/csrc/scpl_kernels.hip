@@ -1442,24 +1442,18 @@ __global__ __launch_bounds__(64) void fill_kernel(const Job *jobs)
 // default is (4, 2048), the others are for the batch autotuner.
 constexpr int kUpdSeams = 64;                          // seams per row staged in LDS
 
-template <int ROWS, int SPAN>
-__global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
+// Compaction of row i of job J in iteration r (width Wr, kk seams): the
+// column map and, when a further iteration reads them, the keys.  One
+// wavefront; thr: its kUpdSeams + 1 threshold slots in LDS, holding R_s - s
+// (and INT_MAX beyond) when kk <= kUpdSeams; sM, sK: its staging (SPAN +
+// kUpdSeams + 8 entries each).  Rows with more seams read the thresholds
+// from J.seams.
+template <int SPAN>
+__device__ __forceinline__ void compact_row(const Job &J, int r, int Wr, int kk, int i, const int *thr, uint16_t *sM,
+                                            uint16_t *sK, int lane)
 {
     static_assert(SPAN % 512 == 0, "passes of whole 512-column chunks");
     constexpr int kUpdStage = SPAN + kUpdSeams + 8;    // old entries staged per pass
-    __shared__ int thr[ROWS][kUpdSeams + 1];
-    __shared__ __align__(16) uint16_t stM[ROWS][kUpdStage];
-    __shared__ __align__(16) uint16_t stK[ROWS][kUpdStage];
-    const Job &J = jobs[blockIdx.y];
-    // job state read from memory: the same in every lane
-    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
-    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
-    if (Wr <= J.Wt) return;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * ROWS + w);
-    if (i >= J.H) return;
-    const int lane = threadIdx.x & 63;
-    const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
     const int Wn = Wr - kk;
     const int Wp = J.Wp;
     // in place: new column j never reads an old column left of j, and every
@@ -1470,13 +1464,8 @@ __global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
     const int16_t *__restrict__ R = J.seams + (size_t)i * J.kcap;  // removed columns of row i, increasing
     // seam s removed old column R[s]; new column j reads old column j + #{s : R[s] - s <= j}
     const bool staged = kk <= kUpdSeams;
-    if (staged) {
-        thr[w][lane] = lane < kk ? (int)R[lane] - lane : 0x7fffffff;
-        if (lane == 0) thr[w][kUpdSeams] = 0x7fffffff;
-        __builtin_amdgcn_wave_barrier();
-    }
     auto rs = [&](int s) -> int {
-        if (staged) return thr[w][min(s, kUpdSeams)];
+        if (staged) return thr[min(s, kUpdSeams)];
         return s < kk ? (int)R[s] - s : 0x7fffffff;
     };
     // row buffers (Wp and Kp - KL entries, multiples of 64) as buffer resources
@@ -1513,7 +1502,6 @@ __global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
         }
     };
     if (staged) {
-        uint16_t *sM = stM[w], *sK = stK[w];
         for (int j0 = jstart; j0 < Wn; j0 += SPAN) {
             // old columns [j0, hi) hold every source of new columns [j0, j0 + SPAN)
             const int hi = min(j0 + SPAN + kk, Wr);
@@ -1577,6 +1565,119 @@ __global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
     // previous width of this buffer already are
     const int wprev = r > 0 ? J.log[4 * (r - 1)] : J.W;
     for (int j = Wn + lane; j < wprev; j += 64) Kr[j] = kRowInf;
+}
+
+template <int ROWS, int SPAN>
+__global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
+{
+    constexpr int kUpdStage = SPAN + kUpdSeams + 8;
+    __shared__ int thr[ROWS][kUpdSeams + 1];
+    __shared__ __align__(16) uint16_t stM[ROWS][kUpdStage];
+    __shared__ __align__(16) uint16_t stK[ROWS][kUpdStage];
+    const Job &J = jobs[blockIdx.y];
+    // job state read from memory: the same in every lane
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
+    if (Wr <= J.Wt) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * ROWS + w);
+    if (i >= J.H) return;
+    const int lane = threadIdx.x & 63;
+    const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
+    if (kk <= kUpdSeams) {
+        const int16_t *R = J.seams + (size_t)i * J.kcap;
+        thr[w][lane] = lane < kk ? (int)R[lane] - lane : 0x7fffffff;
+        if (lane == 0) thr[w][kUpdSeams] = 0x7fffffff;
+        __builtin_amdgcn_wave_barrier();
+    }
+    compact_row<SPAN>(J, r, Wr, kk, i, thr[w], stM[w], stK[w], lane);
+}
+
+// ------------------------------------------- backtrack within a band + compaction
+//
+// The fill and compaction of one iteration fused: one workgroup of WAVES
+// wavefronts per (band of 32 rows, job).  First the seams' paths through the
+// band, as fill_kernel: a wavefront stages the window of the band's
+// indicator rows a seam can reach from its column at the band's last row, and
+// one lane follows it upward.  Then every seam's column in every row of the
+// band (for the refresh) and its removal mark in the buffer mask, through the
+// column map before it moves.  Then the band's rows are compacted, as
+// update_kernel, with their thresholds taken from the paths in LDS.  No row
+// of the band needs anything from another band.  Serves launches whose jobs
+// all have 32-row bands and at most kUpdSeams seams per iteration.
+constexpr int kFuseB = 32;
+constexpr int kFuseSpan = 1024;                // new columns per compaction pass
+constexpr int kFuseWin = 2 * kFuseB + 8;       // window pitch: a seam's window is at most 2 B - 1 wide, staged from a word
+constexpr int kFuseStage = kFuseSpan + kUpdSeams + 8;
+
+__host__ __device__ constexpr size_t band_update_lds(int waves)
+{
+    return (size_t)waves * 2 * kFuseStage * 2 +           // staged column-map and key entries, per wavefront
+           (size_t)waves * (kFuseB - 1) * kFuseWin +       // seam windows, per wavefront
+           (size_t)kUpdSeams * kFuseB * 2 +                // paths: column of seam s in row lo + q
+           (size_t)waves * (kUpdSeams + 1) * 4;            // thresholds of the row a wavefront compacts
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void band_update_kernel(const Job *jobs)
+{
+    extern __shared__ __align__(16) uint8_t fsm[];
+    uint16_t *stM = reinterpret_cast<uint16_t *>(fsm);
+    uint16_t *stK = stM + (size_t)WAVES * kFuseStage;
+    uint8_t *win = reinterpret_cast<uint8_t *>(stK + (size_t)WAVES * kFuseStage);
+    int16_t *path = reinterpret_cast<int16_t *>(win + (size_t)WAVES * (kFuseB - 1) * kFuseWin);  // [kUpdSeams][kFuseB]
+    int *thr = reinterpret_cast<int *>(path + (size_t)kUpdSeams * kFuseB);
+    const Job &J = jobs[blockIdx.y];
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
+    if (Wr <= J.Wt) return;
+    const int b = blockIdx.x;
+    if (b >= J.nb) return;
+    const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
+    const int H = J.H, nb = J.nb, W = J.W, Wp = J.Wp;
+    const int lo = b * kFuseB, hi = min(lo + kFuseB, H) - 1;
+    const int span = hi - lo;  // < kFuseB
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    // 1. the seams' paths through the band
+    uint8_t *ww = win + (size_t)w * (kFuseB - 1) * kFuseWin;
+    for (int s = w; s < kk; s += WAVES) {
+        const int c_end = J.bcol[s * nb + b];
+        const int wlo = max(c_end - span, 0), whi = min(c_end + span + 1, Wr);
+        const int sh = stage_bytes(ww, kFuseWin, J.dir, Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            int c = c_end;
+            path[s * kFuseB + span] = (int16_t)c;
+            for (int i = hi; i > lo; --i) {
+                c += code_step(ww[(i - lo - 1) * kFuseWin + c + sh]);
+                path[s * kFuseB + i - 1 - lo] = (int16_t)c;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the window is read before the next seam's staging
+    }
+    __syncthreads();
+    // 2. the seams' columns in every row of the band, and their marks in the
+    // buffer mask (original columns, through the column map before it moves)
+    const int rows = span + 1;
+    for (int x = (int)threadIdx.x; x < kk * rows; x += 64 * WAVES) {
+        const int s = x / rows, q = x - s * rows;
+        const int i = lo + q;
+        const int col = path[s * kFuseB + q];
+        J.seams[(size_t)i * J.kcap + s] = (int16_t)col;
+        J.bmask[(size_t)i * W + mcol(J.M + (size_t)i * Wp, col, W)] = (uint16_t)(r + 1);
+    }
+    __syncthreads();  // every mark has read the column map
+    // 3. the band's rows compacted
+    int *tw = thr + (size_t)w * (kUpdSeams + 1);
+    uint16_t *sM = stM + (size_t)w * kFuseStage, *sK = stK + (size_t)w * kFuseStage;
+    for (int q = w; q < rows; q += WAVES) {
+        tw[lane] = lane < kk ? (int)path[lane * kFuseB + q] - lane : 0x7fffffff;
+        if (lane == 0) tw[kUpdSeams] = 0x7fffffff;
+        __builtin_amdgcn_wave_barrier();
+        compact_row<kFuseSpan>(J, r, Wr, kk, lo + q, tw, sM, sK, lane);
+        __builtin_amdgcn_wave_barrier();  // the thresholds are read before the next row's
+    }
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -2193,6 +2294,10 @@ void set_kernel_attributes(size_t lds_cap)
     for (const void *f : dps) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&band_update_kernel<8>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_update_lds(8));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&band_update_kernel<16>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_update_lds(16));
 }
 
 void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s)
@@ -2203,6 +2308,16 @@ void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_c
 void launch_jump_only(const Job *d_jobs, int njobs, hipStream_t s)
 {
     hipLaunchKernelGGL(jump_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
+}
+
+bool band_update_fits(int kmax, int Bmax) { return Bmax == kFuseB && kmax <= kUpdSeams; }
+
+void launch_band_update(const Job *d_jobs, int njobs, int nbmax, int variant, hipStream_t s)
+{
+    if (variant == 2)
+        hipLaunchKernelGGL(band_update_kernel<16>, dim3(nbmax, njobs), dim3(1024), band_update_lds(16), s, d_jobs);
+    else
+        hipLaunchKernelGGL(band_update_kernel<8>, dim3(nbmax, njobs), dim3(512), band_update_lds(8), s, d_jobs);
 }
 
 void launch_fill(const Job *d_jobs, int njobs, int kmax, int nbmax, int Bmax, hipStream_t s)

@@ -83,7 +83,7 @@ _sig = {
     "scpl_retarget": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P, C.c_uint64, _P], C.c_int),
     "scpl_retarget_noalloc": ([_P, C.POINTER(scpl_params), _P, _P, _P, _P, C.POINTER(_I32), _P], C.c_int),
     "scpl_retarget_batch": ([_P, C.POINTER(scpl_clip), _I32, _P], C.c_int),
-    "scpl_kernel_variants": ([_P, _I32, _I32, _I32, _I32], C.c_int),
+    "scpl_kernel_variants": ([_P, _I32, _I32, _I32, _I32, _I32], C.c_int),
     "scpl_autotune_batch": ([_P, C.POINTER(scpl_clip), _I32, _I32, C.POINTER(_I32), C.POINTER(C.c_double), _P],
                             C.c_int),
     "scpl_last_log": ([_P, _P, _I64, C.POINTER(_I64)], C.c_int),
@@ -271,17 +271,19 @@ class Context:
             arr[i] = scpl_clip(p.c(), _ptr(fr), _ptr(c["out"]), _ptr(c.get("masks")), _ptr(c["buffer_id"]))
         return arr
 
-    def kernel_variants(self, update: int = 0, refresh: int = 0, borg: int = 0, gather: int = 0) -> None:
+    def kernel_variants(self, update: int = 0, refresh: int = 0, borg: int = 0, gather: int = 0,
+                        fuse: int = 0) -> None:
         """Compaction kernel variant (0-6), refresh kernel variant (0-2),
-        band-origin kernel variant (0-2), gather variant (0-3)."""
-        _check(scpl_kernel_variants(self.h, update, refresh, borg, gather), "scpl_kernel_variants")
+        band-origin kernel variant (0-2), gather variant (0-3), fill and
+        compaction fused per band (0: no; 1, 2: 8 or 16 wavefronts)."""
+        _check(scpl_kernel_variants(self.h, update, refresh, borg, gather, fuse), "scpl_kernel_variants")
 
     def autotune_batch(self, clips, reps: int = 2, stream=None) -> dict:
         """scpl_autotune_batch on these clips (dicts as for retarget_batch,
         whose outputs it writes); returns the chosen configuration and the
         best time of a whole batched retarget."""
         arr = self._clip_array(clips)
-        ch = (C.c_int32 * 12)()
+        ch = (C.c_int32 * 13)()
         ms = C.c_double(0)
         _check(scpl_autotune_batch(self.h, arr, len(clips), reps, ch, C.byref(ms), _stream(stream)),
                "scpl_autotune_batch")
@@ -289,7 +291,7 @@ class Context:
         return {"streams": v[0], "dp_geometry": dict(zip(("cols_per_lane", "halo_rows", "prefetch_rows", "exclusive_cu",
                                                           "chunk_rows", "chunk_cols"), v[1:7])) if v[9] else None,
                 "update_variant": v[7], "refresh_variant": v[8], "borg_variant": v[10], "gather_variant": v[11],
-                "ms": ms.value}
+                "fuse_variant": v[12], "ms": ms.value}
 
     def retarget_batch(self, clips, stream=None):
         """clips: list of dicts with keys frames (cuda uint8 tensor),

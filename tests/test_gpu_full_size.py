@@ -111,17 +111,21 @@ def run_batch(ctx, recs, frames, nstreams=3):
     return out
 
 
-@pytest.mark.parametrize("geom", [None, (4, 16, 8, 1, 256, 384)])
-def test_1080p_clip_every_iteration(ctx, geom):
+@pytest.mark.parametrize("geom,variants", [(None, None), ((4, 16, 8, 1, 256, 384), None),
+                                           ((8, 16, 8, 1, 0, 0), (1, 0, 1, 1, 1)), (None, (0, 0, 0, 0, 2))])
+def test_1080p_clip_every_iteration(ctx, geom, variants):
     (rec,) = need("clip1080p_s2")
     d = dev(frames_of(rec["recipe"]))
     if geom:
         ctx.dp_geometry(*geom[:4])
         ctx.dp_chunking(*geom[4:])
+    if variants:
+        ctx.kernel_variants(*variants)
     try:
         res, log = run_plain(ctx, rec["recipe"], d)
     finally:
         ctx.dp_geometry(0)
+        ctx.kernel_variants(0, 0, 0, 0, 0)
     check("clip1080p_s2", res, log)
 
 
@@ -137,6 +141,14 @@ def test_1080p_batch_as_benchmarked_every_iteration(ctx):
         res = run_batch(ctx, rr, frames)
     finally:
         ctx.dp_geometry(0)
+    for n, (c, log) in zip(names, res):
+        check(n, c, log)
+    # and with the fused per-band kernel and the other kernel variants
+    ctx.kernel_variants(1, 0, 0, 1, 1)
+    try:
+        res = run_batch(ctx, rr, frames)
+    finally:
+        ctx.kernel_variants(0, 0, 0, 0, 0)
     for n, (c, log) in zip(names, res):
         check(n, c, log)
     # the same clips alone on the plain path (default geometry)

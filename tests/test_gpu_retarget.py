@@ -428,18 +428,20 @@ def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
         scpl._check(scpl.scpl_profile_kinds(ctx.h, 1 << len(scpl.KERNELS)), "scpl_profile_kinds")
 
 
-@pytest.mark.parametrize("upd,ref,borg,gat", [(0, 0, 0, 0), (1, 0, 0, 0), (2, 0, 0, 0), (3, 0, 0, 0), (4, 0, 0, 0),
-                                              (5, 0, 0, 0), (6, 0, 0, 0), (0, 1, 0, 0), (0, 2, 0, 0), (0, 0, 1, 0),
-                                              (0, 0, 2, 0), (0, 0, 0, 1), (0, 0, 0, 2), (0, 0, 0, 3), (4, 2, 2, 3),
-                                              (5, 1, 1, 2)])
-def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat):
+@pytest.mark.parametrize("upd,ref,borg,gat,fuse", [
+    (0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (2, 0, 0, 0, 0), (3, 0, 0, 0, 0), (4, 0, 0, 0, 0), (5, 0, 0, 0, 0),
+    (6, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 2, 0, 0, 0), (0, 0, 1, 0, 0), (0, 0, 2, 0, 0), (0, 0, 0, 1, 0),
+    (0, 0, 0, 2, 0), (0, 0, 0, 3, 0), (4, 2, 2, 3, 0), (5, 1, 1, 2, 0), (0, 0, 0, 0, 1), (0, 0, 0, 0, 2),
+    (3, 1, 2, 2, 1)])
+def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat, fuse):
     """Every compaction variant (rows per workgroup x columns per pass, so
     widths of several passes), refresh variant, band-origin variant and
     gather variant (frames per pass; buffers whose length is not a multiple
-    of it), on the plain path and in a batch, against the oracle."""
+    of it), and the fill and compaction fused per band, on the plain path
+    and in a batch, against the oracle."""
     clip = synth.make_clip(660, 6, 50, 2600, C=1, n_obj=3, cut_at=3, lattice=16)
     small = synth.make_clip(661, 9, 40, 300, C=3, n_obj=3, cut_at=4, lattice=8)
-    ctx.kernel_variants(upd, ref, borg, gat)
+    ctx.kernel_variants(upd, ref, borg, gat, fuse)
     try:
         compare(ctx, orc, clip, 2450, 20)
         clips = [dict(frames=dev(clip), target_width=2450, seams_per_iter=20, want_masks=True),
@@ -447,7 +449,7 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat):
         ctx.retarget_batch(clips)
         torch.cuda.synchronize()
     finally:
-        ctx.kernel_variants(0, 0, 0, 0)
+        ctx.kernel_variants(0, 0, 0, 0, 0)
     for c, f, wt, k in zip(clips, (clip, small), (2450, 210), (20, 6)):
         want = orc.retarget(f, wt, k)
         assert np.array_equal(c["out"].cpu().numpy(), want["out"])
@@ -456,10 +458,10 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat):
 
 def test_kernel_variants_refused(ctx):
     from paper_1903_03180_amd import scpl
-    for u, r, b, g in ((-1, 0, 0, 0), (7, 0, 0, 0), (0, -1, 0, 0), (0, 3, 0, 0), (0, 0, -1, 0), (0, 0, 3, 0),
-                       (0, 0, 0, -1), (0, 0, 0, 4)):
+    for v in ((-1, 0, 0, 0, 0), (7, 0, 0, 0, 0), (0, -1, 0, 0, 0), (0, 3, 0, 0, 0), (0, 0, -1, 0, 0),
+              (0, 0, 3, 0, 0), (0, 0, 0, -1, 0), (0, 0, 0, 4, 0), (0, 0, 0, 0, -1), (0, 0, 0, 0, 3)):
         with pytest.raises(scpl.ScplError):
-            ctx.kernel_variants(u, r, b, g)
+            ctx.kernel_variants(*v)
 
 
 def test_autotune_batch_keeps_results(orc):
@@ -478,6 +480,7 @@ def test_autotune_batch_keeps_results(orc):
         assert choice["streams"] in (2, 3, 4) and choice["ms"] > 0
         assert 0 <= choice["update_variant"] < 7 and 0 <= choice["refresh_variant"] < 3
         assert 0 <= choice["borg_variant"] < 3 and 0 <= choice["gather_variant"] < 4
+        assert 0 <= choice["fuse_variant"] < 3
         for cl, f in zip(clips, frames):
             want = orc.retarget(f, cl["target_width"], 8)
             assert np.array_equal(cl["out"].cpu().numpy(), want["out"])
@@ -492,3 +495,28 @@ def test_autotune_batch_keeps_results(orc):
             c.autotune_batch(clips, reps=1)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_fused_band_update_uneven_and_tall(ctx, orc, fuse):
+    """The fused per-band kernel on shapes with a ragged last band, one-row
+    and 33-row frames, several buffers, RGB and luma, and widths over its
+    1024-column compaction pass, against the oracle; and a launch it does not
+    serve (more than 64 seams per iteration) falling back to two launches."""
+    cases = [(synth.make_clip(680, 9, 33, 300, C=3, n_obj=3, cut_at=4, lattice=8), 220, 6),
+             (synth.make_clip(681, 5, 1, 90, C=1, n_obj=2, lattice=8), 60, 4),
+             (synth.make_clip(682, 6, 70, 2300, C=1, n_obj=3, cut_at=3, lattice=16), 2200, 16),
+             (synth.make_clip(683, 7, 64, 120, C=1, n_obj=3, cut_at=3, lattice=8), 80, 200)]
+    ctx.kernel_variants(0, 0, 0, 0, fuse)
+    try:
+        for f, wt, k in cases:
+            compare(ctx, orc, f, wt, k)
+        clips = [dict(frames=dev(f), target_width=wt, seams_per_iter=k, want_masks=True) for f, wt, k in cases[:3]]
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+    finally:
+        ctx.kernel_variants(0, 0, 0, 0, 0)
+    for c, (f, wt, k) in zip(clips, cases):
+        want = orc.retarget(f, wt, k)
+        assert np.array_equal(c["out"].cpu().numpy(), want["out"])
+        assert np.array_equal(masks_u16(c["masks"]), want["masks"])
