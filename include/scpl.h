@@ -193,6 +193,50 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
 #define SCPL_MAX_STREAMS 8
 scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
 
+/* How scpl_retarget_batch runs the iterations of its jobs (performance
+ * only: results are identical in both modes).
+ * SCPL_BATCH_GROUPS (default): the job groups of scpl_batch_streams, each
+ * replaying a captured graph of a few iterations (one launch per stage per
+ * iteration over the group's jobs) while the host reads back the jobs'
+ * states between replays.
+ * SCPL_BATCH_PERSISTENT: one persistent launch for all jobs, captured as a
+ * graph with the two small kernels that set up its work ring.  Its
+ * workgroups take work items (a column range of a chunk of DP rows, a band
+ * of the backtrack and compaction, 16 rows of the energy refresh, a job's
+ * selection...) from the ring; the workgroup that finishes the last item of
+ * a job's stage queues the job's next stage, so every job follows its own
+ * iteration chain with no host in the loop and no lock-step between jobs
+ * (Sec. 3.1 and 3.2: the same SCPL iterations, scheduled on the device).
+ * On a device whose XCDs each have their own L2 cache, every job is dealt
+ * to one XCD and only the workgroups running there take its items, so that
+ * its data meet in one L2 and items publish their results without L2
+ * write-backs; context creation checks with a probe launch that the
+ * workgroups' XCD register follows the dispatcher's round robin, and
+ * otherwise the batch runs as job groups.  SCPL_BATCH_PERSISTENT_AGENT (one
+ * ring served by every workgroup, with agent-scope release and acquire
+ * around each item) is switched off in this build: scpl_batch_mode refuses
+ * it with SCPL_ERR_DEVICE.
+ * A workgroup that waits longer than 4 s for an item stops the launch and
+ * the call returns SCPL_ERR_INTERNAL.  Batches it does not serve (a clip
+ * wider than 8192 columns) run as job groups.  The DP takes the column-split
+ * chunking forced by scpl_dp_chunking when its rows R and columns P give
+ * P + 2 R in (672, 896], else 256 x 384. */
+enum { SCPL_BATCH_GROUPS = 0, SCPL_BATCH_PERSISTENT = 1, SCPL_BATCH_PERSISTENT_AGENT = 2 };
+scpl_status scpl_batch_mode(scpl_ctx *ctx, int32_t mode);
+/* XCDs the context's probe launch found (the persistent launch serves each
+ * with a ring of its own), or 0 when XCD-local mode is unavailable and
+ * SCPL_BATCH_PERSISTENT runs as job groups. */
+scpl_status scpl_device_xcds(scpl_ctx *ctx, int32_t *h_n);
+/* Where the last persistent launch made while kernels were timed
+ * (scpl_profile_enable) spent its workgroups' time, summed over the
+ * workgroups (device wall clock): h_ms[0..4] in items of the DP, band
+ * origins, selection, band trace and compaction, and energy refresh, with
+ * h_items[0..4] their counts; h_ms[5] waiting for an item (h_items[5]:
+ * items taken, and the final waits); h_ms[6] counting items done and
+ * queueing the next stages (h_items[6] = h_items[5]).  7 entries each.
+ * SCPL_ERR_NOT_READY before any such launch. */
+scpl_status scpl_persist_stats(scpl_ctx *ctx, double *h_ms, int64_t *h_items);
+
 /* ---- request server (continuous batching) ----
  * Retarget requests are queued in arrival order.  Each of `lanes` worker
  * threads owns a context and a stream; whenever a lane is free it takes the
@@ -264,7 +308,8 @@ enum {
     SCPL_KERNEL_GATHER = 8,
     SCPL_KERNEL_INIT = 9,
     SCPL_KERNEL_REFRESH = 10, /* energies of the pixels whose neighbourhood changed */
-    SCPL_KERNEL_COUNT = 11
+    SCPL_KERNEL_PERSIST = 11, /* the persistent launch of SCPL_BATCH_PERSISTENT */
+    SCPL_KERNEL_COUNT = 12
 };
 scpl_status scpl_profile_enable(scpl_ctx *ctx, int32_t on);
 scpl_status scpl_profile_read(scpl_ctx *ctx, int32_t kernel, double *h_total_ms, int64_t *h_launches);

@@ -59,6 +59,13 @@ struct scpl_ctx {
     int borg_variant = 0;                // band-origin kernel variant
     int gather_variant = 0;              // gather kernel variant (frames per pass)
     int fuse_variant = 0;                // fill + compaction: 0 two launches, 1/2 fused per band
+    int batch_mode = SCPL_BATCH_GROUPS;  // how the batched path runs its iterations
+    int persist_grid = 0;                // workgroups of the persistent launch (resident at once)
+    int nxcd = 0;                        // XCDs the probe found, 0: XCD-local mode unavailable
+    int xcc_ring[16] = {};               // their XCC_IDs' rings
+    long long wall_khz = 0;              // device wall clock (the persistent launch's wait bound)
+    unsigned long long persist_trace[kPTrace] = {};  // the last timed persistent launch's counters
+    bool persist_traced = false;
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
@@ -164,13 +171,14 @@ struct JobShape {
     int32_t H, W, Wt, k;
     DpGeom g;  // DP geometry of the launch the job runs in
     bool bound = false;  // sizes for every geometry and band height (workspace bounds)
+    int32_t band = 0;    // rows per band forced (the persistent launch: 32), 0: by the frame size
     int32_t Wp() const { return (int32_t)align_up((size_t)W, 64); }
     const DpGeom &geom() const { return g; }
     int32_t Kp() const
     {
         return kKeyLeft + (int32_t)align_up((size_t)(bound ? W + kCoverSlack : geom().cover(W)), 64);
     }
-    int32_t B() const { return bound ? 32 : band_rows(H, W, g_lds_cap); }
+    int32_t B() const { return bound ? 32 : band > 0 ? band : band_rows(H, W, g_lds_cap); }
     int32_t nb() const { return (H + B() - 1) / B(); }
     int32_t kcap() const { return std::min(k, W); }
     int32_t logcap() const { return W - Wt + 2; }
@@ -824,6 +832,134 @@ scpl_status run_groups(scpl_ctx *ctx, std::vector<Group> &gs, bool use_graph, hi
     return SCPL_OK;
 }
 
+// The persistent launch's DP chunking: the caller's (or the batch
+// autotuner's) column split when its four-wavefront cover is exact, else
+// 256 rows by 384 columns.
+DpGeom persist_geom(const scpl_ctx *ctx)
+{
+    for (const DpGeom *g : {&ctx->forced, &ctx->batch_forced})
+        if (g->Q == 4 && g->HB == 16 && g->PF == 8 && g->R > 0 && g->chunk_waves() == 4 && dp_geom_fits(*g, 1))
+            return DpGeom{4, 16, 1, 8, 0, g->R, g->P};
+    return DpGeom{4, 16, 1, 8, 0, 256, 384};
+}
+
+// Ring slots of a persistent launch over jobs of these shapes: a power of
+// two, at least 4 times the most items that can wait at once (each job has
+// the items of one stage outstanding at a time), and at least 65536.
+int persist_ring(const std::vector<JobShape> &shapes, const DpGeom &g)
+{
+    int64_t most = 0;
+    for (const JobShape &s : shapes)
+        most += std::max<int64_t>({(s.W + g.P - 1) / g.P, s.nb(), (s.H + 15) / 16, 1});
+    int64_t cap = 65536;
+    while (cap < 4 * most) cap *= 2;
+    return (int)cap;
+}
+
+size_t persist_bytes(int njobs, int cap, int nring)
+{
+    return align_up(sizeof(PState) * (size_t)nring) + align_up((size_t)njobs * 4) +
+           2 * align_up((size_t)cap * 8 * (size_t)nring) + align_up(kPTrace * 8);
+}
+
+// Rings of a persistent launch: one per XCD in XCD-local mode.
+int persist_rings(const scpl_ctx *ctx)
+{
+    return ctx->batch_mode == SCPL_BATCH_PERSISTENT && ctx->nxcd > 0 ? ctx->nxcd : 1;
+}
+
+// Deals the jobs to the rings: heaviest first (rows x columns x columns to
+// remove), each to the ring with the least work so far.
+void deal_rings(std::vector<Job> &jobs, int nring)
+{
+    std::vector<int> order(jobs.size());
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](const Job &J) { return (double)J.H * J.W * (double)std::max(J.W - J.Wt, 0); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(jobs[a]) > work(jobs[b]); });
+    std::vector<double> load((size_t)nring, 0.0);
+    for (int q : order) {
+        const int r = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        jobs[q].ring = r;
+        load[r] += work(jobs[q]);
+    }
+}
+
+// Every iteration of the jobs d_jobs[0, nj) in one persistent launch on
+// stream s (captured as a graph with the ring's set-up when use_graph),
+// then their outputs gathered.  area: persist_bytes(nj, cap) of device
+// memory.  With a graph it returns after the launch has run (the graph is
+// freed then); the caller reads the states.
+scpl_status run_persistent(scpl_ctx *ctx, const Job *d_jobs, int nj, const LaunchShape &ls, const DpGeom &g, int cap,
+                           int nring, char *area, bool use_graph, hipStream_t s)
+{
+    const bool local = ctx->batch_mode == SCPL_BATCH_PERSISTENT && ctx->nxcd > 0;
+    Bump b{area};
+    PArgs a{};
+    a.jobs = d_jobs;
+    a.st = b.take<PState>((size_t)nring);
+    a.cnt = b.take<int>((size_t)nj);
+    a.seq = b.take<unsigned long long>((size_t)cap * nring);
+    a.item = b.take<unsigned long long>((size_t)cap * nring);
+    a.nring = nring;
+    for (int q = 0; q < 16; ++q) a.xcc_ring[q] = local ? ctx->xcc_ring[q] : -1;
+    unsigned long long *trace = b.take<unsigned long long>(kPTrace);
+    a.trace = ctx->profiling ? trace : nullptr;  // counted while kernels are timed
+    a.njobs = nj;
+    a.cap_mask = cap - 1;
+    a.R = g.R;
+    a.P = g.P;
+    a.lds_bytes = (int)persist_lds_bytes();
+    a.sel_lds = a.lds_bytes;
+    a.wait_ticks = 4000LL * ctx->wall_khz;  // 4 s
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_INIT, s);
+        launch_init_jobs(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+    }
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_ENERGY, s);
+        launch_energy(d_jobs, nj, ls.Hmax, ls.Wmax, s);
+    }
+    SCPL_CHECK_LAUNCH();
+    if (use_graph && !ctx->profiling && s != nullptr) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ge = nullptr;
+        SCPL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        launch_persist_clear(a, s);
+        launch_persist_seed(a, s);
+        launch_persist(a, ctx->persist_grid, local, s);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(s, &gr);
+        SCPL_TRY(le);
+        SCPL_TRY(ce);
+        hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        hipError_t xe = ie == hipSuccess ? hipGraphLaunch(ge, s) : ie;
+        // the graph is freed only once it has run
+        hipError_t se = hipStreamSynchronize(s);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(gr);
+        SCPL_TRY(xe);
+        SCPL_TRY(se);
+    } else {
+        if (a.trace) SCPL_TRY(hipMemsetAsync(a.trace, 0, kPTrace * 8, s));
+        launch_persist_clear(a, s);
+        launch_persist_seed(a, s);
+        ProfScope ps(ctx, SCPL_KERNEL_PERSIST, s);
+        launch_persist(a, ctx->persist_grid, local, s);
+    }
+    if (a.trace) {
+        SCPL_TRY(hipMemcpyAsync(ctx->persist_trace, a.trace, sizeof(ctx->persist_trace), hipMemcpyDeviceToHost, s));
+        SCPL_TRY(hipStreamSynchronize(s));
+        ctx->persist_traced = true;
+    }
+    SCPL_CHECK_LAUNCH();
+    {
+        ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
+        launch_gather(d_jobs, nj, ls.Hmax, ls.gin, ls.gout, ctx->gather_variant, s);
+    }
+    SCPL_CHECK_LAUNCH();
+    return SCPL_OK;
+}
+
 // Copies the per-iteration records of the jobs into ctx->last_log.
 scpl_status collect_logs(scpl_ctx *ctx, const std::vector<Job> &jobs, hipStream_t s)
 {
@@ -952,6 +1088,36 @@ scpl_status scpl_create(int32_t hip_device, scpl_ctx **out)
     c->lds_cap = prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : prop.sharedMemPerBlock;
     g_lds_cap = c->lds_cap;
     set_kernel_attributes(c->lds_cap);
+    // the persistent launch: as many workgroups as are resident at once, and
+    // the wall-clock rate its wait bound counts in
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0) {
+        c->wall_khz = khz;
+        c->persist_grid = std::min(persist_blocks_per_cu() * prop.multiProcessorCount, 8192);
+    }
+    // XCD-local persistent mode: the XCC_ID of the workgroups of a probe
+    // launch must follow the dispatcher's round robin over the XCDs
+    // (workgroup i on the (i mod n)-th), else the mode stays off
+    if (c->persist_grid > 0) {
+        std::vector<int> ids(4096);
+        if (probe_xcc((int)ids.size(), ids.data()) == 0) {
+            std::vector<int> first;
+            for (int v : ids) {
+                if (std::find(first.begin(), first.end(), v) != first.end()) break;
+                first.push_back(v);
+            }
+            const int n = (int)first.size();
+            // (at least two XCDs: a register that read the same everywhere
+            // would otherwise pass as a one-XCD device)
+            bool ok = n >= 2 && n <= 16 && (n & (n - 1)) == 0;
+            for (size_t i = 0; ok && i < ids.size(); ++i) ok = ids[i] == first[i % n];
+            if (ok) {
+                c->nxcd = n;
+                for (int q = 0; q < 16; ++q) c->xcc_ring[q] = -1;
+                for (int q = 0; q < n; ++q) c->xcc_ring[first[q] & 15] = q;
+            }
+        }
+    }
     // everything the plain path needs besides its workspace is made here, so
     // that scpl_retarget_noalloc allocates nothing: the events of one job
     // group, host staging for the most frames a call may have, and this
@@ -1140,14 +1306,23 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     const int nm = (int)memo.size();
     int Wall = 0;
     for (int c = 0; c < nc; ++c) Wall = std::max(Wall, clips[c].p.width);
+    // the persistent launch serves batches up to 8192 columns wide
+    // (only in XCD-local mode: without the probe's XCDs the batch runs as job
+    // groups)
+    const bool persist = batched && ctx->batch_mode == SCPL_BATCH_PERSISTENT && Wall <= 8192 && nj > 0 &&
+                         ctx->persist_grid > 0 && ctx->nxcd > 0;
+    const int nring = persist ? persist_rings(ctx) : 1;
+    const DpGeom gpers = persist_geom(ctx);
     // a batched DP launch serves every job: its geometry follows the widest
     // (a geometry forced by the caller first, then the batch autotuner's)
-    const DpGeom gall = (ctx->forced.Q == 0 && ctx->batch_forced.Q > 0 && dp_geom_fits(ctx->batch_forced, Wall))
+    const DpGeom gall = persist ? gpers
+                        : (ctx->forced.Q == 0 && ctx->batch_forced.Q > 0 && dp_geom_fits(ctx->batch_forced, Wall))
                             ? ctx->batch_forced
                             : select_geom(ctx, Wall, nj);
     auto shape_of = [&](const Pending &q) {
         const scpl_params &p = clips[q.clip].p;
         JobShape js{p.height, p.width, p.target_width, p.seams_per_iter, batched ? gall : select_geom(ctx, p.width, 1)};
+        if (persist) js.band = 32;
         return js;
     };
     // area B: job workspaces (all jobs when batched; one shared per clip shape
@@ -1157,11 +1332,20 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         const size_t jb = job_bytes(shape_of(q));
         job_area = batched ? job_area + jb : std::max(job_area, jb);
     }
-    SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)(nj + nm)) + align_up(16 * (size_t)nj)));
+    int pcap = 0;
+    if (persist) {
+        std::vector<JobShape> shapes;
+        for (const Pending &q : pend) shapes.push_back(shape_of(q));
+        pcap = persist_ring(shapes, gpers);
+    }
+    const size_t pbytes = persist ? persist_bytes(nj, pcap, nring) : 0;
+    SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)(nj + nm)) + align_up(16 * (size_t)nj) +
+                                 pbytes));
     Bump jdev{static_cast<char *>(ctx->jws)};
     char *job_ws = jdev.take<char>(job_area);
     Job *d_jobs = jdev.take<Job>((size_t)(nj + nm));  // carving jobs, then memorised buffers
     int32_t *d_states = jdev.take<int32_t>(4 * (size_t)nj);
+    char *parea = persist ? jdev.take<char>(pbytes) : nullptr;
     // batched: the jobs are dealt to the groups in order of decreasing
     // length, so that every group gets a share of the heavy buffers; a
     // group's jobs are consecutive in the job table
@@ -1188,6 +1372,10 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         carve_job(J, js, jb, d_states + 4 * slot[q]);
         h_jobs[slot[q]] = J;
         jobs.push_back(J);
+    }
+    if (persist) {  // each job's work ring (XCD)
+        deal_rings(jobs, nring);
+        for (int q = 0; q < nj; ++q) h_jobs[slot[q]].ring = jobs[q].ring;
     }
     // a memorised buffer is gathered like its source job (same column map
     // and mask, which hold that job's result once it is done) over its own
@@ -1231,6 +1419,28 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
             }
         return G;
     };
+    if (persist) {
+        LaunchShape ls;
+        for (const Pending &q : pend) ls.add(shape_of(q), clips[q.clip].p.channels);
+        st = run_persistent(ctx, d_jobs, nj, ls, gpers, pcap, nring, parea, use_graph, s);
+        if (st != SCPL_OK) {
+            (void)hipStreamSynchronize(s);
+            return st;
+        }
+        // every job must have reached its target width, and no workgroup
+        // may have given up waiting
+        // (the abort flag lands in the window-sum staging, unused after the segmentation)
+        int32_t *h_abort = reinterpret_cast<int32_t *>(h_sums);
+        SCPL_TRY(hipMemcpyAsync(h_states, d_states, (size_t)nj * 16, hipMemcpyDeviceToHost, s));
+        SCPL_TRY(hipMemcpyAsync(h_abort, &reinterpret_cast<PState *>(parea)->abort, 4, hipMemcpyDeviceToHost, s));
+        SCPL_TRY(hipStreamSynchronize(s));
+        if (*h_abort != 0) return SCPL_ERR_INTERNAL;
+        for (int j = 0; j < nj; ++j)
+            if (h_states[4 * j] < 0) return SCPL_ERR_INTERNAL;
+        st = gather_memo(0, nm);
+        if (st != SCPL_OK) return st;
+        return collect_logs(ctx, jobs, s);
+    }
     if (batched) {
         std::vector<Group> gs;
         for (int g = 0; g < ng; ++g)
@@ -1386,6 +1596,37 @@ scpl_status scpl_retarget_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     }
     SCPL_TRY(hipSetDevice(ctx->device));
     return run_clips_2d(ctx, clips, n_clips, true, nullptr, static_cast<hipStream_t>(stream));
+}
+
+scpl_status scpl_persist_stats(scpl_ctx *ctx, double *h_ms, int64_t *h_items)
+{
+    if (!ctx || !h_ms || !h_items) return SCPL_ERR_INVALID_ARG;
+    if (!ctx->persist_traced || ctx->wall_khz <= 0) return SCPL_ERR_NOT_READY;
+    const double ms_per_tick = 1.0 / (double)ctx->wall_khz;
+    for (int q = 0; q < 7; ++q) {
+        const int at = q < 5 ? 2 * q : q == 5 ? kPTraceWait : kPTraceDone;
+        h_ms[q] = (double)ctx->persist_trace[at] * ms_per_tick;
+        h_items[q] = q < 6 ? (int64_t)ctx->persist_trace[at + 1] : ctx->persist_trace[kPTraceWait + 1];
+    }
+    return SCPL_OK;
+}
+
+scpl_status scpl_device_xcds(scpl_ctx *ctx, int32_t *h_n)
+{
+    if (!ctx || !h_n) return SCPL_ERR_INVALID_ARG;
+    *h_n = ctx->nxcd;
+    return SCPL_OK;
+}
+
+scpl_status scpl_batch_mode(scpl_ctx *ctx, int32_t mode)
+{
+    if (!ctx || mode < SCPL_BATCH_GROUPS || mode > SCPL_BATCH_PERSISTENT_AGENT) return SCPL_ERR_INVALID_ARG;
+    // the one-ring agent-scope kernel is switched off: a run of it faulted
+    // the GPU with no cause found in its code
+    if (mode == SCPL_BATCH_PERSISTENT_AGENT) return SCPL_ERR_DEVICE;
+    if (mode != SCPL_BATCH_GROUPS && ctx->persist_grid <= 0) return SCPL_ERR_DEVICE;
+    ctx->batch_mode = mode;
+    return SCPL_OK;
 }
 
 scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n)

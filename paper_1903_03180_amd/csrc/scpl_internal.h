@@ -60,6 +60,7 @@ struct Job {
     int32_t kcap;           // min(k, W): room for children / seams
     int32_t logcap;         // records in log
     int32_t buffer_index;   // index of the buffer within its clip
+    int32_t ring;           // persistent launch: the work ring (XCD) that serves the job
     // workspace (device)
     int16_t *M;             // column map (carved column -> original column), H x Wp, compacted in place
     uint16_t *K;            // DP input rows: 4 floor(SE / T) of carved column j at [i Kp + KL + j],
@@ -174,6 +175,51 @@ void launch_seams_out(const int16_t *src, int pitch, int32_t *dst, int kk, int H
 // indicator codes <-> int8 {-1, 0, 1} with pitch change (stage entry points)
 void launch_dir_out(const uint8_t *codes, int pitch, int8_t *dst, int H, int W, hipStream_t s);
 void launch_dir_in(const int8_t *src, uint8_t *codes, int pitch, int H, int W, hipStream_t s);
+// Persistent launch: every iteration of every job of a batch in one launch
+// of workgroups that take work items from a ring in device memory.
+constexpr int kPersistThreads = 256;
+struct PState {  // scheduler of one launch, one 256-byte line per field
+    int head;    // next ring slot to take
+    int pad0[63];
+    int tail;    // next ring slot to fill
+    int pad1[63];
+    int active;  // jobs still carving
+    int pad2[63];
+    int abort;   // set by a workgroup that waited too long for an item
+    int pad3[63];
+};
+struct PArgs {
+    const Job *jobs;
+    PState *st;                // per ring (the first one's abort flag serves all)
+    int *cnt;                  // per job: items of its current phase done
+    unsigned long long *seq;   // per ring slot: the slot number it holds (generation), all ones when empty
+    unsigned long long *item;  // per ring slot: (job << 32) | (phase << 24) | part
+    int njobs;
+    int nring;                 // rings: one per XCD in XCD-local mode, else one
+    int xcc_ring[16];          // XCD-local mode: ring of the workgroups on each XCC_ID (-1: none)
+    int cap_mask;              // slots per ring - 1 (a power of two)
+    int R, P;                  // DP: rows per chunk, columns per item (P + 2 R <= 896)
+    int lds_bytes;             // dynamic LDS of a workgroup (persist_lds_bytes)
+    int sel_lds;               // of which the selection may use
+    long long wait_ticks;      // wall-clock ticks a workgroup waits for an item before it aborts
+    unsigned long long *trace; // null, or kPTrace counters summed over the workgroups (wall-clock ticks)
+};
+// trace counters: [2 p] ticks in items of phase p (DP, BORG, SELECT, BAND,
+// REFRESH), [2 p + 1] their count; [kPTraceWait] ticks waiting for an item,
+// [kPTraceWait + 1] items taken (and final waits); [kPTraceDone] ticks
+// counting items done and queueing the next phases
+constexpr int kPTraceWait = 10;
+constexpr int kPTraceDone = 12;
+constexpr int kPTrace = 13;
+size_t persist_lds_bytes();
+int persist_blocks_per_cu();
+void launch_persist_clear(const PArgs &a, hipStream_t s);
+void launch_persist_seed(const PArgs &a, hipStream_t s);
+// local: the XCD-local kernel (every job's ring served by the workgroups of
+// one XCD), else the agent-scope one (one ring)
+void launch_persist(const PArgs &a, int grid, bool local, hipStream_t s);
+// XCC_ID of each of n workgroups of a probe launch (synchronises); 0 on success
+int probe_xcc(int n, int *h_out);
 size_t select_lds_bytes(size_t lds_cap);
 void set_kernel_attributes(size_t lds_cap);
 

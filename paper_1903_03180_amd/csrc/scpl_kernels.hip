@@ -1015,23 +1015,21 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_band_kernel(const Jo
 // than one workgroup per buffer can afford, a row costs fewer instructions
 // per wavefront, and the launch boundaries replace any wait between
 // workgroups.
+// Workgroup gx of the chunk of rows [r0, r0 + R) of job J in iteration r
+// (width Wr > Wt), with nthreads threads; rowbuf: 2 x nwv C keys of LDS.
 template <int Q, int HB, int PF>
-__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int r0, int R, int P)
+__device__ __forceinline__ void dp_chunk_body(const Job &J, int Wr, int gx, int r0, int R, int P, int nthreads,
+                                              uint32_t *rowbuf)
 {
     constexpr int C = 64 * Q - 2 * HB;
     static_assert(HB % Q == 0 && C > 0, "halo must be whole lanes");
-    extern __shared__ uint32_t rowbuf[];  // 2 x nwv C keys: the cover
-    const Job &J = jobs[blockIdx.y];
-    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
-    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
-    if (Wr <= J.Wt) return;
     const int H = J.H, Kp = J.Kp, Wp = J.Wp;
     if (r0 >= H) return;
-    const int A = (int)blockIdx.x * P;
+    const int A = gx * P;
     if (A >= Wr) return;
     const int B = min(A + P, Wr);
     const int Bs = B == Wr ? Wp : B;  // the last workgroup also stores the padding codes
-    const int nwv = blockDim.x >> 6;
+    const int nwv = nthreads >> 6;
     const int cw = nwv * C;
     const int X0 = max(A - R, 0);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1146,6 +1144,17 @@ __global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const J
     }
 }
 
+template <int Q, int HB, int PF>
+__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int r0, int R, int P)
+{
+    extern __shared__ uint32_t rowbuf[];  // 2 x nwv C keys: the cover
+    const Job &J = jobs[blockIdx.y];
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
+    if (Wr <= J.Wt) return;
+    dp_chunk_body<Q, HB, PF>(J, Wr, (int)blockIdx.x, r0, R, P, (int)blockDim.x, rowbuf);
+}
+
 // ----------------------------------------------------------- band origins
 //
 // For band b (rows [lo, hi]) and every column j at row hi: follow the
@@ -1198,18 +1207,11 @@ __device__ __forceinline__ int stage_bytes(uint8_t *lds, int lp, const uint8_t *
     return c0 - a0;
 }
 
+// Columns [c0, c0 + COLS) of band b of job J (width Wr); COLS threads;
+// tile: B rows x (COLS + 2B + 8) bytes of LDS.
 template <int COLS>
-__global__ __launch_bounds__(COLS) void borg_kernel(const Job *jobs)
+__device__ __forceinline__ void borg_body(const Job &J, int Wr, int b, int c0, uint8_t *tile)
 {
-    extern __shared__ uint8_t tile[];  // B rows x (COLS + 2B + 8) bytes
-    const Job &J = jobs[blockIdx.z];
-    const int r = job_iter(J);
-    const int Wr = job_width(J, r);
-    if (Wr <= J.Wt) return;
-    const int b = blockIdx.y;
-    if (b >= J.nb) return;
-    const int c0 = blockIdx.x * COLS;
-    if (c0 >= Wr) return;
     const int B = J.B;
     const int lo = b * B, hi = min(lo + B, J.H) - 1;
     const int rlo = max(lo, 1);
@@ -1224,6 +1226,21 @@ __global__ __launch_bounds__(COLS) void borg_kernel(const Job *jobs)
         for (int i = hi; i >= rlo; --i) c += code_step(tile[(i - rlo) * lp + c + sh]);
         J.borg[(size_t)b * J.Wp + j] = (int8_t)(c - j);
     }
+}
+
+template <int COLS>
+__global__ __launch_bounds__(COLS) void borg_kernel(const Job *jobs)
+{
+    extern __shared__ uint8_t tile[];  // B rows x (COLS + 2B + 8) bytes
+    const Job &J = jobs[blockIdx.z];
+    const int r = job_iter(J);
+    const int Wr = job_width(J, r);
+    if (Wr <= J.Wt) return;
+    const int b = blockIdx.y;
+    if (b >= J.nb) return;
+    const int c0 = blockIdx.x * COLS;
+    if (c0 >= Wr) return;
+    borg_body<COLS>(J, Wr, b, c0, tile);
 }
 
 // Parent labels of the last row from the band origins (stage entry point
@@ -1263,22 +1280,14 @@ __device__ void band_jumps(const Job &J, int kk, const int8_t *bo, int bo_pitch,
     }
 }
 
-__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_bytes, int use_lab_array)
+// Selection of job J in iteration r (width Wr > Wt) by NT threads; dsm:
+// lds_bytes of LDS, scan_tmp: 16 ints of LDS.  NT = 256 serves widths up to
+// 8192 (32 candidates per thread at most).
+template <int NT>
+__device__ __forceinline__ void select_body(const Job &J, int r, int Wr, int lds_bytes, int use_lab_array,
+                                            uint64_t *dsm, int *scan_tmp)
 {
-    extern __shared__ uint64_t dsm[];
-    __shared__ int scan_tmp[16];
-    const Job &J = jobs[blockIdx.x];
-    const int r = job_iter(J);
-    const int Wr = job_width(J, r);
     const int tid = threadIdx.x;
-    if (Wr <= J.Wt) {
-        if (tid == 0 && r + 1 < J.logcap) {
-            J.log[4 * (r + 1)] = Wr;
-            J.log[4 * (r + 1) + 1] = 0;
-            J.log[4 * (r + 1) + 2] = 0;
-        }
-        return;
-    }
     const int nb = J.nb;
     const size_t key_bytes = (size_t)2 * Wr * sizeof(uint64_t);
     const bool keys_lds = key_bytes <= (size_t)lds_bytes;
@@ -1290,25 +1299,58 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_b
     uint8_t *bo_s = reinterpret_cast<uint8_t *>(dsm) + key_room;
     const int8_t *bo = bo_lds ? reinterpret_cast<const int8_t *>(bo_s) : J.borg;
     const int bo_pitch = bo_lds ? bo_lp : J.Wp;
+    // band origins that do not all fit beside the keys: staged G bands at a
+    // time, and the label and jump walks advance group by group (their
+    // positions kept in the candidate half of the key array)
+    const int G = !bo_lds ? (int)(((size_t)lds_bytes - key_room) / (size_t)bo_lp) : 0;
+    const bool grouped = G >= 2 && !use_lab_array;
     constexpr uint64_t kNone = ~0ull;
+    auto stage_bands = [&](int lo, int hi) {
+        __syncthreads();  // the previous group's rows are read
+        stage_bytes(bo_s, bo_lp, reinterpret_cast<const uint8_t *>(J.borg), J.Wp, lo, hi - lo + 1, 0, Wr, tid, NT);
+        __syncthreads();
+    };
 
-    for (int j = tid; j < Wr; j += 1024) key[j] = kNone;
-    if (bo_lds) stage_bytes(bo_s, bo_lp, reinterpret_cast<const uint8_t *>(J.borg), J.Wp, 0, nb, 0, Wr, tid, 1024);
-    __syncthreads();
-    for (int j = tid; j < Wr; j += 1024) {
-        int l;
-        if (use_lab_array) {
-            l = J.lab_last[j];
-        } else {
-            l = j;
-            for (int b = nb - 1; b >= 0; --b) l += bo[(size_t)b * bo_pitch + l];
+    if (grouped) {
+        int *lab = reinterpret_cast<int *>(cand);
+        for (int j = tid; j < Wr; j += NT) {
+            key[j] = kNone;
+            lab[j] = j;
         }
-        const uint64_t kv = ((uint64_t)(uint32_t)J.ce_last[j] << 15) | (uint64_t)j;
-        if ((unsigned)l < (unsigned)Wr) atomicMin((unsigned long long *)&key[l], (unsigned long long)kv);
+        for (int hi = nb - 1; hi >= 0; hi -= G) {
+            const int lo = max(hi - G + 1, 0);
+            stage_bands(lo, hi);
+            for (int j = tid; j < Wr; j += NT) {
+                int l = lab[j];
+                for (int b = hi; b >= lo; --b) l += (int8_t)bo_s[(b - lo) * bo_lp + l];
+                lab[j] = l;
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < Wr; j += NT) {
+            const int l = lab[j];
+            const uint64_t kv = ((uint64_t)(uint32_t)J.ce_last[j] << 15) | (uint64_t)j;
+            if ((unsigned)l < (unsigned)Wr) atomicMin((unsigned long long *)&key[l], (unsigned long long)kv);
+        }
+    } else {
+        for (int j = tid; j < Wr; j += NT) key[j] = kNone;
+        if (bo_lds) stage_bytes(bo_s, bo_lp, reinterpret_cast<const uint8_t *>(J.borg), J.Wp, 0, nb, 0, Wr, tid, NT);
+        __syncthreads();
+        for (int j = tid; j < Wr; j += NT) {
+            int l;
+            if (use_lab_array) {
+                l = J.lab_last[j];
+            } else {
+                l = j;
+                for (int b = nb - 1; b >= 0; --b) l += bo[(size_t)b * bo_pitch + l];
+            }
+            const uint64_t kv = ((uint64_t)(uint32_t)J.ce_last[j] << 15) | (uint64_t)j;
+            if ((unsigned)l < (unsigned)Wr) atomicMin((unsigned long long *)&key[l], (unsigned long long)kv);
+        }
     }
     __syncthreads();
 
-    const int chunk = (Wr + 1023) / 1024;
+    const int chunk = (Wr + NT - 1) / NT;
     const int l0 = min(tid * chunk, Wr), l1 = min(l0 + chunk, Wr);
     int cnt = 0;
     for (int l = l0; l < l1; ++l) cnt += key[l] != kNone;
@@ -1319,7 +1361,7 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_b
     __syncthreads();
 
     const int kk = min(min(J.k, peff), Wr - J.Wt);
-    const int chunk2 = (peff + 1023) / 1024;  // <= 32
+    const int chunk2 = (peff + NT - 1) / NT;  // <= 32
     const int a0 = min(tid * chunk2, peff), a1 = min(a0 + chunk2, peff);
     uint32_t selmask = 0;
     int nsel = 0;
@@ -1338,7 +1380,25 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_b
         if (selmask & (1u << (a - a0))) J.children[soff++] = (int)(cand[a] & 0x7fff);
     __syncthreads();
 
-    band_jumps(J, kk, bo, bo_pitch, tid, 1024);
+    if (grouped) {
+        // every taken child walks the band origins upward, G bands at a time
+        int *cpos = reinterpret_cast<int *>(cand);
+        for (int q = tid; q < kk; q += NT) cpos[q] = J.children[q];
+        for (int hi = nb - 1; hi >= 0; hi -= G) {
+            const int lo = max(hi - G + 1, 0);
+            stage_bands(lo, hi);
+            for (int q = tid; q < kk; q += NT) {
+                int c = cpos[q];
+                for (int b = hi; b >= lo; --b) {
+                    J.bcol[q * nb + b] = c;
+                    if (b > 0) c += (int8_t)bo_s[(b - lo) * bo_lp + c];
+                }
+                cpos[q] = c;
+            }
+        }
+    } else {
+        band_jumps(J, kk, bo, bo_pitch, tid, NT);
+    }
 
     if (tid == 0) {
         J.log[4 * r + 1] = peff;
@@ -1353,6 +1413,24 @@ __global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_b
         J.state[2] = kk;
         if (Wr - kk <= J.Wt) J.state[0] = r + 1;
     }
+}
+
+__global__ __launch_bounds__(1024) void select_kernel(const Job *jobs, int lds_bytes, int use_lab_array)
+{
+    extern __shared__ uint64_t dsm[];
+    __shared__ int scan_tmp[16];
+    const Job &J = jobs[blockIdx.x];
+    const int r = job_iter(J);
+    const int Wr = job_width(J, r);
+    if (Wr <= J.Wt) {
+        if (threadIdx.x == 0 && r + 1 < J.logcap) {
+            J.log[4 * (r + 1)] = Wr;
+            J.log[4 * (r + 1) + 1] = 0;
+            J.log[4 * (r + 1) + 2] = 0;
+        }
+        return;
+    }
+    select_body<1024>(J, r, Wr, lds_bytes, use_lab_array, dsm, scan_tmp);
 }
 
 // Band jumps alone, for the backtrack stage entry point (children and
@@ -1601,10 +1679,11 @@ __global__ __launch_bounds__(64 * ROWS) void update_kernel(const Job *jobs)
 // indicator rows a seam can reach from its column at the band's last row, and
 // one lane follows it upward.  Then every seam's column in every row of the
 // band (for the refresh) and its removal mark in the buffer mask, through the
-// column map before it moves.  Then the band's rows are compacted, as
-// update_kernel, with their thresholds taken from the paths in LDS.  No row
-// of the band needs anything from another band.  Serves launches whose jobs
-// all have 32-row bands and at most kUpdSeams seams per iteration.
+// column map before it moves.  Seams are taken 64 at a time.  Then the band's
+// rows are compacted, as update_kernel, with their thresholds taken from the
+// paths in LDS (from the seam rows just written when there are more than 64
+// seams).  No row of the band needs anything from another band.  Serves jobs
+// with 32-row bands.
 constexpr int kFuseB = 32;
 constexpr int kFuseSpan = 1024;                // new columns per compaction pass
 constexpr int kFuseWin = 2 * kFuseB + 8;       // window pitch: a seam's window is at most 2 B - 1 wide, staged from a word
@@ -1618,66 +1697,78 @@ __host__ __device__ constexpr size_t band_update_lds(int waves)
            (size_t)waves * (kUpdSeams + 1) * 4;            // thresholds of the row a wavefront compacts
 }
 
+// Band b of job J in iteration r (width Wr > Wt) by 64 WAVES threads; fsm:
+// band_update_lds(WAVES) bytes of LDS, 16-byte aligned.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void band_update_kernel(const Job *jobs)
+__device__ __forceinline__ void band_update_body(const Job &J, int r, int Wr, int b, uint8_t *fsm)
 {
-    extern __shared__ __align__(16) uint8_t fsm[];
     uint16_t *stM = reinterpret_cast<uint16_t *>(fsm);
     uint16_t *stK = stM + (size_t)WAVES * kFuseStage;
     uint8_t *win = reinterpret_cast<uint8_t *>(stK + (size_t)WAVES * kFuseStage);
     int16_t *path = reinterpret_cast<int16_t *>(win + (size_t)WAVES * (kFuseB - 1) * kFuseWin);  // [kUpdSeams][kFuseB]
     int *thr = reinterpret_cast<int *>(path + (size_t)kUpdSeams * kFuseB);
-    const Job &J = jobs[blockIdx.y];
-    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
-    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
-    if (Wr <= J.Wt) return;
-    const int b = blockIdx.x;
-    if (b >= J.nb) return;
     const int kk = __builtin_amdgcn_readfirstlane(J.log[4 * r + 2]);
     const int H = J.H, nb = J.nb, W = J.W, Wp = J.Wp;
     const int lo = b * kFuseB, hi = min(lo + kFuseB, H) - 1;
     const int span = hi - lo;  // < kFuseB
+    const int rows = span + 1;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    // 1. the seams' paths through the band
     uint8_t *ww = win + (size_t)w * (kFuseB - 1) * kFuseWin;
-    for (int s = w; s < kk; s += WAVES) {
-        const int c_end = J.bcol[s * nb + b];
-        const int wlo = max(c_end - span, 0), whi = min(c_end + span + 1, Wr);
-        const int sh = stage_bytes(ww, kFuseWin, J.dir, Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            int c = c_end;
-            path[s * kFuseB + span] = (int16_t)c;
-            for (int i = hi; i > lo; --i) {
-                c += code_step(ww[(i - lo - 1) * kFuseWin + c + sh]);
-                path[s * kFuseB + i - 1 - lo] = (int16_t)c;
+    for (int s0 = 0; s0 < kk; s0 += kUpdSeams) {
+        const int ns = min(kUpdSeams, kk - s0);
+        // 1. the paths of seams [s0, s0 + ns) through the band
+        for (int s = w; s < ns; s += WAVES) {
+            const int c_end = J.bcol[(s0 + s) * nb + b];
+            const int wlo = max(c_end - span, 0), whi = min(c_end + span + 1, Wr);
+            const int sh = stage_bytes(ww, kFuseWin, J.dir, Wp, lo + 1, span, wlo, whi, lane, 64) - wlo;
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                int c = c_end;
+                path[s * kFuseB + span] = (int16_t)c;
+                for (int i = hi; i > lo; --i) {
+                    c += code_step(ww[(i - lo - 1) * kFuseWin + c + sh]);
+                    path[s * kFuseB + i - 1 - lo] = (int16_t)c;
+                }
             }
+            __builtin_amdgcn_wave_barrier();  // the window is read before the next seam's staging
         }
-        __builtin_amdgcn_wave_barrier();  // the window is read before the next seam's staging
+        __syncthreads();
+        // 2. their columns in every row of the band, and their marks in the
+        // buffer mask (original columns, through the column map before it moves)
+        for (int x = (int)threadIdx.x; x < ns * rows; x += 64 * WAVES) {
+            const int s = x / rows, q = x - s * rows;
+            const int i = lo + q;
+            const int col = path[s * kFuseB + q];
+            J.seams[(size_t)i * J.kcap + s0 + s] = (int16_t)col;
+            J.bmask[(size_t)i * W + mcol(J.M + (size_t)i * Wp, col, W)] = (uint16_t)(r + 1);
+        }
+        __syncthreads();  // every mark has read the column map; the paths may be overwritten
     }
-    __syncthreads();
-    // 2. the seams' columns in every row of the band, and their marks in the
-    // buffer mask (original columns, through the column map before it moves)
-    const int rows = span + 1;
-    for (int x = (int)threadIdx.x; x < kk * rows; x += 64 * WAVES) {
-        const int s = x / rows, q = x - s * rows;
-        const int i = lo + q;
-        const int col = path[s * kFuseB + q];
-        J.seams[(size_t)i * J.kcap + s] = (int16_t)col;
-        J.bmask[(size_t)i * W + mcol(J.M + (size_t)i * Wp, col, W)] = (uint16_t)(r + 1);
-    }
-    __syncthreads();  // every mark has read the column map
     // 3. the band's rows compacted
     int *tw = thr + (size_t)w * (kUpdSeams + 1);
     uint16_t *sM = stM + (size_t)w * kFuseStage, *sK = stK + (size_t)w * kFuseStage;
     for (int q = w; q < rows; q += WAVES) {
-        tw[lane] = lane < kk ? (int)path[lane * kFuseB + q] - lane : 0x7fffffff;
-        if (lane == 0) tw[kUpdSeams] = 0x7fffffff;
+        if (kk <= kUpdSeams) {
+            tw[lane] = lane < kk ? (int)path[lane * kFuseB + q] - lane : 0x7fffffff;
+            if (lane == 0) tw[kUpdSeams] = 0x7fffffff;
+        }
         __builtin_amdgcn_wave_barrier();
         compact_row<kFuseSpan>(J, r, Wr, kk, lo + q, tw, sM, sK, lane);
         __builtin_amdgcn_wave_barrier();  // the thresholds are read before the next row's
     }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void band_update_kernel(const Job *jobs)
+{
+    extern __shared__ __align__(16) uint8_t fsm[];
+    const Job &J = jobs[blockIdx.y];
+    const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
+    const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
+    if (Wr <= J.Wt) return;
+    if ((int)blockIdx.x >= J.nb) return;
+    band_update_body<WAVES>(J, r, Wr, (int)blockIdx.x, fsm);
 }
 
 // Refresh of the pixels whose 3x3 neighbourhood changed.  Column-map rows
@@ -1722,23 +1813,29 @@ __device__ __forceinline__ void end_iteration(const Job &J, int r)
         J.state[3] = r + 1;
 }
 
+struct RefreshLds {
+    int R[kRefreshRows + 2][kRefreshSeams];  // rows i0-1 .. i0+16 (clamped): old column - s
+    int flist[kRefreshList];                 // (row in band << 16) | new column
+    Stencil fst[kRefreshList];
+    uint32_t fsum[kRefreshList];
+    int nf;
+};
+
+// Rows [16 bx, 16 bx + 16) of job J in iteration r (width Wr > Wt) by NT
+// threads, with L in LDS.
 template <int NT>
-__global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
+__device__ __forceinline__ void refresh_body(const Job &J, int r, int Wr, int bx, RefreshLds &L)
 {
-    __shared__ int R[kRefreshRows + 2][kRefreshSeams];  // rows i0-1 .. i0+16 (clamped): old column - s
-    __shared__ int flist[kRefreshList];                 // (row in band << 16) | new column
-    __shared__ Stencil fst[kRefreshList];
-    __shared__ uint32_t fsum[kRefreshList];
-    __shared__ int nf;
-    const Job &J = jobs[blockIdx.y];
-    const int r = job_iter(J);
-    const int Wr = job_width(J, r);
-    if (Wr <= J.Wt) return;  // finished before this iteration: no iteration to end
+    auto &R = L.R;
+    auto &flist = L.flist;
+    auto &fst = L.fst;
+    auto &fsum = L.fsum;
+    auto &nf = L.nf;
     const int kk = J.log[4 * r + 2];
     const int Wn = Wr - kk;
     const int H = J.H, Wp = J.Wp, W = J.W, T = J.T;
     const int Kp = J.Kp;
-    const int i0 = blockIdx.x * kRefreshRows;
+    const int i0 = bx * kRefreshRows;
     // the job's last iteration needs no refresh, nor do rows past its height,
     // but every workgroup of the job counts itself done below
     if (Wn > J.Wt && i0 < H) {
@@ -1837,7 +1934,344 @@ __global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
             Kn[(size_t)i * Kp + c] = (uint16_t)((fsum[p] / (uint32_t)T) << 2);
         }
     }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void refresh_kernel(const Job *jobs)
+{
+    __shared__ RefreshLds L;
+    const Job &J = jobs[blockIdx.y];
+    const int r = job_iter(J);
+    const int Wr = job_width(J, r);
+    if (Wr <= J.Wt) return;  // finished before this iteration: no iteration to end
+    refresh_body<NT>(J, r, Wr, (int)blockIdx.x, L);
     end_iteration(J, r);
+}
+
+// ------------------------------------------------------ persistent launch
+//
+// Every iteration of every job of a batch in one launch.  Workgroups of 256
+// threads take work items from rings in device memory; an item is one phase
+// of one job's iteration, or one part of it:
+//   DP        a workgroup's columns of a chunk of R rows (dp_chunk_body),
+//             chunk after chunk;
+//   BORG      one band's origins over 512 columns;
+//   SELECT    the job's selection (one item);
+//   BAND      one band's seam trace and compaction (band_update_body);
+//   REFRESH   16 rows of the partial energy refresh.
+// Each job counts the finished items of its current phase; the workgroup
+// that finishes the last one puts the next phase's items in the job's ring
+// (after the last band of a job's last iteration: the job is done).  So every
+// job runs its own iteration chain, and the jobs fill the device between
+// them.
+//
+// XCD-local mode (LOCAL): there is one ring per XCD; each job belongs to one
+// ring, and only the workgroups running on that XCD (hardware register
+// XCC_ID) take its items.  All of a job's reads and writes then meet in that
+// XCD's L2 cache: a workgroup publishes its results by waiting until its
+// stores have reached the L2 (no L2 write-back), and a workgroup that takes
+// an item makes an agent-scope acquire (its L1 forgets what it holds).
+// Agent mode: one ring served by every workgroup, with agent-scope release
+// (L2 write-back) and acquire around every item, for devices where the XCD
+// of a workgroup cannot be trusted.
+//
+// Ring slot t holds an item and its generation t; a workgroup takes the next
+// slot number of its ring and waits until that generation appears.  It
+// leaves when no job of its ring is carving, or when it has waited longer
+// than wait_ticks of the wall clock (then it raises the abort flag, every
+// workgroup leaves and the host reports an error): no wait is unbounded.
+
+enum : int { kPDp = 0, kPBorg = 1, kPSelect = 2, kPBand = 3, kPRefresh = 4 };
+constexpr int kPBorgCols = 512;  // columns of one band-origin item
+
+__device__ __forceinline__ unsigned long long p_make(int job, int phase, int x)
+{
+    return ((unsigned long long)(unsigned)job << 32) | ((unsigned long long)(unsigned)phase << 24) |
+           (unsigned long long)(unsigned)(x & 0xffffff);
+}
+
+// items of a phase of job J at width Wr (DP: per chunk)
+__device__ __forceinline__ int p_items(const Job &J, int phase, int Wr, int P)
+{
+    switch (phase) {
+    case kPDp: return (Wr + P - 1) / P;
+    case kPBorg: return J.nb * ((Wr + kPBorgCols - 1) / kPBorgCols);
+    case kPBand: return J.nb;
+    case kPSelect: return 1;
+    default: return (J.H + kRefreshRows - 1) / kRefreshRows;
+    }
+}
+
+__device__ __forceinline__ int p_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ void p_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Waits until this wavefront's global stores have reached the L2 cache
+// (s_waitcnt vmcnt(0)).  A workgroup barrier waits only for LDS, so each
+// wavefront waits for its own stores before the barrier after which the
+// workgroup's results count as published.
+__device__ __forceinline__ void p_stores_done() { __builtin_amdgcn_s_waitcnt(0x0f70); }
+
+// A value another workgroup wrote with an ordinary store: LOCAL, an ordinary
+// load (after p_acquire_wave: it reads this XCD's L2, where the store is);
+// agent mode, after the agent-scope acquire, any load.
+template <bool LOCAL>
+__device__ __forceinline__ int p_read(const int *p)
+{
+    if constexpr (LOCAL) return *p;
+    else return p_load(p);
+}
+
+// Before a wavefront reads what other workgroups published: an agent-scope
+// acquire, which invalidates the compute unit's L1 (and the L2's lines of
+// memory that is not this XCD's to cache; in LOCAL mode the data it reads
+// were written on this XCD and sit in its L2 or in memory).
+template <bool LOCAL>
+__device__ __forceinline__ void p_acquire_wave()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Everything the workgroup wrote is published: every wavefront's stores
+// reach the L2; in agent mode thread 0 then writes the L2 back.
+template <bool LOCAL>
+__device__ __forceinline__ void p_release_block()
+{
+    p_stores_done();
+    __syncthreads();
+    if constexpr (!LOCAL) {
+        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+}
+
+struct PRing {
+    PState *st;
+    unsigned long long *seq, *item;
+};
+
+__device__ __forceinline__ PRing p_ring(const PArgs &a, int ring)
+{
+    const size_t cap = (size_t)a.cap_mask + 1;
+    return PRing{a.st + ring, a.seq + (size_t)ring * cap, a.item + (size_t)ring * cap};
+}
+
+// n items (job, phase, xf(i)) into ring q, by the whole workgroup; what
+// every thread wrote before is published with them.
+template <bool LOCAL, class XF>
+__device__ void p_push(const PArgs &a, const PRing &q, int job, int phase, int n, XF xf, int *s_t0)
+{
+    if (threadIdx.x == 0) *s_t0 = __hip_atomic_fetch_add(&q.st->tail, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t0 = *s_t0;
+    for (int i = threadIdx.x; i < n; i += kPersistThreads)
+        q.item[(unsigned)(t0 + i) & a.cap_mask] = p_make(job, phase, xf(i));
+    p_release_block<LOCAL>();
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kPersistThreads)
+        __hip_atomic_store(&q.seq[(unsigned)(t0 + i) & a.cap_mask], (unsigned long long)(unsigned)(t0 + i),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A job's iteration ends: it moves to iteration r + 1 and carves on (its DP
+// items), or it is done.
+template <bool LOCAL>
+__device__ void p_end_iteration(const PArgs &a, const PRing &q, const Job &J, int job, int r, int Wn, int *s_t0)
+{
+    if (threadIdx.x == 0) p_store(&J.state[3], r + 1);
+    if (Wn > J.Wt) {
+        if (r + 2 >= J.logcap) {  // every iteration removes a column: cannot happen
+            if (threadIdx.x == 0) p_store(&a.st->abort, 1);
+            return;
+        }
+        p_push<LOCAL>(a, q, job, kPDp, (Wn + a.P - 1) / a.P, [](int i) { return i; }, s_t0);
+        return;
+    }
+    p_stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&q.st->active, -1, LOCAL ? __ATOMIC_RELAXED : __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LOCAL>
+__global__ __launch_bounds__(kPersistThreads, 4) void persist_kernel(PArgs a)
+{
+    extern __shared__ __align__(16) uint8_t psm[];
+    __shared__ unsigned long long s_item;
+    __shared__ int s_flag, s_t0;
+    __shared__ int scan_tmp[16];
+    __shared__ unsigned long long tr[kPTrace];  // this workgroup's trace counters (thread 0)
+    const int tid = threadIdx.x;
+    if (tid < kPTrace) tr[tid] = 0;
+    // the ring this workgroup serves: its XCD's (LOCAL), or the only one
+    int ring = 0;
+    if constexpr (LOCAL) ring = a.xcc_ring[__builtin_amdgcn_s_getreg((3 << 11) | 20) & 15];  // XCC_ID[3:0]
+    ring = __builtin_amdgcn_readfirstlane(ring);
+    if (ring < 0 || ring >= a.nring) return;  // an XCD with no ring: nothing to take
+    const PRing q = p_ring(a, ring);
+    for (;;) {
+        // take the next slot and wait for its item
+        if (tid == 0) {
+            const long long w0 = a.trace ? (long long)wall_clock64() : 0;
+            const int t = __hip_atomic_fetch_add(&q.st->head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long want = (unsigned long long)(unsigned)t;
+            const unsigned long long *sp = q.seq + ((unsigned)t & a.cap_mask);
+            const long long t_start = (long long)wall_clock64();
+            int stop = 0;
+            for (unsigned spins = 0;; ++spins) {
+                if (__hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) break;
+                if ((spins & 7) == 7) {
+                    if (p_load(&q.st->active) == 0 || p_load(&a.st->abort) != 0) {
+                        stop = 1;
+                        break;
+                    }
+                    if ((long long)wall_clock64() - t_start > a.wait_ticks) {
+                        p_store(&a.st->abort, 1);
+                        stop = 1;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+            if (!stop) {
+                p_acquire_wave<LOCAL>();
+                if constexpr (LOCAL) s_item = q.item[(unsigned)t & a.cap_mask];
+                else s_item = __hip_atomic_load(q.item + ((unsigned)t & a.cap_mask), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_flag = stop;
+            if (a.trace) {
+                tr[kPTraceWait] += (unsigned long long)((long long)wall_clock64() - w0);
+                tr[kPTraceWait + 1] += 1;
+            }
+        }
+        __syncthreads();
+        if (s_flag) {
+            if (tid == 0 && a.trace)
+                for (int k = 0; k < kPTrace; ++k)
+                    if (tr[k]) __hip_atomic_fetch_add(&a.trace[k], tr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        if (tid >= 64) p_acquire_wave<LOCAL>();
+        const long long b0 = (tid == 0 && a.trace) ? (long long)wall_clock64() : 0;
+        const unsigned long long it = s_item;
+        const int job = __builtin_amdgcn_readfirstlane((int)(it >> 32));
+        const int phase = __builtin_amdgcn_readfirstlane((int)((it >> 24) & 0xff));
+        const int x = __builtin_amdgcn_readfirstlane((int)(it & 0xffffff));
+        const Job &J = a.jobs[job];
+        const int r = __builtin_amdgcn_readfirstlane(p_load(&J.state[3]));
+        const int Wr = __builtin_amdgcn_readfirstlane(r < J.logcap ? p_read<LOCAL>(&J.log[4 * r]) : J.Wt);
+        switch (phase) {
+        case kPDp:
+            dp_chunk_body<4, 16, 8>(J, Wr, x & 0xfff, (x >> 12) * a.R, a.R, a.P, kPersistThreads,
+                                    reinterpret_cast<uint32_t *>(psm));
+            break;
+        case kPBorg: {
+            const int cg = x >> 12;  // column group of kPBorgCols columns
+            for (int c0 = cg * kPBorgCols; c0 < min((cg + 1) * kPBorgCols, Wr); c0 += kPersistThreads) {
+                borg_body<kPersistThreads>(J, Wr, x & 0xfff, c0, psm);
+                __syncthreads();  // the tile is read before the next columns are staged
+            }
+            break;
+        }
+        case kPSelect:
+            select_body<kPersistThreads>(J, r, Wr, a.sel_lds, 0, reinterpret_cast<uint64_t *>(psm), scan_tmp);
+            break;
+        case kPBand: band_update_body<kPersistThreads / 64>(J, r, Wr, x, psm); break;
+        default: refresh_body<kPersistThreads>(J, r, Wr, x, *reinterpret_cast<RefreshLds *>(psm)); break;
+        }
+        // count the item done; the last of its phase starts the next phase
+        const long long b1 = (tid == 0 && a.trace) ? (long long)wall_clock64() : 0;
+        p_stores_done();
+        __syncthreads();
+        if (tid == 0) {
+            const int n = p_items(J, phase, Wr, a.P);
+            const int old = __hip_atomic_fetch_add(&a.cnt[job], 1, LOCAL ? __ATOMIC_RELAXED : __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = old == n - 1;
+            if (old == n - 1) p_store(&a.cnt[job], 0);
+        }
+        __syncthreads();
+        if (s_flag) {
+            if (LOCAL || tid >= 64) p_acquire_wave<LOCAL>();
+            switch (phase) {
+            case kPDp: {
+                const int ci = x >> 12;
+                if ((ci + 1) * a.R < J.H) {
+                    p_push<LOCAL>(a, q, job, kPDp, (Wr + a.P - 1) / a.P, [ci](int i) { return ((ci + 1) << 12) | i; },
+                                  &s_t0);
+                } else {
+                    const int nb = J.nb;
+                    p_push<LOCAL>(a, q, job, kPBorg, nb * ((Wr + kPBorgCols - 1) / kPBorgCols),
+                                  [nb](int i) { return ((i / nb) << 12) | (i % nb); }, &s_t0);
+                }
+                break;
+            }
+            case kPBorg: p_push<LOCAL>(a, q, job, kPSelect, 1, [](int i) { return i; }, &s_t0); break;
+            case kPSelect: p_push<LOCAL>(a, q, job, kPBand, J.nb, [](int i) { return i; }, &s_t0); break;
+            case kPBand: {
+                const int Wn = Wr - __builtin_amdgcn_readfirstlane(p_read<LOCAL>(&J.log[4 * r + 2]));
+                if (Wn > J.Wt)
+                    p_push<LOCAL>(a, q, job, kPRefresh, (J.H + kRefreshRows - 1) / kRefreshRows,
+                                  [](int i) { return i; }, &s_t0);
+                else p_end_iteration<LOCAL>(a, q, J, job, r, Wn, &s_t0);
+                break;
+            }
+            default: {
+                const int Wn = Wr - __builtin_amdgcn_readfirstlane(p_read<LOCAL>(&J.log[4 * r + 2]));
+                p_end_iteration<LOCAL>(a, q, J, job, r, Wn, &s_t0);
+                break;
+            }
+            }
+        }
+        if (tid == 0 && a.trace) {
+            const long long b2 = (long long)wall_clock64();
+            tr[2 * phase] += (unsigned long long)(b1 - b0);
+            tr[2 * phase + 1] += 1;
+            tr[kPTraceDone] += (unsigned long long)(b2 - b1);
+        }
+        __syncthreads();  // s_flag, s_t0 and s_item are read before the next item overwrites them
+    }
+}
+
+// Empties the rings (every generation unset), the phase counters and the
+// ring states.
+__global__ __launch_bounds__(256) void persist_clear_kernel(PArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int nslots = a.nring * (a.cap_mask + 1);
+    if (i < nslots) a.seq[i] = ~0ull;
+    if (i < a.njobs) a.cnt[i] = 0;
+    if (i < a.nring) {
+        a.st[i].head = 0;
+        a.st[i].tail = 0;
+        a.st[i].active = 0;
+        a.st[i].abort = 0;
+    }
+}
+
+// The first DP chunk of every job that has columns to remove, in its ring.
+__global__ __launch_bounds__(64) void persist_seed_kernel(PArgs a)
+{
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < a.njobs; ++j) {
+        const Job &J = a.jobs[j];
+        const int Wr = J.log[0];
+        if (Wr <= J.Wt) continue;
+        const PRing q = p_ring(a, J.ring);
+        const int n = (Wr + a.P - 1) / a.P;
+        for (int i = 0; i < n; ++i) {
+            const int t = q.st->tail++;
+            q.item[(unsigned)t & a.cap_mask] = p_make(j, kPDp, i);
+            q.seq[(unsigned)t & a.cap_mask] = (unsigned long long)(unsigned)t;
+        }
+        q.st->active += 1;
+    }
+}
+
+// The XCD (hardware register XCC_ID) of every workgroup of a launch.
+__global__ __launch_bounds__(64) void xcc_probe_kernel(int *out)
+{
+    if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15;
 }
 
 // ----------------------------------------------------------------- gather
@@ -2298,6 +2732,10 @@ void set_kernel_attributes(size_t lds_cap)
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_update_lds(8));
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&band_update_kernel<16>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_update_lds(16));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&persist_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)persist_lds_bytes());
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&persist_kernel<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)persist_lds_bytes());
 }
 
 void launch_select(const Job *d_jobs, int njobs, int use_lab_array, size_t lds_cap, hipStream_t s)
@@ -2384,6 +2822,57 @@ void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb
     case 8: launch_gather_v<8>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
     default: launch_gather_v<1>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;
     }
+}
+
+size_t persist_lds_bytes()
+{
+    // the selection's keys of a 1920-column frame (30 KB) and four rows of
+    // band origins beside them; the other stages need less
+    size_t b = (size_t)2 * 1920 * 8 + 4 * (1920 + 8);
+    b = std::max(b, band_update_lds(kPersistThreads / 64));
+    b = std::max(b, sizeof(RefreshLds));
+    b = std::max(b, (size_t)2 * 4 * (64 * 4 - 2 * 16) * sizeof(uint32_t));  // DP (4, 16, 8), four wavefronts
+    b = std::max(b, (size_t)kFuseB * (kPersistThreads + 2 * kFuseB + 8));  // band origins
+    return (b + 15) & ~(size_t)15;
+}
+
+int persist_blocks_per_cu()
+{
+    int n = 0, m = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&persist_kernel<true>),
+                                                     kPersistThreads, persist_lds_bytes()) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&persist_kernel<false>),
+                                                     kPersistThreads, persist_lds_bytes()) != hipSuccess)
+        return 0;
+    return std::min(n, m);
+}
+
+void launch_persist_clear(const PArgs &a, hipStream_t s)
+{
+    const int n = std::max(a.nring * (a.cap_mask + 1), std::max(a.njobs, a.nring));
+    hipLaunchKernelGGL(persist_clear_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+}
+
+int probe_xcc(int n, int *h_out)
+{
+    int *d = nullptr;
+    if (hipMalloc(&d, sizeof(int) * (size_t)n) != hipSuccess) return -1;
+    hipLaunchKernelGGL(xcc_probe_kernel, dim3(n), dim3(64), 0, nullptr, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(h_out, d, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e == hipSuccess ? 0 : -1;
+}
+
+void launch_persist_seed(const PArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(persist_seed_kernel, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_persist(const PArgs &a, int grid, bool local, hipStream_t s)
+{
+    if (local) hipLaunchKernelGGL(persist_kernel<true>, dim3(grid), dim3(kPersistThreads), (size_t)a.lds_bytes, s, a);
+    else hipLaunchKernelGGL(persist_kernel<false>, dim3(grid), dim3(kPersistThreads), (size_t)a.lds_bytes, s, a);
 }
 
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s)

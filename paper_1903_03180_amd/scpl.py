@@ -32,13 +32,16 @@ SCPL_ERR_INTERNAL = 6
 SCPL_ENERGY_GRADIENT = 0
 SCPL_ENERGY_MOTION = 1
 SCPL_NOALLOC_SCRATCH_BYTES = 64 << 20
+SCPL_BATCH_GROUPS = 0
+SCPL_BATCH_PERSISTENT = 1
+SCPL_BATCH_PERSISTENT_AGENT = 2
 
 EXPORTS = [
     "scpl_create", "scpl_destroy", "scpl_status_str", "scpl_workspace_size", "scpl_retarget",
     "scpl_retarget_noalloc", "scpl_kernel_variants", "scpl_autotune_batch",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_profile_kinds", "scpl_dp_geometry",
-    "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_server_create",
+    "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_batch_mode", "scpl_device_xcds", "scpl_persist_stats", "scpl_server_create",
     "scpl_server_submit", "scpl_server_poll",
     "scpl_server_wait", "scpl_server_ticket_times", "scpl_server_release", "scpl_server_destroy",
     "scpl_server_footprint", "scpl_asde", "scpl_compact",
@@ -56,7 +59,8 @@ DP_CHUNKED = [(4, 16, 8, 256, 384), (4, 16, 8, 384, 256), (4, 16, 8, 320, 384), 
               (2, 8, 16, 192, 64), (2, 8, 16, 160, 128), (2, 8, 16, 128, 192), (2, 8, 16, 208, 32),
               (2, 8, 16, 216, 16)]
 
-KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh"]
+KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh",
+           "persist"]
 
 
 class scpl_params(C.Structure):
@@ -100,6 +104,9 @@ _sig = {
     "scpl_dp_chunking": ([_P, _I32, _I32], C.c_int),
     "scpl_dp_chosen": ([_P, _I32, C.POINTER(_I32)], C.c_int),
     "scpl_batch_streams": ([_P, _I32], C.c_int),
+    "scpl_batch_mode": ([_P, _I32], C.c_int),
+    "scpl_persist_stats": ([_P, _P, _P], C.c_int),
+    "scpl_device_xcds": ([_P, _P], C.c_int),
     "scpl_server_create": ([_I32, C.POINTER(scpl_server_config), C.POINTER(C.c_void_p)], C.c_int),
     "scpl_server_submit": ([_P, C.POINTER(scpl_clip), C.POINTER(_I64)], C.c_int),
     "scpl_server_poll": ([_P, _I64, C.POINTER(_I32), C.POINTER(C.c_int)], C.c_int),
@@ -316,6 +323,32 @@ class Context:
         """Number of independently advancing job groups (streams) of the
         batched path."""
         _check(scpl_batch_streams(self.h, n), "scpl_batch_streams")
+
+    def batch_mode(self, mode: int) -> None:
+        """How the batched path runs its iterations: SCPL_BATCH_GROUPS (job
+        groups replaying graphs), SCPL_BATCH_PERSISTENT (one persistent
+        launch whose workgroups take work items from rings on the device, one
+        ring per XCD) or SCPL_BATCH_PERSISTENT_AGENT (the same with one ring
+        and agent-scope ordering)."""
+        _check(scpl_batch_mode(self.h, mode), "scpl_batch_mode")
+
+    def device_xcds(self) -> int:
+        """XCDs whose workgroups each serve a ring of their own in the
+        persistent launch (0: one ring, agent-scope ordering)."""
+        n = C.c_int32(0)
+        _check(scpl_device_xcds(self.h, C.byref(n)), "scpl_device_xcds")
+        return n.value
+
+    def persist_stats(self) -> dict:
+        """Workgroup time of the last persistent launch made while kernels
+        were timed: {part: (ms summed over workgroups, items)} for dp, borg,
+        select, band (seam trace and compaction), refresh, wait (for an item)
+        and done (counting items and queueing the next stages)."""
+        ms = (C.c_double * 7)()
+        n = (C.c_int64 * 7)()
+        _check(scpl_persist_stats(self.h, ms, n), "scpl_persist_stats")
+        keys = ["dp", "borg", "select", "band", "refresh", "wait", "done"]
+        return {k: (ms[q], n[q]) for q, k in enumerate(keys)}
 
     # ---------------------------------------------------------- timing
     def profile(self, on: bool = True, kinds=None) -> None:

@@ -40,6 +40,9 @@ calls = [
     lambda: L.scpl_retarget_noalloc(nul, C.byref(p), nul, nul, nul, nul, nul, nul),
     lambda: L.scpl_retarget_batch(nul, nul, 0, nul),
     lambda: L.scpl_kernel_variants(nul, 0, 0, 0, 0, 0),
+    lambda: L.scpl_batch_mode(nul, 1),
+    lambda: L.scpl_persist_stats(nul, None, None),
+    lambda: L.scpl_device_xcds(nul, None),
     lambda: L.scpl_autotune_batch(nul, nul, 1, 1, nul, nul, nul),
     lambda: L.scpl_batch_streams(nul, 1),
     lambda: L.scpl_last_log(nul, nul, C.c_int64(0), C.byref(i64)),

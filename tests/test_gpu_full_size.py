@@ -13,7 +13,9 @@ benchmark times, and the digests of its results must be the oracle's:
     benchmark's autotuner picks), and each of the first four alone;
   * the 4K clip at alpha 3/20, 1/5 and 1/4 on the plain path, and the three
     in one batched call;
-  * the first 16 clips of the uneven mix in one batched call.
+  * the first 16 clips of the uneven mix in one batched call;
+  * the 1080p batch, the three 4K runs and the mix also in the persistent
+    launch (SCPL_BATCH_PERSISTENT), on a stream of their own.
 """
 import hashlib
 import json
@@ -91,15 +93,26 @@ def run_plain(ctx, rec, frames):
     return res, ctx.last_log()
 
 
-def run_batch(ctx, recs, frames, nstreams=3):
+def run_batch(ctx, recs, frames, nstreams=3, persistent=False):
+    from paper_1903_03180_amd import scpl
     clips = [dict(frames=f, target_width=r["Wt"], seams_per_iter=r["k"], alpha_num=r["anum"],
                   alpha_den=r["aden"], want_masks=True) for r, f in zip(recs, frames)]
     ctx.batch_streams(nstreams)
+    if persistent:
+        ctx.batch_mode(scpl.SCPL_BATCH_PERSISTENT)
     try:
-        ctx.retarget_batch(clips)
-        torch.cuda.synchronize()
+        if persistent:
+            torch.cuda.synchronize()
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                ctx.retarget_batch(clips, stream=s)
+            s.synchronize()
+        else:
+            ctx.retarget_batch(clips)
+            torch.cuda.synchronize()
     finally:
         ctx.batch_streams(3)
+        ctx.batch_mode(scpl.SCPL_BATCH_GROUPS)
     log = ctx.last_log()
     # the batched log holds the clips' records in order
     out, at = [], 0
@@ -151,6 +164,9 @@ def test_1080p_batch_as_benchmarked_every_iteration(ctx):
         ctx.kernel_variants(0, 0, 0, 0, 0)
     for n, (c, log) in zip(names, res):
         check(n, c, log)
+    # and in the persistent launch
+    for n, (c, log) in zip(names, run_batch(ctx, rr, frames, persistent=True)):
+        check(n, c, log)
     # the same clips alone on the plain path (default geometry)
     for n, r, f in list(zip(names, rr, frames))[:4]:
         got, log = run_plain(ctx, r, f)
@@ -167,6 +183,8 @@ def test_4k_clip_alpha_sweep_every_iteration(ctx):
         check(n, got, log)
     for n, (c, log) in zip(names, run_batch(ctx, rr, [d, d, d])):
         check(n, c, log)
+    for n, (c, log) in zip(names, run_batch(ctx, rr, [d, d, d], persistent=True)):
+        check(n, c, log)
 
 
 def test_uneven_mix_batch_every_iteration(ctx):
@@ -175,4 +193,6 @@ def test_uneven_mix_batch_every_iteration(ctx):
     rr = [dict(G[n]["recipe"], _name=n) for n in names]
     frames = [dev(frames_of(r)) for r in rr]
     for n, (c, log) in zip(names, run_batch(ctx, rr, frames)):
+        check(n, c, log)
+    for n, (c, log) in zip(names, run_batch(ctx, rr, frames, persistent=True)):
         check(n, c, log)

@@ -99,6 +99,9 @@ def test_null_context_and_pointers_rejected(lib):
     assert lib.scpl_last_log(None, None, 0, C.byref(n)) == lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_profile_kinds(None, 1) == lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_dp_chunking(None, 256, 384) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_batch_mode(None, lib.SCPL_BATCH_PERSISTENT) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_persist_stats(None, None, None) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_device_xcds(None, None) == lib.SCPL_ERR_INVALID_ARG
 
 
 def test_target_width_rule_for_batch_mix():
