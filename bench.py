@@ -216,6 +216,41 @@ def run_table1(np, torch, scpl, ctx):
             "inputs": "synthetic RGB clips of each row's size, length and target (seeds 6000-6011)"}
 
 
+def run_persistent_leg(torch, scpl, ctx, step, n_frames, steps, fps_groups, choice):
+    """The same batched step as one persistent launch (SCPL_BATCH_PERSISTENT,
+    graph-captured, no events): frames/s, and one more step with the
+    persistent kernel timed and its workgroups' time traced."""
+    import time as _t
+    if ctx.device_xcds() == 0:
+        return None
+    ctx.batch_mode(scpl.SCPL_BATCH_PERSISTENT)
+    try:
+        step()
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = _t.perf_counter()
+        ctx.profile(True, kinds=["persist"])
+        step()
+        torch.cuda.synchronize()
+        pk = ctx.profile_read()["persist"]
+        stats = ctx.persist_stats()
+        ctx.profile(False)
+    finally:
+        ctx.batch_mode(scpl.SCPL_BATCH_GROUPS)
+    fps = n_frames * steps / (t1 - t0)
+    log(f"persistent launch: {(t1 - t0) * 1e3 / steps:.2f} ms/step, {fps:.1f} frames/s "
+        f"(job groups {fps_groups:.1f}); persistent kernel {pk[0]:.2f} ms")
+    return {"fps": round(fps, 2), "ms_per_step": round((t1 - t0) * 1e3 / steps, 3),
+            "over_job_groups": round(fps / fps_groups, 4), "persist_kernel_ms": round(pk[0], 3),
+            "xcds": ctx.device_xcds(), "tuner_picked": bool(choice and choice.get("batch_mode") == 1),
+            "workgroup_ms": {k: {"ms": round(v[0], 1), "items": int(v[1])} for k, v in stats.items()},
+            "timing": "graph-captured launch, no per-launch events; workgroup_ms: summed over the workgroups of "
+                      "one more step (device wall clock)"}
+
+
 def run_mix(np, torch, ctx, steps):
     """The 64 clips of uneven size (luma, widths 480-2560, heights 360-1440,
     aspect 1:1-21:9, 30-240 frames, target 3/4 of the width): the batched
@@ -235,14 +270,30 @@ def run_mix(np, torch, ctx, steps):
     choice = ctx.autotune_batch(clips, reps=1)
     if choice["dp_geometry"] is not None:
         g = choice["dp_geometry"]
-    ctx.retarget_batch(clips)  # warm-up (workspace, graphs)
-    torch.cuda.synchronize()
-    t0 = _t.perf_counter()
-    for _ in range(steps):
-        ctx.retarget_batch(clips)
-    torch.cuda.synchronize()
-    t1 = _t.perf_counter()
+
+    def timed():
+        ctx.retarget_batch(clips)  # warm-up (workspace, graphs)
+        torch.cuda.synchronize()
+        a = _t.perf_counter()
+        for _ in range(steps):
+            ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+        return a, _t.perf_counter()
+
+    # the tuner's configuration, and the other batch mode beside it
+    t0, t1 = timed()
     fps = n_frames * steps / (t1 - t0)
+    other = None
+    if ctx.device_xcds() > 0:
+        from paper_1903_03180_amd import scpl as _s
+        om = _s.SCPL_BATCH_GROUPS if choice["batch_mode"] == _s.SCPL_BATCH_PERSISTENT else _s.SCPL_BATCH_PERSISTENT
+        ctx.batch_mode(om)
+        try:
+            o0, o1 = timed()
+        finally:
+            ctx.batch_mode(choice["batch_mode"])
+        other = {"batch_mode": "persistent" if om == _s.SCPL_BATCH_PERSISTENT else "job groups",
+                 "fps": round(n_frames * steps / (o1 - o0), 2), "ms_per_step": round((o1 - o0) * 1e3 / steps, 3)}
     p0 = _t.perf_counter()
     for c in clips:
         ctx.retarget(c["frames"], c["target_width"], c["seams_per_iter"], want_masks=False)
@@ -250,12 +301,14 @@ def run_mix(np, torch, ctx, steps):
     p1 = _t.perf_counter()
     plain = n_frames / (p1 - p0)
     log(f"mix64: batched {fps:.1f} frames/s ({(t1 - t0) * 1e3 / steps:.1f} ms/step), plain {plain:.1f} frames/s, "
-        f"DP {g} ({dpus:.1f} us per DP alone), batch tuning {choice}")
+        f"DP {g} ({dpus:.1f} us per DP alone), batch tuning {choice}; other batch mode {other}")
+    ctx.batch_mode(0)
     del clips
     torch.cuda.empty_cache()
     return {"workload": desc, "frames": n_frames, "steps": steps, "batched_fps": round(fps, 2),
             "ms_per_step": round((t1 - t0) * 1e3 / steps, 3), "plain_fps": round(plain, 2),
-            "batched_over_plain": round(fps / plain, 3), "dp_geometry": g, "batch_tuning": choice}
+            "batched_over_plain": round(fps / plain, 3), "dp_geometry": g, "batch_tuning": choice,
+            "batch_mode": "persistent" if choice["batch_mode"] == 1 else "job groups", "other_batch_mode": other}
 
 
 def run_height(torch, ctx, clip_np, Wt, k, steps):
@@ -521,6 +574,9 @@ def main() -> int:
         log(f"batch autotune ({time.perf_counter() - b0:.1f} s): {batch_choice}")
         if batch_choice["dp_geometry"] is not None:
             dpg = batch_choice["dp_geometry"]
+    # the timed region measures the job-group path (its DP launches carry the
+    # roofline); the persistent launch is timed on its own below
+    ctx.batch_mode(scpl.SCPL_BATCH_GROUPS)
 
     def step_batched():
         ctx.retarget_batch(clips)
@@ -566,6 +622,8 @@ def main() -> int:
     g1 = time.perf_counter()
     fps_graph = n_frames * args.steps / (g1 - g0)
     log(f"batched (graph, no event timing): {(g1 - g0) * 1e3 / args.steps:.2f} ms/step, {fps_graph:.1f} frames/s")
+
+    persistent = run_persistent_leg(torch, scpl, ctx, step_batched, n_frames, args.steps, fps_graph, batch_choice)
 
     # seam memorisation (only buffers b with b mod m == 0 carved): graph-timed
     # steps of the same workload, and how much of the output it changes
@@ -753,6 +811,7 @@ def main() -> int:
                           "energy recompute the partial refresh never performs)",
             "bytes_per_step": int(balg), "GBps": round(balg / (ms_per_step * 1e-3) / 1e9, 1),
             "frac_of_peak": round(balg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "persistent": persistent,
         "mix64": mix,
         "serving": serving,
         "raw_vs_proposed": table1,

@@ -223,6 +223,9 @@ scpl_status scpl_batch_streams(scpl_ctx *ctx, int32_t n);
  * P + 2 R in (672, 896], else 256 x 384. */
 enum { SCPL_BATCH_GROUPS = 0, SCPL_BATCH_PERSISTENT = 1, SCPL_BATCH_PERSISTENT_AGENT = 2 };
 scpl_status scpl_batch_mode(scpl_ctx *ctx, int32_t mode);
+/* Workgroups per compute unit of the persistent launch: 0 (default) as many
+ * as fit at once, else at most per_cu (performance only). */
+scpl_status scpl_persist_workgroups(scpl_ctx *ctx, int32_t per_cu);
 /* XCDs the context's probe launch found (the persistent launch serves each
  * with a ring of its own), or 0 when XCD-local mode is unavailable and
  * SCPL_BATCH_PERSISTENT runs as job groups. */
@@ -387,16 +390,21 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
  * take without it, the single-workgroup (8,16,8) and (4,16,16), the
  * column-split (4,16,8) with 256 rows x 384 columns and (2,8,16) with 128 x
  * 640, all with EX = 1), then the compaction variant, then the refresh
- * variant, then the band-origin, fused and gather variants; each candidate is run once
- * untimed and then `reps` times, and its best time counts.  The
+ * variant, then the band-origin and fused variants, then (where the context
+ * found the XCDs) the persistent launch (SCPL_BATCH_PERSISTENT) with its DP
+ * chunked 256 x 384, 192 x 512 or 128 x 640 and as many workgroups per
+ * compute unit as fit, or one or two fewer, then the gather variant; each
+ * candidate is run once untimed and then `reps` times, and its best time
+ * counts.  The
  * configuration the calls would use before the call is timed first, and a
  * candidate replaces the best so far only when it is at least 1% faster
  * (so that run-to-run noise does not decide the choice).  Synchronises
- * `stream`.  h_choice (nullable, 13 int32): job groups, Q, HB, PF, EX, R, P
+ * `stream`.  h_choice (nullable, 15 int32): job groups, Q, HB, PF, EX, R, P
  * of the DP geometry (Q = 0: not forced), compaction variant, refresh
  * variant, 1 if a DP geometry is forced for batched calls, band-origin
- * variant, gather variant, fused variant; *h_ms (nullable): the best time of a whole retarget in
- * milliseconds.  A geometry forced with scpl_dp_geometry takes
+ * variant, gather variant, fused variant, batch mode (scpl_batch_mode),
+ * workgroups of the persistent launch; *h_ms (nullable): the best time of a
+ * whole retarget in milliseconds.  A geometry forced with scpl_dp_geometry takes
  * precedence over the batch choice, and the batch autotuner then returns
  * SCPL_ERR_INVALID_ARG, as it does with kernel timing enabled. */
 scpl_status scpl_kernel_variants(scpl_ctx *ctx, int32_t update_variant, int32_t refresh_variant,

@@ -61,6 +61,8 @@ struct scpl_ctx {
     int fuse_variant = 0;                // fill + compaction: 0 two launches, 1/2 fused per band
     int batch_mode = SCPL_BATCH_GROUPS;  // how the batched path runs its iterations
     int persist_grid = 0;                // workgroups of the persistent launch (resident at once)
+    int persist_max_per_cu = 0;          // of which per compute unit
+    int ncu = 0;                         // compute units
     int nxcd = 0;                        // XCDs the probe found, 0: XCD-local mode unavailable
     int xcc_ring[16] = {};               // their XCC_IDs' rings
     long long wall_khz = 0;              // device wall clock (the persistent launch's wait bound)
@@ -1093,7 +1095,9 @@ scpl_status scpl_create(int32_t hip_device, scpl_ctx **out)
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0) {
         c->wall_khz = khz;
-        c->persist_grid = std::min(persist_blocks_per_cu() * prop.multiProcessorCount, 8192);
+        c->ncu = prop.multiProcessorCount;
+        c->persist_max_per_cu = persist_blocks_per_cu();
+        c->persist_grid = std::min(c->persist_max_per_cu * c->ncu, 8192);
     }
     // XCD-local persistent mode: the XCC_ID of the workgroups of a probe
     // launch must follow the dispatcher's round robin over the XCDs
@@ -1611,6 +1615,15 @@ scpl_status scpl_persist_stats(scpl_ctx *ctx, double *h_ms, int64_t *h_items)
     return SCPL_OK;
 }
 
+scpl_status scpl_persist_workgroups(scpl_ctx *ctx, int32_t per_cu)
+{
+    if (!ctx || per_cu < 0) return SCPL_ERR_INVALID_ARG;
+    if (ctx->persist_max_per_cu <= 0) return SCPL_ERR_DEVICE;
+    const int n = per_cu == 0 ? ctx->persist_max_per_cu : std::min<int>(per_cu, ctx->persist_max_per_cu);
+    ctx->persist_grid = std::min(n * ctx->ncu, 8192);
+    return SCPL_OK;
+}
+
 scpl_status scpl_device_xcds(scpl_ctx *ctx, int32_t *h_n)
 {
     if (!ctx || !h_n) return SCPL_ERR_INVALID_ARG;
@@ -1930,6 +1943,8 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         int streams;
         DpGeom g;  // Q = 0: whatever the launches would take unforced (tuned or default)
         int upd, refresh, borg, gather, fuse;
+        int mode;   // SCPL_BATCH_GROUPS or SCPL_BATCH_PERSISTENT
+        int pgrid;  // workgroups of the persistent launch
     };
     // the best of `reps` whole batched retargets after one untimed one (graphs,
     // workspace); the caller's outputs are written each time, identically
@@ -1941,6 +1956,8 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
         ctx->borg_variant = c.borg;
         ctx->gather_variant = c.gather;
         ctx->fuse_variant = c.fuse;
+        ctx->batch_mode = c.mode;
+        ctx->persist_grid = c.pgrid;
         SCPL_TRY(run_clips_2d(ctx, clips, n_clips, true, nullptr, s, true));
         SCPL_TRY(hipStreamSynchronize(s));
         double best = 1e300;
@@ -1956,7 +1973,8 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     };
     if (ctx->forced.Q > 0) return SCPL_ERR_INVALID_ARG;  // a geometry forced by the caller would win anyway
     const Cfg start{ctx->nstreams,     ctx->batch_forced,   ctx->upd_variant, ctx->refresh_variant,
-                    ctx->borg_variant, ctx->gather_variant, ctx->fuse_variant};
+                    ctx->borg_variant, ctx->gather_variant, ctx->fuse_variant, ctx->batch_mode,
+                    ctx->persist_grid};
     std::vector<DpGeom> geoms{DpGeom{0, 0, 0, 0, 0}, DpGeom{8, 16, 1, 8, 1}, DpGeom{4, 16, 1, 16, 1},
                               DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{2, 8, 1, 16, 1, 128, 640}};
     if (start.g.Q > 0) geoms[0] = start.g;
@@ -1980,8 +1998,9 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     const Cfg inc = best;
     for (int ns : {2, 3, 4})
         for (const DpGeom &g : geoms)
-            if (ns != inc.streams || std::memcmp(&g, &inc.g, sizeof g) != 0)
-                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg, inc.gather, inc.fuse});
+            if (inc.mode != SCPL_BATCH_GROUPS || ns != inc.streams || std::memcmp(&g, &inc.g, sizeof g) != 0)
+                challenge(Cfg{ns, g, inc.upd, inc.refresh, inc.borg, inc.gather, inc.fuse, SCPL_BATCH_GROUPS,
+                              inc.pgrid});
     for (int u = 0; u < kNumUpdateVariants; ++u)
         if (u != best.upd) {
             Cfg c = best;
@@ -2006,6 +2025,20 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
             c.fuse = f;
             challenge(c);
         }
+    // the persistent launch (where the probe found the XCDs): its DP
+    // chunking and workgroups per compute unit
+    if (ctx->nxcd > 0 && ctx->persist_max_per_cu > 0) {
+        const Cfg gb = best;
+        for (const DpGeom &g : {DpGeom{4, 16, 1, 8, 1, 256, 384}, DpGeom{4, 16, 1, 8, 1, 192, 512},
+                                DpGeom{4, 16, 1, 8, 1, 128, 640}})
+            for (int per_cu = ctx->persist_max_per_cu; per_cu >= std::max(2, ctx->persist_max_per_cu - 2); --per_cu) {
+                Cfg c = gb;
+                c.mode = SCPL_BATCH_PERSISTENT;
+                c.g = g;
+                c.pgrid = std::min(per_cu * ctx->ncu, 8192);
+                challenge(c);
+            }
+    }
     for (int g = 0; g < kNumGatherVariants; ++g)
         if (g != best.gather) {
             Cfg c = best;
@@ -2020,11 +2053,13 @@ scpl_status scpl_autotune_batch(scpl_ctx *ctx, const scpl_clip *clips, int32_t n
     ctx->borg_variant = keep.borg;
     ctx->gather_variant = keep.gather;
     ctx->fuse_variant = keep.fuse;
+    ctx->batch_mode = keep.mode;
+    ctx->persist_grid = keep.pgrid;
     if (st != SCPL_OK) return st;
     if (h_choice) {
-        const int32_t v[13] = {keep.streams, keep.g.Q,  keep.g.HB,   keep.g.PF,    keep.g.EX,
-                               keep.g.R,     keep.g.P,  keep.upd,    keep.refresh, keep.g.Q > 0 ? 1 : 0,
-                               keep.borg,    keep.gather, keep.fuse};
+        const int32_t v[15] = {keep.streams, keep.g.Q,    keep.g.HB, keep.g.PF,    keep.g.EX,
+                               keep.g.R,     keep.g.P,    keep.upd,  keep.refresh, keep.g.Q > 0 ? 1 : 0,
+                               keep.borg,    keep.gather, keep.fuse, keep.mode,    keep.pgrid};
         std::memcpy(h_choice, v, sizeof v);
     }
     if (h_ms) *h_ms = best_ms;

@@ -41,7 +41,7 @@ EXPORTS = [
     "scpl_retarget_noalloc", "scpl_kernel_variants", "scpl_autotune_batch",
     "scpl_retarget_batch", "scpl_last_log", "scpl_luma", "scpl_energy", "scpl_dp", "scpl_select",
     "scpl_backtrack", "scpl_segment", "scpl_profile_enable", "scpl_profile_read", "scpl_profile_kinds", "scpl_dp_geometry",
-    "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_batch_mode", "scpl_device_xcds", "scpl_persist_stats", "scpl_server_create",
+    "scpl_autotune_dp", "scpl_dp_chunking", "scpl_dp_chosen", "scpl_batch_streams", "scpl_batch_mode", "scpl_device_xcds", "scpl_persist_stats", "scpl_persist_workgroups", "scpl_server_create",
     "scpl_server_submit", "scpl_server_poll",
     "scpl_server_wait", "scpl_server_ticket_times", "scpl_server_release", "scpl_server_destroy",
     "scpl_server_footprint", "scpl_asde", "scpl_compact",
@@ -107,6 +107,7 @@ _sig = {
     "scpl_batch_mode": ([_P, _I32], C.c_int),
     "scpl_persist_stats": ([_P, _P, _P], C.c_int),
     "scpl_device_xcds": ([_P, _P], C.c_int),
+    "scpl_persist_workgroups": ([_P, _I32], C.c_int),
     "scpl_server_create": ([_I32, C.POINTER(scpl_server_config), C.POINTER(C.c_void_p)], C.c_int),
     "scpl_server_submit": ([_P, C.POINTER(scpl_clip), C.POINTER(_I64)], C.c_int),
     "scpl_server_poll": ([_P, _I64, C.POINTER(_I32), C.POINTER(C.c_int)], C.c_int),
@@ -290,7 +291,7 @@ class Context:
         whose outputs it writes); returns the chosen configuration and the
         best time of a whole batched retarget."""
         arr = self._clip_array(clips)
-        ch = (C.c_int32 * 13)()
+        ch = (C.c_int32 * 15)()
         ms = C.c_double(0)
         _check(scpl_autotune_batch(self.h, arr, len(clips), reps, ch, C.byref(ms), _stream(stream)),
                "scpl_autotune_batch")
@@ -298,7 +299,7 @@ class Context:
         return {"streams": v[0], "dp_geometry": dict(zip(("cols_per_lane", "halo_rows", "prefetch_rows", "exclusive_cu",
                                                           "chunk_rows", "chunk_cols"), v[1:7])) if v[9] else None,
                 "update_variant": v[7], "refresh_variant": v[8], "borg_variant": v[10], "gather_variant": v[11],
-                "fuse_variant": v[12], "ms": ms.value}
+                "fuse_variant": v[12], "batch_mode": v[13], "persist_workgroups": v[14], "ms": ms.value}
 
     def retarget_batch(self, clips, stream=None):
         """clips: list of dicts with keys frames (cuda uint8 tensor),
@@ -331,6 +332,11 @@ class Context:
         ring per XCD) or SCPL_BATCH_PERSISTENT_AGENT (the same with one ring
         and agent-scope ordering)."""
         _check(scpl_batch_mode(self.h, mode), "scpl_batch_mode")
+
+    def persist_workgroups(self, per_cu: int = 0) -> None:
+        """Workgroups per compute unit of the persistent launch (0: as many
+        as fit at once)."""
+        _check(scpl_persist_workgroups(self.h, per_cu), "scpl_persist_workgroups")
 
     def device_xcds(self) -> int:
         """XCDs whose workgroups each serve a ring of their own in the

@@ -43,6 +43,7 @@ calls = [
     lambda: L.scpl_batch_mode(nul, 1),
     lambda: L.scpl_persist_stats(nul, None, None),
     lambda: L.scpl_device_xcds(nul, None),
+    lambda: L.scpl_persist_workgroups(nul, 0),
     lambda: L.scpl_autotune_batch(nul, nul, 1, 1, nul, nul, nul),
     lambda: L.scpl_batch_streams(nul, 1),
     lambda: L.scpl_last_log(nul, nul, C.c_int64(0), C.byref(i64)),

@@ -102,6 +102,7 @@ def test_null_context_and_pointers_rejected(lib):
     assert lib.scpl_batch_mode(None, lib.SCPL_BATCH_PERSISTENT) == lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_persist_stats(None, None, None) == lib.SCPL_ERR_INVALID_ARG
     assert lib.scpl_device_xcds(None, None) == lib.SCPL_ERR_INVALID_ARG
+    assert lib.scpl_persist_workgroups(None, 0) == lib.SCPL_ERR_INVALID_ARG
 
 
 def test_target_width_rule_for_batch_mix():
