@@ -92,18 +92,23 @@ def serving_pool(n_mix, n_4k):
 
 
 def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=400, warm=0.1, p4k=0.1, n_cap=64,
-                fracs=(0.5, 0.8, 0.95), lanes=4, seed=5):
+                fracs=(0.5, 0.8, 0.95), lanes=4, seed=5, whole_batch_at=0.8):
     """Poisson arrivals of retarget requests at fractions of the measured
     capacity.  A request is a clip of the uneven mix, or with probability
     p4k a 4K clip; the first `warm` fraction of each rate's requests (by
     arrival) is left out of the latency figures.  p50 / p99 of completion
-    minus arrival, and frames/s over the whole rate."""
+    minus arrival (all requests, mix clips, 4K clips), and frames/s over the
+    whole rate; then the rate whole_batch_at once more with requests done
+    only when their whole batch is (the comparison for early completion)."""
     import time as _t
     clips_np, wts, ks = serving_pool(n_mix, n_4k)
     dev = [torch.from_numpy(c).cuda() for c in clips_np]
     torch.cuda.synchronize()
     srv = scpl.Server(0, lanes=lanes, max_batch=8)
     rng = np.random.default_rng(seed)
+
+    def pct(a, q):
+        return None if len(a) == 0 else round(float(np.percentile(a, q)), 2)
 
     def draw(n):
         is4k = rng.random(n) < p4k
@@ -130,7 +135,15 @@ def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=400, warm=0.1, p4k=0.1,
            "pool": f"{n_mix} clips of the uneven mix, and with probability {p4k} one of {n_4k} 4K clips",
            "requests_per_rate": n_req, "warmup_requests": n_warm, "latency_samples": n_req - n_warm,
            "lanes": lanes, "rates": []}
-    for f in fracs:
+    runs = [(f, False) for f in fracs] + ([(whole_batch_at, True)] if whole_batch_at else [])
+    for f, whole in runs:
+        if whole:  # the same rate, requests done with their whole batch
+            srv.close()
+            srv = scpl.Server(0, lanes=lanes, max_batch=8, whole_batch=True)
+            for q in range(len(dev)):
+                t = srv.submit(req(q))
+                srv.wait(t)
+                srv.release(t)
         lam = f * cap
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
         picks = draw(n_req)
@@ -142,23 +155,30 @@ def run_serving(np, torch, scpl, n_mix=14, n_4k=2, n_req=400, warm=0.1, p4k=0.1,
                 _t.sleep(a - now)
             lag = max(0.0, (_t.perf_counter() - start) - a)
             tickets.append((srv.submit(req(int(q))), lag, int(q)))
-        lat, frames, n4k = [], 0, 0
+        lat, is4k, frames = [], [], 0
         for i, (t, lag, q) in enumerate(tickets):
             srv.wait(t)
             _, total_ms = srv.times(t)
             if i >= n_warm:
                 lat.append(total_ms + 1e3 * lag)
-                n4k += q >= n_mix
+                is4k.append(q >= n_mix)
             frames += dev[q].shape[0]
             srv.release(t)
         span = _t.perf_counter() - start
-        lat = np.array(lat)
-        rec = {"load": f, "arrival_req_per_s": round(lam, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
-               "p99_ms": round(float(np.percentile(lat, 99)), 2), "frames_per_s": round(frames / span, 1),
-               "samples": int(len(lat)), "samples_4k": int(n4k)}
-        log(f"serving at {f:.2f} x capacity: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms over "
-            f"{len(lat)} requests ({n4k} 4K), {rec['frames_per_s']} frames/s")
-        out["rates"].append(rec)
+        lat, is4k = np.array(lat), np.array(is4k, dtype=bool)
+        rec = {"load": f, "arrival_req_per_s": round(lam, 3), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+               "mix_p50_ms": pct(lat[~is4k], 50), "mix_p99_ms": pct(lat[~is4k], 99),
+               "4k_p50_ms": pct(lat[is4k], 50), "4k_p99_ms": pct(lat[is4k], 99),
+               "frames_per_s": round(frames / span, 1), "samples": int(len(lat)), "samples_4k": int(is4k.sum()),
+               "completion": "with the whole batch" if whole else "with the request's own buffers"}
+        log(f"serving at {f:.2f} x capacity{' (whole-batch completion)' if whole else ''}: p50 {rec['p50_ms']} ms, "
+            f"p99 {rec['p99_ms']} ms over {len(lat)} requests ({rec['samples_4k']} 4K; mix p50 {rec['mix_p50_ms']} "
+            f"p99 {rec['mix_p99_ms']}, 4K p50 {rec['4k_p50_ms']} p99 {rec['4k_p99_ms']}), "
+            f"{rec['frames_per_s']} frames/s")
+        if whole:
+            out["whole_batch_completion"] = rec
+        else:
+            out["rates"].append(rec)
     srv.close()
     del dev
     torch.cuda.synchronize()

@@ -250,6 +250,10 @@ scpl_status scpl_persist_stats(scpl_ctx *ctx, double *h_ms, int64_t *h_items);
  * share can claim (its tiled and pixel-major luma and buffer controller
  * plus one carving job per frame); the admitted requests' bounds never
  * exceed hbm_budget.
+ * A request is done as soon as its own buffers are carved and its outputs
+ * gathered (its gather runs beside the rest of the batch), unless
+ * whole_batch is set: then every request of a batch is done when the batch
+ * is.  Its bound counts against the budget until its batch ends.
  * Requests that arrive while batches run are admitted as lanes and memory
  * free up, and their work overlaps on the device with the batches in
  * flight.  Results are bit-identical to scpl_retarget on each clip alone.
@@ -276,6 +280,7 @@ typedef struct {
     int32_t lanes;
     int32_t max_batch;
     uint64_t hbm_budget;
+    int32_t whole_batch; /* 1: requests are done with their batch; 0 (default): with their own buffers */
 } scpl_server_config;
 scpl_status scpl_server_create(int32_t hip_device, const scpl_server_config *cfg, scpl_server **out);
 scpl_status scpl_server_submit(scpl_server *srv, const scpl_clip *clip, int64_t *h_ticket);

@@ -72,6 +72,9 @@ struct scpl_ctx {
     std::vector<hipEvent_t> gevents;     // one per group
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
     hipEvent_t side_in = nullptr, side_out = nullptr;  // pixel-major lumas beside the segmentation
+    hipStream_t gather_stream = nullptr;  // gathers of clips done early (default priority)
+    std::vector<hipEvent_t> clip_events;  // one per clip gathered early
+    hipEvent_t gathers_done = nullptr;
 };
 
 namespace {
@@ -370,7 +373,20 @@ size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8); }
 size_t pinned_bytes(int nc, int64_t Ntot)
 {
     return align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) + align_up(16 * (size_t)Ntot) +
-           align_up(sizeof(Job) * (size_t)Ntot) + align_up(sizeof(SegArgs) * (size_t)nc);
+           2 * align_up(sizeof(Job) * (size_t)Ntot) + align_up(sizeof(SegArgs) * (size_t)nc);
+}
+
+// The gather stream and one event per clip of clips gathered early.
+scpl_status ensure_clip_tracking(scpl_ctx *ctx, int nc)
+{
+    if (!ctx->gather_stream) SCPL_TRY(hipStreamCreateWithFlags(&ctx->gather_stream, hipStreamNonBlocking));
+    if (!ctx->gathers_done) SCPL_TRY(hipEventCreateWithFlags(&ctx->gathers_done, hipEventDisableTiming));
+    while ((int)ctx->clip_events.size() < nc) {
+        hipEvent_t e;
+        SCPL_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->clip_events.push_back(e);
+    }
+    return SCPL_OK;
 }
 
 // ------------------------------------------------------- height retargeting
@@ -702,6 +718,7 @@ struct Group {
     hipGraphExec_t ge = nullptr;
     int r = 0;                    // iterations enqueued so far
     bool done = false;
+    bool gather = true;           // gather the group's outputs when it is done (else its clips are gathered one by one)
     void release()
     {
         if (ge) (void)hipGraphExecDestroy(ge);
@@ -775,7 +792,7 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
         more = std::max(more, (rem + last - 1) / last);
     }
     if (all) {
-        {
+        if (G.gather) {
             ProfScope ps(ctx, SCPL_KERNEL_GATHER, G.st);
             launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gin, G.ls.gout, ctx->gather_variant, G.st);
         }
@@ -789,10 +806,61 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
     return group_readback(G);
 }
 
+// Clips gathered as soon as their own buffers are carved (run_clips with a
+// ClipDone).  After each state read-back the clips whose jobs have all
+// reached their target width get their gather on the gather stream, and are
+// reported once the gather's event has completed.  A state is read only
+// once the read-back that wrote it has completed, so the job's last
+// iteration has too (a job never leaves the done state); the host states
+// start at -1 so that no state of an earlier call is taken for one.
+struct ClipTracker {
+    scpl_ctx *ctx = nullptr;
+    const ClipDone *cb = nullptr;
+    const int32_t *h_states = nullptr;      // every job's state (pinned), by slot
+    std::vector<std::vector<int>> slots;   // per clip: its jobs' slots
+    std::vector<const Job *> gjobs;         // per clip: its gather table (carving jobs, then memorised buffers)
+    std::vector<int> ngj;
+    std::vector<LaunchShape> ls;
+    std::vector<char> launched, reported;
+    // gathers of the clips whose jobs are all done
+    scpl_status progress()
+    {
+        for (size_t c = 0; c < slots.size(); ++c) {
+            if (launched[c]) continue;
+            bool all = true;
+            for (int q : slots[c]) all = all && h_states[4 * q] >= 0;
+            if (!all) continue;
+            if (ngj[c] > 0) {
+                ProfScope ps(ctx, SCPL_KERNEL_GATHER, ctx->gather_stream);
+                launch_gather(gjobs[c], ngj[c], ls[c].Hmax, ls[c].gin, ls[c].gout, ctx->gather_variant,
+                              ctx->gather_stream);
+            }
+            SCPL_CHECK_LAUNCH();
+            SCPL_TRY(hipEventRecord(ctx->clip_events[c], ctx->gather_stream));
+            launched[c] = 1;
+        }
+        return poll();
+    }
+    // reports the clips whose gathers have completed
+    scpl_status poll()
+    {
+        for (size_t c = 0; c < slots.size(); ++c) {
+            if (!launched[c] || reported[c]) continue;
+            const hipError_t q = hipEventQuery(ctx->clip_events[c]);
+            if (q == hipErrorNotReady) continue;
+            SCPL_TRY(q);
+            reported[c] = 1;
+            (*cb)((int)c);
+        }
+        return SCPL_OK;
+    }
+};
+
 // Runs the groups to completion after the work already on stream s, and
 // makes s wait for all of them.  The host polls the groups' read-backs and
-// feeds whichever is ready.
-scpl_status run_groups(scpl_ctx *ctx, std::vector<Group> &gs, bool use_graph, hipStream_t s)
+// feeds whichever is ready.  trk (nullable): clips gathered one by one.
+scpl_status run_groups(scpl_ctx *ctx, std::vector<Group> &gs, bool use_graph, hipStream_t s,
+                       ClipTracker *trk = nullptr)
 {
     struct Cleanup {
         std::vector<Group> &gs;
@@ -822,14 +890,21 @@ scpl_status run_groups(scpl_ctx *ctx, std::vector<Group> &gs, bool use_graph, hi
             hipError_t q = open == 1 ? hipEventSynchronize(G.ev) : hipEventQuery(G.ev);
             if (q == hipErrorNotReady) continue;
             SCPL_TRY(q);
+            if (trk) SCPL_TRY(trk->progress());  // the read-back has completed
             SCPL_TRY(group_advance(ctx, G));
             if (G.done) --open;
             progressed = true;
         }
+        if (trk && !progressed) SCPL_TRY(trk->poll());
         if (!progressed) std::this_thread::yield();
     }
+    if (trk) SCPL_TRY(trk->progress());
     for (Group &G : gs)
         if (G.st != s) SCPL_TRY(hipStreamWaitEvent(s, G.ev, 0));
+    if (trk) {  // s waits for the clips' gathers too
+        SCPL_TRY(hipEventRecord(ctx->gathers_done, ctx->gather_stream));
+        SCPL_TRY(hipStreamWaitEvent(s, ctx->gathers_done, 0));
+    }
     cleanup.ok = true;
     return SCPL_OK;
 }
@@ -1152,6 +1227,9 @@ void scpl_destroy(scpl_ctx *ctx)
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->side_in) (void)hipEventDestroy(ctx->side_in);
     if (ctx->side_out) (void)hipEventDestroy(ctx->side_out);
+    if (ctx->gather_stream) (void)hipStreamDestroy(ctx->gather_stream);
+    for (hipEvent_t e : ctx->clip_events) (void)hipEventDestroy(e);
+    if (ctx->gathers_done) (void)hipEventDestroy(ctx->gathers_done);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->jws) (void)hipFree(ctx->jws);
     if (ctx->tws) (void)hipFree(ctx->tws);
@@ -1209,7 +1287,7 @@ uint64_t scpl::clip_footprint(const scpl_params &p)
 // clips together, then the carving jobs (one per buffer) -- all at once
 // (batched) or one buffer after another (plain).
 scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
-                            hipStream_t s, bool use_graph)
+                            hipStream_t s, bool use_graph, const ClipDone *on_done)
 {
     // area A: tiled lumas, controller states, window sums
     size_t a_bytes = align_up((size_t)nc * kSegWindow * 8);
@@ -1230,6 +1308,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     int32_t *h_bid_all = host.take<int32_t>((size_t)Ntot);
     int32_t *h_states = host.take<int32_t>(4 * (size_t)Ntot);
     Job *h_jobs = host.take<Job>((size_t)Ntot);
+    Job *h_gjobs = host.take<Job>((size_t)Ntot);  // gather tables of clips gathered early
 
     Bump dev{static_cast<char *>(ctx->ws)};
     unsigned long long *d_sums = dev.take<unsigned long long>((size_t)nc * kSegWindow);
@@ -1343,13 +1422,17 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         pcap = persist_ring(shapes, gpers);
     }
     const size_t pbytes = persist ? persist_bytes(nj, pcap, nring) : 0;
+    // clips gathered as soon as their own buffers are done (job groups)
+    const bool early = batched && !persist && on_done != nullptr && static_cast<bool>(*on_done);
+    const size_t gbytes = early ? align_up(sizeof(Job) * (size_t)(nj + nm)) : 0;
     SCPL_TRY(ensure_jws(ctx, job_area + align_up(sizeof(Job) * (size_t)(nj + nm)) + align_up(16 * (size_t)nj) +
-                                 pbytes));
+                                 pbytes + gbytes));
     Bump jdev{static_cast<char *>(ctx->jws)};
     char *job_ws = jdev.take<char>(job_area);
     Job *d_jobs = jdev.take<Job>((size_t)(nj + nm));  // carving jobs, then memorised buffers
     int32_t *d_states = jdev.take<int32_t>(4 * (size_t)nj);
     char *parea = persist ? jdev.take<char>(pbytes) : nullptr;
+    Job *d_gjobs = early ? jdev.take<Job>((size_t)(nj + nm)) : nullptr;
     // batched: the jobs are dealt to the groups in order of decreasing
     // length, so that every group gets a share of the heavy buffers; a
     // group's jobs are consecutive in the job table
@@ -1393,6 +1476,42 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         h_jobs[nj + q] = J;
     }
     SCPL_TRY(hipMemcpyAsync(d_jobs, h_jobs, sizeof(Job) * (size_t)(nj + nm), hipMemcpyHostToDevice, s));
+    // clips gathered early: per clip, its carving jobs and then its memorised
+    // buffers, contiguous
+    ClipTracker trk;
+    if (early) {
+        SCPL_TRY(ensure_clip_tracking(ctx, nc));
+        trk.ctx = ctx;
+        trk.cb = on_done;
+        trk.h_states = h_states;
+        trk.slots.assign(nc, {});
+        trk.gjobs.assign(nc, nullptr);
+        trk.ngj.assign(nc, 0);
+        trk.ls.assign(nc, LaunchShape{});
+        trk.launched.assign(nc, 0);
+        trk.reported.assign(nc, 0);
+        int at = 0;
+        for (int c = 0; c < nc; ++c) {
+            const int first = at;
+            for (int q = 0; q < nj; ++q)
+                if (pend[q].clip == c) {
+                    trk.slots[c].push_back(slot[q]);
+                    trk.ls[c].add(shape_of(pend[q]), clips[c].p.channels);
+                    h_gjobs[at++] = h_jobs[slot[q]];
+                }
+            for (int q = 0; q < nm; ++q)
+                if (pend[memo[q].src].clip == c) {
+                    trk.ls[c].add(shape_of(pend[memo[q].src]), clips[c].p.channels);
+                    h_gjobs[at++] = h_jobs[nj + q];
+                }
+            trk.gjobs[c] = d_gjobs + first;
+            trk.ngj[c] = at - first;
+        }
+        SCPL_TRY(hipMemcpyAsync(d_gjobs, h_gjobs, sizeof(Job) * (size_t)at, hipMemcpyHostToDevice, s));
+        // the gathers start after the work the call has put on s so far
+        SCPL_TRY(hipEventRecord(ctx->gathers_done, s));
+        SCPL_TRY(hipStreamWaitEvent(ctx->gather_stream, ctx->gathers_done, 0));
+    }
     // gathers the memorised buffers [lo, hi) on stream s, after their sources
     auto gather_memo = [&](int lo, int hi) -> scpl_status {
         if (lo >= hi) return SCPL_OK;
@@ -1449,10 +1568,16 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         std::vector<Group> gs;
         for (int g = 0; g < ng; ++g)
             gs.push_back(make_group(gfirst[g], gsize[g], ng > 1 ? ctx->gstreams[g] : s, ctx->gevents[g]));
-        st = run_groups(ctx, gs, use_graph, s);
+        if (early) {
+            for (Group &G : gs) G.gather = false;
+            for (int q = 0; q < 4 * nj; ++q) h_states[q] = -1;  // before any read-back is enqueued
+        }
+        st = run_groups(ctx, gs, use_graph, s, early ? &trk : nullptr);
         if (st != SCPL_OK) return st;
-        st = gather_memo(0, nm);
-        if (st != SCPL_OK) return st;
+        if (!early) {
+            st = gather_memo(0, nm);
+            if (st != SCPL_OK) return st;
+        }
         return collect_logs(ctx, jobs, s);
     }
     // plain: the next buffer reuses the job area, so a source's memorised
@@ -1477,7 +1602,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
 // Width pass for every clip, then the height pass (transposed) for the clips
 // with a target height.  Each pass is one run of the clips it concerns.
 scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool batched, int32_t *h_nbuf_first,
-                               hipStream_t s, bool use_graph)
+                               hipStream_t s, bool use_graph, const ClipDone *on_done)
 {
     bool any = false;
     size_t tbytes = 0;
@@ -1487,7 +1612,7 @@ scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bo
             tbytes += height_temp_bytes(clips[c].p);
             if (clips[c].p.target_width < clips[c].p.width && clips[c].d_masks) return SCPL_ERR_INVALID_ARG;
         }
-    if (!any) return run_clips(ctx, clips, nc, batched, h_nbuf_first, s, use_graph);
+    if (!any) return run_clips(ctx, clips, nc, batched, h_nbuf_first, s, use_graph, on_done);
     SCPL_TRY(ensure_tws(ctx, tbytes));
     std::vector<scpl_clip> pass1, pass2;
     struct Back {
@@ -1498,10 +1623,12 @@ scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bo
     std::vector<Back> back;
     Bump tb{static_cast<char *>(ctx->tws)};
     std::vector<uint8_t *> src2(nc, nullptr);
+    std::vector<int> orig1;  // clip of each width-pass entry, -1 for the width pass of a 2-D clip
     for (int c = 0; c < nc; ++c) {
         const scpl_clip &cl = clips[c];
         if (!height_pass(cl.p)) {
             pass1.push_back(cl);
+            orig1.push_back(c);
             continue;
         }
         const size_t N = cl.p.n_frames, H = cl.p.height, C = cl.p.channels, Ws = cl.p.target_width;
@@ -1512,12 +1639,17 @@ scpl_status scpl::run_clips_2d(scpl_ctx *ctx, const scpl_clip *clips, int nc, bo
             w.d_masks = nullptr;
             src2[c] = w.d_out;
             pass1.push_back(w);
+            orig1.push_back(-1);
         }
     }
     int32_t nb1 = 0;
     std::vector<int32_t> log1;
     if (!pass1.empty()) {
-        SCPL_TRY(run_clips(ctx, pass1.data(), (int)pass1.size(), batched, &nb1, s, use_graph));
+        const ClipDone done1 = [&](int i) {
+            if (orig1[i] >= 0) (*on_done)(orig1[i]);
+        };
+        SCPL_TRY(run_clips(ctx, pass1.data(), (int)pass1.size(), batched, &nb1, s, use_graph,
+                           on_done ? &done1 : nullptr));
         log1 = ctx->last_log;
     }
     for (int c = 0; c < nc; ++c) {

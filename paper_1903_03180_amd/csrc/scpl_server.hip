@@ -2,11 +2,13 @@
 // one device.  Requests wait in a FIFO queue; each of `lanes` worker threads
 // owns a context and a stream, and whenever it is free takes every queued
 // request that fits the device-memory budget (up to max_batch), admits them
-// by their footprint bound and retargets them as one batch.  Requests that
-// arrive while other batches run are admitted as lanes and memory free up,
-// and their work overlaps on the device with the batches in flight.  Each
-// result is the one scpl_retarget gives for the clip alone: jobs never
-// interact.  Declarations: include/scpl.h.
+// by their footprint bound and retargets them as one batch.  A request is
+// done as soon as its own buffers are carved and its outputs gathered, while
+// the rest of its batch carves on.  Requests that arrive while other batches
+// run are admitted as lanes and memory free up, and their work overlaps on
+// the device with the batches in flight.  Each result is the one
+// scpl_retarget gives for the clip alone: jobs never interact.
+// Declarations: include/scpl.h.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -88,20 +90,42 @@ void lane_main(scpl_server *S, int li)
                 S->queue.pop_front();
             }
         }
+        // a request is done as soon as its own buffers are carved and
+        // gathered; its memory counts against the budget until the batch ends
+        // (the batch's workspace is one)
+        std::vector<uint64_t> bytes;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (int64_t id : batch) bytes.push_back(S->tickets[id].bytes);
+        }
+        const scpl::ClipDone done = [&](int c) {
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                auto it = S->tickets.find(batch[c]);
+                if (it != S->tickets.end() && !it->second.done) {
+                    it->second.done = true;
+                    it->second.result = SCPL_OK;
+                    it->second.t_done = now_us();
+                }
+            }
+            S->cv_done.notify_all();
+        };
         // no graph capture here: the caller's threads may synchronise the
         // device at any time
-        scpl_status res = scpl::run_clips_2d(ctx, clips.data(), (int)clips.size(), true, nullptr, st, false);
+        scpl_status res = scpl::run_clips_2d(ctx, clips.data(), (int)clips.size(), true, nullptr, st, false,
+                                             S->cfg.whole_batch ? nullptr : &done);
         if (res == SCPL_OK && hipStreamSynchronize(st) != hipSuccess) res = SCPL_ERR_DEVICE;
         if (res == SCPL_OK) res = scpl::trim_workspace(ctx, kLaneKeep);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             const double t = now_us();
-            for (int64_t id : batch) {
-                Ticket &tk = S->tickets[id];
-                tk.done = true;
-                tk.result = res;
-                tk.t_done = t;
-                S->in_use -= tk.bytes;
+            for (size_t q = 0; q < batch.size(); ++q) {
+                S->in_use -= bytes[q];
+                auto it = S->tickets.find(batch[q]);
+                if (it == S->tickets.end() || it->second.done) continue;  // done early (and maybe released)
+                it->second.done = true;
+                it->second.result = res;
+                it->second.t_done = t;
             }
         }
         S->cv_done.notify_all();

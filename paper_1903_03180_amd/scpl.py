@@ -75,7 +75,8 @@ class scpl_clip(C.Structure):
 
 
 class scpl_server_config(C.Structure):
-    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("hbm_budget", C.c_uint64)]
+    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("hbm_budget", C.c_uint64),
+                ("whole_batch", C.c_int32)]
 
 
 _P, _I32, _I64 = C.c_void_p, C.c_int32, C.c_int64
@@ -484,9 +485,10 @@ class Server:
     ticket; the dict's tensors must stay alive and untouched until the
     ticket is done."""
 
-    def __init__(self, device: int = 0, lanes: int = 4, max_batch: int = 8, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, lanes: int = 4, max_batch: int = 8, hbm_budget: int = 0,
+                 whole_batch: bool = False):
         h = C.c_void_p()
-        cfg = scpl_server_config(lanes, max_batch, hbm_budget)
+        cfg = scpl_server_config(lanes, max_batch, hbm_budget, 1 if whole_batch else 0)
         _check(scpl_server_create(device, C.byref(cfg), C.byref(h)), "scpl_server_create")
         self.h = h
         self._live = {}

@@ -1,7 +1,7 @@
 """Request server (continuous batching): every request's result is
 bit-identical alone, inside a mix of uneven clips submitted while others
-are running, and to the oracle; admission follows the device-memory
-budget."""
+are running, and to the oracle; a request is done when its own buffers are,
+not when its batch is; admission follows the device-memory budget."""
 import time
 
 import numpy as np
@@ -80,6 +80,42 @@ def test_server_results_alone_and_in_the_mix(ctx, orc):
         assert np.array_equal(a["out"].cpu().numpy(), want["out"])
         assert np.array_equal(a["masks"].cpu().numpy().view(np.uint16), want["masks"])
         assert np.array_equal(a["buffer_id"].cpu().numpy(), want["buffer_id"])
+
+
+def test_small_request_done_before_its_batch(ctx, orc):
+    """One lane: a long request (one seam per iteration) and a small one
+    taken in the same batch.  The small request is done as soon as its own
+    buffers are carved and gathered, well before the long one; both results
+    are the plain path's, the small one also the oracle's."""
+    from paper_1903_03180_amd import scpl
+    big = synth.make_clip(911, 8, 1080, 1920, C=1, n_obj=4, lattice=32)
+    small = make(MIX[0])
+    dbig, dsmall = dev(big), dev(small)
+    solo_big = ctx.retarget(dbig, 1420, 1)
+    torch.cuda.synchronize()
+    srv = scpl.Server(0, lanes=1, max_batch=4)
+    try:
+        # a first request keeps the lane busy, so that the next two are queued
+        # together and taken as one batch
+        first = dev(synth.make_clip(912, 6, 540, 960, C=1, n_obj=3, lattice=32))
+        torch.cuda.synchronize()
+        t0 = srv.submit(dict(frames=first, target_width=880, seams_per_iter=1))
+        tb = srv.submit(dict(frames=dbig, target_width=1420, seams_per_iter=1, want_masks=True))
+        ts = srv.submit(dict(frames=dsmall, target_width=MIX[0]["Wt"], seams_per_iter=MIX[0]["k"], want_masks=True))
+        srv.wait(t0)
+        rs = srv.wait(ts)
+        done_big, _ = srv.poll(tb)
+        qs, tot_s = srv.times(ts)
+        rb = srv.wait(tb)
+        qb, tot_b = srv.times(tb)
+    finally:
+        srv.close()
+    assert not done_big  # the small request was done while the long one carved on
+    assert tot_s - qs + 20.0 < tot_b - qb  # its time in the lane, against the long one's
+    want = orc.retarget(small, MIX[0]["Wt"], MIX[0]["k"])
+    assert np.array_equal(rs["out"].cpu().numpy(), want["out"])
+    assert np.array_equal(rs["masks"].cpu().numpy().view(np.uint16), want["masks"])
+    assert torch.equal(rb["out"], solo_big["out"]) and torch.equal(rb["masks"], solo_big["masks"])
 
 
 @pytest.mark.skip(reason="iteration-level joining (a live job table per lane) was taken out after the benchmark's serving run with it faulted the GPU (memory aperture violation) without a cause found in the code; the server runs each admitted batch to completion again")
