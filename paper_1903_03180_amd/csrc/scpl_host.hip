@@ -368,12 +368,24 @@ scpl_status prof_drain(scpl_ctx *ctx)
 // and the window sums.
 size_t seg_bytes(int64_t HW) { return align_up(HW * 4) + align_up(HW * 8); }
 
+// Buffers of a clip whose first key rows the segmentation keeps, and the
+// device bytes they take.
+int seg_keep_buffers(const scpl_params &p)
+{
+    return (p.use_buffer && p.n_frames >= 2) ? std::min<int>(p.n_frames, kSegKeepBuffers) : 0;
+}
+size_t seg_keep_bytes(const scpl_params &p)
+{
+    return (size_t)seg_keep_buffers(p) * align_up((size_t)p.height * p.width * 2);
+}
+
 // Host staging of one run of nc clips with Ntot frames in all: window sums,
 // segmentation arguments, buffer ids, job states and the job table.
 size_t pinned_bytes(int nc, int64_t Ntot)
 {
     return align_up((size_t)nc * kSegWindow * 8) + align_up(4 * (size_t)Ntot) + align_up(16 * (size_t)Ntot) +
-           2 * align_up(sizeof(Job) * (size_t)Ntot) + align_up(sizeof(SegArgs) * (size_t)nc);
+           2 * align_up(sizeof(Job) * (size_t)Ntot) + align_up(sizeof(SegArgs) * (size_t)nc) +
+           align_up(sizeof(SegFinish) * (size_t)nc);
 }
 
 // The gather stream and one event per clip of clips gathered early.
@@ -434,7 +446,7 @@ size_t area_a_bytes(const scpl_params &p)
     const size_t N = p.n_frames;
     return align_up(kSegWindow * 8) + align_up(N * tiled_frame_bytes(p.height, p.width)) +
            align_up((size_t)p.height * p.width * seq_pitch(p.n_frames)) + seg_bytes((int64_t)p.height * p.width) +
-           align_up(sizeof(SegArgs));
+           align_up(sizeof(SegArgs)) + align_up(sizeof(SegFinish)) + seg_keep_bytes(p);
 }
 
 size_t area_b_bytes(const scpl_params &p)
@@ -509,6 +521,9 @@ struct SegClip {
     void *state;           // seg_bytes(H W)
     int32_t *bid;          // host, N
     int64_t *trace;        // host, N, nullable
+    uint16_t *keep = nullptr;  // device, nkeep x H x W: first key rows of finished buffers
+    int nkeep = 0, kept = 0;
+    std::vector<int> keep_of;  // per buffer: its slot of keep, or -1
     int32_t nbuf = 0;
     // controller
     int t0 = 0, n = 1, nb = 0, t = 1, te = 0;
@@ -521,10 +536,53 @@ struct SegClip {
 // launches, for every clip still open, a speculative scan of a window of
 // candidate frames; after one synchronisation the host accepts each clip's
 // candidates in order and restarts that clip from its first rejected frame.
+// With d_fin / h_fin (room for one per clip), the moments S1 of each
+// finished buffer (up to SegClip::nkeep per clip, memorised buffers skipped)
+// also give its first key rows, which the energy kernel then copies
+// (seg_finish_kernel): before a clip's state is restarted, the frames
+// scanned past the buffer's end are taken out of it.
 scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long long *d_sums,
-                          unsigned long long *h_sums, SegArgs *d_args, SegArgs *h_args, hipStream_t s)
+                          unsigned long long *h_sums, SegArgs *d_args, SegArgs *h_args, hipStream_t s,
+                          SegFinish *d_fin, SegFinish *h_fin)
 {
     const int nc = (int)cl.size();
+    int nfin = 0, fin_ntc = 0, fin_h = 0;
+    // buffer b of clip c, frames [t0, tlo), its moments covering [t0, thi)
+    auto finish = [&](SegClip &c, int b, int t0, int tlo, int thi) {
+        const int m = c.p->memo_period;
+        if (!h_fin || nfin >= nc || c.kept >= c.nkeep || (m >= 2 && b % m != 0)) return;
+        if ((int)c.keep_of.size() <= b) c.keep_of.resize((size_t)b + 1, -1);
+        const int64_t HW = (int64_t)c.p->height * c.p->width;
+        c.keep_of[(size_t)b] = c.kept;
+        SegFinish f{};
+        f.luma = c.tiled;
+        f.FS = c.FS;
+        f.ntc = c.ntc;
+        f.s1 = static_cast<const uint32_t *>(c.state);  // the first array of the state
+        f.out = c.keep + (size_t)c.kept * (align_up((size_t)HW * 2) / 2);
+        f.H = c.p->height;
+        f.W = c.p->width;
+        f.mode = c.p->energy_mode;
+        f.tlo = tlo;
+        f.thi = thi;
+        f.T = tlo - t0;
+        ++c.kept;
+        h_fin[nfin++] = f;
+        fin_ntc = std::max(fin_ntc, c.ntc);
+        fin_h = std::max(fin_h, c.p->height);
+    };
+    // launched before the next window scan, which may restart the states
+    auto launch_finish = [&]() -> scpl_status {
+        if (nfin == 0) return SCPL_OK;
+        SCPL_TRY(hipMemcpyAsync(d_fin, h_fin, sizeof(SegFinish) * (size_t)nfin, hipMemcpyHostToDevice, s));
+        {
+            ProfScope ps(ctx, SCPL_KERNEL_SEGMENT, s);
+            launch_seg_finish(d_fin, nfin, fin_ntc, fin_h, s);
+        }
+        SCPL_CHECK_LAUNCH();
+        nfin = fin_ntc = fin_h = 0;
+        return SCPL_OK;
+    };
     for (SegClip &c : cl) {
         const int N = c.p->n_frames;
         c.bid[0] = 0;
@@ -552,6 +610,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
             const int N = p->n_frames;
             // frames forced into a new buffer by max_buffer need no test
             while (c.t < N && p->max_buffer > 0 && c.n >= p->max_buffer) {
+                if (c.valid) finish(c, c.nb, c.t0, c.t, c.t);
                 if (c.trace) c.trace[c.t] = -1;
                 c.bid[c.t] = ++c.nb;
                 c.t0 = c.t;
@@ -560,6 +619,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
                 ++c.t;
             }
             if (c.t >= N) {
+                if (c.valid) finish(c, c.nb, c.t0, N, N);
                 c.nbuf = c.nb + 1;
                 c.done = true;
                 continue;
@@ -588,6 +648,8 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
             c.launched = true;
             any = true;
         }
+        // the buffers finished so far, before their states are restarted
+        SCPL_TRY(launch_finish());
         if (!any) break;
         // one launch scans the windows of every open clip
         SCPL_TRY(hipMemsetAsync(d_sums, 0, (size_t)nc * kSegWindow * 8, s));
@@ -611,6 +673,7 @@ scpl_status segment_clips(scpl_ctx *ctx, std::vector<SegClip> &cl, unsigned long
                 const int64_t nn = tt - c.t0 + 1;
                 if (c.trace) c.trace[tt] = (int64_t)S;
                 if (asde_rejects(S, nn, HW, emax, p->alpha_num, p->alpha_den)) {
+                    finish(c, c.nb, c.t0, tt, c.te);
                     c.bid[tt] = ++c.nb;
                     c.t0 = tt;
                     c.n = 1;
@@ -1269,14 +1332,14 @@ uint64_t scpl::clip_footprint(const scpl_params &p)
     const uint64_t N = (uint64_t)p.n_frames;
     uint64_t b = align_up((size_t)N * tiled_frame_bytes(p.height, p.width));
     b += align_up((size_t)p.height * p.width * seq_pitch((int)N));
-    b += seg_bytes((int64_t)p.height * p.width) + align_up(kSegWindow * 8);
+    b += seg_bytes((int64_t)p.height * p.width) + seg_keep_bytes(p) + align_up(kSegWindow * 8);
     b += N * (job_bytes(js) + sizeof(Job) + 16) + 2 * kAlign;
     if (height_pass(p)) {
         const scpl_params q = transposed_params(p);
         JobShape jq{q.height, q.width, q.target_width, q.seams_per_iter, dp_geom(q.width)};
         uint64_t b2 = align_up((size_t)N * tiled_frame_bytes(q.height, q.width));
         b2 += align_up((size_t)q.height * q.width * seq_pitch((int)N));
-        b2 += seg_bytes((int64_t)q.height * q.width) + align_up(kSegWindow * 8);
+        b2 += seg_bytes((int64_t)q.height * q.width) + seg_keep_bytes(q) + align_up(kSegWindow * 8);
         b2 += N * (job_bytes(jq) + sizeof(Job) + 16) + 2 * kAlign;
         b = std::max(b, b2) + height_temp_bytes(p);
     }
@@ -1296,15 +1359,16 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         const scpl_params &p = clips[c].p;
         a_bytes += align_up((size_t)p.n_frames * tiled_frame_bytes(p.height, p.width));
         a_bytes += align_up((size_t)p.height * p.width * seq_pitch(p.n_frames));
-        a_bytes += seg_bytes((int64_t)p.height * p.width);
+        a_bytes += seg_bytes((int64_t)p.height * p.width) + seg_keep_bytes(p);
         Ntot += p.n_frames;
     }
-    a_bytes += align_up(sizeof(SegArgs) * (size_t)nc);
+    a_bytes += align_up(sizeof(SegArgs) * (size_t)nc) + align_up(sizeof(SegFinish) * (size_t)nc);
     SCPL_TRY(ensure_ws(ctx, a_bytes));
     SCPL_TRY(ensure_pinned(ctx, pinned_bytes(nc, Ntot)));
     Bump host{static_cast<char *>(ctx->pinned)};
     unsigned long long *h_sums = host.take<unsigned long long>((size_t)nc * kSegWindow);
     SegArgs *h_args = host.take<SegArgs>((size_t)nc);
+    SegFinish *h_fin = host.take<SegFinish>((size_t)nc);
     int32_t *h_bid_all = host.take<int32_t>((size_t)Ntot);
     int32_t *h_states = host.take<int32_t>(4 * (size_t)Ntot);
     Job *h_jobs = host.take<Job>((size_t)Ntot);
@@ -1313,6 +1377,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     Bump dev{static_cast<char *>(ctx->ws)};
     unsigned long long *d_sums = dev.take<unsigned long long>((size_t)nc * kSegWindow);
     SegArgs *d_args = dev.take<SegArgs>((size_t)nc);
+    SegFinish *d_fin = dev.take<SegFinish>((size_t)nc);
     std::vector<SegClip> seg(nc);
     int64_t off = 0;
     for (int c = 0; c < nc; ++c) {
@@ -1326,6 +1391,8 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         sc.tiled = tiled;
         sc.seq = seq;
         sc.state = dev.take<char>(seg_bytes((int64_t)p.height * p.width));
+        sc.nkeep = seg_keep_buffers(p);
+        sc.keep = reinterpret_cast<uint16_t *>(dev.take<char>(seg_keep_bytes(p)));
         sc.bid = h_bid_all + off;
         sc.trace = nullptr;
         off += p.n_frames;
@@ -1349,7 +1416,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     }
     SCPL_CHECK_LAUNCH();
     SCPL_TRY(hipEventRecord(ctx->side_out, side));
-    scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
+    scpl_status st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s, d_fin, h_fin);
     if (st != SCPL_OK) {
         (void)hipStreamSynchronize(side);  // no workspace is released under it
         return st;
@@ -1455,6 +1522,13 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
                          pend[q].bindex);
         J.seq = seg[pend[q].clip].seq;
         J.seqp = seq_pitch(cl.p.n_frames);
+        {
+            const SegClip &sc = seg[pend[q].clip];
+            const int b = pend[q].bindex;
+            const int64_t HW = (int64_t)cl.p.height * cl.p.width;
+            if (b < (int)sc.keep_of.size() && sc.keep_of[(size_t)b] >= 0)
+                J.u0 = sc.keep + (size_t)sc.keep_of[(size_t)b] * (align_up((size_t)HW * 2) / 2);
+        }
         if (!batched) jb.off = 0;  // plain: every buffer reuses the same area
         carve_job(J, js, jb, d_states + 4 * slot[q]);
         h_jobs[slot[q]] = J;
@@ -2319,7 +2393,7 @@ scpl_status scpl_segment(scpl_ctx *ctx, const scpl_params *p, const uint8_t *d_l
     seg[0].trace = h_s_trace;
     launch_tile_luma(d_luma, 1, p->n_frames, p->height, p->width, tiled, s);
     SCPL_CHECK_LAUNCH();
-    st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s);
+    st = segment_clips(ctx, seg, d_sums, h_sums, d_args, h_args, s, nullptr, nullptr);
     if (h_n_buffers) *h_n_buffers = seg[0].nbuf;
     return st;
 }

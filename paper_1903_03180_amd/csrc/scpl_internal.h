@@ -35,6 +35,9 @@ constexpr int kSegWindow = 64;
 // right after another (a scene cut leaves a one-frame buffer), and a long
 // scan that ends early wastes the candidates after the rejection
 constexpr int kSegRestart = 8;
+// buffers per clip whose first key rows the segmentation keeps (later ones are
+// computed by the energy kernel)
+constexpr int kSegKeepBuffers = 4;
 constexpr int kDpThreads = 1024;
 
 // One buffer of one clip: a carving job.  Every iteration of SCPL runs on
@@ -80,6 +83,8 @@ struct Job {
     int32_t *log;           // logcap x 4: (W_r, P_eff, k_iter, 0)
     int32_t *state;         // [0]: iteration at which W_r reached Wt (-1 while running),
                             // [1]: current W_r, [2]: last k_iter, [3]: current iteration
+    const uint16_t *u0;     // the first key rows 4 floor(SE / T), H x W, as the segmentation left them, or
+                            // null (the energy kernel computes them)
 };
 
 struct SegArgs {
@@ -95,6 +100,19 @@ struct SegArgs {
     int32_t init;         // 1: start the moments from frame t0
 };
 
+// A buffer the segmentation has finished, [tlo - T, tlo), whose moments S1
+// cover frames up to thi (seg_finish_kernel).
+struct SegFinish {
+    const uint8_t *luma;  // N tiled frames
+    int64_t FS;           // bytes per tiled frame
+    int32_t ntc;          // tiles per tile row
+    const uint32_t *s1;   // H x W moments
+    uint16_t *out;        // H x W key rows
+    int32_t H, W, mode;
+    int32_t tlo, thi;     // frames scanned past the buffer's end
+    int32_t T;            // the buffer's frames
+};
+
 // Kernel launchers (scpl_kernels.hip).  All take the stream explicitly.
 void launch_luma(const uint8_t *rgb, uint8_t *y, int64_t npx, hipStream_t s);
 // N frames H x W x C (C = 1 or 3, row-major) -> tiled luma
@@ -108,6 +126,8 @@ void launch_seq(const uint8_t *tiled, int N, int H, int W, uint8_t *seq, int seq
 void launch_untile(const uint8_t *src, int N, int H, int W, uint8_t *dst, hipStream_t s);
 // window scans of n clips (d_args: n SegArgs in device memory), one grid layer each
 void launch_seg_windows(const SegArgs *d_args, int n, int ntc_max, int Hmax, hipStream_t s);
+// the first key rows of finished buffers (one grid layer per SegFinish)
+void launch_seg_finish(const SegFinish *d_args, int n, int ntc_max, int Hmax, hipStream_t s);
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s);
 // DP geometry of a launch, chosen from its widest job: Q columns per

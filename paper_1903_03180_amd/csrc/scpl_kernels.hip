@@ -364,6 +364,28 @@ __global__ __launch_bounds__(128) void seq_kernel(const uint8_t *__restrict__ ti
 
 constexpr int kSegRows = 2;
 
+// Energies of the kSegRows x 8 pixels from row r0, tile column tc, of tiled
+// frame t (with the difference to frame t - 1 when diff).
+__device__ __forceinline__ void seg_energies(const uint8_t *luma, int64_t FS, int t, bool diff, int r0, int H, int tc,
+                                             int ntc, int W, int mode, uint32_t (&e)[kSegRows][8])
+{
+    const GLOBAL uint8_t *f = gp(luma) + (size_t)t * FS;
+    const GLOBAL uint8_t *pf = diff ? f - FS : nullptr;
+    int ra[10], rb[10], rc[10];
+    row10(f, r0 - 1, H, tc, ntc, W, ra);
+    row10(f, r0, H, tc, ntc, W, rb);
+#pragma unroll
+    for (int q = 0; q < kSegRows; ++q) {
+        row10(f, r0 + q + 1, H, tc, ntc, W, rc);
+        energy8(ra, rb, rc, pf, r0 + q, H, tc, ntc, mode, e[q]);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            ra[k] = rb[k];
+            rb[k] = rc[k];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void seg_window_kernel(const SegArgs *args)
 {
     __shared__ unsigned long long part[kSegWindow];
@@ -382,21 +404,7 @@ __global__ __launch_bounds__(256) void seg_window_kernel(const SegArgs *args)
     uint32_t s1[kSegRows][8];
     uint64_t s2[kSegRows][8];
     auto energies = [&](int t, bool diff, uint32_t (&e)[kSegRows][8]) {
-        const GLOBAL uint8_t *f = gp(a.luma) + (size_t)t * FS;
-        const GLOBAL uint8_t *pf = diff ? f - FS : nullptr;
-        int ra[10], rb[10], rc[10];
-        row10(f, r0 - 1, a.H, tcc, n, a.W, ra);
-        row10(f, r0, a.H, tcc, n, a.W, rb);
-#pragma unroll
-        for (int q = 0; q < kSegRows; ++q) {
-            row10(f, r0 + q + 1, a.H, tcc, n, a.W, rc);
-            energy8(ra, rb, rc, pf, r0 + q, a.H, tcc, n, a.mode, e[q]);
-#pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                ra[k] = rb[k];
-                rb[k] = rc[k];
-            }
-        }
+        seg_energies(a.luma, FS, t, diff, r0, a.H, tcc, n, a.W, a.mode, e);
     };
     if (valid) {
         if (a.init) {
@@ -453,6 +461,42 @@ __global__ __launch_bounds__(256) void seg_window_kernel(const SegArgs *args)
     }
     __syncthreads();
     if (tid < a.te - a.tb) atomicAdd(&a.sout[tid], part[tid]);
+}
+
+// A finished buffer [t0, t0 + T) whose moments the window scans left
+// covering frames [t0, thi): S1 less the energies of the frames [tlo, thi)
+// scanned past its end (tlo = t0 + T) is the sum over its frames of the
+// energy maps, and 4 floor(S1 / T) its first DP key rows (Sec. 3.2, the
+// uniform energy of the buffer), written to out (H x W).  The energies are
+// those of the window scan, so the difference is exact.
+__global__ __launch_bounds__(256) void seg_finish_kernel(const SegFinish *args)
+{
+    const SegFinish &a = args[blockIdx.z];
+    const int tid = threadIdx.x;
+    const int tc = blockIdx.x * 64 + (tid >> 2);
+    const int r0 = (blockIdx.y * 4 + (tid & 3)) * kSegRows;
+    if (tc >= a.ntc || r0 >= a.H) return;
+    const int nv = min(a.W - 8 * tc, 8);
+    uint32_t acc[kSegRows][8];
+#pragma unroll
+    for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+            acc[q][x] = (r0 + q < a.H && x < nv) ? a.s1[(int64_t)(r0 + q) * a.W + 8 * tc + x] : 0u;
+    for (int t = a.tlo; t < a.thi; ++t) {
+        uint32_t e[kSegRows][8];
+        seg_energies(a.luma, a.FS, t, a.mode == 1, r0, a.H, tc, a.ntc, a.W, a.mode, e);
+#pragma unroll
+        for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+            for (int x = 0; x < 8; ++x) acc[q][x] -= e[q][x];
+    }
+    const uint32_t T = (uint32_t)a.T;
+#pragma unroll
+    for (int q = 0; q < kSegRows; ++q)
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+            if (r0 + q < a.H && x < nv) a.out[(int64_t)(r0 + q) * a.W + 8 * tc + x] = (uint16_t)((acc[q][x] / T) << 2);
 }
 
 // ------------------------------------------------------------ job set-up
@@ -582,6 +626,19 @@ __global__ __launch_bounds__(256) void energy_kernel(const Job *jobs)
     const int r0 = blockIdx.y * 16 + (tid & 3) * 4;
     if (tc >= n || r0 >= H) return;
     const int nv = min(W - 8 * tc, 8);
+    if (J.u0) {  // the key rows the segmentation left (seg_finish_kernel)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = r0 + q;
+            if (i >= H) break;
+            const uint16_t *src = J.u0 + (size_t)i * W + 8 * tc;
+            uint16_t *dst = J.K + (size_t)i * J.Kp + J.KL + 8 * tc;
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+                if (x < nv) dst[x] = src[x];
+        }
+        return;
+    }
     uint32_t acc[4][8];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -2547,6 +2604,12 @@ void launch_seg_windows(const SegArgs *d_args, int n, int ntc_max, int Hmax, hip
 void launch_init_jobs(const Job *d_jobs, int njobs, int Hmax, int, hipStream_t s)
 {
     hipLaunchKernelGGL(init_jobs_kernel, dim3(Hmax + 1, njobs), dim3(256), 0, s, d_jobs);
+}
+
+void launch_seg_finish(const SegFinish *d_args, int n, int ntc_max, int Hmax, hipStream_t s)
+{
+    hipLaunchKernelGGL(seg_finish_kernel, dim3(blocks_for(ntc_max, 64), blocks_for(Hmax, 4 * kSegRows), n),
+                       dim3(256), 0, s, d_args);
 }
 
 void launch_energy(const Job *d_jobs, int njobs, int Hmax, int Wmax, hipStream_t s)

@@ -78,14 +78,17 @@ def test_workspace_size_scales(lib):
 def test_workspace_size_covers_the_clip_areas(lib):
     """The plain path holds the clip's luma twice (16 x 8 tiles for the
     stencils, pixel-major 16-frame pieces for the refresh: N + 1 entries per
-    pixel rounded up to 16) and one job per buffer at a time."""
+    pixel rounded up to 16), the segmentation's moments (S1 in 32 bits, S2 in
+    64), the first key rows of up to four buffers that the segmentation
+    leaves, and one job per buffer at a time."""
     N, H, W = 120, 1080, 1920
     st, a = wsize(lib, base())
     tiled = N * ((H + 15) // 16) * ((W + 7) // 8) * 128
     seq = H * W * ((N + 1 + 15) // 16 * 16)
+    seg = H * W * (4 + 8) + 4 * H * W * 2
     job = H * W * (2 + 2 + 1 + 2)  # column map, key rows, indicator codes, mask
-    assert a >= tiled + seq + job
-    assert a < tiled + seq + 4 * job
+    assert a >= tiled + seq + seg + job
+    assert a < tiled + seq + seg + 3 * job
 
 
 def test_null_context_and_pointers_rejected(lib):
