@@ -740,7 +740,7 @@ def main() -> int:
                     batch_choice["gather_variant"], batch_choice["fuse_variant"]]
     elif args.variants:
         variants = [int(x) for x in args.variants.split(",")]
-    step_rec = measured_step_traffic(args.workload, dpg, variants or [0, 0, 0, 0, 0])
+    step_rec = measured_step_traffic(args.workload, dpg, variants or [0, 0, 0, 4, 0])
     if step_rec is not None:
         gbs = step_rec["bytes_per_step"] / (ms_per_step * 1e-3) / 1e9
         step_hbm = {"source": "rocprofv3 FETCH_SIZE + WRITE_SIZE over every dispatch of a step (calibrated), "

@@ -383,7 +383,10 @@ scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs
  * borg_variant 0 (256), 1 (128) or 2 (512); and the output gather's
  * frames per pass (rows of that many frames staged in LDS together),
  * gather_variant 0 (1), 1 (2), 2 (4) or 3 (8), fewer when the rows do not
- * fit 64 KiB; and whether the seam trace within bands and the compaction
+ * fit 64 KiB, or 4 (the default): each row streamed over its frames, two
+ * wavefronts loading rows two frames ahead and two assembling and storing
+ * them (rows that are not 16-byte multiples or exceed 16 KiB as variant 0);
+ * and whether the seam trace within bands and the compaction
  * run as two launches (fuse_variant 0) or as one kernel per band of rows
  * with 8 (1) or 16 (2) wavefronts per workgroup, which serves launches whose
  * buffers all have 32-row bands and at most 64 seams per iteration (the

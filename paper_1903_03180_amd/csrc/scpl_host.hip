@@ -57,7 +57,7 @@ struct scpl_ctx {
     int upd_variant = 0;                 // compaction kernel variant (kUpdateVariants)
     int refresh_variant = 0;             // refresh kernel variant (0 automatic)
     int borg_variant = 0;                // band-origin kernel variant
-    int gather_variant = 0;              // gather kernel variant (frames per pass)
+    int gather_variant = 4;              // gather kernel variant (frames per pass; 4: streamed)
     int fuse_variant = 0;                // fill + compaction: 0 two launches, 1/2 fused per band
     int batch_mode = SCPL_BATCH_GROUPS;  // how the batched path runs its iterations
     int persist_grid = 0;                // workgroups of the persistent launch (resident at once)
@@ -857,7 +857,7 @@ scpl_status group_advance(scpl_ctx *ctx, Group &G)
     if (all) {
         if (G.gather) {
             ProfScope ps(ctx, SCPL_KERNEL_GATHER, G.st);
-            launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gin, G.ls.gout, ctx->gather_variant, G.st);
+            launch_gather(G.d_jobs, G.nj, G.ls.Hmax, G.ls.gin, G.ls.gout, G.ls.Wmax, ctx->gather_variant, G.st);
         }
         SCPL_CHECK_LAUNCH();
         SCPL_TRY(hipEventRecord(G.ev, G.st));
@@ -895,7 +895,7 @@ struct ClipTracker {
             if (!all) continue;
             if (ngj[c] > 0) {
                 ProfScope ps(ctx, SCPL_KERNEL_GATHER, ctx->gather_stream);
-                launch_gather(gjobs[c], ngj[c], ls[c].Hmax, ls[c].gin, ls[c].gout, ctx->gather_variant,
+                launch_gather(gjobs[c], ngj[c], ls[c].Hmax, ls[c].gin, ls[c].gout, ls[c].Wmax, ctx->gather_variant,
                               ctx->gather_stream);
             }
             SCPL_CHECK_LAUNCH();
@@ -1094,7 +1094,7 @@ scpl_status run_persistent(scpl_ctx *ctx, const Job *d_jobs, int nj, const Launc
     SCPL_CHECK_LAUNCH();
     {
         ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
-        launch_gather(d_jobs, nj, ls.Hmax, ls.gin, ls.gout, ctx->gather_variant, s);
+        launch_gather(d_jobs, nj, ls.Hmax, ls.gin, ls.gout, ls.Wmax, ctx->gather_variant, s);
     }
     SCPL_CHECK_LAUNCH();
     return SCPL_OK;
@@ -1593,7 +1593,7 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
         for (int q = lo; q < hi; ++q) ls.add(shape_of(pend[memo[q].src]), clips[pend[memo[q].src].clip].p.channels);
         {
             ProfScope ps(ctx, SCPL_KERNEL_GATHER, s);
-            launch_gather(d_jobs + nj + lo, hi - lo, ls.Hmax, ls.gin, ls.gout, ctx->gather_variant, s);
+            launch_gather(d_jobs + nj + lo, hi - lo, ls.Hmax, ls.gin, ls.gout, ls.Wmax, ctx->gather_variant, s);
         }
         SCPL_CHECK_LAUNCH();
         return SCPL_OK;

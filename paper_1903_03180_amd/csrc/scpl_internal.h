@@ -180,7 +180,8 @@ void launch_refresh(const Job *d_jobs, int njobs, int kmax, int Hmax, int varian
 // the launch's widest rows would not fit); inb_max / outb_max: the launch's
 // largest source and output row in bytes
 extern const int kNumGatherVariants;
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int variant, hipStream_t s);
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int wmax, int variant,
+                   hipStream_t s);
 // U (H x W int32) -> key rows; *bad |= 1 if some U is outside [0, 16382]
 void launch_u_to_keys(const int32_t *src, uint16_t *dst, int H, int W, int pitch, int32_t *bad, hipStream_t s);
 void launch_keys_to_u(const uint16_t *src, int32_t *dst, int H, int W, int pitch, hipStream_t s);

@@ -2347,12 +2347,8 @@ constexpr size_t kGatherLds = 65536;  // LDS a gather workgroup may take
 __device__ __forceinline__ uint32_t div3(uint32_t x) { return __umulhi(x, 0xAAAAAAABu) >> 1; }
 
 template <int FPB>
-__global__ __launch_bounds__(256) void gather_kernel(const Job *jobs, int lds_bytes)
+__device__ void gather_body(const Job &J, int i, int lds_bytes, uint8_t *gsm)
 {
-    extern __shared__ __align__(16) uint8_t gsm[];
-    const Job &J = jobs[blockIdx.y];
-    const int i = blockIdx.x;
-    if (i >= J.H) return;
     const int16_t *__restrict__ M = J.M + (size_t)i * J.Wp;
     const int C = J.C, W = J.W, Wt = J.Wt, H = J.H;
     const int inb = W * C, outb = Wt * C;
@@ -2442,6 +2438,134 @@ __global__ __launch_bounds__(256) void gather_kernel(const Job *jobs, int lds_by
                 for (int b = tid; b < outb; b += 256) dst[b] = sr[ofs[b]];
             }
             if (J.masks) copy_mask(t0 + f);
+        }
+    }
+}
+
+template <int FPB>
+__global__ __launch_bounds__(256) void gather_kernel(const Job *jobs, int lds_bytes)
+{
+    extern __shared__ __align__(16) uint8_t gsm[];
+    const Job &J = jobs[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= J.H) return;
+    gather_body<FPB>(J, i, lds_bytes, gsm);
+}
+
+// The gather of a row streamed over its frames by two kinds of wavefront.
+// Waves 0-1 load the source row D frames ahead into registers (KL 16-byte
+// loads per lane and frame) and write each frame's row into one of two LDS
+// rows; waves 2-3 assemble the output row (and copy the mask row, staged in
+// LDS once) from the LDS row of the frame before and store it.  gfx9's
+// vmcnt counts loads and stores alike, so a wave that did both would wait
+// for its stores before each frame's loads; here loaders wait only for
+// loads and storers never wait.  Every load takes a clamped frame and
+// offset, so each loader issues the same loads every frame (the compiler
+// can then wait for exactly the oldest frame's).  Rows not 16-byte aligned,
+// wider than 128 KL 16-byte pieces, or that do not fit the LDS gather as in
+// gather_kernel<1>.
+template <int KL, int D>
+__global__ __launch_bounds__(256) void gather_stream_kernel(const Job *jobs, int lds_bytes)
+{
+    extern __shared__ __align__(16) uint8_t gsm[];
+    const Job &J = jobs[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= J.H) return;
+    const int C = J.C, W = J.W, Wt = J.Wt, H = J.H;
+    const int inb = W * C, outb = Wt * C;
+    const int ip = (inb + 15) & ~15;
+    const int q16 = inb / 16, o16 = outb / 16;
+    const int mrow = J.masks ? ((2 * W + 15) & ~15) : 0;
+    const bool aligned = ((((uintptr_t)J.frames) | ((uintptr_t)J.out) | (uintptr_t)inb | (uintptr_t)outb) & 15) == 0 &&
+                         (!J.masks || ((((uintptr_t)J.masks) | (uintptr_t)(2 * W)) & 15) == 0);
+    if (!aligned || q16 > 128 * KL || 2 * (size_t)ip + 2 * (size_t)outb + (size_t)mrow > (size_t)lds_bytes) {
+        gather_body<1>(J, i, lds_bytes, gsm);
+        return;
+    }
+    // the job's fields in registers: stores through out and masks could
+    // alias the job table, which would make every frame reload them
+    const uint8_t *const frames = uniform_ptr(J.frames);
+    uint8_t *const out = uniform_ptr(J.out);
+    uint16_t *const masks = J.masks ? uniform_ptr(J.masks) : nullptr;
+    uint8_t *srow = gsm;                                                  // 2 x ip
+    uint16_t *ofs = reinterpret_cast<uint16_t *>(gsm + 2 * (size_t)ip);  // outb
+    u32x4 *mk = reinterpret_cast<u32x4 *>(gsm + 2 * (size_t)ip + 2 * (size_t)outb);
+    const int16_t *__restrict__ M = J.M + (size_t)i * J.Wp;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < outb; b += 256) {
+        const int j = C == 1 ? b : (int)div3((uint32_t)b);
+        ofs[b] = (uint16_t)(mcol(M, j, W) * C + (b - j * C));
+    }
+    if (masks) {
+        const u32x4 *msrc = reinterpret_cast<const u32x4 *>(J.bmask + (size_t)i * W);
+        for (int q = tid; q < 2 * W / 16; q += 256) mk[q] = gp(msrc)[q];
+    }
+    const int t0 = J.t0, T = J.T;
+    const bool loader = tid < 128;  // waves 0 and 1
+    const int lt = tid & 127;
+    u32x4 v[D][KL];
+    auto load = [&](u32x4(&r)[KL], int t) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(frames + ((size_t)min(t, t0 + T - 1) * H + i) * inb);
+#pragma unroll
+        for (int u = 0; u < KL; ++u) r[u] = gp(src)[min(lt + 128 * u, q16 - 1)];
+    };
+    auto put = [&](const u32x4(&r)[KL], int b) {
+        u32x4 *dst = reinterpret_cast<u32x4 *>(srow + (size_t)b * ip);
+#pragma unroll
+        for (int u = 0; u < KL; ++u)
+            if (lt + 128 * u < q16) dst[lt + 128 * u] = r[u];
+    };
+    if (loader) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(v[d], t0 + d);
+        put(v[0], 0);
+        load(v[0], t0 + D);
+    }
+    __syncthreads();  // offsets, mask row, frame 0's row
+    // Two loops, one per kind of wavefront, with one barrier per frame each
+    // (waves 0-1 take the first, 2-3 the second: the branch is uniform in
+    // every wavefront), so that the compiler counts each kind's memory
+    // operations apart.
+    if (loader) {
+        for (int f = 0; f < T; f += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                if (f + d >= T) break;
+                // frame f + d + 1 into the LDS row the storers left at the
+                // last barrier; its set reloads D frames ahead
+                put(v[(d + 1) % D], (f + d + 1) & 1);
+                load(v[(d + 1) % D], t0 + f + d + 1 + D);
+                __syncthreads();
+            }
+        }
+    } else {
+        const int st = tid - 128;
+        for (int f = 0; f < T; f += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int ff = f + d;
+                if (ff >= T) break;
+                const uint8_t *sr = srow + (size_t)(ff & 1) * ip;
+                u32x4 *dst = reinterpret_cast<u32x4 *>(out + ((size_t)(t0 + ff) * H + i) * outb);
+                for (int q = st; q < o16; q += 128) {
+                    const u32x4 oa = reinterpret_cast<const u32x4 *>(ofs)[2 * q];
+                    const u32x4 ob = reinterpret_cast<const u32x4 *>(ofs)[2 * q + 1];
+                    const uint32_t o[8] = {oa.x, oa.y, oa.z, oa.w, ob.x, ob.y, ob.z, ob.w};
+                    uint32_t w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t p0 = o[2 * k], p1 = o[2 * k + 1];
+                        w[k] = (uint32_t)sr[p0 & 0xffff] | ((uint32_t)sr[p0 >> 16] << 8) |
+                               ((uint32_t)sr[p1 & 0xffff] << 16) | ((uint32_t)sr[p1 >> 16] << 24);
+                    }
+                    gp(dst)[q] = u32x4{w[0], w[1], w[2], w[3]};
+                }
+                if (masks) {
+                    u32x4 *mdst = reinterpret_cast<u32x4 *>(masks + ((size_t)(t0 + ff) * H + i) * W);
+                    for (int q = st; q < 2 * W / 16; q += 128) gp(mdst)[q] = mk[q];
+                }
+                __syncthreads();  // frame ff's row read; frame ff + 1's row written
+            }
         }
     }
 }
@@ -2860,9 +2984,20 @@ void launch_refresh(const Job *d_jobs, int njobs, int, int Hmax, int variant, hi
     else hipLaunchKernelGGL(refresh_kernel<256>, g, dim3(256), 0, s, d_jobs);
 }
 
-// frames staged per pass of the gather variants
-constexpr int kGatherFrames[] = {1, 2, 4, 8};
+// frames staged per pass of the gather variants (0: the streamed kernel)
+constexpr int kGatherFrames[] = {1, 2, 4, 8, 0};
 const int kNumGatherVariants = (int)(sizeof(kGatherFrames) / sizeof(kGatherFrames[0]));
+
+static void launch_gather_stream(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int wmax,
+                                 hipStream_t s)
+{
+    const size_t ip = ((size_t)inb_max + 15) & ~(size_t)15;
+    const size_t lds = std::min(kGatherLds, 2 * ip + 2 * (size_t)outb_max + (((size_t)2 * wmax + 15) & ~(size_t)15));
+    if (inb_max <= 128 * 4 * 16)
+        hipLaunchKernelGGL((gather_stream_kernel<4, 2>), dim3(Hmax, njobs), dim3(256), lds, s, d_jobs, (int)lds);
+    else
+        hipLaunchKernelGGL((gather_stream_kernel<8, 2>), dim3(Hmax, njobs), dim3(256), lds, s, d_jobs, (int)lds);
+}
 
 template <int FPB>
 static void launch_gather_v(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, hipStream_t s)
@@ -2873,11 +3008,16 @@ static void launch_gather_v(const Job *d_jobs, int njobs, int Hmax, int inb_max,
     hipLaunchKernelGGL((gather_kernel<FPB>), dim3(Hmax, njobs), dim3(256), lds, s, d_jobs, (int)lds);
 }
 
-void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int variant, hipStream_t s)
+void launch_gather(const Job *d_jobs, int njobs, int Hmax, int inb_max, int outb_max, int wmax, int variant,
+                   hipStream_t s)
 {
+    int v = std::min(std::max(variant, 0), kNumGatherVariants - 1);
+    if (kGatherFrames[v] == 0) {
+        launch_gather_stream(d_jobs, njobs, Hmax, inb_max, outb_max, wmax, s);
+        return;
+    }
     // fewer frames per pass when the variant's rows do not fit the LDS
     const size_t ip = ((size_t)inb_max + 15) & ~(size_t)15;
-    int v = std::min(std::max(variant, 0), kNumGatherVariants - 1);
     while (v > 0 && (size_t)kGatherFrames[v] * ip + 2 * (size_t)outb_max > kGatherLds) --v;
     switch (kGatherFrames[v]) {
     case 2: launch_gather_v<2>(d_jobs, njobs, Hmax, inb_max, outb_max, s); break;

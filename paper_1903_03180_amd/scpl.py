@@ -280,11 +280,12 @@ class Context:
             arr[i] = scpl_clip(p.c(), _ptr(fr), _ptr(c["out"]), _ptr(c.get("masks")), _ptr(c["buffer_id"]))
         return arr
 
-    def kernel_variants(self, update: int = 0, refresh: int = 0, borg: int = 0, gather: int = 0,
+    def kernel_variants(self, update: int = 0, refresh: int = 0, borg: int = 0, gather: int = 4,
                         fuse: int = 0) -> None:
         """Compaction kernel variant (0-6), refresh kernel variant (0-2),
-        band-origin kernel variant (0-2), gather variant (0-3), fill and
-        compaction fused per band (0: no; 1, 2: 8 or 16 wavefronts)."""
+        band-origin kernel variant (0-2), gather variant (0-4), fill and
+        compaction fused per band (0: no; 1, 2: 8 or 16 wavefronts); no
+        arguments: the context's defaults."""
         _check(scpl_kernel_variants(self.h, update, refresh, borg, gather, fuse), "scpl_kernel_variants")
 
     def autotune_batch(self, clips, reps: int = 2, stream=None) -> dict:

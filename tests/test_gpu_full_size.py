@@ -138,7 +138,7 @@ def test_1080p_clip_every_iteration(ctx, geom, variants):
         res, log = run_plain(ctx, rec["recipe"], d)
     finally:
         ctx.dp_geometry(0)
-        ctx.kernel_variants(0, 0, 0, 0, 0)
+        ctx.kernel_variants()
     check("clip1080p_s2", res, log)
 
 
@@ -161,7 +161,7 @@ def test_1080p_batch_as_benchmarked_every_iteration(ctx):
     try:
         res = run_batch(ctx, rr, frames)
     finally:
-        ctx.kernel_variants(0, 0, 0, 0, 0)
+        ctx.kernel_variants()
     for n, (c, log) in zip(names, res):
         check(n, c, log)
     # and in the persistent launch

@@ -431,8 +431,8 @@ def test_profile_kinds_bracket_only_the_chosen_kernels(ctx):
 @pytest.mark.parametrize("upd,ref,borg,gat,fuse", [
     (0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (2, 0, 0, 0, 0), (3, 0, 0, 0, 0), (4, 0, 0, 0, 0), (5, 0, 0, 0, 0),
     (6, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 2, 0, 0, 0), (0, 0, 1, 0, 0), (0, 0, 2, 0, 0), (0, 0, 0, 1, 0),
-    (0, 0, 0, 2, 0), (0, 0, 0, 3, 0), (4, 2, 2, 3, 0), (5, 1, 1, 2, 0), (0, 0, 0, 0, 1), (0, 0, 0, 0, 2),
-    (3, 1, 2, 2, 1)])
+    (0, 0, 0, 2, 0), (0, 0, 0, 3, 0), (0, 0, 0, 4, 0), (4, 2, 2, 3, 0), (5, 1, 1, 2, 0), (0, 0, 0, 0, 1),
+    (0, 0, 0, 0, 2), (3, 1, 2, 2, 1), (3, 0, 0, 4, 1)])
 def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat, fuse):
     """Every compaction variant (rows per workgroup x columns per pass, so
     widths of several passes), refresh variant, band-origin variant and
@@ -449,17 +449,57 @@ def test_kernel_variants_retarget(ctx, orc, upd, ref, borg, gat, fuse):
         ctx.retarget_batch(clips)
         torch.cuda.synchronize()
     finally:
-        ctx.kernel_variants(0, 0, 0, 0, 0)
+        ctx.kernel_variants()
     for c, f, wt, k in zip(clips, (clip, small), (2450, 210), (20, 6)):
         want = orc.retarget(f, wt, k)
         assert np.array_equal(c["out"].cpu().numpy(), want["out"])
         assert np.array_equal(masks_u16(c["masks"]), want["masks"])
 
 
+# (seed, N, H, W, C, Wt, k)
+STREAMED = [
+    (670, 7, 24, 320, 3, 240, 8),       # 960-byte rows, 720-byte output rows: streamed
+    (671, 5, 20, 2048, 1, 1600, 64),    # streamed
+    (672, 5, 12, 3840, 3, 2880, 96),    # 11,520-byte rows: the loaders' wider register set
+    (673, 3, 10, 6000, 3, 5400, 100),   # 18,000-byte rows: gathered as by variant 0
+    (674, 9, 30, 300, 3, 210, 6),       # 900-byte rows (not 16-byte multiples): as variant 0
+]
+
+
+@pytest.mark.parametrize("want_masks", [True, False])
+def test_gather_streamed_rows(ctx, orc, want_masks):
+    """Gather variant 4 streams each row over its frames (two wavefronts
+    load rows two frames ahead, two assemble and store), for rows that are
+    16-byte multiples of at most 16 KiB; other rows of the same launch are
+    gathered as by variant 0.  Buffers of odd length, with and without
+    masks, batched and plain, against the oracle."""
+    host = [synth.make_clip(seed, N, H, W, C=C, n_obj=2, cut_at=N // 2, lattice=8)
+            for seed, N, H, W, C, Wt, k in STREAMED]
+    want = [orc.retarget(f, sp[5], sp[6]) for f, sp in zip(host, STREAMED)]
+    ctx.kernel_variants(0, 0, 0, 4, 0)
+    try:
+        clips = [dict(frames=dev(f), target_width=sp[5], seams_per_iter=sp[6], want_masks=want_masks)
+                 for f, sp in zip(host, STREAMED)]
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+        plain = [ctx.retarget(dev(f), sp[5], sp[6], want_masks=want_masks) for f, sp in zip(host, STREAMED[:3])]
+        torch.cuda.synchronize()
+    finally:
+        ctx.kernel_variants()
+    for c, w in zip(clips, want):
+        assert np.array_equal(c["out"].cpu().numpy(), w["out"])
+        if want_masks:
+            assert np.array_equal(masks_u16(c["masks"]), w["masks"])
+    for g, w in zip(plain, want):
+        assert np.array_equal(g["out"].cpu().numpy(), w["out"])
+        if want_masks:
+            assert np.array_equal(masks_u16(g["masks"]), w["masks"])
+
+
 def test_kernel_variants_refused(ctx):
     from paper_1903_03180_amd import scpl
     for v in ((-1, 0, 0, 0, 0), (7, 0, 0, 0, 0), (0, -1, 0, 0, 0), (0, 3, 0, 0, 0), (0, 0, -1, 0, 0),
-              (0, 0, 3, 0, 0), (0, 0, 0, -1, 0), (0, 0, 0, 4, 0), (0, 0, 0, 0, -1), (0, 0, 0, 0, 3)):
+              (0, 0, 3, 0, 0), (0, 0, 0, -1, 0), (0, 0, 0, 5, 0), (0, 0, 0, 0, -1), (0, 0, 0, 0, 3)):
         with pytest.raises(scpl.ScplError):
             ctx.kernel_variants(*v)
 
@@ -516,7 +556,7 @@ def test_fused_band_update_uneven_and_tall(ctx, orc, fuse):
         ctx.retarget_batch(clips)
         torch.cuda.synchronize()
     finally:
-        ctx.kernel_variants(0, 0, 0, 0, 0)
+        ctx.kernel_variants()
     for c, (f, wt, k) in zip(clips, cases):
         want = orc.retarget(f, wt, k)
         assert np.array_equal(c["out"].cpu().numpy(), want["out"])
