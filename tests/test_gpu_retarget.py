@@ -519,7 +519,7 @@ def test_autotune_batch_keeps_results(orc):
         torch.cuda.synchronize()
         assert choice["streams"] in (2, 3, 4) and choice["ms"] > 0
         assert 0 <= choice["update_variant"] < 7 and 0 <= choice["refresh_variant"] < 3
-        assert 0 <= choice["borg_variant"] < 3 and 0 <= choice["gather_variant"] < 4
+        assert 0 <= choice["borg_variant"] < 3 and 0 <= choice["gather_variant"] < 5
         assert 0 <= choice["fuse_variant"] < 3
         assert choice["batch_mode"] in (0, 1) and choice["persist_workgroups"] > 0
         for cl, f in zip(clips, frames):
