@@ -2774,15 +2774,16 @@ const DpGeom kDpChunked[] = {
     {4, 16, 1, 8, 0, 384, 128},  {4, 16, 1, 8, 0, 352, 192},  {4, 16, 1, 8, 0, 288, 320},
     {2, 8, 1, 16, 0, 128, 640},  {2, 8, 1, 16, 0, 64, 768},   {4, 8, 1, 8, 0, 128, 704},
     {2, 8, 1, 16, 0, 192, 64},   {2, 8, 1, 16, 0, 160, 128},  {2, 8, 1, 16, 0, 128, 192},
-    {2, 8, 1, 16, 0, 208, 32},   {2, 8, 1, 16, 0, 216, 16}};
+    {2, 8, 1, 16, 0, 208, 32},   {2, 8, 1, 16, 0, 216, 16},
+    {4, 16, 1, 16, 0, 256, 384}, {4, 16, 1, 16, 0, 320, 384}, {4, 16, 1, 16, 0, 192, 512}};
 const int kNumDpChunked = (int)(sizeof(kDpChunked) / sizeof(kDpChunked[0]));
 
 bool dp_geom_fits(const DpGeom &g, int Wmax)
 {
     if (!g.banded) return true;
     if (g.R > 0)  // the instantiated dp_chunk_kernel variants
-        return ((g.Q == 4 && g.HB == 16 && g.PF == 8) || (g.Q == 2 && g.HB == 8 && g.PF == 16) ||
-                (g.Q == 4 && g.HB == 8 && g.PF == 8)) &&
+        return ((g.Q == 4 && g.HB == 16 && (g.PF == 8 || g.PF == 16)) ||
+                (g.Q == 2 && g.HB == 8 && g.PF == 16) || (g.Q == 4 && g.HB == 8 && g.PF == 8)) &&
                g.C() > 0 && g.P > 0 && g.P % g.Q == 0 && g.R % g.Q == 0 && g.R >= g.HB &&
                g.threads(Wmax) <= dp_max_threads(g.Q, g.PF) && (size_t)2 * g.chunk_waves() * g.C() * 4 <= 65536;
     return g.C() > 0 && g.threads(Wmax) <= dp_max_threads(g.Q, g.PF) && (size_t)2 * (g.cover(Wmax) + 64) * 4 <= 65536;
@@ -2820,6 +2821,7 @@ void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax
         return;                                                                                           \
     }
         SCPL_DPC_CASE(4, 16, 8)
+        SCPL_DPC_CASE(4, 16, 16)
         SCPL_DPC_CASE(2, 8, 16)
         SCPL_DPC_CASE(4, 8, 8)
 #undef SCPL_DPC_CASE
@@ -2911,7 +2913,8 @@ void set_kernel_attributes(size_t lds_cap)
         reinterpret_cast<const void *>(&dp_band_kernel<8, 16, 16>), reinterpret_cast<const void *>(&dp_band_kernel<8, 32, 8>),
         reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 4>), reinterpret_cast<const void *>(&dp_band_kernel<16, 32, 8>),
         reinterpret_cast<const void *>(&dp_band_kernel<16, 64, 4>), reinterpret_cast<const void *>(&dp_chunk_kernel<4, 16, 8>),
-        reinterpret_cast<const void *>(&dp_chunk_kernel<2, 8, 16>), reinterpret_cast<const void *>(&dp_chunk_kernel<4, 8, 8>)};
+        reinterpret_cast<const void *>(&dp_chunk_kernel<2, 8, 16>), reinterpret_cast<const void *>(&dp_chunk_kernel<4, 8, 8>),
+        reinterpret_cast<const void *>(&dp_chunk_kernel<4, 16, 16>)};
     for (const void *f : dps) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&select_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);

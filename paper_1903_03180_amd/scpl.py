@@ -57,7 +57,8 @@ DP_CHUNKED = [(4, 16, 8, 256, 384), (4, 16, 8, 384, 256), (4, 16, 8, 320, 384), 
               (4, 16, 8, 384, 128), (4, 16, 8, 352, 192), (4, 16, 8, 288, 320),
               (2, 8, 16, 128, 640), (2, 8, 16, 64, 768), (4, 8, 8, 128, 704),
               (2, 8, 16, 192, 64), (2, 8, 16, 160, 128), (2, 8, 16, 128, 192), (2, 8, 16, 208, 32),
-              (2, 8, 16, 216, 16)]
+              (2, 8, 16, 216, 16), (4, 16, 16, 256, 384), (4, 16, 16, 320, 384),
+              (4, 16, 16, 192, 512)]
 
 KERNELS = ["luma", "segment", "energy", "dp", "borg", "select", "fill", "update", "gather", "init", "refresh",
            "persist"]

@@ -293,7 +293,8 @@ def test_forced_geometry_retarget(ctx, orc, geom):
         ctx.dp_geometry(0)
 
 
-@pytest.mark.parametrize("geom", [(4, 16, 8, 1, 32, 64), (2, 8, 16, 0, 16, 96), (4, 16, 8, 1, 128, 640)])
+@pytest.mark.parametrize("geom", [(4, 16, 8, 1, 32, 64), (2, 8, 16, 0, 16, 96), (4, 16, 8, 1, 128, 640),
+                                  (4, 16, 16, 1, 40, 96), (4, 16, 16, 0, 64, 128)])
 def test_chunked_geometry_retarget(ctx, orc, geom):
     """Whole retargets with a column-split DP (many row chunks and
     workgroups for the small R, P), against the oracle."""

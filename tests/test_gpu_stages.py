@@ -179,7 +179,8 @@ def test_dp_every_geometry(ctx, orc, geom):
         ctx.dp_geometry(0)
 
 
-CHUNKED = DP_CHUNKED + [(4, 16, 8, 16, 64), (2, 8, 16, 8, 16), (4, 8, 8, 32, 96)]
+CHUNKED = DP_CHUNKED + [(4, 16, 8, 16, 64), (2, 8, 16, 8, 16), (4, 8, 8, 32, 96), (4, 16, 16, 20, 64),
+                        (4, 16, 16, 48, 96)]
 
 
 @pytest.mark.parametrize("geom", [g + (ex,) for g in CHUNKED for ex in (0, 1)])
