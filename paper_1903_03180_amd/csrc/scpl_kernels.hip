@@ -1201,15 +1201,25 @@ __device__ __forceinline__ void dp_chunk_body(const Job &J, int Wr, int gx, int 
     }
 }
 
+// Workgroups go to the eight XCDs in turn by their number, and each XCD has
+// an L2 of its own.  The ngx workgroups of a job read overlapping covers
+// (neighbours share 2R columns), so they are numbered to land on one XCD:
+// workgroup gx of job y is number 8 (gx + ngx floor(y / 8)) + y mod 8.  The
+// grid has ngx ceil(njobs / 8) 8 workgroups; those past the last job return.
 template <int Q, int HB, int PF>
-__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int r0, int R, int P)
+__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int njobs, int ngx, int r0,
+                                                                          int R, int P)
 {
     extern __shared__ uint32_t rowbuf[];  // 2 x nwv C keys: the cover
-    const Job &J = jobs[blockIdx.y];
+    const int L = (int)blockIdx.x;
+    const int job = 8 * ((L >> 3) / ngx) + (L & 7);
+    const int gx = (L >> 3) % ngx;
+    if (job >= njobs) return;
+    const Job &J = jobs[job];
     const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
     const int Wr = __builtin_amdgcn_readfirstlane(job_width(J, r));
     if (Wr <= J.Wt) return;
-    dp_chunk_body<Q, HB, PF>(J, Wr, (int)blockIdx.x, r0, R, P, (int)blockDim.x, rowbuf);
+    dp_chunk_body<Q, HB, PF>(J, Wr, gx, r0, R, P, (int)blockDim.x, rowbuf);
 }
 
 // ----------------------------------------------------------- band origins
@@ -2811,13 +2821,15 @@ size_t g_dp_lds_cap = 65536;  // LDS of one compute unit as a workgroup may requ
 void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax, hipStream_t s)
 {
     if (g.banded && g.R > 0) {
-        const dim3 grid(g.groups(Wmax), njobs), block(g.threads(Wmax));
+        const int ngx = g.groups(Wmax);
+        const dim3 grid(ngx * ((njobs + 7) / 8) * 8), block(g.threads(Wmax));
         size_t lds = (size_t)2 * g.chunk_waves() * g.C() * sizeof(uint32_t);
         if (g.EX && lds < g_dp_lds_cap) lds = g_dp_lds_cap;
 #define SCPL_DPC_CASE(q, hb, pf)                                                                          \
     if (g.Q == q && g.HB == hb && g.PF == pf) {                                                           \
         for (int r0 = 0; r0 < Hmax; r0 += g.R)                                                            \
-            hipLaunchKernelGGL((dp_chunk_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, r0, g.R, g.P);  \
+            hipLaunchKernelGGL((dp_chunk_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, njobs, ngx, r0, g.R, \
+                               g.P);                                                                      \
         return;                                                                                           \
     }
         SCPL_DPC_CASE(4, 16, 8)
