@@ -1203,17 +1203,18 @@ __device__ __forceinline__ void dp_chunk_body(const Job &J, int Wr, int gx, int 
 
 // Workgroups go to the eight XCDs in turn by their number, and each XCD has
 // an L2 of its own.  The ngx workgroups of a job read overlapping covers
-// (neighbours share 2R columns), so they are numbered to land on one XCD:
-// workgroup gx of job y is number 8 (gx + ngx floor(y / 8)) + y mod 8.  The
-// grid has ngx ceil(njobs / 8) 8 workgroups; those past the last job return.
+// (neighbours share 2R columns), so with xcd_local they are numbered to land
+// on one XCD: workgroup gx of job y is number 8 (gx + ngx floor(y / 8)) +
+// y mod 8, in a grid of ngx ceil(njobs / 8) 8 workgroups (those past the
+// last job return); otherwise it is number gx + ngx y.
 template <int Q, int HB, int PF>
-__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int njobs, int ngx, int r0,
-                                                                          int R, int P)
+__global__ __launch_bounds__(dp_max_threads(Q, PF)) void dp_chunk_kernel(const Job *jobs, int njobs, int ngx,
+                                                                          int xcd_local, int r0, int R, int P)
 {
     extern __shared__ uint32_t rowbuf[];  // 2 x nwv C keys: the cover
     const int L = (int)blockIdx.x;
-    const int job = 8 * ((L >> 3) / ngx) + (L & 7);
-    const int gx = (L >> 3) % ngx;
+    const int job = xcd_local ? 8 * ((L >> 3) / ngx) + (L & 7) : L / ngx;
+    const int gx = xcd_local ? (L >> 3) % ngx : L % ngx;
     if (job >= njobs) return;
     const Job &J = jobs[job];
     const int r = __builtin_amdgcn_readfirstlane(job_iter(J));
@@ -2822,14 +2823,17 @@ void launch_dp(const Job *d_jobs, int njobs, const DpGeom &g, int Wmax, int Hmax
 {
     if (g.banded && g.R > 0) {
         const int ngx = g.groups(Wmax);
-        const dim3 grid(ngx * ((njobs + 7) / 8) * 8), block(g.threads(Wmax));
+        // a job's workgroups on one XCD once every XCD has a job (with fewer
+        // jobs, spreading them over all XCDs measured faster)
+        const int xl = njobs >= 8 ? 1 : 0;
+        const dim3 grid(xl ? ngx * ((njobs + 7) / 8) * 8 : ngx * njobs), block(g.threads(Wmax));
         size_t lds = (size_t)2 * g.chunk_waves() * g.C() * sizeof(uint32_t);
         if (g.EX && lds < g_dp_lds_cap) lds = g_dp_lds_cap;
 #define SCPL_DPC_CASE(q, hb, pf)                                                                          \
     if (g.Q == q && g.HB == hb && g.PF == pf) {                                                           \
         for (int r0 = 0; r0 < Hmax; r0 += g.R)                                                            \
-            hipLaunchKernelGGL((dp_chunk_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, njobs, ngx, r0, g.R, \
-                               g.P);                                                                      \
+            hipLaunchKernelGGL((dp_chunk_kernel<q, hb, pf>), grid, block, lds, s, d_jobs, njobs, ngx, xl, r0,  \
+                               g.R, g.P);                                                                 \
         return;                                                                                           \
     }
         SCPL_DPC_CASE(4, 16, 8)
