@@ -577,11 +577,11 @@ def main() -> int:
         dpg = ctx.dp_chosen(Wmax)
         log(f"DP geometry forced: {dpg}")
     else:
-        if args.plain_steps > 0 and len(clips) > 1:  # the plain path runs one buffer at a time
-            ctx.autotune_dp(Hmax, Wmax, n_jobs=1)
-        dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
+        # the library's default geometry for the batch (the one the counter
+        # profiles cover); the DP autotuner runs with the batch autotuner
+        # below, on a context of its own
         dpg = ctx.dp_chosen(Wmax)
-        log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
+        log(f"DP geometry (default): {dpg}")
 
     # the batch autotuner (whole steps of this workload under each candidate
     # configuration: job groups, DP geometry, kernel variants, the persistent
@@ -597,6 +597,10 @@ def main() -> int:
         tctx = scpl.Context(0)
         try:
             b0 = time.perf_counter()
+            nj_dp = min(3 * len(clips), 256)
+            dpus = tctx.autotune_dp(Hmax, Wmax, n_jobs=nj_dp)[4]
+            dp_tuned = {"jobs": nj_dp, "geometry": tctx.dp_chosen(Wmax), "us_per_dp": round(dpus, 1)}
+            log(f"DP autotune for {nj_dp} jobs of {Hmax}x{Wmax}: {dp_tuned['geometry']}: {dpus:.1f} us per DP")
             batch_choice = tctx.autotune_batch(clips, reps=2)
             log(f"batch autotune ({time.perf_counter() - b0:.1f} s): {batch_choice}")
             tctx.retarget_batch(clips)
@@ -608,7 +612,7 @@ def main() -> int:
             tms = (time.perf_counter() - t0) * 1e3 / args.steps
         finally:
             tctx.close()
-        batch_tuned = {"choice": batch_choice, "ms_per_step": round(tms, 3),
+        batch_tuned = {"dp_autotune": dp_tuned, "choice": batch_choice, "ms_per_step": round(tms, 3),
                        "fps": round(n_frames / (tms * 1e-3), 2),
                        "timing": "graph-replayed steps in the autotuner's configuration, on a context of its own"}
         log(f"autotuned configuration: {tms:.2f} ms/step, {batch_tuned['fps']:.1f} frames/s")
@@ -710,6 +714,8 @@ def main() -> int:
     # plain path: clips one after another, buffers one after another
     plain_fps = None
     if args.plain_steps > 0:
+        if not args.dp_geometry and len(clips) > 1:  # the plain path runs one buffer at a time
+            ctx.autotune_dp(Hmax, Wmax, n_jobs=1)
         p0 = time.perf_counter()
         for _ in range(args.plain_steps):
             for c in clips:
