@@ -1614,10 +1614,15 @@ __device__ __forceinline__ void compact_row(const Job &J, int r, int Wr, int kk,
         if (staged) return thr[min(s, kUpdSeams)];
         return s < kk ? (int)R[s] - s : 0x7fffffff;
     };
-    // row buffers (Wp and Kp - KL entries, multiples of 64) as buffer resources
-    const __amdgpu_buffer_rsrc_t rM = __builtin_amdgcn_make_buffer_rsrc((void *)Mr, (short)0, 2 * Wp, 0x00020000);
+    // the rows' first Wr entries (rounded up to whole 16-byte groups, within
+    // the Wp and Kp - KL entries of the row buffers) as buffer resources: the
+    // staged passes request whole groups up to SPAN + kk columns past their
+    // start, and those past the current width read 0 and move no data
+    const int wr8 = (Wr + 7) & ~7;
+    const __amdgpu_buffer_rsrc_t rM =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Mr, (short)0, 2 * min(wr8, Wp), 0x00020000);
     const __amdgpu_buffer_rsrc_t rK =
-        __builtin_amdgcn_make_buffer_rsrc((void *)Kr, (short)0, 2 * (J.Kp - J.KL), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)Kr, (short)0, 2 * min(wr8, J.Kp - J.KL), 0x00020000);
     // columns left of the first threshold keep their entries: passes start at
     // the 8-aligned column below it
     const int jstart = min(rs(0), Wn) & ~7;
