@@ -70,6 +70,22 @@ struct scpl_ctx {
     bool persist_traced = false;
     std::vector<hipStream_t> gstreams;   // their streams (default priority)
     std::vector<hipEvent_t> gevents;     // one per group
+    // per job group: its iteration graph and the launch arguments it was
+    // captured with; a later call with the same arguments replays it
+    struct GraphCache {
+        std::vector<int64_t> key;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        void release()
+        {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            ge = nullptr;
+            g = nullptr;
+            key.clear();
+        }
+    };
+    std::vector<GraphCache> gcache;
     hipEvent_t fork = nullptr;           // groups start after the caller's stream reaches it
     hipEvent_t side_in = nullptr, side_out = nullptr;  // pixel-major lumas beside the segmentation
     hipStream_t gather_stream = nullptr;  // gathers of clips done early (default priority)
@@ -779,17 +795,32 @@ struct Group {
     hipEvent_t ev = nullptr;      // completes with the group's latest state read-back
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    int slot = -1;                // index of the group in the context's graph cache (-1: none)
+    bool cached = false;          // g and ge belong to the context's graph cache
     int r = 0;                    // iterations enqueued so far
     bool done = false;
     bool gather = true;           // gather the group's outputs when it is done (else its clips are gathered one by one)
     void release()
     {
-        if (ge) (void)hipGraphExecDestroy(ge);
-        if (g) (void)hipGraphDestroy(g);
+        if (!cached) {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+        }
         ge = nullptr;
         g = nullptr;
     }
 };
+
+// Everything enqueue_iteration's launches depend on besides the stream: the
+// job table, the launch shape, the DP geometry and the kernel variants.
+std::vector<int64_t> graph_key(const scpl_ctx *ctx, const Group &G)
+{
+    const LaunchShape &l = G.ls;
+    return {(int64_t)(uintptr_t)G.d_jobs, G.nj,          l.Hmax,    l.Wmax,    l.nbmax,   l.kmax,
+            l.Bmax,                       l.g.Q,         l.g.HB,    l.g.banded, l.g.PF,   l.g.EX,
+            l.g.R,                        l.g.P,         ctx->borg_variant,    ctx->upd_variant,
+            ctx->refresh_variant,         ctx->fuse_variant, (int64_t)ctx->lds_cap, kGraphIters};
+}
 
 scpl_status group_readback(Group &G)
 {
@@ -827,13 +858,35 @@ scpl_status group_start(scpl_ctx *ctx, Group &G, bool use_graph)
     }
     SCPL_CHECK_LAUNCH();
     if (use_graph && !ctx->profiling && s != nullptr && G.rfirst > 0) {
-        SCPL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int q = 0; q < kGraphIters; ++q) enqueue_iteration(ctx, G.d_jobs, G.nj, G.ls, s);
-        hipError_t le = hipGetLastError();
-        hipError_t ce = hipStreamEndCapture(s, &G.g);
-        SCPL_TRY(le);
-        SCPL_TRY(ce);
-        SCPL_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
+        // the graph of the previous call of this group when its launches
+        // would be the same (the kernels read the job table when they run)
+        std::vector<int64_t> key;
+        scpl_ctx::GraphCache *c = nullptr;
+        if (G.slot >= 0) {
+            if ((int)ctx->gcache.size() <= G.slot) ctx->gcache.resize((size_t)G.slot + 1);
+            c = &ctx->gcache[(size_t)G.slot];
+            key = graph_key(ctx, G);
+        }
+        if (c && c->ge && c->key == key) {
+            G.g = c->g;
+            G.ge = c->ge;
+            G.cached = true;
+        } else {
+            SCPL_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int q = 0; q < kGraphIters; ++q) enqueue_iteration(ctx, G.d_jobs, G.nj, G.ls, s);
+            hipError_t le = hipGetLastError();
+            hipError_t ce = hipStreamEndCapture(s, &G.g);
+            SCPL_TRY(le);
+            SCPL_TRY(ce);
+            SCPL_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
+            if (c) {  // the previous call's graph has finished running
+                c->release();
+                c->key = std::move(key);
+                c->g = G.g;
+                c->ge = G.ge;
+                G.cached = true;
+            }
+        }
     }
     SCPL_TRY(group_iterate(ctx, G, std::min(G.rfirst, kMaxAhead)));
     return group_readback(G);
@@ -1286,6 +1339,7 @@ void scpl_destroy(scpl_ctx *ctx)
         (void)hipEventDestroy(pp.b);
     }
     for (hipStream_t st : ctx->gstreams) (void)hipStreamDestroy(st);
+    for (scpl_ctx::GraphCache &c : ctx->gcache) c.release();
     for (hipEvent_t e : ctx->gevents) (void)hipEventDestroy(e);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->side_in) (void)hipEventDestroy(ctx->side_in);
@@ -1640,8 +1694,10 @@ scpl_status scpl::run_clips(scpl_ctx *ctx, const scpl_clip *clips, int nc, bool 
     }
     if (batched) {
         std::vector<Group> gs;
-        for (int g = 0; g < ng; ++g)
+        for (int g = 0; g < ng; ++g) {
             gs.push_back(make_group(gfirst[g], gsize[g], ng > 1 ? ctx->gstreams[g] : s, ctx->gevents[g]));
+            gs.back().slot = g;
+        }
         if (early) {
             for (Group &G : gs) G.gather = false;
             for (int q = 0; q < 4 * nj; ++q) h_states[q] = -1;  // before any read-back is enqueued

@@ -562,3 +562,28 @@ def test_fused_band_update_uneven_and_tall(ctx, orc, fuse):
         want = orc.retarget(f, wt, k)
         assert np.array_equal(c["out"].cpu().numpy(), want["out"])
         assert np.array_equal(masks_u16(c["masks"]), want["masks"])
+
+
+def test_batch_graph_replayed_across_calls(ctx, orc):
+    """A job group replays the iteration graph of the previous call when its
+    launches would be the same (same job table, shapes, geometry and kernel
+    variants; the kernels read the job table when they run).  Batches of
+    the same shapes with other frames, one after another, and the first
+    again, each against the oracle; then a batch of other shapes."""
+    shapes = [(9, 40, 120, 3, 90, 6), (12, 33, 150, 1, 110, 4), (7, 50, 96, 1, 70, 8), (10, 24, 200, 3, 150, 5)]
+
+    def batch(seed0, shp):
+        host = [synth.make_clip(seed0 + q, N, H, W, C=C, n_obj=3, cut_at=N // 2, lattice=8)
+                for q, (N, H, W, C, Wt, k) in enumerate(shp)]
+        clips = [dict(frames=dev(f), target_width=Wt, seams_per_iter=k, want_masks=True)
+                 for f, (N, H, W, C, Wt, k) in zip(host, shp)]
+        ctx.retarget_batch(clips)
+        torch.cuda.synchronize()
+        for c, f, (N, H, W, C, Wt, k) in zip(clips, host, shp):
+            want = orc.retarget(f, Wt, k)
+            assert np.array_equal(c["out"].cpu().numpy(), want["out"])
+            assert np.array_equal(masks_u16(c["masks"]), want["masks"])
+
+    for seed0 in (720, 730, 720):
+        batch(seed0, shapes)
+    batch(740, [(8, 30, 100, 1, 80, 3), (6, 28, 64, 3, 50, 2)])
