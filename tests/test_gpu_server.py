@@ -222,3 +222,28 @@ def test_server_rejects_invalid_requests():
             srv.poll(12345)
     finally:
         srv.close()
+
+
+def test_whole_batch_completion_results(ctx):
+    """With whole_batch, every request of a batch completes with its batch
+    (the early-completion path switched off): the results are still the ones
+    each clip gets alone."""
+    from paper_1903_03180_amd import scpl
+    frames = [make(s) for s in MIX]
+    solo = [ctx.retarget(dev(f), s["Wt"], s["k"], **kwargs(s)) for f, s in zip(frames, MIX)]
+    torch.cuda.synchronize()
+    srv = scpl.Server(0, lanes=1, max_batch=len(MIX), whole_batch=True)
+    try:
+        clips = [dict(frames=dev(f), target_width=s["Wt"], seams_per_iter=s["k"], want_masks=True, **kwargs(s))
+                 for f, s in zip(frames, MIX)]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(c) for c in clips]
+        results = [srv.wait(t) for t in tickets]
+        for r, a in zip(results, solo):
+            assert torch.equal(r["out"], a["out"])
+            assert torch.equal(r["masks"], a["masks"])
+            assert torch.equal(r["buffer_id"], a["buffer_id"])
+        for t in tickets:
+            srv.release(t)
+    finally:
+        srv.close()
