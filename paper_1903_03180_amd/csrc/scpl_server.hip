@@ -39,6 +39,16 @@ struct Ticket {
     double t_submit = 0, t_start = 0, t_done = 0;
 };
 
+// A request the batched path would refuse for the whole batch: masks asked
+// for a clip carved in both dimensions (the masks of the width pass and of
+// the height pass do not fit one array).  Such a request fails alone.
+bool refused_in_batch(const scpl_clip &c)
+{
+    const scpl_params &p = c.p;
+    const bool height = p.target_height > 0 && p.target_height < p.height;
+    return height && p.target_width < p.width && c.d_masks != nullptr;
+}
+
 // Workspace a lane keeps between batches (more is returned to the device;
 // freeing device memory waits for the whole device, so it is kept rare).
 constexpr uint64_t kLaneKeep = 16ull << 30;
@@ -80,8 +90,17 @@ void lane_main(scpl_server *S, int li)
             });
             if (S->stop) return;
             const double t = now_us();
+            bool refused = false;
             while (!S->queue.empty() && (int)batch.size() < S->cfg.max_batch) {
                 Ticket &tk = S->tickets[S->queue.front()];
+                if (refused_in_batch(tk.clip)) {  // completes with its error, outside any batch
+                    tk.t_start = tk.t_done = t;
+                    tk.result = SCPL_ERR_INVALID_ARG;
+                    tk.done = true;
+                    refused = true;
+                    S->queue.pop_front();
+                    continue;
+                }
                 if (S->in_use + tk.bytes > S->cfg.hbm_budget) break;
                 S->in_use += tk.bytes;
                 tk.t_start = t;
@@ -89,7 +108,9 @@ void lane_main(scpl_server *S, int li)
                 clips.push_back(tk.clip);
                 S->queue.pop_front();
             }
+            if (refused) S->cv_done.notify_all();
         }
+        if (batch.empty()) continue;
         // a request is done as soon as its own buffers are carved and
         // gathered; its memory counts against the budget until the batch ends
         // (the batch's workspace is one)

@@ -150,9 +150,8 @@ def test_small_request_joins_and_leaves_before_a_large_one(ctx, orc):
     assert torch.equal(rb["out"], solo_big["out"]) and torch.equal(rb["masks"], solo_big["masks"])
 
 
-@pytest.mark.skip(reason="iteration-level joining (a live job table per lane) was taken out after the benchmark's serving run with it faulted the GPU (memory aperture violation) without a cause found in the code; the server runs each admitted batch to completion again")
 def test_failing_request_fails_alone(ctx):
-    """A request that fails at admission (masks asked for a clip carved in
+    """A request the batched path refuses (masks asked for a clip carved in
     both dimensions) reports its error; the requests around it in the same
     lane are unaffected and bit-identical to their plain results."""
     from paper_1903_03180_amd import scpl
