@@ -2,7 +2,8 @@
 RGB, both energies, with and without buffers, varied alpha, seams per
 iteration, buffer-length limits and seam memorisation, some with a target
 height; each on the plain path, and all of them in one batched call (several
-job groups, uneven shapes side by side) and in one persistent launch.  Output frames, masks and buffer
+job groups, uneven shapes side by side) and in one persistent launch; and
+frames 450 to 2600 columns wide, plain and batched.  Output frames, masks and buffer
 ids must equal the oracle's."""
 import numpy as np
 import pytest
@@ -113,3 +114,46 @@ def test_random_clips_persistent(cases):
             check(seed, d["out"], d.get("masks"), d["buffer_id"], want)
     finally:
         c.close()
+
+
+def draw_wide(seed):
+    rng = np.random.default_rng(seed)
+    N = int(rng.integers(2, 8))
+    H = int(rng.integers(16, 160))
+    W = int(rng.integers(450, 2600))
+    C = int(rng.choice([1, 3]))
+    Wt = int(rng.integers(int(W * 0.8), W))
+    k = int(rng.choice([4, 16, 64]))
+    kw = dict(energy_mode=int(rng.integers(0, 2)), alpha_num=1, alpha_den=int(rng.choice([5, 20])),
+              max_buffer=int(rng.choice([0, 3])))
+    f = synth.make_clip(seed, N, H, W, C=C, n_obj=3, cut_at=N // 2, lattice=16)
+    return f, Wt, k, kw
+
+
+WIDE_SEEDS = list(range(7500, 7540))
+
+
+@pytest.fixture(scope="module")
+def wide_cases(orc):
+    out = []
+    for s in WIDE_SEEDS:
+        f, Wt, k, kw = draw_wide(s)
+        want = orc.retarget(f, Wt, k, mode=kw["energy_mode"], anum=kw["alpha_num"], aden=kw["alpha_den"],
+                            max_buffer=kw["max_buffer"])
+        out.append((s, f, Wt, k, kw, want))
+    return out
+
+
+def test_random_wide_clips(ctx, wide_cases):
+    """Frames 450 to 2600 columns wide (the column-split DP, several bands
+    and compaction passes): plain, then all in one batch."""
+    for seed, f, Wt, k, kw, want in wide_cases:
+        got = ctx.retarget(dev(f), Wt, k, **kw)
+        torch.cuda.synchronize()
+        check(seed, got["out"], got["masks"], got["buffer_id"], want)
+    clips = [dict(frames=dev(f), target_width=Wt, seams_per_iter=k, want_masks=True, **kw)
+             for seed, f, Wt, k, kw, want in wide_cases]
+    ctx.retarget_batch(clips)
+    torch.cuda.synchronize()
+    for c, (seed, f, Wt, k, kw, want) in zip(clips, wide_cases):
+        check(seed, c["out"], c["masks"], c["buffer_id"], want)
