@@ -95,13 +95,16 @@ def test_small_request_done_before_its_batch(ctx, orc):
     torch.cuda.synchronize()
     srv = scpl.Server(0, lanes=1, max_batch=4)
     try:
-        # a first request keeps the lane busy, so that the next two are queued
-        # together and taken as one batch
+        # a first request keeps the lane busy (a few hundred iterations), so
+        # that the next two are queued together and taken as one batch; the
+        # pause lets the lane take the first one alone before they arrive
         first = dev(synth.make_clip(912, 6, 540, 960, C=1, n_obj=3, lattice=32))
         torch.cuda.synchronize()
-        t0 = srv.submit(dict(frames=first, target_width=880, seams_per_iter=1))
+        t0 = srv.submit(dict(frames=first, target_width=660, seams_per_iter=1))
+        time.sleep(0.02)
         tb = srv.submit(dict(frames=dbig, target_width=1420, seams_per_iter=1, want_masks=True))
         ts = srv.submit(dict(frames=dsmall, target_width=MIX[0]["Wt"], seams_per_iter=MIX[0]["k"], want_masks=True))
+        assert not srv.poll(t0)[0]  # still running: the two were queued behind it
         srv.wait(t0)
         rs = srv.wait(ts)
         done_big, _ = srv.poll(tb)
