@@ -570,18 +570,28 @@ def main() -> int:
                                           device="cuda"),
                           buffer_id=torch.empty(c.shape[0], dtype=torch.int32, device="cuda")))
     torch.cuda.synchronize()
+    # workloads with committed counter profiles time the configuration the
+    # profiles were taken in (the library's defaults)
+    profiled = os.path.exists(os.path.join(ROOT, "profiles", f"step_traffic_{args.workload.replace('-', '_')}.json"))
     if args.dp_geometry:
         q, hb, pf, ex, r, p = (int(x) for x in args.dp_geometry.split(","))
         ctx.dp_geometry(q, hb, pf, ex)
         ctx.dp_chunking(r, p)
         dpg = ctx.dp_chosen(Wmax)
         log(f"DP geometry forced: {dpg}")
-    else:
+    elif profiled:
         # the library's default geometry for the batch (the one the counter
         # profiles cover); the DP autotuner runs with the batch autotuner
         # below, on a context of its own
         dpg = ctx.dp_chosen(Wmax)
-        log(f"DP geometry (default): {dpg}")
+        log(f"DP geometry (default, profiled): {dpg}")
+    else:
+        # no counter profiles for this workload: the DP geometry tuned for its
+        # number of concurrent jobs (and, for the plain path of a single clip,
+        # the nearest tuned job count)
+        dpus = ctx.autotune_dp(Hmax, Wmax, n_jobs=min(3 * len(clips), 256))[4]
+        dpg = ctx.dp_chosen(Wmax)
+        log(f"DP autotune for {min(3 * len(clips), 256)} jobs of {Hmax}x{Wmax}: {dpg}: {dpus:.1f} us per DP")
 
     # the batch autotuner (whole steps of this workload under each candidate
     # configuration: job groups, DP geometry, kernel variants, the persistent
