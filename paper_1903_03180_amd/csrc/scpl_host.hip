@@ -332,7 +332,19 @@ DpGeom select_geom(const scpl_ctx *ctx, int Wmax, int njobs = 1 << 20)
                 bd = d;
             }
         }
-    return best ? best->g : dp_geom(Wmax);
+    if (best) return best->g;
+    // untuned: launches of at most four buffers from 449 to 8960 columns take
+    // the column split (2,8,16), 192 rows by 64 columns (the autotuner's pick
+    // for one to three 1080- and 2160-row buffers); more buffers the default
+    // of dp_geom.  The job workspaces are sized for dp_geom's, which covers
+    // more columns.
+    if (njobs <= 4 && Wmax > 448 && Wmax <= 8960) {
+        DpGeom g{2, 8, 1, 16, 1};
+        g.R = 192;
+        g.P = 64;
+        return g;
+    }
+    return dp_geom(Wmax);
 }
 
 // ----------------------------------------------------------- kernel timing
