@@ -359,14 +359,15 @@ scpl_status scpl_dp_geometry(scpl_ctx *ctx, int32_t Q, int32_t HB, int32_t PF, i
  * side, which stay exact for the R rows).  scpl_dp_chunking(ctx, R, P)
  * applies to the geometry last forced by scpl_dp_geometry (R = 0: one
  * launch of one workgroup per buffer again); valid for (Q, HB, PF) in
- * (4,16,8) (2,8,16) (4,8,8) with R and P multiples of Q, R >= HB, and a
- * cover of P + 2R columns that the workgroup's wavefronts can hold.
+ * (4,16,8) (4,16,16) (2,8,16) (4,8,8) with R and P multiples of Q, R >= HB,
+ * and a cover of P + 2R columns that the workgroup's wavefronts can hold.
  * scpl_dp_chosen writes the geometry used for launches whose widest job has
  * width W and that run the most concurrent jobs any choice at W was timed
  * with: h_geom[6] = (Q, HB, PF, EX, R, P).
- * Without a forced or tuned geometry: (2,8,8) for W <= 448; the column-split
- * (4,16,8) with EX = 1, R = 256 and P = 384 up to W = 8960; the
- * row-synchronous kernel beyond. */
+ * Without a forced or tuned geometry: (2,8,8) for W <= 448; up to W = 8960
+ * the column-split (2,8,16) with EX = 1, R = 192 and P = 64 for launches of
+ * at most four jobs, else the column-split (4,16,8) with EX = 1, R = 256 and
+ * P = 384 (what scpl_dp_chosen reports); the row-synchronous kernel beyond. */
 scpl_status scpl_dp_chunking(scpl_ctx *ctx, int32_t R, int32_t P);
 scpl_status scpl_dp_chosen(scpl_ctx *ctx, int32_t W, int32_t *h_geom);
 scpl_status scpl_autotune_dp(scpl_ctx *ctx, int32_t H, int32_t W, int32_t n_jobs, int32_t *h_Q, int32_t *h_HB,
